@@ -1,0 +1,168 @@
+"""Pins of the oracle's intermediate-state solvers.
+
+* ``direct_solve`` is checked against the U_c = 0 closed form, the
+  complex-symmetric resolvent identity and the a-posteriori bound.
+* ``msbicg_reference`` (Appendix D in the corrected reading) is checked against
+  ``direct_solve``, against the collinearity of the shifted true residuals
+  with the seed residual (Eqs. shiftCoeff / collinearity), against the m = 0
+  closed form, and against exact termination for a diagonal H.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import groundstate as gs
+from oracle import hubbard as hb
+from oracle import solve as so
+
+
+@pytest.fixture(scope="module")
+def ring():
+    B = hb.Basis(6, 3, 3)
+    bonds = W.chain_bonds(6, 1.0)
+    H = hb.hamiltonian(B, bonds, 8.0)
+    Hp = hb.hamiltonian(B, bonds, 8.0, core_site=0, Uc=-4.0)
+    E_G, G, _ = gs.dense_ground_state(H)
+    return B, H, Hp, E_G, G
+
+
+def test_direct_methods_agree(ring):
+    B, H, Hp, E_G, G = ring
+    E = W.random_complex(B.dim, 3)
+    w = np.linspace(-5, 5, 7)
+    a = so.direct_solve(Hp, E, E_G, 1.0, w, "eig")
+    b = so.direct_solve(Hp, E, E_G, 1.0, w, "lu")
+    c = so.direct_solve(Hp, E, E_G, 1.0, w, "splu")
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+    assert np.max(np.abs(a - c)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_uc_zero_closed_form(ring):
+    """U_c = 0: E = G is an eigenvector of A, Psi = -G / (w + i Gamma)."""
+    B, H, Hp, E_G, G = ring
+    w = np.array([-3.0, 0.0, 0.7, 5.0])
+    psi = so.direct_solve(H, G.astype(complex), E_G, 0.5, w, "lu")
+    for k, wk in enumerate(w):
+        assert np.allclose(psi[k], -G / (wk + 0.5j), rtol=0, atol=1e-12)
+
+
+def test_resolvent_identity(ring):
+    """E^T (Psi_1 - Psi_2) = (w_1 - w_2) Psi_1^T Psi_2 for complex-symmetric A."""
+    B, H, Hp, E_G, G = ring
+    E = W.random_complex(B.dim, 4)
+    w = np.array([-2.0, 1.3])
+    p = so.direct_solve(Hp, E, E_G, 1.0, w, "lu")
+    lhs = E @ (p[0] - p[1])
+    rhs = (w[0] - w[1]) * (p[0] @ p[1])
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
+def test_reference_recurrence_matches_direct_solve(ring):
+    B, H, Hp, E_G, G = ring
+    E = G.astype(complex)
+    w = np.linspace(-10, 10, 41)
+    ref = so.direct_solve(Hp, E, E_G, 1.0, w, "eig")
+    A = lambda x: Hp @ x - (E_G + 1j) * x
+    res = so.msbicg_reference(A, E, w, 1e-13, 2000)
+    assert res.converged and not res.breakdown
+    err = np.linalg.norm(res.psi - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= 1e-10
+
+
+def test_reference_with_seed_shift_and_complex_rhs(ring):
+    B, H, Hp, E_G, G = ring
+    E = W.random_complex(B.dim, 8)
+    w = np.linspace(-6, 6, 13)
+    ref = so.direct_solve(Hp, E, E_G, 0.7, w, "eig")
+    A = lambda x: Hp @ x - (E_G + 0.7j) * x
+    res = so.msbicg_reference(A, E, w, 1e-12, 3000, seed_shift=2.5)
+    err = np.linalg.norm(res.psi - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= 1e-9
+
+
+def test_printed_plus_sign_solves_mirrored_shifts(ring):
+    """The zeta recurrence with (1 + alpha w) (as printed) reproduces the solve at -w,
+    so the oracle's (1 - alpha w) reading is the one that solves (A - w) Psi = E."""
+    B, H, Hp, E_G, G = ring
+    E = G.astype(complex)
+    w = np.array([-4.0, 3.0])
+    A = lambda x: Hp @ x - (E_G + 1j) * x
+    res_minus = so.msbicg_reference(A, E, -w, 1e-12, 2000)    # run with -w == "+" sign at w
+    ref_plus = so.direct_solve(Hp, E, E_G, 1.0, w, "eig")
+    ref_mirror = so.direct_solve(Hp, E, E_G, 1.0, -w, "eig")
+    assert np.max(np.abs(res_minus.psi - ref_mirror)) <= 1e-9 * np.max(np.abs(ref_mirror))
+    assert np.max(np.abs(res_minus.psi - ref_plus)) > 1e-3 * np.max(np.abs(ref_plus))
+
+
+@pytest.mark.parametrize("m", [1, 4, 15, 40])
+def test_shifted_residuals_are_collinear_with_seed(ring, m):
+    """True residual of every shifted iterate = r_m / zeta_m (Eq. collinearity).
+
+    The seed itself is one of the shifts (w = seed shift -> zeta = 1), so its true
+    residual is the seed residual r_m; every other shift's true residual must equal
+    it divided by the recurrence's zeta_m(w)."""
+    B, H, Hp, E_G, G = ring
+    E = W.random_complex(B.dim, 6)
+    seed = 0.0
+    w = np.array([seed, -7.0, -1.0, 2.5, 9.0])
+    A = lambda x: Hp @ x - (E_G + 1j) * x
+    res = so.msbicg_reference(A, E, w, 1e-30, m, seed_shift=seed, keep_zeta=True)
+    assert res.iters == m
+    zeta = res.zeta[-1]
+    assert np.all(res.zeta[:, 0] == 1.0)           # the seed's zeta stays exactly 1
+    r_true = np.stack([E - (A(res.psi[k]) - w[k] * res.psi[k]) for k in range(len(w))])
+    r_seed = r_true[0]
+    for k in range(1, len(w)):
+        pred = r_seed / zeta[k]
+        assert np.linalg.norm(r_true[k] - pred) <= 1e-8 * np.linalg.norm(E) + 1e-8 * np.linalg.norm(pred)
+
+
+def test_first_iterate_closed_form(ring):
+    """After one iteration Psi_1(w) = alpha_0(w) E with alpha_0(w) = rho_0 / (E^T A E - w rho_0)."""
+    B, H, Hp, E_G, G = ring
+    E = W.random_complex(B.dim, 7)
+    w = np.array([-2.0, 0.0, 3.0])
+    A = lambda x: Hp @ x - (E_G + 1j) * x
+    res = so.msbicg_reference(A, E, w, 1e-30, 1)
+    rho0 = E @ E
+    for k, wk in enumerate(w):
+        a0 = rho0 / (E @ A(E) - wk * rho0)
+        assert np.allclose(res.psi[k], a0 * E, rtol=1e-12, atol=0)
+
+
+def test_diagonal_hamiltonian_terminates_exactly():
+    """t = 0: A is diagonal with few distinct values; the Krylov space is exhausted
+    after (#distinct eigenvalues) iterations and the solve is exact."""
+    B = hb.Basis(6, 3, 3)
+    Hp = hb.hamiltonian(B, [(i, (i + 1) % 6, 0.0) for i in range(6)], 4.0, core_site=0, Uc=-3.0)
+    n_distinct = len(np.unique(Hp.diagonal()))
+    E = W.random_vector(B.dim, 2).astype(complex)
+    w = np.linspace(-3, 3, 5)
+    A = lambda x: Hp @ x - (0.5 + 1j) * x
+    res = so.msbicg_reference(A, E, w, 1e-12, 50)
+    assert res.iters <= n_distinct
+    ref = so.direct_solve(Hp, E, 0.5, 1.0, w, "eig")
+    assert np.max(np.abs(res.psi - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_a_posteriori_bound(ring):
+    """A - w is normal with |(A - w)^{-1}| <= 1/Gamma, so |Psi - Psi*| <= |r_true| / Gamma."""
+    B, H, Hp, E_G, G = ring
+    E = W.random_complex(B.dim, 9)
+    w = np.linspace(-5, 5, 6)
+    A = lambda x: Hp @ x - (E_G + 0.8j) * x
+    res = so.msbicg_reference(A, E, w, 1e-5, 2000)
+    ref = so.direct_solve(Hp, E, E_G, 0.8, w, "eig")
+    for k in range(len(w)):
+        r = E - (A(res.psi[k]) - w[k] * res.psi[k])
+        assert np.linalg.norm(res.psi[k] - ref[k]) <= np.linalg.norm(r) / 0.8 * (1 + 1e-10)
+
+
+def test_rho_breakdown_detected():
+    """E = e_0 + i e_1 has E^T E = 0 (COCG cannot start)."""
+    B = hb.Basis(4, 2, 2)
+    Hp = hb.hamiltonian(B, W.chain_bonds(4, 1.0), 4.0, core_site=0, Uc=-2.0)
+    E = np.zeros(B.dim, complex)
+    E[0], E[1] = 1.0, 1.0j
+    res = so.msbicg_reference(lambda x: Hp @ x - (1 + 1j) * x, E, [0.0, 1.0], 1e-10, 10)
+    assert res.breakdown and res.iters == 0

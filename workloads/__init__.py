@@ -1,0 +1,227 @@
+"""Seeded synthetic workloads shared by the oracle tests, the GPU tests and the bench.
+
+This module holds only the *description* of each workload: lattice geometry
+(the list of hopping bonds), model parameters, incident-energy and energy-loss
+grids, and seeded random numbers.  It contains none of the method's
+arithmetic: no basis, no Hamiltonian, no solver and no spectrum code.  Both
+the CPU oracle (``oracle/``) and the HIP library receive these values as plain
+arguments, so neither side imports the other.
+
+Models follow the single-band Hubbard Hamiltonian with nearest-neighbour
+hopping t and next-nearest-neighbour hopping t' (paper Sec. III, Eq.
+``Hubbard``); the core hole adds U_c on one site of the intermediate-state
+Hamiltonian (Eq. ``intermediate_H``).  Energies are in units of t.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "chain_bonds", "square_bonds", "Workload", "WORKLOADS", "get",
+    "random_vector", "random_complex", "sobol_params", "sector_dim",
+]
+
+
+def chain_bonds(L: int, t: float = 1.0, tp: float = 0.0, periodic: bool = True):
+    """Bonds (i, j, t_ij) of an L-site chain.
+
+    Nearest-neighbour bonds carry ``t``; if ``tp`` is non-zero, next-nearest
+    bonds (i, i+2) carry ``tp``.  With ``periodic`` the wrap-around bonds are
+    included as ordinary bonds.  Each unordered pair appears once.
+    """
+    bonds = []
+    seen = set()
+
+    def add(i, j, amp):
+        key = (min(i, j), max(i, j))
+        if i == j or key in seen:
+            return
+        seen.add(key)
+        bonds.append((i, j, float(amp)))
+
+    for i in range(L):
+        j = i + 1
+        if j < L:
+            add(i, j, t)
+        elif periodic:
+            add(i, j % L, t)
+    if tp != 0.0:
+        for i in range(L):
+            j = i + 2
+            if j < L:
+                add(i, j, tp)
+            elif periodic:
+                add(i, j % L, tp)
+    return bonds
+
+
+def square_bonds(Lx: int, Ly: int, t: float = 1.0, tp: float = 0.0):
+    """Bonds of an Lx x Ly periodic square cluster; site index = x + Lx*y.
+
+    Nearest neighbours (x+1, y), (x, y+1) carry ``t``; diagonal neighbours
+    (x+1, y+1), (x+1, y-1) carry ``tp``.  Each unordered pair appears once.
+    """
+    bonds = []
+    seen = set()
+
+    def site(x, y):
+        return (x % Lx) + Lx * (y % Ly)
+
+    def add(a, b, amp):
+        key = (min(a, b), max(a, b))
+        if a == b or key in seen:
+            return
+        seen.add(key)
+        bonds.append((a, b, float(amp)))
+
+    for y in range(Ly):
+        for x in range(Lx):
+            s = site(x, y)
+            add(s, site(x + 1, y), t)
+            add(s, site(x, y + 1), t)
+    if tp != 0.0:
+        for y in range(Ly):
+            for x in range(Lx):
+                s = site(x, y)
+                add(s, site(x + 1, y + 1), tp)
+                add(s, site(x + 1, y - 1), tp)
+    return bonds
+
+
+def sector_dim(L: int, n_up: int, n_dn: int) -> int:
+    """Dimension of the fixed-(N_up, N_dn) sector: C(L, N_up) * C(L, N_dn)."""
+    return math.comb(L, n_up) * math.comb(L, n_dn)
+
+
+@dataclass
+class Workload:
+    """One synthetic workload: model, right-hand sides and grids."""
+    name: str
+    n_sites: int
+    n_up: int
+    n_dn: int
+    bonds: list
+    U: float
+    Uc: float
+    Gamma: float
+    w_in: np.ndarray            # incident energies (measured from the edge)
+    tol: float
+    dtype: str                  # "c128" or "c64"
+    core_sites: list            # core-hole site of each right-hand side
+    o2_weights: list            # (w_up, w_dn) of O2 = w_up n_up(j) + w_dn n_dn(j); None = identity
+    phases: list                # complex phase of each right-hand side in the coherent sum
+    w_loss: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    eta: float = 0.1
+    gs_seed: int = 12345
+    seed_shift: float = 0.0
+    maxit: int = 2000
+    note: str = ""
+
+    @property
+    def dim(self) -> int:
+        return sector_dim(self.n_sites, self.n_up, self.n_dn)
+
+    @property
+    def nrhs(self) -> int:
+        return len(self.core_sites)
+
+
+def _tiny():
+    L = 8
+    return Workload(
+        name="tiny_L8_N4", n_sites=L, n_up=4, n_dn=4,
+        bonds=chain_bonds(L, 1.0), U=8.0, Uc=-4.0, Gamma=1.0,
+        w_in=np.linspace(-10.0, 10.0, 64), tol=1e-13, dtype="c128",
+        core_sites=[0], o2_weights=[None], phases=[1.0 + 0j],
+        w_loss=np.linspace(0.0, 10.0, 256), eta=0.1,
+        note="L=8 ring, N=4+4, D=4900, 64 shifts in [-10,10], 256 losses in [0,10]")
+
+
+def _scale():
+    L = 12
+    q = math.pi / 2
+    return Workload(
+        name="scale_L12_N6", n_sites=L, n_up=6, n_dn=6,
+        bonds=chain_bonds(L, 1.0, 0.0), U=8.0, Uc=-4.0, Gamma=1.0,
+        w_in=np.linspace(-12.0, 12.0, 200), tol=1e-10, dtype="c128",
+        core_sites=list(range(L)), o2_weights=[None] * L,
+        phases=[complex(math.cos(q * j), math.sin(q * j)) for j in range(L)],
+        w_loss=np.linspace(0.0, 10.0, 256), eta=0.1,
+        note="L=12 ring, N=6+6, D=853776, 12 core-hole sites x 200 shifts in [-12,12], q=pi/2")
+
+
+def _precision():
+    L = 14
+    return Workload(
+        name="precision_L14_N7", n_sites=L, n_up=7, n_dn=7,
+        bonds=chain_bonds(L, 1.0), U=8.0, Uc=-4.0, Gamma=1.0,
+        w_in=np.linspace(-12.0, 12.0, 256), tol=1e-8, dtype="c64",
+        core_sites=[0], o2_weights=[None], phases=[1.0 + 0j],
+        w_loss=np.linspace(0.0, 10.0, 256), eta=0.1,
+        note="L=14 ring, N=7+7, D=11778624, 256 shifts in [-12,12]")
+
+
+def _batched():
+    # Two core-hole sites x two diagonal O2 patterns (charge-like n_up+n_dn,
+    # spin-like n_up-n_dn) -> four real right-hand sides.
+    return Workload(
+        name="batched_4x4_N5", n_sites=16, n_up=5, n_dn=5,
+        bonds=square_bonds(4, 4, 1.0, -0.25), U=8.0, Uc=-4.0, Gamma=1.0,
+        w_in=np.linspace(-10.0, 10.0, 64), tol=1e-8, dtype="c64",
+        core_sites=[0, 0, 5, 5], o2_weights=[(1.0, 1.0), (1.0, -1.0), (1.0, 1.0), (1.0, -1.0)],
+        phases=[1.0 + 0j] * 4,
+        w_loss=np.linspace(0.0, 10.0, 256), eta=0.1,
+        note="4x4 periodic, t'=-0.25, N=5+5, D=19079424, 4 RHS x 64 shifts in [-10,10]")
+
+
+def _learned():
+    L = 10
+    return Workload(
+        name="learned_L10_N5", n_sites=L, n_up=5, n_dn=5,
+        bonds=chain_bonds(L, 1.0, -0.2), U=8.0, Uc=-4.0, Gamma=1.0,
+        w_in=np.linspace(-10.0, 10.0, 128), tol=1e-8, dtype="c128",
+        core_sites=[0], o2_weights=[None], phases=[1.0 + 0j],
+        w_loss=np.linspace(0.0, 10.0, 256), eta=0.1,
+        note="L=10 ring, N=5+5, D=63504; per-sample (U, t', Uc, Gamma) vary")
+
+
+WORKLOADS = {
+    "tiny": _tiny,
+    "scale": _scale,
+    "precision": _precision,
+    "batched": _batched,
+    "learned": _learned,
+}
+
+
+def get(name: str) -> Workload:
+    return WORKLOADS[name]()
+
+
+def random_vector(dim: int, seed: int) -> np.ndarray:
+    """Seeded standard-normal real vector (float64)."""
+    return np.random.default_rng(seed).standard_normal(dim)
+
+
+def random_complex(dim: int, seed: int) -> np.ndarray:
+    """Seeded complex vector with standard-normal real and imaginary parts."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(dim) + 1j * rng.standard_normal(dim)
+
+
+def sobol_params(n: int, seed: int = 7, skip: int = 0) -> np.ndarray:
+    """Scrambled-Sobol samples of (U, t', U_c, Gamma) in the learned-form box.
+
+    Ranges: U in [4, 12], t' in [-0.4, 0], U_c in [-6, -2], Gamma in [0.5, 2].
+    """
+    from scipy.stats import qmc
+    eng = qmc.Sobol(d=4, scramble=True, seed=seed)
+    if skip:
+        eng.fast_forward(skip)
+    u = eng.random(n)
+    lo = np.array([4.0, -0.4, -6.0, 0.5])
+    hi = np.array([12.0, 0.0, -2.0, 2.0])
+    return lo + u * (hi - lo)
