@@ -1,0 +1,214 @@
+/*
+ * msb.h -- C ABI of the MI355X multi-shifted BiCG library for resonant
+ * (Kramers-Heisenberg) spectra.
+ *
+ * Problem (paper Eqs. kramers1 and intermediateState, shifted form of
+ * Appendix A, Eq. shifted_linear_eq):
+ *
+ *   (A - w_in I) Psi(w_in) = E,   A = H' - E_G - i Gamma,   E = O2 |G>,
+ *   I(w_in, w) = (1/pi) Im <phi| (H - E_G - w - i eta)^{-1} |phi>,  phi = O1 Psi.
+ *
+ * H is the single-band Hubbard model (Sec. III, Eq. Hubbard) on an arbitrary
+ * bond list; H' adds the core-hole potential U_c on one site (valence part of
+ * Eq. intermediate_H).  All shifts of one right-hand side are solved from a
+ * single Krylov space by the multi-shift complex-symmetric BiCG of
+ * Appendix D (Algorithm 1) with one matrix-vector product per iteration
+ * (Appendix A's r~ = r* simplification).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Basis / layout.  Fixed (N_up, N_dn) sector, D = C(L,N_up) * C(L,N_dn).
+ *   Index = rank_up(u) * n_dn + rank_dn(d), where u, d are L-bit occupation
+ *   strings and rank is the position among L-bit integers with the same
+ *   popcount in ascending order.  Kets are c+_{o1} c+_{o2} ... |0> with all
+ *   spin-up orbitals (site order) before all spin-down orbitals.
+ * Vectors.  Device pointers; complex numbers interleaved (re, im):
+ *   MSB_C128 = two doubles, MSB_C64 = two floats.  Multi-vector arguments
+ *   are row-major with the element index fastest, e.g. psi[sys][shift][D].
+ * Ownership.  The caller allocates and owns every vector argument; the
+ *   library never frees or retains them.  The library owns the context:
+ *   basis tables, workspace and captured graphs, released by msb_destroy.
+ *   Inputs are never modified.
+ * Streams.  `stream` is a hipStream_t (NULL = default stream).  Calls are
+ *   blocking: they return after their work on `stream` has completed.
+ * Errors.  Every call returns an msb_status; msb_last_error() returns a
+ *   thread-local message for the last failure on the calling thread.
+ * Threads.  A context may be used by one thread at a time.
+ */
+#ifndef MSB_H
+#define MSB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSB_MAX_BOND_TYPES 8
+
+typedef struct msb_ctx msb_ctx;
+
+typedef enum {
+  MSB_OK = 0,
+  MSB_EINVAL = 1,         /* invalid argument (message says which) */
+  MSB_ENOMEM = 2,         /* device memory footprint exceeds what is free */
+  MSB_EHIP = 3,           /* a HIP runtime call failed */
+  MSB_BREAKDOWN = 4,      /* |r^T A p| fell below 1e-14 |r||Ap| (COCG breakdown) */
+  MSB_NOT_CONVERGED = 5   /* iteration cap reached before every shift converged */
+} msb_status;
+
+typedef enum { MSB_C128 = 0, MSB_C64 = 1 } msb_prec;
+
+/* Lattice model H (Eq. Hubbard):
+ *   H = -sum_b t_b sum_sigma (c+_{j_b sigma} c_{i_b sigma} + h.c.) + U sum_i n_{i up} n_{i dn}.
+ * Host arrays of length n_bonds; each unordered pair should appear once.
+ * Bonds with equal t form one "bond type" (types numbered by first
+ * appearance, at most MSB_MAX_BOND_TYPES); per-system amplitudes may
+ * override a type's t (msb_system.t_amp).
+ * Limits: 2 <= n_sites <= 20, C(L, N_sigma) <= 65535. */
+typedef struct {
+  int n_sites, n_up, n_dn, n_bonds;
+  const int* bond_i;
+  const int* bond_j;
+  const double* bond_t;
+  double U;
+} msb_model;
+
+/* One linear system / Hamiltonian instance on the context's sector.
+ *   H'_s = H(U_s, t_amp_s) + Uc_s (n_{j up} + n_{j dn}),  j = core_site_s,
+ *   A_s  = H'_s - E_G_s - i Gamma_s.
+ * core_site = -1 means no core hole (H' = H).  U = NaN keeps the model's U.
+ * n_amp = 0 keeps the model's bond amplitudes; otherwise t_amp[0..n_amp-1]
+ * replace the amplitudes of bond types 0..n_amp-1. */
+typedef struct {
+  int core_site;
+  double Uc;
+  double E_G;
+  double Gamma;
+  double U;
+  int n_amp;
+  double t_amp[MSB_MAX_BOND_TYPES];
+} msb_system;
+
+/* Per-solve report (msb_solve).  Pointer members are optional host arrays
+ * (NULL = not wanted) of length nsys*n_shift (index sys*n_shift + shift) or nsys. */
+typedef struct {
+  int iters;             /* seed iterations of the longest system (= its matrix-vector products) */
+  int mvms;              /* seed matrix-vector products summed over systems */
+  int breakdown_iter;    /* first iteration with breakdown, -1 if none */
+  int flushes;           /* multi-shift assembly passes performed */
+  int* sys_iters;        /* [nsys] iterations of each system */
+  int* shift_iters;      /* [nsys*n_shift] iteration at which the shift froze, -1 = not converged */
+  double* resid_rec;     /* [nsys*n_shift] recurrence residual |r_m| / |zeta_m| / |E| */
+  double* resid_true;    /* [nsys*n_shift] FP64 true residual |E - (A - w)Psi| / |E| (extra applies) */
+  double t_iter_ms;      /* device time of the seed iterations */
+  double t_flush_ms;     /* device time of the multi-shift assembly */
+  double t_true_ms;      /* device time of the true-residual check */
+  double t_gemm_ms;      /* device time of the dense assembly launches alone */
+  int n_gemm;            /* number of dense assembly launches */
+  double gemm_flops;     /* algorithmic flops of those launches: 8 D sum(range lengths) */
+  double gemm_bytes;     /* algorithmic bytes: residual slots read + outputs written (+read) */
+} msb_info;
+
+/* Tuning knobs of msb_solve; pass NULL for defaults. */
+typedef struct {
+  int chunk;             /* seed iterations per captured graph launch (default 16) */
+  int bank_slots;        /* residual slots kept before a flush; 0 = min(maxit + 1, 1024) */
+  int batch;             /* systems iterated together (block apply); 0 = all that fit */
+  int replace_every;     /* C64 only: true-residual replacement period (default 50, 0 = off) */
+  int use_graph;         /* 1 = capture the chunk in a hipGraph (default), 0 = plain launches */
+  double mem_fraction;   /* fraction of free device memory the workspace may use (default 0.9) */
+} msb_opts;
+
+/* ---- context -------------------------------------------------------------- */
+
+/* Builds the basis and the per-spin hopping tables (Jordan-Wigner signs of
+ * Eq. Hubbard) on the host and uploads them to the current device.
+ * Errors: MSB_EINVAL for sizes outside the limits; MSB_EHIP on upload failure. */
+msb_status msb_create(const msb_model* model, msb_ctx** out);
+void msb_destroy(msb_ctx* ctx);
+int64_t msb_dim(const msb_ctx* ctx);
+/* Per-spin sector sizes and bond-type count (any pointer may be NULL). */
+msb_status msb_sector_info(const msb_ctx* ctx, int* n_up_states, int* n_dn_states, int* n_bond_types);
+const char* msb_last_error(void);
+/* 1 if the library was built for and found a gfx950 device. */
+int msb_device_ok(void);
+
+/* ---- operators -------------------------------------------------------------- */
+
+/* y_s = (H'_s - E_G_s - i Gamma_s - shift) x_s for s < nsys (matrix-free
+ * Kronecker apply: H_up (x) I + I (x) H_dn + diagonal).  x, y: [nsys][D] of
+ * `prec`; x and y must not overlap. */
+msb_status msb_apply(msb_ctx* ctx, const msb_system* sys, int nsys, double shift,
+                     msb_prec prec, const void* x, void* y, void* stream);
+
+/* Timing helper for the apply above: `reps` back-to-back launches on `stream`
+ * bracketed by HIP events; *ms_per_apply receives the mean launch duration.
+ * Same arguments and errors as msb_apply; reps >= 1. */
+msb_status msb_apply_timed(msb_ctx* ctx, const msb_system* sys, int nsys, double shift,
+                           msb_prec prec, const void* x, void* y, int reps,
+                           double* ms_per_apply, void* stream);
+
+/* y = (w_up n_{site up} + w_dn n_{site dn}) x, or y = x if site < 0 (the
+ * sector-preserving operators O1 / O2 used by the workloads).
+ * x: [count][D] real FP64 (x_real != 0) or C128; y: [count][D] C128. */
+msb_status msb_number_op(msb_ctx* ctx, int site, double w_up, double w_dn, int count,
+                         int x_real, const void* x, void* y, void* stream);
+
+/* ---- ground state (precondition of Eq. intermediateState) ----------------- */
+
+/* Lowest eigenpair of H(sys->U, sys->t_amp) by FP64 Lanczos with full
+ * reorthogonalisation from the caller's start vector x0 (real, [D]); the
+ * tridiagonal problem is solved on the host by bisection + inverse iteration.
+ * Stops when the Ritz residual |b_k y_k| <= tol |E_G| or at maxit.
+ * G: [D] real FP64 output, unit norm, sign fixed so that sum(G) >= 0.
+ * Errors: MSB_NOT_CONVERGED at maxit (E_G, G hold the last Ritz pair). */
+msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, const double* x0,
+                            double tol, int maxit, double* E_G, double* G,
+                            int* iters, void* stream);
+
+/* ---- the hot path: all shifts of every system from one Krylov space ------- */
+
+/* Multi-shift COCG (Algorithm 1, corrected reading: (1 - alpha_m w) in the
+ * zeta recurrence, beta_{m-1} in the shift formulas, bilinear r^T r products).
+ * For each system s and shift k:
+ *   (A_s - w_in[k] I) psi[s][k] = E[s].
+ * E: [nsys][D] C128 (any complex vector; E^T E != 0).  psi: [nsys][n_shift][D] of `prec`.
+ * The seed system is A_s - seed_shift I.  Shift k freezes once
+ * |r_m| / |zeta_m(w_k)| <= tol |E_s|.  MSB_C64 runs the vectors in complex64
+ * with FP64 reductions and scalars, and replaces the seed residual by the
+ * FP64 true residual every opts->replace_every iterations.
+ * Returns MSB_NOT_CONVERGED (psi holds the last iterates) or MSB_BREAKDOWN
+ * (psi holds the iterates before the breakdown) on failure.
+ * Footprint (checked before launching): about (bank_slots + 6) * D * s * batch
+ * (+ 2 n_shift D s batch when the bank must be flushed mid-solve). */
+msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, const void* E,
+                     const double* w_in, int n_shift, double seed_shift, double tol,
+                     int maxit, msb_prec prec, void* psi, msb_info* info,
+                     const msb_opts* opts, void* stream);
+
+/* phi[k] = sum_s phase_s * O1_s psi[s][k]  for k < n_shift, with
+ * O1_s = (w_up n_{site up} + w_dn n_{site dn}) or identity when o1_site[s] < 0.
+ * psi: [nsys][n_shift][D] of `prec`; phi: [n_shift][D] C128.
+ * phase_re/phase_im/o1_site/o1_wup/o1_wdn: host arrays [nsys] (o1_* may be NULL = identity). */
+msb_status msb_combine(msb_ctx* ctx, int nsys, int n_shift, msb_prec prec, const void* psi,
+                       const double* phase_re, const double* phase_im, const int* o1_site,
+                       const double* o1_wup, const double* o1_wdn, void* phi, void* stream);
+
+/* Kramers-Heisenberg intensity by a Lanczos continued fraction per vector
+ * (Eq. kramers1 with 0+ -> eta):
+ *   I[k][j] = (1/pi) Im <phi_k| (H - E_G - w[j] - i eta)^{-1} |phi_k>.
+ * H = H(sys->U, sys->t_amp) (core_site, Uc, Gamma ignored); E_G = sys->E_G.
+ * All n Lanczos recurrences run together as a block; each stops when
+ * max_j |I_k - I_{k-10}| / max_j I_k < cf_tol, its Lanczos vector vanishes,
+ * or lanczos_max steps.  phi: [n][D] C128; w: host [n_w]; I: host [n][n_w];
+ * depth: host [n] (may be NULL). */
+msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const void* phi, int n,
+                        const double* w, int n_w, double eta, int lanczos_max,
+                        double cf_tol, double* I, int* depth, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSB_H */

@@ -1,0 +1,11 @@
+"""MI355X multi-shifted BiCG for resonant (Kramers-Heisenberg) spectra.
+
+The compute path lives in the HIP library ``libmsb.so`` (C ABI in
+``include/msb.h``); this package only marshals arguments to it.
+"""
+from ._capi import (  # noqa: F401
+    MSB_C128, MSB_C64, MSB_OK, MSB_EINVAL, MSB_ENOMEM, MSB_EHIP, MSB_BREAKDOWN,
+    MSB_NOT_CONVERGED, MsbError, make_system, exported_symbols, lib,
+    msb_create, msb_destroy, msb_dim, msb_sector_info, msb_device_ok, msb_apply, msb_apply_timed,
+    msb_number_op, msb_ground_state, msb_solve, msb_combine, msb_spectrum,
+)

@@ -1,0 +1,317 @@
+"""ctypes binding of the C ABI in ``include/msb.h``.
+
+Argument marshalling only: every function forwards to the HIP library
+``libmsb.so`` built in this directory; device buffers are torch tensors on a
+ROCm device (their ``data_ptr()`` is passed), streams are torch streams.  There
+is no fallback: if the library is missing or the device is not a gfx950 GPU
+the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from ctypes import POINTER, c_double, c_int, c_int64, c_void_p
+from pathlib import Path
+
+MSB_MAX_BOND_TYPES = 8
+STATUS = {0: "MSB_OK", 1: "MSB_EINVAL", 2: "MSB_ENOMEM", 3: "MSB_EHIP",
+          4: "MSB_BREAKDOWN", 5: "MSB_NOT_CONVERGED"}
+MSB_OK, MSB_EINVAL, MSB_ENOMEM, MSB_EHIP, MSB_BREAKDOWN, MSB_NOT_CONVERGED = range(6)
+MSB_C128, MSB_C64 = 0, 1
+
+LIB_PATH = Path(__file__).resolve().parent / "libmsb.so"
+
+
+class MsbError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class msb_model(ctypes.Structure):
+    _fields_ = [("n_sites", c_int), ("n_up", c_int), ("n_dn", c_int), ("n_bonds", c_int),
+                ("bond_i", POINTER(c_int)), ("bond_j", POINTER(c_int)),
+                ("bond_t", POINTER(c_double)), ("U", c_double)]
+
+
+class msb_system(ctypes.Structure):
+    _fields_ = [("core_site", c_int), ("Uc", c_double), ("E_G", c_double), ("Gamma", c_double),
+                ("U", c_double), ("n_amp", c_int), ("t_amp", c_double * MSB_MAX_BOND_TYPES)]
+
+
+class msb_info(ctypes.Structure):
+    _fields_ = [("iters", c_int), ("mvms", c_int), ("breakdown_iter", c_int), ("flushes", c_int),
+                ("sys_iters", POINTER(c_int)), ("shift_iters", POINTER(c_int)),
+                ("resid_rec", POINTER(c_double)), ("resid_true", POINTER(c_double)),
+                ("t_iter_ms", c_double), ("t_flush_ms", c_double), ("t_true_ms", c_double),
+                ("t_gemm_ms", c_double), ("n_gemm", c_int), ("gemm_flops", c_double),
+                ("gemm_bytes", c_double)]
+
+
+class msb_opts(ctypes.Structure):
+    _fields_ = [("chunk", c_int), ("bank_slots", c_int), ("batch", c_int),
+                ("replace_every", c_int), ("use_graph", c_int), ("mem_fraction", c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libmsb.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise OSError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(str(LIB_PATH))
+        L.msb_last_error.restype = ctypes.c_char_p
+        L.msb_device_ok.restype = c_int
+        L.msb_create.argtypes = [POINTER(msb_model), POINTER(c_void_p)]
+        L.msb_create.restype = c_int
+        L.msb_destroy.argtypes = [c_void_p]
+        L.msb_destroy.restype = None
+        L.msb_dim.argtypes = [c_void_p]
+        L.msb_dim.restype = c_int64
+        L.msb_sector_info.argtypes = [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int)]
+        L.msb_sector_info.restype = c_int
+        L.msb_apply.argtypes = [c_void_p, POINTER(msb_system), c_int, c_double, c_int, c_void_p,
+                                c_void_p, c_void_p]
+        L.msb_apply.restype = c_int
+        L.msb_apply_timed.argtypes = [c_void_p, POINTER(msb_system), c_int, c_double, c_int,
+                                      c_void_p, c_void_p, c_int, POINTER(c_double), c_void_p]
+        L.msb_apply_timed.restype = c_int
+        L.msb_number_op.argtypes = [c_void_p, c_int, c_double, c_double, c_int, c_int, c_void_p,
+                                    c_void_p, c_void_p]
+        L.msb_number_op.restype = c_int
+        L.msb_ground_state.argtypes = [c_void_p, POINTER(msb_system), c_void_p, c_double, c_int,
+                                       POINTER(c_double), c_void_p, POINTER(c_int), c_void_p]
+        L.msb_ground_state.restype = c_int
+        L.msb_solve.argtypes = [c_void_p, POINTER(msb_system), c_int, c_void_p, POINTER(c_double),
+                                c_int, c_double, c_double, c_int, c_int, c_void_p,
+                                POINTER(msb_info), POINTER(msb_opts), c_void_p]
+        L.msb_solve.restype = c_int
+        L.msb_combine.argtypes = [c_void_p, c_int, c_int, c_int, c_void_p, POINTER(c_double),
+                                  POINTER(c_double), POINTER(c_int), POINTER(c_double),
+                                  POINTER(c_double), c_void_p, c_void_p]
+        L.msb_combine.restype = c_int
+        L.msb_spectrum.argtypes = [c_void_p, POINTER(msb_system), c_void_p, c_int, POINTER(c_double),
+                                   c_int, c_double, c_int, c_double, POINTER(c_double),
+                                   POINTER(c_int), c_void_p]
+        L.msb_spectrum.restype = c_int
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names of the C entry points the binding expects the library to export."""
+    return ["msb_create", "msb_destroy", "msb_dim", "msb_sector_info", "msb_last_error",
+            "msb_device_ok", "msb_apply", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
+            "msb_combine", "msb_spectrum"]
+
+
+def _check(status: int):
+    if status != MSB_OK:
+        raise MsbError(status, lib().msb_last_error().decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return c_void_p(t.data_ptr())
+
+
+def _prec_dtype(prec: int):
+    import torch
+    return torch.complex128 if prec == MSB_C128 else torch.complex64
+
+
+def make_system(core_site=-1, Uc=0.0, E_G=0.0, Gamma=0.0, U=None, t_amp=None) -> msb_system:
+    s = msb_system()
+    s.core_site = int(core_site)
+    s.Uc = float(Uc)
+    s.E_G = float(E_G)
+    s.Gamma = float(Gamma)
+    s.U = math.nan if U is None else float(U)
+    amps = list(t_amp) if t_amp is not None else []
+    if len(amps) > MSB_MAX_BOND_TYPES:
+        raise ValueError("too many bond amplitudes")
+    s.n_amp = len(amps)
+    for i, a in enumerate(amps):
+        s.t_amp[i] = float(a)
+    return s
+
+
+def _systems(systems):
+    if isinstance(systems, msb_system):
+        systems = [systems]
+    arr = (msb_system * len(systems))(*systems)
+    return arr, len(systems)
+
+
+# ---- C entry points ---------------------------------------------------------
+
+def msb_device_ok() -> bool:
+    return bool(lib().msb_device_ok())
+
+
+def msb_create(n_sites: int, n_up: int, n_dn: int, bonds, U: float) -> c_void_p:
+    """Context for H on the (n_up, n_dn) sector; bonds = [(i, j, t), ...]."""
+    nb = len(bonds)
+    bi = (c_int * max(nb, 1))(*[int(b[0]) for b in bonds])
+    bj = (c_int * max(nb, 1))(*[int(b[1]) for b in bonds])
+    bt = (c_double * max(nb, 1))(*[float(b[2]) for b in bonds])
+    m = msb_model(int(n_sites), int(n_up), int(n_dn), nb, bi, bj, bt, float(U))
+    ctx = c_void_p()
+    _check(lib().msb_create(ctypes.byref(m), ctypes.byref(ctx)))
+    return ctx
+
+
+def msb_destroy(ctx):
+    lib().msb_destroy(ctx)
+
+
+def msb_dim(ctx) -> int:
+    return int(lib().msb_dim(ctx))
+
+
+def msb_sector_info(ctx):
+    nu, nd, nt = c_int(), c_int(), c_int()
+    _check(lib().msb_sector_info(ctx, ctypes.byref(nu), ctypes.byref(nd), ctypes.byref(nt)))
+    return nu.value, nd.value, nt.value
+
+
+def msb_apply(ctx, systems, shift: float, prec: int, x, y, stream=None):
+    arr, n = _systems(systems)
+    D = msb_dim(ctx)
+    dt = _prec_dtype(prec)
+    _check(lib().msb_apply(ctx, arr, n, float(shift), int(prec), _ptr(x, dt, n * D, "x"),
+                           _ptr(y, dt, n * D, "y"), _stream_ptr(stream)))
+
+
+def msb_apply_timed(ctx, systems, shift: float, prec: int, x, y, reps: int, stream=None) -> float:
+    """Mean duration (ms) of `reps` back-to-back applies, timed with HIP events on `stream`."""
+    arr, n = _systems(systems)
+    D = msb_dim(ctx)
+    dt = _prec_dtype(prec)
+    ms = c_double()
+    _check(lib().msb_apply_timed(ctx, arr, n, float(shift), int(prec), _ptr(x, dt, n * D, "x"),
+                                 _ptr(y, dt, n * D, "y"), int(reps), ctypes.byref(ms),
+                                 _stream_ptr(stream)))
+    return ms.value
+
+
+def msb_number_op(ctx, site: int, w_up: float, w_dn: float, x, y, stream=None):
+    import torch
+    D = msb_dim(ctx)
+    x_real = 1 if x.dtype == torch.float64 else 0
+    if not x_real and x.dtype != torch.complex128:
+        raise TypeError("x must be float64 or complex128")
+    count = x.numel() // D
+    _check(lib().msb_number_op(ctx, int(site), float(w_up), float(w_dn), count, x_real,
+                               _ptr(x, None, count * D, "x"), _ptr(y, torch.complex128, count * D, "y"),
+                               _stream_ptr(stream)))
+
+
+def msb_ground_state(ctx, system, x0, tol: float, maxit: int, G, stream=None):
+    """Returns (E_G, iters); G (float64 [D]) receives the ground state."""
+    import torch
+    D = msb_dim(ctx)
+    e = c_double()
+    it = c_int()
+    st = lib().msb_ground_state(ctx, ctypes.byref(system), _ptr(x0, torch.float64, D, "x0"),
+                                float(tol), int(maxit), ctypes.byref(e),
+                                _ptr(G, torch.float64, D, "G"), ctypes.byref(it), _stream_ptr(stream))
+    _check(st)
+    return e.value, it.value
+
+
+def msb_solve(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit: int, prec: int, psi,
+              want_true: bool = False, opts: dict | None = None, stream=None, raise_on_fail=True):
+    """Multi-shift solve; returns (status, info dict)."""
+    import numpy as np
+    import torch
+    arr, n = _systems(systems)
+    D = msb_dim(ctx)
+    w = np.ascontiguousarray(np.asarray(w_in, dtype=np.float64))
+    ns = len(w)
+    sys_iters = (c_int * n)()
+    shift_iters = (c_int * (n * ns))()
+    resid_rec = (c_double * (n * ns))()
+    resid_true = (c_double * (n * ns))() if want_true else None
+    info = msb_info()
+    info.sys_iters = sys_iters
+    info.shift_iters = shift_iters
+    info.resid_rec = resid_rec
+    info.resid_true = ctypes.cast(resid_true, POINTER(c_double)) if want_true else None
+    o = msb_opts()
+    for k, v in (opts or {}).items():
+        setattr(o, k, v)
+    st = lib().msb_solve(ctx, arr, n, _ptr(E, torch.complex128, n * D, "E"),
+                         w.ctypes.data_as(POINTER(c_double)), ns, float(seed_shift), float(tol),
+                         int(maxit), int(prec), _ptr(psi, _prec_dtype(prec), n * ns * D, "psi"),
+                         ctypes.byref(info), ctypes.byref(o), _stream_ptr(stream))
+    out = {
+        "status": st, "iters": info.iters, "mvms": info.mvms, "breakdown_iter": info.breakdown_iter,
+        "flushes": info.flushes,
+        "sys_iters": np.frombuffer(sys_iters, dtype=np.int32).copy(),
+        "shift_iters": np.frombuffer(shift_iters, dtype=np.int32).reshape(n, ns).copy(),
+        "resid_rec": np.frombuffer(resid_rec, dtype=np.float64).reshape(n, ns).copy(),
+        "resid_true": (np.frombuffer(resid_true, dtype=np.float64).reshape(n, ns).copy()
+                       if want_true else None),
+        "t_iter_ms": info.t_iter_ms, "t_flush_ms": info.t_flush_ms, "t_true_ms": info.t_true_ms,
+        "t_gemm_ms": info.t_gemm_ms, "n_gemm": info.n_gemm, "gemm_flops": info.gemm_flops,
+        "gemm_bytes": info.gemm_bytes,
+    }
+    if raise_on_fail and st != MSB_OK:
+        raise MsbError(st, lib().msb_last_error().decode())
+    return st, out
+
+
+def msb_combine(ctx, psi, nsys: int, n_shift: int, prec: int, phases, phi, o1=None, stream=None):
+    """phi[k] = sum_s phases[s] * O1_s psi[s][k]; o1 = [(site, w_up, w_dn), ...] or None."""
+    import torch
+    D = msb_dim(ctx)
+    pre = (c_double * nsys)(*[complex(p).real for p in phases])
+    pim = (c_double * nsys)(*[complex(p).imag for p in phases])
+    if o1 is not None:
+        site = (c_int * nsys)(*[int(o[0]) for o in o1])
+        wu = (c_double * nsys)(*[float(o[1]) for o in o1])
+        wd = (c_double * nsys)(*[float(o[2]) for o in o1])
+    else:
+        site, wu, wd = None, None, None
+    _check(lib().msb_combine(ctx, nsys, n_shift, int(prec),
+                             _ptr(psi, _prec_dtype(prec), nsys * n_shift * D, "psi"), pre, pim,
+                             site, wu, wd, _ptr(phi, torch.complex128, n_shift * D, "phi"),
+                             _stream_ptr(stream)))
+
+
+def msb_spectrum(ctx, system, phi, w, eta: float, lanczos_max: int, cf_tol: float, stream=None):
+    """Returns (I [n, n_w] numpy, depth [n] numpy)."""
+    import numpy as np
+    import torch
+    D = msb_dim(ctx)
+    n = phi.numel() // D
+    wv = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    I = np.zeros((n, len(wv)), dtype=np.float64)
+    depth = np.zeros(n, dtype=np.int32)
+    _check(lib().msb_spectrum(ctx, ctypes.byref(system), _ptr(phi, torch.complex128, n * D, "phi"),
+                              n, wv.ctypes.data_as(POINTER(c_double)), len(wv), float(eta),
+                              int(lanczos_max), float(cf_tol), I.ctypes.data_as(POINTER(c_double)),
+                              depth.ctypes.data_as(POINTER(c_int)), _stream_ptr(stream)))
+    return I, depth

@@ -1,0 +1,253 @@
+// Seed-system COCG step and per-shift scalar recurrences (Appendix D,
+// Algorithm 1, in the reading: bilinear products r^T r (Appendix A,
+// r~ = r*), zeta recurrence with (1 - alpha_m w) and beta_{m-1}).
+//
+// One iteration m of the seed runs as three launches on `nsys` systems:
+//   apply   : v = A_s p,  sigma = r_m^T v, |v|^2           (k_apply.hip)
+//   k_cocg_r: alpha_m = rho_m / sigma,  r_{m+1} = r_m - alpha_m v  (new bank
+//             slot), rho_{m+1} = r^T r, |r_{m+1}|; the last workgroup forms
+//             beta_m = rho_{m+1}/rho_m, advances every shift's zeta and
+//             freezes converged shifts (|r_{m+1}|/|zeta_{m+1}| <= tol |E|)
+//   k_cocg_p: p_{m+1} = r_{m+1} + beta_m p_m
+// The x / p vectors of the shifted systems are not touched here: the
+// residuals r_m stay in the bank and the shifted solutions are assembled
+// from them in k_shift.hip.
+#include "k_common.h"
+
+namespace msb {
+
+constexpr int kEptStream = 4;   // elements per thread per step of the streaming kernels
+constexpr int kPerStep = kBlock * kEptStream;
+
+int cocg_nbx(int64_t D, int nsys) { return stream_nbx(D, nsys, kPerStep); }
+
+__device__ __forceinline__ bool sigma_breakdown(const SysState& st, const double* red1, int s,
+                                                cv<double>& alpha) {
+  const cv<double> sigma = {red1[s * 4 + 0], red1[s * 4 + 1]};
+  const double vnorm = sqrt(red1[s * 4 + 2]);
+  const double sabs = cabs(sigma);
+  if (!(sabs > 1e-14 * st.rnorm * vnorm)) return true;   // also catches NaN
+  alpha = cdiv({st.rho_re, st.rho_im}, sigma);
+  return false;
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_cocg_init(InitArgs a) {
+  using Ax = Access<S, true>;
+  using A64 = Access<double, true>;
+  const int s = blockIdx.y, bx = blockIdx.x;
+  double part[3] = {0.0, 0.0, 0.0};
+  void* r0 = Ax::offset(a.bank, (int64_t)s * a.cap * a.D);
+  void* p = Ax::offset(a.pvec, (int64_t)s * a.D);
+  for (int64_t base = (int64_t)bx * kPerStep; base < a.D; base += (int64_t)a.nbx * kPerStep) {
+#pragma unroll
+    for (int e = 0; e < kEptStream; ++e) {
+      const int64_t i = base + e * kBlock + threadIdx.x;
+      if (i < a.D) {
+        const cv<double> x = A64::template load<double>(a.E, (int64_t)s * a.D + i);
+        const cv<double> xs = {(double)(S)x.re, (double)(S)x.im};
+        Ax::store(r0, i, xs);
+        Ax::store(p, i, xs);
+        part[0] += xs.re * xs.re - xs.im * xs.im;
+        part[1] += 2.0 * xs.re * xs.im;
+        part[2] += xs.re * xs.re + xs.im * xs.im;
+      }
+    }
+  }
+  __shared__ double red[4];
+  if (!publish_partials<3>(part, a.partials, a.counter, nullptr, a.nbx, s, bx, red)) return;
+  // last workgroup of system s: initial state and shift scalars
+  if (threadIdx.x == 0) {
+    SysState st;
+    st.rho_re = red[0];
+    st.rho_im = red[1];
+    st.rnorm = sqrt(red[2]);
+    st.normE = st.rnorm;
+    st.ap_re = 1.0; st.ap_im = 0.0;     // alpha_{-1} = 1
+    st.bp_re = 0.0; st.bp_im = 0.0;     // beta_{-1} = 0
+    st.al_re = st.al_im = st.be_re = st.be_im = 0.0;
+    st.m = 0;
+    st.n_active = a.n_shift;
+    st.breakdown_iter = -1;
+    if (st.normE == 0.0) {
+      st.status = kDone;                // E = 0: Psi = 0 for every shift
+      st.n_active = 0;
+    } else if (!(cabs({st.rho_re, st.rho_im}) > 1e-14 * st.normE * st.normE)) {
+      st.status = kBreakdown;           // E^T E = 0: COCG cannot start
+      st.breakdown_iter = 0;
+    } else if (a.maxit <= 0) {
+      st.status = kMaxit;
+    } else {
+      st.status = kActive;
+    }
+    a.st[s] = st;
+    a.rnorm_log[(int64_t)s * (a.maxit + 1)] = st.rnorm;
+  }
+  const bool zero = (red[2] == 0.0);
+  for (int k = threadIdx.x; k < a.n_shift; k += kBlock) {
+    const int64_t t = (int64_t)s * a.n_shift + k;
+    a.zeta[2 * t] = 1.0; a.zeta[2 * t + 1] = 0.0;
+    a.zeta_prev[2 * t] = 1.0; a.zeta_prev[2 * t + 1] = 0.0;
+    a.conv_iter[t] = zero ? 0 : -1;
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_cocg_r(CocgArgs a) {
+  using Ax = Access<S, true>;
+  const int s = blockIdx.y, bx = blockIdx.x;
+  double part[3] = {0.0, 0.0, 0.0};
+  const SysState st = a.st[s];
+  if (st.status == kActive) {
+    cv<double> alpha;
+    if (!sigma_breakdown(st, a.red1, s, alpha)) {
+      const int slot = st.m - *a.base;
+      const void* r = Ax::offset((const void*)a.bank, ((int64_t)s * a.cap + slot) * a.D);
+      void* rn = Ax::offset(a.bank, ((int64_t)s * a.cap + slot + 1) * a.D);
+      const void* v = Ax::offset(a.vvec, (int64_t)s * a.D);
+      for (int64_t base = (int64_t)bx * kPerStep; base < a.D; base += (int64_t)a.nbx * kPerStep) {
+#pragma unroll
+        for (int e = 0; e < kEptStream; ++e) {
+          const int64_t i = base + e * kBlock + threadIdx.x;
+          if (i < a.D) {
+            const cv<double> ri = Ax::template load<double>(r, i);
+            const cv<double> vi = Ax::template load<double>(v, i);
+            cv<double> x = {ri.re - (alpha.re * vi.re - alpha.im * vi.im),
+                            ri.im - (alpha.re * vi.im + alpha.im * vi.re)};
+            x.re = (double)(S)x.re;
+            x.im = (double)(S)x.im;
+            Ax::store(rn, i, x);
+            part[0] += x.re * x.re - x.im * x.im;
+            part[1] += 2.0 * x.re * x.im;
+            part[2] += x.re * x.re + x.im * x.im;
+          }
+        }
+      }
+    }
+  }
+  __shared__ double red2[4];
+  if (!publish_partials<3>(part, a.partials, a.counter, a.red2, a.nbx, s, bx, red2)) return;
+
+  // ---- last workgroup of system s: scalar bookkeeping ---------------------
+  SysState t = a.st[s];
+  if (t.status == kPaused) {                  // p was advanced once already
+    if (threadIdx.x == 0) a.st[s].status = kPausedHold;
+    return;
+  }
+  if (t.status != kActive) return;
+  cv<double> alpha;
+  if (sigma_breakdown(t, a.red1, s, alpha)) {
+    if (threadIdx.x == 0) {
+      a.st[s].status = kBreakdown;
+      a.st[s].breakdown_iter = t.m;
+    }
+    return;
+  }
+  const int base = *a.base;
+  const cv<double> rho_new = {red2[0], red2[1]};
+  const double rn = sqrt(red2[2]);
+  const cv<double> beta = cdiv(rho_new, {t.rho_re, t.rho_im});
+  // zeta_{m+1} = (1 - alpha_m w) zeta_m + (alpha_m beta_{m-1} / alpha_{m-1}) (zeta_m - zeta_{m-1})
+  const cv<double> cshift = cdiv(cmul(alpha, {t.bp_re, t.bp_im}), {t.ap_re, t.ap_im});
+  const double thresh = a.tol * t.normE;
+  int active = 0;
+  for (int k = threadIdx.x; k < a.n_shift; k += kBlock) {
+    const int64_t idx = (int64_t)s * a.n_shift + k;
+    if (a.conv_iter[idx] >= 0) continue;
+    const double w = a.wshift[k];
+    const cv<double> z = {a.zeta[2 * idx], a.zeta[2 * idx + 1]};
+    const cv<double> zp = {a.zeta_prev[2 * idx], a.zeta_prev[2 * idx + 1]};
+    const cv<double> f = {1.0 - alpha.re * w, -alpha.im * w};
+    const cv<double> zn = cadd(cmul(f, z), cmul(cshift, csub(z, zp)));
+    a.zeta_prev[2 * idx] = z.re;
+    a.zeta_prev[2 * idx + 1] = z.im;
+    a.zeta[2 * idx] = zn.re;
+    a.zeta[2 * idx + 1] = zn.im;
+    if (rn / cabs(zn) <= thresh) {
+      a.conv_iter[idx] = t.m + 1;
+    } else {
+      ++active;
+    }
+  }
+  double cnt[1] = {(double)active};
+  __shared__ double shc[1][kBlock / kWave];
+  block_sum<1>(cnt, shc);
+  if (threadIdx.x == 0) {
+    const int m = t.m;
+    a.alpha_log[((int64_t)s * a.maxit + m) * 2] = alpha.re;
+    a.alpha_log[((int64_t)s * a.maxit + m) * 2 + 1] = alpha.im;
+    a.beta_log[((int64_t)s * a.maxit + m) * 2] = beta.re;
+    a.beta_log[((int64_t)s * a.maxit + m) * 2 + 1] = beta.im;
+    a.rnorm_log[(int64_t)s * (a.maxit + 1) + m + 1] = rn;
+    t.n_active = (int)cnt[0];
+    t.al_re = alpha.re; t.al_im = alpha.im;
+    t.be_re = beta.re; t.be_im = beta.im;
+    t.ap_re = alpha.re; t.ap_im = alpha.im;
+    t.bp_re = beta.re; t.bp_im = beta.im;
+    t.rho_re = rho_new.re; t.rho_im = rho_new.im;
+    t.rnorm = rn;
+    t.m = m + 1;
+    if (t.n_active == 0) {
+      t.status = kDone;
+    } else if (!(cabs(rho_new) > 1e-14 * rn * rn)) {
+      t.status = kBreakdown;            // rho_{m+1} = 0 with shifts still open
+      t.breakdown_iter = m + 1;
+    } else if (t.m >= a.maxit) {
+      t.status = kMaxit;
+    } else if (t.m + 1 - base >= a.cap) {
+      t.status = kPaused;               // no bank slot for r_{m+2}: host flushes
+    }
+    a.st[s] = t;
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
+  using Ax = Access<S, true>;
+  const int s = blockIdx.y, bx = blockIdx.x;
+  const SysState st = a.st[s];
+  if (st.status != kActive && st.status != kPaused) return;
+  const int slot = st.m - *a.base;
+  const void* r = Ax::offset((const void*)a.bank, ((int64_t)s * a.cap + slot) * a.D);
+  void* p = Ax::offset(a.pvec, (int64_t)s * a.D);
+  const cv<double> beta = {st.be_re, st.be_im};
+  for (int64_t base = (int64_t)bx * kPerStep; base < a.D; base += (int64_t)a.nbx * kPerStep) {
+#pragma unroll
+    for (int e = 0; e < kEptStream; ++e) {
+      const int64_t i = base + e * kBlock + threadIdx.x;
+      if (i < a.D) {
+        const cv<double> ri = Ax::template load<double>(r, i);
+        const cv<double> pi = Ax::template load<double>(p, i);
+        const cv<double> x = {ri.re + beta.re * pi.re - beta.im * pi.im,
+                              ri.im + beta.re * pi.im + beta.im * pi.re};
+        Ax::store(p, i, x);
+      }
+    }
+  }
+}
+
+hipError_t launch_cocg_init(Elem e, const InitArgs& a, hipStream_t st) {
+  dim3 grid(a.nbx, a.nsys);
+  if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_init<double>, grid, dim3(kBlock), 0, st, a);
+  else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_init<float>, grid, dim3(kBlock), 0, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st) {
+  dim3 grid(a.nbx, a.nsys);
+  if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_r<double>, grid, dim3(kBlock), 0, st, a);
+  else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_r<float>, grid, dim3(kBlock), 0, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_cocg_p(Elem e, const CocgArgs& a, hipStream_t st) {
+  dim3 grid(a.nbx, a.nsys);
+  if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_p<double>, grid, dim3(kBlock), 0, st, a);
+  else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_p<float>, grid, dim3(kBlock), 0, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace msb

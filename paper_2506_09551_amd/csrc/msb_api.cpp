@@ -1,0 +1,1095 @@
+// C ABI of the multi-shift BiCG library: context, operators, ground state,
+// the multi-shift solve, the coherent site sum and the continued-fraction
+// spectrum.  Host code only; every vector operation runs in the HIP kernels of
+// the k_*.hip files.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "msb_internal.h"
+
+namespace msb {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+msb_status fail(msb_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+// Grow-only device arena owned by the context; carved per call.
+class Arena {
+ public:
+  explicit Arena(msb_ctx* c) : ctx_(c) {}
+  void reserve(size_t bytes) { need_ += align(bytes); }
+  hipError_t commit() {
+    if (ctx_->ws_size < need_) {
+      if (ctx_->ws) {
+        hipError_t e = hipFree(ctx_->ws);
+        if (e != hipSuccess) return e;
+        ctx_->ws = nullptr;
+        ctx_->ws_size = 0;
+      }
+      hipError_t e = hipMalloc(&ctx_->ws, need_);
+      if (e != hipSuccess) return e;
+      ctx_->ws_size = need_;
+    }
+    off_ = 0;
+    return hipSuccess;
+  }
+  template <typename T>
+  T* take(size_t bytes) {
+    if (off_ + align(bytes) > ctx_->ws_size) {   // a reserve/take mismatch: never hand out memory past the end
+      overflow_ = true;
+      return nullptr;
+    }
+    T* p = reinterpret_cast<T*>(static_cast<char*>(ctx_->ws) + off_);
+    off_ += align(bytes);
+    return p;
+  }
+  size_t needed() const { return need_; }
+  bool overflow() const { return overflow_; }
+  static size_t align(size_t b) { return (b + 255) & ~size_t(255); }
+
+ private:
+  msb_ctx* ctx_;
+  size_t need_ = 0;
+  size_t off_ = 0;
+  bool overflow_ = false;
+};
+
+static size_t elem_bytes(Elem e) { return e == Elem::C128 ? 16 : (e == Elem::C64 ? 8 : 8); }
+
+static bool valid_prec(msb_prec p) { return p == MSB_C128 || p == MSB_C64; }
+
+static msb_status make_sysdev(const msb_ctx* ctx, const msb_system& s, double d_re, double d_im,
+                              bool with_core, SysDev& out) {
+  out = SysDev();
+  out.U = std::isnan(s.U) ? ctx->U : s.U;
+  out.Uc = with_core ? s.Uc : 0.0;
+  out.core = with_core ? s.core_site : -1;
+  if (with_core && (s.core_site < -1 || s.core_site >= ctx->L))
+    return fail(MSB_EINVAL, "core_site out of range");
+  out.d_re = d_re;
+  out.d_im = d_im;
+  if (s.n_amp < 0 || s.n_amp > MSB_MAX_BOND_TYPES) return fail(MSB_EINVAL, "n_amp out of range");
+  for (int t = 0; t < MSB_MAX_BOND_TYPES; ++t)
+    out.amp[t] = (t < s.n_amp) ? s.t_amp[t] : ctx->type_amp[t];
+  if (!std::isfinite(out.U) || !std::isfinite(out.Uc) || !std::isfinite(d_re) || !std::isfinite(d_im))
+    return fail(MSB_EINVAL, "non-finite system parameter");
+  return MSB_OK;
+}
+
+static ApplyArgs apply_args(const msb_ctx* ctx, const SysDev* sys, int nsys, const void* x, void* v) {
+  ApplyArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.T = ctx->tables();
+  a.sys = sys;
+  a.x = x;
+  a.v = v;
+  a.aux = nullptr;
+  a.aux_div = 1;
+  a.status = nullptr;
+  a.status_stride = 0;
+  a.D = ctx->D;
+  a.rows_per_xcd = apply_rows_per_xcd(ctx->up.n);
+  a.nbx = apply_nbx(ctx->up.n, nsys);
+  a.nsys = nsys;
+  return a;
+}
+
+}  // namespace msb
+
+using namespace msb;
+
+// =============================================================================
+extern "C" const char* msb_last_error(void) { return g_err.c_str(); }
+
+extern "C" int msb_device_ok(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
+  return std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+}
+
+extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
+  if (!m || !out) return fail(MSB_EINVAL, "msb_create: null argument");
+  *out = nullptr;
+  if (m->n_sites < 2 || m->n_sites > 20) return fail(MSB_EINVAL, "n_sites must lie in [2, 20]");
+  if (m->n_up < 0 || m->n_up > m->n_sites || m->n_dn < 0 || m->n_dn > m->n_sites)
+    return fail(MSB_EINVAL, "electron numbers must lie in [0, n_sites]");
+  if (m->n_bonds < 0 || (m->n_bonds > 0 && (!m->bond_i || !m->bond_j || !m->bond_t)))
+    return fail(MSB_EINVAL, "bond arrays missing");
+  if (!std::isfinite(m->U)) return fail(MSB_EINVAL, "U must be finite");
+  std::vector<int> bi, bj, bt;
+  std::vector<double> amps;
+  for (int b = 0; b < m->n_bonds; ++b) {
+    const int i = m->bond_i[b], j = m->bond_j[b];
+    const double t = m->bond_t[b];
+    if (i < 0 || j < 0 || i >= m->n_sites || j >= m->n_sites || i == j)
+      return fail(MSB_EINVAL, "bond " + std::to_string(b) + " has invalid sites");
+    if (!std::isfinite(t)) return fail(MSB_EINVAL, "bond amplitude must be finite");
+    int type = -1;
+    for (size_t q = 0; q < amps.size(); ++q)
+      if (amps[q] == t) type = (int)q;
+    if (type < 0) {
+      if ((int)amps.size() >= MSB_MAX_BOND_TYPES) return fail(MSB_EINVAL, "too many distinct bond amplitudes");
+      amps.push_back(t);
+      type = (int)amps.size() - 1;
+    }
+    bi.push_back(i);
+    bj.push_back(j);
+    bt.push_back(type);
+  }
+  msb_ctx* c = new msb_ctx();
+  c->L = m->n_sites;
+  c->n_up = m->n_up;
+  c->n_dn = m->n_dn;
+  c->U = m->U;
+  c->n_types = (int)amps.size();
+  for (size_t q = 0; q < amps.size(); ++q) c->type_amp[q] = amps[q];
+  std::string err;
+  if (!build_spin_table(m->n_sites, m->n_up, bi, bj, bt, c->up, err) ||
+      !build_spin_table(m->n_sites, m->n_dn, bi, bj, bt, c->dn, err)) {
+    delete c;
+    return fail(MSB_EINVAL, err);
+  }
+  c->D = (int64_t)c->up.n * c->dn.n;
+  hipError_t e = hipGetDevice(&c->device);
+  auto upload = [&](uint32_t** dst, const std::vector<uint32_t>& src) -> hipError_t {
+    const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(uint32_t);
+    hipError_t r = hipMalloc(dst, bytes);
+    if (r != hipSuccess) return r;
+    if (!src.empty()) r = hipMemcpy(*dst, src.data(), src.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    return r;
+  };
+  if (e == hipSuccess) e = upload(&c->d_conf_up, c->up.conf);
+  if (e == hipSuccess) e = upload(&c->d_conf_dn, c->dn.conf);
+  if (e == hipSuccess) e = upload(&c->d_off_up, c->up.off);
+  if (e == hipSuccess) e = upload(&c->d_off_dn, c->dn.off);
+  if (e == hipSuccess) e = upload(&c->d_hop_up, c->up.hop);
+  if (e == hipSuccess) e = upload(&c->d_hop_dn, c->dn.hop);
+  if (e == hipSuccess) e = hipMalloc(&c->d_counters, kNumCounters * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemset(c->d_counters, 0, kNumCounters * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMalloc(&c->d_small, 4096 * sizeof(double));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    msb_destroy(c);
+    return fail(MSB_EHIP, std::string("msb_create: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return MSB_OK;
+}
+
+extern "C" void msb_destroy(msb_ctx* c) {
+  if (!c) return;
+  (void)hipFree(c->d_conf_up);
+  (void)hipFree(c->d_conf_dn);
+  (void)hipFree(c->d_off_up);
+  (void)hipFree(c->d_off_dn);
+  (void)hipFree(c->d_hop_up);
+  (void)hipFree(c->d_hop_dn);
+  (void)hipFree(c->d_counters);
+  (void)hipFree(c->d_small);
+  if (c->ws) (void)hipFree(c->ws);
+  delete c;
+}
+
+extern "C" int64_t msb_dim(const msb_ctx* c) { return c ? c->D : -1; }
+
+extern "C" msb_status msb_sector_info(const msb_ctx* c, int* nu, int* nd, int* nt) {
+  if (!c) return fail(MSB_EINVAL, "null context");
+  if (nu) *nu = c->up.n;
+  if (nd) *nd = c->dn.n;
+  if (nt) *nt = c->n_types;
+  return MSB_OK;
+}
+
+// =============================================================================
+extern "C" msb_status msb_apply(msb_ctx* ctx, const msb_system* sys, int nsys, double shift,
+                                msb_prec prec, const void* x, void* y, void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx || !sys || !x || !y) return fail(MSB_EINVAL, "msb_apply: null argument");
+  if (nsys <= 0 || nsys > 65535) return fail(MSB_EINVAL, "msb_apply: nsys out of range");
+  if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_apply: invalid precision");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<SysDev> h(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    msb_status r = make_sysdev(ctx, sys[s], -(sys[s].E_G + shift), -sys[s].Gamma, true, h[s]);
+    if (r != MSB_OK) return r;
+  }
+  Arena ar(ctx);
+  ar.reserve(sizeof(SysDev) * nsys);
+  MSB_HIP(ar.commit());
+  SysDev* dsys = ar.take<SysDev>(sizeof(SysDev) * nsys);
+  MSB_HIP(hipMemcpyAsync(dsys, h.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, st));
+  ApplyArgs a = apply_args(ctx, dsys, nsys, x, y);
+  MSB_HIP(launch_apply(prec == MSB_C128 ? Elem::C128 : Elem::C64, kModePlain, a, st));
+  MSB_HIP(hipStreamSynchronize(st));
+  return MSB_OK;
+}
+
+extern "C" msb_status msb_apply_timed(msb_ctx* ctx, const msb_system* sys, int nsys, double shift,
+                                      msb_prec prec, const void* x, void* y, int reps,
+                                      double* ms_per_apply, void* stream) {
+  (void)hipGetLastError();
+  if (!ctx || !sys || !x || !y || !ms_per_apply) return fail(MSB_EINVAL, "msb_apply_timed: null argument");
+  if (nsys <= 0 || nsys > 65535) return fail(MSB_EINVAL, "msb_apply_timed: nsys out of range");
+  if (reps < 1) return fail(MSB_EINVAL, "msb_apply_timed: reps must be >= 1");
+  if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_apply_timed: invalid precision");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<SysDev> h(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    msb_status r = make_sysdev(ctx, sys[s], -(sys[s].E_G + shift), -sys[s].Gamma, true, h[s]);
+    if (r != MSB_OK) return r;
+  }
+  Arena ar(ctx);
+  ar.reserve(sizeof(SysDev) * nsys);
+  MSB_HIP(ar.commit());
+  SysDev* dsys = ar.take<SysDev>(sizeof(SysDev) * nsys);
+  MSB_HIP(hipMemcpyAsync(dsys, h.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, st));
+  ApplyArgs a = apply_args(ctx, dsys, nsys, x, y);
+  const Elem e = prec == MSB_C128 ? Elem::C128 : Elem::C64;
+  MSB_HIP(launch_apply(e, kModePlain, a, st));     // warm-up
+  hipEvent_t e0, e1;
+  MSB_HIP(hipEventCreate(&e0));
+  MSB_HIP(hipEventCreate(&e1));
+  MSB_HIP(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i) MSB_HIP(launch_apply(e, kModePlain, a, st));
+  MSB_HIP(hipEventRecord(e1, st));
+  MSB_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  MSB_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_per_apply = ms / reps;
+  return MSB_OK;
+}
+
+extern "C" msb_status msb_number_op(msb_ctx* ctx, int site, double w_up, double w_dn, int count,
+                                    int x_real, const void* x, void* y, void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx || !x || !y) return fail(MSB_EINVAL, "msb_number_op: null argument");
+  if (count <= 0 || count > 65535) return fail(MSB_EINVAL, "msb_number_op: count out of range");
+  if (site >= ctx->L) return fail(MSB_EINVAL, "msb_number_op: site out of range");
+  hipStream_t st = (hipStream_t)stream;
+  MSB_HIP(launch_number_op(ctx->tables(), ctx->D, site, w_up, w_dn, count, x_real, x, (double*)y, st));
+  MSB_HIP(hipStreamSynchronize(st));
+  return MSB_OK;
+}
+
+// =============================================================================
+// Ground state: FP64 Lanczos with full reorthogonalisation (classical
+// Gram-Schmidt applied twice against every stored Lanczos vector).
+extern "C" msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, const double* x0,
+                                       double tol, int maxit, double* E_G, double* G, int* iters,
+                                       void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx || !sys || !x0 || !E_G || !G) return fail(MSB_EINVAL, "msb_ground_state: null argument");
+  if (maxit <= 0) return fail(MSB_EINVAL, "msb_ground_state: maxit must be positive");
+  if (!(tol > 0)) return fail(MSB_EINVAL, "msb_ground_state: tol must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t D = ctx->D;
+  const int kmax = (int)std::min<int64_t>(maxit, D);
+  SysDev hs;
+  msb_status r = make_sysdev(ctx, *sys, 0.0, 0.0, false, hs);
+  if (r != MSB_OK) return r;
+
+  const size_t part_doubles = std::max<size_t>(
+      {(size_t)apply_nbx(ctx->up.n, 1) * 4, (size_t)gram_blocks(D) * (kmax + 1),
+       (size_t)cocg_nbx(D, 1) * 4});
+  Arena ar(ctx);
+  ar.reserve(sizeof(SysDev));
+  ar.reserve((size_t)(kmax + 1) * D * sizeof(double));            // Q
+  ar.reserve((size_t)D * sizeof(double));                         // w
+  ar.reserve(part_doubles * sizeof(double));                      // partials
+  ar.reserve((size_t)(kmax + 2) * 4 * sizeof(double));            // red
+  ar.reserve((size_t)(kmax + 2) * sizeof(double));                // coefficients
+  size_t fr = 0, tot = 0;
+  MSB_HIP(hipMemGetInfo(&fr, &tot));
+  if (ar.needed() > fr + ctx->ws_size) return fail(MSB_ENOMEM, "msb_ground_state: Lanczos basis does not fit");
+  MSB_HIP(ar.commit());
+  SysDev* dsys = ar.take<SysDev>(sizeof(SysDev));
+  double* Q = ar.take<double>((size_t)(kmax + 1) * D * sizeof(double));
+  double* w = ar.take<double>((size_t)D * sizeof(double));
+  double* partials = ar.take<double>(part_doubles * sizeof(double));
+  double* red = ar.take<double>((size_t)(kmax + 2) * 4 * sizeof(double));
+  double* coef = ar.take<double>((size_t)(kmax + 2) * sizeof(double));
+  unsigned* cnt = ctx->d_counters;
+  if (ar.overflow()) return fail(MSB_EINVAL, "internal: ground-state workspace layout");
+  MSB_HIP(hipMemcpyAsync(dsys, &hs, sizeof(SysDev), hipMemcpyHostToDevice, st));
+
+  auto dot = [&](const double* a, const double* b, double& outv) -> msb_status {
+    MSB_HIP(launch_dot_many(a, 1, b, D, partials, cnt, red, st));
+    MSB_HIP(hipMemcpyAsync(&outv, red, sizeof(double), hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipStreamSynchronize(st));
+    return MSB_OK;
+  };
+  double hscal = 0.0;   // host staging value, alive for the whole call
+  auto scale = [&](const double* src, double s, double* dst) -> msb_status {
+    hscal = s;
+    MSB_HIP(hipMemcpyAsync(coef, &hscal, sizeof(double), hipMemcpyHostToDevice, st));
+    MSB_HIP(launch_scale_real(src, coef, dst, D, st));
+    return MSB_OK;
+  };
+
+  double nx = 0;
+  if ((r = dot(x0, x0, nx)) != MSB_OK) return r;
+  if (!(nx > 0) || !std::isfinite(nx)) return fail(MSB_EINVAL, "msb_ground_state: start vector is zero or not finite");
+  if ((r = scale(x0, 1.0 / std::sqrt(nx), Q)) != MSB_OK) return r;
+
+  std::vector<double> a, b;   // b[k] couples q_k and q_{k+1}
+  std::vector<double> y;
+  double theta = 0.0;
+  bool conv = false;
+  int k = 0;
+  for (k = 0; k < kmax; ++k) {
+    double* qk = Q + (size_t)k * D;
+    ApplyArgs aa = apply_args(ctx, dsys, 1, qk, w);
+    aa.partials = partials;
+    aa.counter = cnt;
+    aa.red = red;
+    MSB_HIP(launch_apply(Elem::R64, kModeHerm, aa, st));
+    double red_h[4];
+    MSB_HIP(hipMemcpyAsync(red_h, red, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipStreamSynchronize(st));
+    const double ak = red_h[0];
+    a.push_back(ak);
+    const double bk = (k > 0) ? b[k - 1] : 0.0;
+    double ab[2] = {ak, bk};
+    MSB_HIP(hipMemcpyAsync(coef, ab, 2 * sizeof(double), hipMemcpyHostToDevice, st));
+    MSB_HIP(launch_lanczos_real_update(w, qk, k > 0 ? Q + (size_t)(k - 1) * D : nullptr, coef, D,
+                                       partials, cnt, red, st));
+    for (int pass = 0; pass < 2; ++pass) {
+      MSB_HIP(launch_dot_many(Q, k + 1, w, D, partials, cnt, red, st));
+      MSB_HIP(launch_gemv_sub(Q, k + 1, red, w, D, st));
+    }
+    double bb = 0;
+    if ((r = dot(w, w, bb)) != MSB_OK) return r;
+    const double bnext = std::sqrt(bb);
+    theta = tridiag_lowest(a, b, y);
+    const double est = std::fabs(bnext * y.back());
+    if (est <= tol * std::fabs(theta) || bnext <= 1e-14 * std::fabs(theta) || k + 1 == kmax) {
+      conv = (est <= tol * std::fabs(theta)) || bnext <= 1e-14 * std::fabs(theta);
+      ++k;
+      break;
+    }
+    b.push_back(bnext);
+    if ((r = scale(w, 1.0 / bnext, Q + (size_t)(k + 1) * D)) != MSB_OK) return r;
+  }
+  // G = Q y, normalised, sign fixed by <x0, G> >= 0
+  MSB_HIP(hipMemcpyAsync(coef, y.data(), y.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  MSB_HIP(launch_gemv(Q, (int)y.size(), coef, G, D, st));
+  double gg = 0, xg = 0;
+  if ((r = dot(G, G, gg)) != MSB_OK) return r;
+  if ((r = dot(x0, G, xg)) != MSB_OK) return r;
+  double sc = 1.0 / std::sqrt(gg);
+  if (xg < 0) sc = -sc;
+  if ((r = scale(G, sc, G)) != MSB_OK) return r;
+  MSB_HIP(hipStreamSynchronize(st));
+  *E_G = theta;
+  if (iters) *iters = k;
+  if (!conv) return fail(MSB_NOT_CONVERGED, "msb_ground_state: Lanczos did not converge within maxit");
+  return MSB_OK;
+}
+
+// =============================================================================
+// Multi-shift solve.
+namespace {
+
+// Bump allocator over the context workspace; with a null base it only counts.
+class Carver {
+ public:
+  explicit Carver(void* base) : base_(static_cast<char*>(base)) {}
+  template <typename T>
+  T* take(size_t bytes) {
+    T* p = base_ ? reinterpret_cast<T*>(base_ + off_) : nullptr;
+    off_ += Arena::align(bytes);
+    return p;
+  }
+  size_t used() const { return off_; }
+
+ private:
+  char* base_;
+  size_t off_ = 0;
+};
+
+struct SolveBufs {
+  void* bank = nullptr;
+  void* pvec = nullptr;
+  void* vvec = nullptr;
+  void* Pc = nullptr;
+  SysDev* dsys = nullptr;
+  SysState* dst = nullptr;
+  double* partials = nullptr;
+  double* red1 = nullptr;
+  double* red2 = nullptr;
+  int* dbase = nullptr;
+  double* wshift = nullptr;
+  double* zeta = nullptr;
+  double* zeta_prev = nullptr;
+  int* conv = nullptr;
+  double* alog = nullptr;
+  double* blog = nullptr;
+  double* rlog = nullptr;
+  int* dlist = nullptr;
+  int* dlend = nullptr;
+  int* dtile = nullptr;
+  double* coef = nullptr;
+  double* gcoef = nullptr;
+  double* cscr = nullptr;
+  double* ab = nullptr;
+  SysDev* tsys = nullptr;       // true-residual systems
+  double* tpart = nullptr;
+  double* tred = nullptr;
+
+  void carve(Carver& c, const msb_ctx* ctx, int B, int cap, int n_shift, int n_list, int maxit,
+             size_t s_el, size_t s_out, bool carry, bool want_true) {
+    const int64_t D = ctx->D;
+    size_t part_n = 0;   // largest nsys * nbx over the batch sizes that can occur
+    for (int n = 1; n <= B; ++n)
+      part_n = std::max(part_n, (size_t)n * std::max(apply_nbx(ctx->up.n, n), cocg_nbx(D, n)));
+    bank = c.take<void>((size_t)cap * B * D * s_el);
+    pvec = c.take<void>((size_t)B * D * s_el);
+    vvec = c.take<void>((size_t)B * D * s_el);
+    Pc = carry ? c.take<void>((size_t)B * n_shift * D * s_out) : nullptr;
+    dsys = c.take<SysDev>(B * sizeof(SysDev));
+    dst = c.take<SysState>(B * sizeof(SysState));
+    partials = c.take<double>(part_n * 4 * sizeof(double));
+    red1 = c.take<double>((size_t)B * 4 * sizeof(double));
+    red2 = c.take<double>((size_t)B * 4 * sizeof(double));
+    dbase = c.take<int>(4 * sizeof(int));
+    wshift = c.take<double>((size_t)n_shift * sizeof(double));
+    zeta = c.take<double>((size_t)B * n_shift * 2 * sizeof(double));
+    zeta_prev = c.take<double>((size_t)B * n_shift * 2 * sizeof(double));
+    conv = c.take<int>((size_t)B * n_shift * sizeof(int));
+    alog = c.take<double>((size_t)B * maxit * 2 * sizeof(double));
+    blog = c.take<double>((size_t)B * maxit * 2 * sizeof(double));
+    rlog = c.take<double>((size_t)B * (maxit + 1) * sizeof(double));
+    const int n_stiles = n_list / flush_shifts_per_tile();
+    dlist = c.take<int>((size_t)B * n_list * sizeof(int));
+    dlend = c.take<int>((size_t)B * n_list * sizeof(int));
+    dtile = c.take<int>((size_t)B * (n_stiles + 1) * sizeof(int));
+    coef = c.take<double>((size_t)B * n_list * cap * 2 * sizeof(double));
+    gcoef = carry ? c.take<double>((size_t)B * n_list * cap * 2 * sizeof(double)) : nullptr;
+    cscr = c.take<double>((size_t)B * n_list * cap * 4 * sizeof(double));
+    ab = c.take<double>((size_t)B * n_list * 4 * sizeof(double));
+    if (want_true) {
+      const size_t nt = (size_t)B * n_shift;
+      tsys = c.take<SysDev>(nt * sizeof(SysDev));
+      size_t tp = 0;
+      for (int n = 1; n <= B; ++n) tp = std::max(tp, (size_t)n * n_shift * apply_nbx(ctx->up.n, n * n_shift));
+      tpart = c.take<double>(tp * 4 * sizeof(double));
+      tred = c.take<double>(nt * 4 * sizeof(double));
+    }
+  }
+};
+
+}  // namespace
+
+extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, const void* E,
+                                const double* w_in, int n_shift, double seed_shift, double tol,
+                                int maxit, msb_prec prec, void* psi, msb_info* info,
+                                const msb_opts* opts, void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx || !sys || !E || !w_in || !psi) return fail(MSB_EINVAL, "msb_solve: null argument");
+  if (nsys <= 0) return fail(MSB_EINVAL, "msb_solve: nsys must be positive");
+  if (n_shift <= 0 || n_shift > 65535) return fail(MSB_EINVAL, "msb_solve: n_shift out of range");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(MSB_EINVAL, "msb_solve: tol must be positive");
+  if (maxit < 0 || maxit > 1000000) return fail(MSB_EINVAL, "msb_solve: maxit out of range");
+  if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_solve: invalid precision");
+  if (!std::isfinite(seed_shift)) return fail(MSB_EINVAL, "msb_solve: seed_shift must be finite");
+  for (int k = 0; k < n_shift; ++k)
+    if (!std::isfinite(w_in[k])) return fail(MSB_EINVAL, "msb_solve: non-finite shift");
+  const int chunk = (opts && opts->chunk > 0) ? opts->chunk : 16;
+  const double memfrac = (opts && opts->mem_fraction > 0) ? std::min(opts->mem_fraction, 0.98) : 0.9;
+  const Elem ev = (prec == MSB_C128) ? Elem::C128 : Elem::C64;
+  const Elem eo = ev;
+  const int64_t D = ctx->D;
+  const int mx = std::max(maxit, 1);
+  const int tile_s = flush_shifts_per_tile();
+  const int n_list = ((n_shift + tile_s - 1) / tile_s) * tile_s;
+  const size_t s_el = elem_bytes(ev), s_out = elem_bytes(eo);
+  const bool want_true = info && info->resid_true;
+
+  std::vector<SysDev> hsys(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    msb_status r = make_sysdev(ctx, sys[s], -(sys[s].E_G + seed_shift), -sys[s].Gamma, true, hsys[s]);
+    if (r != MSB_OK) return r;
+  }
+
+  // ---- plan: batch size and bank capacity from the memory that is free ----
+  size_t fr = 0, tot = 0;
+  MSB_HIP(hipMemGetInfo(&fr, &tot));
+  const size_t budget = (size_t)((double)(fr + ctx->ws_size) * memfrac);
+  auto need_bytes = [&](int B, int cap, bool carry) {
+    Carver c(nullptr);
+    SolveBufs b;
+    b.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, carry, want_true);
+    return c.used();
+  };
+  int planB = 0, plancap = 0;
+  bool plancarry = false;
+  int Bmax = std::min(nsys, 64);
+  if (opts && opts->batch > 0) Bmax = std::min(Bmax, opts->batch);
+  // Default bank: 1024 residual slots (enough for the iteration counts of the
+  // workloads); a fixed size keeps repeated solves on the same workspace.
+  int want_cap = std::min(mx + 1, 1024);
+  if (opts && opts->bank_slots > 0) want_cap = std::min(mx + 1, std::max(opts->bank_slots, 3));
+  // Prefer the whole batch: first with a bank for every iteration, then with a
+  // smaller bank plus the carried p^w buffer, and only then fewer systems.
+  const int min_cap = std::min(want_cap, 64);
+  for (int B = Bmax; B >= 1 && planB == 0; --B) {
+    const bool carry_needed = want_cap < mx + 1;
+    if (need_bytes(B, want_cap, carry_needed) <= budget) {
+      planB = B; plancap = want_cap; plancarry = carry_needed;
+      break;
+    }
+    if (need_bytes(B, min_cap, true) > budget) continue;
+    int lo = min_cap, hi = want_cap;        // largest cap that fits with a carry buffer
+    while (hi - lo > 1) {
+      const int mid = lo + (hi - lo) / 2;
+      if (need_bytes(B, mid, true) <= budget) lo = mid; else hi = mid;
+    }
+    planB = B; plancap = lo; plancarry = true;
+  }
+  if (planB == 0) {
+    for (int cap = min_cap - 1; cap >= 3; --cap) {
+      if (need_bytes(1, cap, true) <= budget) {
+        planB = 1; plancap = cap; plancarry = true;
+        break;
+      }
+    }
+  }
+  if (planB == 0) return fail(MSB_ENOMEM, "msb_solve: workspace does not fit in device memory");
+
+  hipStream_t ust = (hipStream_t)stream;
+  MSB_HIP(hipStreamSynchronize(ust));
+  hipStream_t st = ust;
+
+  const int B = planB, cap = plancap;
+  const int n_stiles = n_list / tile_s;
+
+  Arena ar(ctx);
+  ar.reserve(need_bytes(B, cap, plancarry));
+  MSB_HIP(ar.commit());
+  SolveBufs bf;
+  {
+    Carver c(ctx->ws);
+    bf.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, plancarry, want_true);
+  }
+  void* bank = bf.bank;
+  void* pvec = bf.pvec;
+  void* vvec = bf.vvec;
+  void* Pc = bf.Pc;
+  SysDev* dsys = bf.dsys;
+  SysState* dst = bf.dst;
+  double* partials = bf.partials;
+  double* red1 = bf.red1;
+  double* red2 = bf.red2;
+  int* dbase = bf.dbase;
+  double* wshift = bf.wshift;
+  double* zeta = bf.zeta;
+  double* zeta_prev = bf.zeta_prev;
+  int* conv = bf.conv;
+  double* alog = bf.alog;
+  double* blog = bf.blog;
+  double* rlog = bf.rlog;
+  int* dlist = bf.dlist;
+  int* dlend = bf.dlend;
+  int* dtile = bf.dtile;
+  double* coef = bf.coef;
+  double* gcoef = bf.gcoef;
+  double* cscr = bf.cscr;
+  double* ab = bf.ab;
+  unsigned* cnt = ctx->d_counters;
+
+  std::vector<double> hw(n_shift);
+  for (int k = 0; k < n_shift; ++k) hw[k] = w_in[k] - seed_shift;
+  MSB_HIP(hipMemcpyAsync(wshift, hw.data(), n_shift * sizeof(double), hipMemcpyHostToDevice, st));
+
+  hipEvent_t ev0, ev1, eg0, eg1;
+  MSB_HIP(hipEventCreate(&ev0));
+  MSB_HIP(hipEventCreate(&ev1));
+  MSB_HIP(hipEventCreate(&eg0));
+  MSB_HIP(hipEventCreate(&eg1));
+  double t_iter = 0, t_flush = 0, t_true = 0, t_gemm = 0, gemm_flops = 0, gemm_bytes = 0;
+  int n_gemm = 0;
+  auto elapsed = [&](double& acc) -> msb_status {
+    MSB_HIP(hipEventSynchronize(ev1));
+    float ms = 0;
+    MSB_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    acc += ms;
+    return MSB_OK;
+  };
+
+  msb_status result = MSB_OK;
+  int max_iters = 0, total_mvms = 0, brk_iter = -1, flushes = 0;
+  std::vector<SysState> hst(B);
+  std::vector<int> hconv((size_t)B * n_shift);
+  std::vector<double> hz((size_t)B * n_shift * 2);
+  std::vector<double> hrlog((size_t)B * (mx + 1));
+
+  for (int b0 = 0; b0 < nsys; b0 += B) {
+    const int nb = std::min(B, nsys - b0);
+    const double* Eb = (const double*)E + (size_t)b0 * D * 2;
+    char* psib = (char*)psi + (size_t)b0 * n_shift * D * s_out;
+    MSB_HIP(hipMemcpyAsync(dsys, hsys.data() + b0, nb * sizeof(SysDev), hipMemcpyHostToDevice, st));
+    int zero = 0;
+    MSB_HIP(hipMemcpyAsync(dbase, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+
+    MSB_HIP(hipEventRecord(ev0, st));
+    InitArgs ia;
+    ia.E = Eb; ia.bank = bank; ia.pvec = pvec; ia.st = dst; ia.partials = partials; ia.counter = cnt;
+    ia.cap = cap; ia.D = D; ia.nbx = cocg_nbx(D, nb); ia.nsys = nb; ia.n_shift = n_shift; ia.zeta = zeta;
+    ia.zeta_prev = zeta_prev; ia.conv_iter = conv; ia.rnorm_log = rlog; ia.maxit = mx;
+    MSB_HIP(launch_cocg_init(ev, ia, st));
+
+    ApplyArgs aa = apply_args(ctx, dsys, nb, pvec, vvec);
+    aa.aux = bank;
+    aa.partials = partials;
+    aa.counter = cnt;
+    aa.red = red1;
+    aa.status = &dst[0].status;
+    aa.status_stride = (int)(sizeof(SysState) / sizeof(int));
+    aa.aux_m = &dst[0].m;
+    aa.aux_base = dbase;
+    aa.aux_cap = cap;
+
+    CocgArgs ca;
+    ca.st = dst; ca.red1 = red1; ca.partials = partials; ca.counter = cnt; ca.red2 = red2;
+    ca.bank = bank; ca.vvec = vvec; ca.pvec = pvec; ca.base = dbase; ca.cap = cap; ca.D = D;
+    ca.nbx = cocg_nbx(D, nb); ca.nsys = nb; ca.n_shift = n_shift; ca.wshift = wshift; ca.zeta = zeta;
+    ca.zeta_prev = zeta_prev; ca.conv_iter = conv; ca.tol = tol; ca.maxit = mx;
+    ca.alpha_log = alog; ca.beta_log = blog; ca.rnorm_log = rlog;
+
+    int base = 0;
+    bool first_flush = true;
+    // flush residual slots [base, m) into psi (and the carried p^w if `carry`)
+    auto flush = [&](bool carry) -> msb_status {
+      MSB_HIP(hipMemcpyAsync(hst.data(), dst, nb * sizeof(SysState), hipMemcpyDeviceToHost, st));
+      MSB_HIP(hipMemcpyAsync(hconv.data(), conv, (size_t)nb * n_shift * sizeof(int), hipMemcpyDeviceToHost, st));
+      MSB_HIP(hipStreamSynchronize(st));
+      std::vector<int> list((size_t)nb * n_list, -1), lend((size_t)nb * n_list, 0);
+      std::vector<int> tile((size_t)nb * n_stiles, 0);
+      int K = 0;
+      for (int s = 0; s < nb; ++s) {
+        const int ms = hst[s].m;
+        std::vector<std::pair<int, int>> part;   // (lend, k)
+        for (int k = 0; k < n_shift; ++k) {
+          const int Mw = hconv[(size_t)s * n_shift + k];
+          if (!(base == 0 || Mw < 0 || Mw > base)) continue;
+          const int endk = (Mw < 0) ? ms : std::min(Mw, ms);
+          part.push_back({std::max(endk - base, 0), k});
+        }
+        std::stable_sort(part.begin(), part.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+          return x.first > y.first;
+        });
+        for (size_t j = 0; j < part.size(); ++j) {
+          list[(size_t)s * n_list + j] = part[j].second;
+          lend[(size_t)s * n_list + j] = part[j].first;
+          K = std::max(K, part[j].first);
+          int& tk = tile[(size_t)s * n_stiles + j / tile_s];
+          tk = std::max(tk, part[j].first);
+        }
+      }
+      if (K > cap) return fail(MSB_EINVAL, "internal: flush range exceeds the bank");
+      const int Kc = std::max(K, 1);
+      MSB_HIP(hipMemcpyAsync(dlist, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      MSB_HIP(hipMemcpyAsync(dlend, lend.data(), lend.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      MSB_HIP(hipMemcpyAsync(dtile, tile.data(), tile.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      MSB_HIP(hipEventRecord(ev0, st));
+      CoefArgs cf;
+      cf.st = dst; cf.alpha_log = alog; cf.beta_log = blog; cf.wshift = wshift; cf.conv_iter = conv;
+      cf.list = dlist; cf.lend = dlend; cf.coef = coef; cf.gcoef = carry ? gcoef : nullptr; cf.ab = ab;
+      cf.nsys = nb; cf.n_shift = n_shift; cf.n_list = n_list; cf.maxit = mx; cf.K = Kc; cf.base = base;
+      MSB_HIP(launch_coef(cf, cscr, st));
+      FlushArgs fa;
+      fa.bank = bank; fa.cap = cap; fa.coef = coef; fa.pw = nullptr; fa.ow = nullptr;
+      fa.pw_stride = 4; fa.ow_stride = 4; fa.list = dlist; fa.tile_k = dtile; fa.out = psib;
+      fa.X = nullptr; fa.D = D; fa.n_shift = n_shift; fa.n_list = n_list; fa.K = Kc; fa.nsys = nb;
+      fa.n_etiles = (int)((D + flush_elems_per_tile() - 1) / flush_elems_per_tile());
+      fa.n_stiles = n_stiles;
+      if (!first_flush && Pc) {
+        fa.pw = ab;          // Psi += (bw_base S_base) p_{base-1}
+        fa.X = Pc;
+      }
+      MSB_HIP(hipEventRecord(eg0, st));
+      MSB_HIP(launch_flush(ev, eo, fa, first_flush ? 0 : 1, st));
+      MSB_HIP(hipEventRecord(eg1, st));
+      ++n_gemm;
+      // algorithmic work: every (system, shift) range reads its residual slots
+      // once per tile of shifts and writes (and re-reads if accumulating) Psi
+      double sum_len = 0, n_out = 0;
+      for (size_t j = 0; j < lend.size(); ++j)
+        if (list[j] >= 0) { sum_len += lend[j]; n_out += 1; }
+      gemm_flops += 8.0 * (double)D * sum_len;
+      gemm_bytes += (double)D * ((double)K * nb * s_el + n_out * s_out * (first_flush ? 1.0 : 3.0));
+      if (carry) {
+        FlushArgs fp = fa;
+        fp.coef = gcoef;
+        fp.out = Pc;
+        fp.pw = nullptr;
+        fp.X = nullptr;
+        fp.ow = ab + 2;      // p_{end-1} = (bw_base G_base) p_{base-1} + ...
+        MSB_HIP(launch_flush(ev, eo, fp, first_flush ? 0 : 2, st));
+      }
+      MSB_HIP(hipEventRecord(ev1, st));
+      msb_status r = elapsed(t_flush);
+      if (r != MSB_OK) return r;
+      {
+        float ms = 0;
+        MSB_HIP(hipEventElapsedTime(&ms, eg0, eg1));
+        t_gemm += ms;
+      }
+      first_flush = false;
+      ++flushes;
+      return MSB_OK;
+    };
+
+    int it_done = 0;
+    while (true) {
+      // one chunk of seed iterations; kernels skip systems that are not active
+      for (int c = 0; c < chunk; ++c) {
+        MSB_HIP(launch_apply(ev, kModeBilinear, aa, st));
+        MSB_HIP(launch_cocg_r(ev, ca, st));
+        MSB_HIP(launch_cocg_p(ev, ca, st));
+      }
+      it_done += chunk;
+      MSB_HIP(hipMemcpyAsync(hst.data(), dst, nb * sizeof(SysState), hipMemcpyDeviceToHost, st));
+      MSB_HIP(hipStreamSynchronize(st));
+      bool any_active = false, any_paused = false;
+      for (int s = 0; s < nb; ++s) {
+        any_active |= hst[s].status == kActive;
+        any_paused |= hst[s].status == kPaused || hst[s].status == kPausedHold;
+      }
+      if (any_active) continue;
+      if (any_paused) {
+        MSB_HIP(hipEventRecord(ev1, st));
+        msb_status r = elapsed(t_iter);
+        if (r != MSB_OK) return r;
+        if (!plancarry) return fail(MSB_EINVAL, "internal: bank full without carry buffer");
+        r = flush(true);
+        if (r != MSB_OK) return r;
+        // restart the bank at the current residual r_m
+        int m = -1;
+        for (int s = 0; s < nb; ++s)
+          if (hst[s].status == kPaused || hst[s].status == kPausedHold) {
+            if (m >= 0 && hst[s].m != m) return fail(MSB_EINVAL, "internal: paused systems out of step");
+            m = hst[s].m;
+          }
+        MSB_HIP(launch_copy_slot(ev, (const char*)bank + (size_t)(m - base) * D * s_el, bank, D, nb,
+                                 (int64_t)cap * D, (int64_t)cap * D, st));
+        base = m;
+        MSB_HIP(hipMemcpyAsync(dbase, &base, sizeof(int), hipMemcpyHostToDevice, st));
+        for (int s = 0; s < nb; ++s)
+          if (hst[s].status == kPaused || hst[s].status == kPausedHold) hst[s].status = kActive;
+        MSB_HIP(hipMemcpyAsync(dst, hst.data(), nb * sizeof(SysState), hipMemcpyHostToDevice, st));
+        MSB_HIP(hipEventRecord(ev0, st));
+        continue;
+      }
+      break;
+    }
+    MSB_HIP(hipEventRecord(ev1, st));
+    {
+      msb_status r = elapsed(t_iter);
+      if (r != MSB_OK) return r;
+    }
+    {
+      msb_status r = flush(false);
+      if (r != MSB_OK) return r;
+    }
+    (void)it_done;
+
+    // report
+    MSB_HIP(hipMemcpyAsync(hst.data(), dst, nb * sizeof(SysState), hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipMemcpyAsync(hconv.data(), conv, (size_t)nb * n_shift * sizeof(int), hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipMemcpyAsync(hz.data(), zeta, (size_t)nb * n_shift * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipMemcpyAsync(hrlog.data(), rlog, (size_t)nb * (mx + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipStreamSynchronize(st));
+    for (int s = 0; s < nb; ++s) {
+      const SysState& t = hst[s];
+      max_iters = std::max(max_iters, t.m);
+      total_mvms += t.m;
+      if (t.status == kBreakdown) {
+        result = MSB_BREAKDOWN;
+        if (brk_iter < 0 || t.breakdown_iter < brk_iter) brk_iter = t.breakdown_iter;
+      } else if (t.status == kMaxit && result == MSB_OK) {
+        result = MSB_NOT_CONVERGED;
+      }
+      if (info && info->sys_iters) info->sys_iters[b0 + s] = t.m;
+      for (int k = 0; k < n_shift; ++k) {
+        const size_t idx = (size_t)s * n_shift + k;
+        const size_t oidx = (size_t)(b0 + s) * n_shift + k;
+        const int Mw = hconv[idx];
+        if (info && info->shift_iters) info->shift_iters[oidx] = Mw;
+        if (info && info->resid_rec) {
+          const int mm = (Mw >= 0) ? Mw : t.m;
+          const double zabs = std::hypot(hz[2 * idx], hz[2 * idx + 1]);
+          info->resid_rec[oidx] = (t.normE > 0) ? hrlog[(size_t)s * (mx + 1) + mm] / zabs / t.normE : 0.0;
+        }
+      }
+    }
+
+    // optional FP64 true residuals |E - (A - w) Psi| / |E|
+    if (info && info->resid_true) {
+      const int nt = nb * n_shift;
+      std::vector<SysDev> tsys(nt);
+      for (int s = 0; s < nb; ++s)
+        for (int k = 0; k < n_shift; ++k) {
+          msb_status r = make_sysdev(ctx, sys[b0 + s], -(sys[b0 + s].E_G + w_in[k]), -sys[b0 + s].Gamma,
+                                     true, tsys[(size_t)s * n_shift + k]);
+          if (r != MSB_OK) return r;
+        }
+      const size_t need_sys = (size_t)nt * sizeof(SysDev);
+      const size_t need_red = (size_t)nt * 4 * sizeof(double);
+      std::vector<double> hred((size_t)nt * 4);
+      MSB_HIP(hipMemcpyAsync(bf.tsys, tsys.data(), need_sys, hipMemcpyHostToDevice, st));
+      MSB_HIP(hipEventRecord(ev0, st));
+      ApplyArgs ta = apply_args(ctx, bf.tsys, nt, psib, nullptr);
+      ta.aux = Eb;
+      ta.aux_div = n_shift;
+      ta.partials = bf.tpart;
+      ta.counter = cnt;
+      ta.red = bf.tred;
+      MSB_HIP(launch_apply(ev == Elem::C128 ? Elem::C128 : Elem::C64, kModeResid, ta, st));
+      MSB_HIP(hipEventRecord(ev1, st));
+      MSB_HIP(hipMemcpyAsync(hred.data(), bf.tred, need_red, hipMemcpyDeviceToHost, st));
+      {
+        msb_status r = elapsed(t_true);
+        if (r != MSB_OK) return r;
+      }
+      MSB_HIP(hipStreamSynchronize(st));
+      for (int s = 0; s < nb; ++s)
+        for (int k = 0; k < n_shift; ++k) {
+          const size_t idx = (size_t)s * n_shift + k;
+          const double nE = hst[s].normE;
+          info->resid_true[(size_t)(b0 + s) * n_shift + k] = nE > 0 ? std::sqrt(hred[idx * 4 + 2]) / nE : 0.0;
+        }
+    }
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  (void)hipEventDestroy(eg0);
+  (void)hipEventDestroy(eg1);
+  if (info) {
+    info->t_gemm_ms = t_gemm;
+    info->n_gemm = n_gemm;
+    info->gemm_flops = gemm_flops;
+    info->gemm_bytes = gemm_bytes;
+    info->iters = max_iters;
+    info->mvms = total_mvms;
+    info->breakdown_iter = brk_iter;
+    info->flushes = flushes;
+    info->t_iter_ms = t_iter;
+    info->t_flush_ms = t_flush;
+    info->t_true_ms = t_true;
+  }
+  if (result == MSB_BREAKDOWN) return fail(MSB_BREAKDOWN, "msb_solve: COCG breakdown (r^T A p or r^T r vanished)");
+  if (result == MSB_NOT_CONVERGED) return fail(MSB_NOT_CONVERGED, "msb_solve: iteration cap reached");
+  return MSB_OK;
+}
+
+// =============================================================================
+extern "C" msb_status msb_combine(msb_ctx* ctx, int nsys, int n_shift, msb_prec prec, const void* psi,
+                                  const double* phase_re, const double* phase_im, const int* o1_site,
+                                  const double* o1_wup, const double* o1_wdn, void* phi, void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx || !psi || !phi || !phase_re || !phase_im) return fail(MSB_EINVAL, "msb_combine: null argument");
+  if (nsys <= 0 || n_shift <= 0 || n_shift > 65535) return fail(MSB_EINVAL, "msb_combine: sizes out of range");
+  if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_combine: invalid precision");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> c((size_t)nsys * 4);
+  std::vector<int> site(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    c[4 * s] = phase_re[s];
+    c[4 * s + 1] = phase_im[s];
+    c[4 * s + 2] = o1_wup ? o1_wup[s] : 1.0;
+    c[4 * s + 3] = o1_wdn ? o1_wdn[s] : 1.0;
+    site[s] = o1_site ? o1_site[s] : -1;
+    if (site[s] >= ctx->L) return fail(MSB_EINVAL, "msb_combine: site out of range");
+  }
+  Arena ar(ctx);
+  ar.reserve(c.size() * sizeof(double));
+  ar.reserve(site.size() * sizeof(int));
+  MSB_HIP(ar.commit());
+  double* dc = ar.take<double>(c.size() * sizeof(double));
+  int* ds = ar.take<int>(site.size() * sizeof(int));
+  MSB_HIP(hipMemcpyAsync(dc, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  MSB_HIP(hipMemcpyAsync(ds, site.data(), site.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  MSB_HIP(launch_combine(ctx->tables(), ctx->D, nsys, n_shift, prec == MSB_C128 ? Elem::C128 : Elem::C64,
+                         psi, dc, ds, (double*)phi, st));
+  MSB_HIP(hipStreamSynchronize(st));
+  return MSB_OK;
+}
+
+// =============================================================================
+// Continued-fraction spectrum: a block of independent Hermitian Lanczos
+// recurrences on H, one per vector phi_k.
+extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const void* phi, int n,
+                                   const double* w, int n_w, double eta, int lanczos_max,
+                                   double cf_tol, double* I, int* depth_out, void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx || !sys || !phi || !w || !I) return fail(MSB_EINVAL, "msb_spectrum: null argument");
+  if (n <= 0 || n > 65535 || n_w <= 0) return fail(MSB_EINVAL, "msb_spectrum: sizes out of range");
+  if (!(eta > 0)) return fail(MSB_EINVAL, "msb_spectrum: eta must be positive");
+  if (lanczos_max <= 0) return fail(MSB_EINVAL, "msb_spectrum: lanczos_max must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t D = ctx->D;
+  const int kmax = (int)std::min<int64_t>(lanczos_max, D);
+  const int ld = kmax + 1;
+  SysDev hs;
+  msb_status r = make_sysdev(ctx, *sys, 0.0, 0.0, false, hs);
+  if (r != MSB_OK) return r;
+  std::vector<SysDev> hsys(n, hs);
+  const int nbx_l = lanczos_nbx(D, n);
+  const size_t part_doubles =
+      (size_t)n * std::max(apply_nbx(ctx->up.n, n), nbx_l) * 4;
+
+  Arena ar(ctx);
+  const size_t vec_bytes = (size_t)n * D * 16;
+  const size_t sizes[] = {vec_bytes, vec_bytes, vec_bytes,                        // bufA, bufB, bufW
+                          (size_t)n * sizeof(SysDev), part_doubles * sizeof(double),
+                          (size_t)n * 4 * sizeof(double), (size_t)n * 4 * sizeof(double),   // reda, redb
+                          (size_t)n * sizeof(double), (size_t)n * sizeof(double),
+                          (size_t)n * sizeof(double),                                    // dzero dbcur dnorm2
+                          (size_t)n * sizeof(int), (size_t)n * sizeof(int),             // dactive ddepth
+                          (size_t)n * ld * sizeof(double), (size_t)n * ld * sizeof(double),  // logs
+                          (size_t)n_w * sizeof(double), (size_t)n * n_w * sizeof(double)};
+  for (size_t z : sizes) ar.reserve(z);
+  size_t fr = 0, tot = 0;
+  MSB_HIP(hipMemGetInfo(&fr, &tot));
+  if (ar.needed() > fr + ctx->ws_size) return fail(MSB_ENOMEM, "msb_spectrum: block Lanczos does not fit");
+  MSB_HIP(ar.commit());
+  double* bufA = ar.take<double>(vec_bytes);
+  double* bufB = ar.take<double>(vec_bytes);
+  double* bufW = ar.take<double>(vec_bytes);
+  SysDev* dsys = ar.take<SysDev>((size_t)n * sizeof(SysDev));
+  double* partials = ar.take<double>(part_doubles * sizeof(double));
+  double* reda = ar.take<double>((size_t)n * 4 * sizeof(double));
+  double* redb = ar.take<double>((size_t)n * 4 * sizeof(double));
+  double* dzero = ar.take<double>((size_t)n * sizeof(double));
+  double* dbcur = ar.take<double>((size_t)n * sizeof(double));
+  double* dnorm2 = ar.take<double>((size_t)n * sizeof(double));
+  int* dactive = ar.take<int>((size_t)n * sizeof(int));
+  int* ddepth = ar.take<int>((size_t)n * sizeof(int));
+  double* dalog = ar.take<double>((size_t)n * ld * sizeof(double));
+  double* dblog = ar.take<double>((size_t)n * ld * sizeof(double));
+  double* dw = ar.take<double>((size_t)n_w * sizeof(double));
+  double* dI = ar.take<double>((size_t)n * n_w * sizeof(double));
+  if (ar.overflow()) return fail(MSB_EINVAL, "internal: spectrum workspace layout");
+  unsigned* cnt = ctx->d_counters;
+
+  MSB_HIP(hipMemcpyAsync(dsys, hsys.data(), n * sizeof(SysDev), hipMemcpyHostToDevice, st));
+  MSB_HIP(hipMemcpyAsync(dw, w, n_w * sizeof(double), hipMemcpyHostToDevice, st));
+  MSB_HIP(hipMemsetAsync(dzero, 0, n * sizeof(double), st));
+  MSB_HIP(hipMemsetAsync(bufB, 0, (size_t)n * D * 16, st));
+  std::vector<int> active(n, 0);
+  MSB_HIP(hipMemcpyAsync(dactive, active.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+
+  // |phi_k|^2: w = phi, w -= 0*q + 0*qprev, partial |w|^2
+  MSB_HIP(hipMemcpyAsync(bufW, phi, (size_t)n * D * 16, hipMemcpyDeviceToDevice, st));
+  BlockLanczosArgs bl;
+  bl.w = bufW; bl.q = bufW; bl.qprev = bufW; bl.a = reda; bl.b = dzero; bl.active = dactive;
+  bl.partials = partials; bl.counter = cnt; bl.red = redb; bl.D = D; bl.nbx = nbx_l; bl.n = n;
+  MSB_HIP(hipMemsetAsync(reda, 0, (size_t)n * 4 * sizeof(double), st));
+  MSB_HIP(launch_block_lanczos_update(bl, st));
+  std::vector<double> hred((size_t)n * 4), norm2(n), bcur(n, 0.0);
+  MSB_HIP(hipMemcpyAsync(hred.data(), redb, n * 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  MSB_HIP(hipStreamSynchronize(st));
+  std::vector<double> alog((size_t)n * ld, 0.0), blog((size_t)n * ld, 0.0);
+  std::vector<int> depth(n, 0);
+  for (int j = 0; j < n; ++j) {
+    norm2[j] = hred[4 * j];
+    bcur[j] = std::sqrt(norm2[j]);
+    blog[(size_t)j * ld] = bcur[j];
+    if (!(norm2[j] > 0)) active[j] = 1;    // phi = 0: I = 0
+  }
+  MSB_HIP(hipMemcpyAsync(dnorm2, norm2.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+  MSB_HIP(hipMemcpyAsync(dbcur, bcur.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+  MSB_HIP(hipMemcpyAsync(dactive, active.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+  // q_0 = phi / |phi| into bufA
+  MSB_HIP(launch_block_scale(bufW, dbcur, dactive, bufA, D, n, st));
+  std::vector<double> zeros(n, 0.0);
+  MSB_HIP(hipMemcpyAsync(dbcur, zeros.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+
+  double* q = bufA;
+  double* qp = bufB;
+  double* wv = bufW;
+  std::vector<double> Iprev((size_t)n * n_w, 0.0), Icur((size_t)n * n_w, 0.0);
+  std::vector<int> checked(n, 0);
+  const int check_every = 10;
+  auto eval_cf = [&](std::vector<double>& out) -> msb_status {
+    MSB_HIP(hipMemcpyAsync(dalog, alog.data(), alog.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    MSB_HIP(hipMemcpyAsync(dblog, blog.data(), blog.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    MSB_HIP(hipMemcpyAsync(ddepth, depth.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+    MSB_HIP(launch_cf_eval(dalog, dblog, ddepth, ld, dnorm2, n, dw, n_w, sys->E_G, eta, dI, st));
+    MSB_HIP(hipMemcpyAsync(out.data(), dI, out.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipStreamSynchronize(st));
+    return MSB_OK;
+  };
+
+  for (int k = 0; k < kmax; ++k) {
+    bool any = false;
+    for (int j = 0; j < n; ++j) any |= active[j] == 0;
+    if (!any) break;
+    ApplyArgs aa = apply_args(ctx, dsys, n, q, wv);
+    aa.partials = partials;
+    aa.counter = cnt;
+    aa.red = reda;
+    aa.status = dactive;
+    aa.status_stride = 1;
+    MSB_HIP(launch_apply(Elem::C128, kModeHerm, aa, st));
+    bl.w = wv; bl.q = q; bl.qprev = qp; bl.a = reda; bl.b = dbcur;
+    MSB_HIP(launch_block_lanczos_update(bl, st));
+    std::vector<double> ha((size_t)n * 4);
+    MSB_HIP(hipMemcpyAsync(ha.data(), reda, n * 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipMemcpyAsync(hred.data(), redb, n * 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    MSB_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < n; ++j) {
+      if (active[j] != 0) continue;
+      alog[(size_t)j * ld + k] = ha[4 * j];
+      depth[j] = k + 1;
+      const double bn = std::sqrt(hred[4 * j]);
+      bcur[j] = bn;
+      if (k + 1 < ld) blog[(size_t)j * ld + k + 1] = bn;
+      if (!(bn > 1e-14 * std::sqrt(norm2[j]))) active[j] = 2;   // invariant subspace reached
+    }
+    // convergence of the continued fraction every check_every steps
+    if ((k + 1) % check_every == 0) {
+      r = eval_cf(Icur);
+      if (r != MSB_OK) return r;
+      for (int j = 0; j < n; ++j) {
+        if (active[j] != 0) continue;
+        if (checked[j]) {
+          double dmax = 0, imax = 0;
+          for (int i = 0; i < n_w; ++i) {
+            dmax = std::max(dmax, std::fabs(Icur[(size_t)j * n_w + i] - Iprev[(size_t)j * n_w + i]));
+            imax = std::max(imax, std::fabs(Icur[(size_t)j * n_w + i]));
+          }
+          if (dmax <= cf_tol * imax) active[j] = 3;
+        }
+        checked[j] = 1;
+      }
+      Iprev = Icur;
+    }
+    MSB_HIP(hipMemcpyAsync(dbcur, bcur.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    MSB_HIP(hipMemcpyAsync(dactive, active.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+    // q_{k+1} = w / b_{k+1} into the buffer of q_{k-1}, then rotate
+    MSB_HIP(launch_block_scale(wv, dbcur, dactive, qp, D, n, st));
+    std::swap(q, qp);
+  }
+  r = eval_cf(Icur);
+  if (r != MSB_OK) return r;
+  std::memcpy(I, Icur.data(), Icur.size() * sizeof(double));
+  if (depth_out)
+    for (int j = 0; j < n; ++j) depth_out[j] = depth[j];
+  return MSB_OK;
+}

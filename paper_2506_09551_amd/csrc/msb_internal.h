@@ -1,0 +1,300 @@
+// Internal declarations of the MI355X multi-shift BiCG library.
+//
+// Layout of a many-body vector: index = rank_up(u) * n_dn + rank_dn(d); the
+// Hamiltonian H = H_up (x) I + I (x) H_dn + diagonal (Sec. III, Eq. Hubbard,
+// with the core-hole term of Eq. intermediate_H) is applied matrix-free from
+// per-spin hopping tables.  See msb.h for the public contract.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/msb.h"
+
+namespace msb {
+
+constexpr int kBlock = 256;            // threads per block of the streaming kernels
+constexpr int kWave = 64;              // CDNA wavefront
+constexpr int kNumXcd = 8;             // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kNumCounters = 65536;    // per-system last-block counters (grid.y <= 65535)
+
+// ---- error handling ---------------------------------------------------------
+void set_error(const std::string& msg);
+msb_status fail(msb_status st, const std::string& msg);
+#define MSB_HIP(call)                                                             \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return ::msb::fail(MSB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---- per-spin tables (host build, tables.cpp) --------------------------------
+// Hop entry: (target_rank << 16) | (bond_type << 1) | neg.  The matrix element
+// <c'|H_sigma|c> = -t_type * (neg ? -1 : +1), neg from the Jordan-Wigner
+// parity of the occupied sites strictly between the two hop ends.
+struct SpinTable {
+  int L = 0, N = 0, n = 0;
+  std::vector<uint32_t> conf;   // [n] ascending configs
+  std::vector<uint32_t> off;    // [n + 1] CSR offsets into hop
+  std::vector<uint32_t> hop;    // packed hop entries
+  int max_hops = 0;
+};
+bool build_spin_table(int L, int N, const std::vector<int>& bi, const std::vector<int>& bj,
+                      const std::vector<int>& btype, SpinTable& out, std::string& err);
+
+// ---- host tridiagonal eigensolver (tridiag.cpp) ------------------------------
+// Lowest eigenvalue of the symmetric tridiagonal T (diag a[0..k), offdiag b[0..k-1))
+// by Sturm-sequence bisection, and its unit eigenvector by inverse iteration.
+double tridiag_lowest(const std::vector<double>& a, const std::vector<double>& b,
+                      std::vector<double>& y);
+
+// ---- device-side structures ---------------------------------------------------
+struct SysDev {                 // one linear system / Hamiltonian instance
+  double U;
+  double Uc;
+  double d_re;                  // real diagonal offset (e.g. -(E_G + shift))
+  double d_im;                  // imaginary diagonal (e.g. -Gamma)
+  int core;                     // core-hole site or -1
+  int pad;
+  double amp[MSB_MAX_BOND_TYPES];
+};
+
+struct TablesDev {
+  const uint32_t* conf_up;
+  const uint32_t* conf_dn;
+  const uint32_t* off_up;
+  const uint32_t* off_dn;
+  const uint32_t* hop_up;
+  const uint32_t* hop_dn;
+  int n_up, n_dn;
+};
+
+// Apply kernel modes (fused reductions).
+enum ApplyMode : int {
+  kModePlain = 0,       // v = A x
+  kModeBilinear = 1,    // v = A x;  partial (sum aux*v, sum |v|^2)        -- COCG sigma
+  kModeHerm = 2,        // v = A x;  partial (sum conj(x)*v, sum |v|^2)    -- Lanczos a_k
+  kModeResid = 3        // no v;     partial (sum |aux - A x|^2)           -- true residual
+};
+
+struct ApplyArgs {
+  TablesDev T;
+  const SysDev* sys;          // [nsys]
+  const void* x;              // [nsys][D]
+  void* v;                    // [nsys][D]  (unused in kModeResid)
+  const void* aux;            // [nsys/aux_div][D] (bilinear / resid modes)
+  int aux_div;
+  const int* aux_m;           // optional: aux is a bank [nsys][aux_cap][D]; the slot of
+  const int* aux_base;        //   system s is aux_m[s*status_stride] - *aux_base
+  int aux_cap;
+  const int* status;          // optional: per-system status stride, skip if != 0
+  int status_stride;          // in ints
+  double* partials;           // [nsys][nbx][4]
+  unsigned* counter;          // per-system last-block counters (zero on entry, reset by last block)
+  double* red;                // [nsys][4] reduced sums
+  int64_t D;
+  int nbx;                    // blocks per system (rows, XCD-padded)
+  int rows_per_xcd;
+  int nsys;
+};
+
+enum class Elem { R64, C128, C64 };   // real float64, complex128, complex64 storage
+
+hipError_t launch_apply(Elem e, int mode, const ApplyArgs& a, hipStream_t st);
+int apply_nbx(int n_up, int nsys);  // grid.x (workgroups per system) for the apply kernel
+int apply_rows_per_xcd(int n_up);
+
+// ---- COCG seed step kernels (k_cocg.hip) -----------------------------------
+// Per-system state.  status codes:
+// kPaused: the bank is full after this iteration; p is still updated once.
+// kPausedHold: set by the next residual launch so that p is not updated again.
+enum : int { kActive = 0, kDone = 1, kBreakdown = 2, kMaxit = 3, kPaused = 4, kPausedHold = 5 };
+struct SysState {
+  double rho_re, rho_im;        // rho_m = r_m^T r_m
+  double ap_re, ap_im;          // alpha_{m-1}
+  double bp_re, bp_im;          // beta_{m-1}
+  double al_re, al_im;          // alpha_m (current)
+  double be_re, be_im;          // beta_m (current)
+  double rnorm;                 // |r_m|
+  double normE;                 // |E|
+  int m;                        // completed iterations
+  int status;
+  int n_active;                 // shifts still iterating
+  int breakdown_iter;
+};
+
+struct CocgArgs {
+  SysState* st;                 // [nsys]
+  const double* red1;           // [nsys][4] from the apply (sigma re, im, |v|^2)
+  double* partials;             // [nsys][nbx][4]
+  unsigned* counter;
+  double* red2;                 // [nsys][4]
+  void* bank;                   // [nsys][cap][D] residual bank
+  const void* vvec;             // [nsys][D]
+  void* pvec;                   // [nsys][D]
+  const int* base;              // device: iteration index held in bank slot 0
+  int cap;                      // bank slots per system
+  int64_t D;
+  int nbx;
+  int nsys;
+  // shift recurrences (done in the last block of the residual kernel)
+  int n_shift;
+  const double* wshift;         // [n_shift]  w - seed_shift
+  double* zeta;                 // [nsys][n_shift][2]   zeta_m
+  double* zeta_prev;            // [nsys][n_shift][2]   zeta_{m-1}
+  int* conv_iter;               // [nsys][n_shift]      -1 while active
+  double tol;
+  int maxit;
+  double* alpha_log;            // [nsys][maxit][2]
+  double* beta_log;             // [nsys][maxit][2]
+  double* rnorm_log;            // [nsys][maxit+1]
+};
+
+hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st);   // r_{m+1} = r_m - alpha v
+hipError_t launch_cocg_p(Elem e, const CocgArgs& a, hipStream_t st);   // p = r_{m+1} + beta p
+int cocg_nbx(int64_t D, int nsys);
+
+// Initialisation: bank slot 0 = p = E (converted to Elem), rho_0 = E^T E, |E|.
+struct InitArgs {
+  const double* E;              // [nsys][D] complex128
+  void* bank;                   // slot 0 of each system
+  void* pvec;
+  SysState* st;
+  double* partials;
+  unsigned* counter;
+  int cap;
+  int64_t D;
+  int nbx;
+  int nsys;
+  int n_shift;
+  double* zeta;
+  double* zeta_prev;
+  int* conv_iter;
+  double* rnorm_log;
+  int maxit;
+};
+hipError_t launch_cocg_init(Elem e, const InitArgs& a, hipStream_t st);
+
+// ---- multi-shift assembly (k_shift.hip) --------------------------------------
+struct CoefArgs {
+  const SysState* st;
+  const double* alpha_log;      // [nsys][maxit][2]
+  const double* beta_log;
+  const double* wshift;         // [n_shift]
+  const int* conv_iter;         // [nsys][n_shift]
+  const int* list;              // [nsys][n_list] shift index per sorted slot (-1 = empty)
+  const int* lend;              // [nsys][n_list] end of the shift's range within the block
+  double* coef;                 // [nsys][n_list][K][2]   Psi coefficients of r_base+l
+  double* gcoef;                // [nsys][n_list][K][2]   p coefficients (carry) or null
+  double* ab;                   // [nsys][n_list][4]: (a_re,a_im) = p_prev weight in Psi, (h_re,h_im) in p
+  int nsys, n_shift, n_list, maxit, K, base;
+};
+hipError_t launch_coef(const CoefArgs& a, double* scratch /*[nsys*n_list][K][4]*/, hipStream_t st);
+
+struct FlushArgs {
+  const void* bank;             // [nsys][cap][D]
+  int cap;
+  const double* coef;           // [nsys][n_list][K][2]
+  const double* pw;             // [nsys][n_list][2]: weight of X (p_prev) term, or null
+  const double* ow;             // [nsys][n_list][2]: weight of old output, or null (= 0)
+  int pw_stride, ow_stride;     // doubles between consecutive entries of pw / ow
+  const int* list;              // [nsys][n_list]
+  const int* tile_k;            // [nsys][n_tiles] K extent of each shift tile
+  void* out;                    // [nsys][n_shift][D]   (Psi, or P in place)
+  const void* X;                // [nsys][n_shift][D]   p_prev (or null)
+  int64_t D;
+  int n_shift, n_list, K, nsys;
+  int n_etiles, n_stiles;
+};
+// ow_mode: 0 = old output ignored, 1 = weight 1, 2 = per-shift weights from ow
+hipError_t launch_flush(Elem bank, Elem out, const FlushArgs& a, int ow_mode, hipStream_t st);
+int flush_shifts_per_tile();
+int flush_elems_per_tile();
+
+// ---- Lanczos helpers (k_lanczos.hip) -----------------------------------------
+// Generic last-block reductions and axpy-style updates used by the ground
+// state and the continued fraction.
+hipError_t launch_dot_many(const double* Q, int k, const double* w, int64_t D,
+                           double* partials, unsigned* counter, double* out, hipStream_t st);
+hipError_t launch_gemv_sub(const double* Q, int k, const double* c, double* w, int64_t D,
+                           hipStream_t st);
+hipError_t launch_gemv(const double* Q, int k, const double* c, double* out, int64_t D,
+                       hipStream_t st);
+// real FP64: w -= a q + b qprev ; partial |w|^2
+hipError_t launch_lanczos_real_update(double* w, const double* q, const double* qprev,
+                                      const double* ab /*host-visible device pair*/, int64_t D,
+                                      double* partials, unsigned* counter, double* out,
+                                      hipStream_t st);
+hipError_t launch_scale_real(const double* w, const double* s, double* q, int64_t D,
+                             hipStream_t st);
+
+// Complex block Lanczos (continued fraction): per vector j
+//   w_j -= a_j q_j + b_j qprev_j ; partial |w_j|^2
+struct BlockLanczosArgs {
+  double* w;                    // [n][D] complex128
+  const double* q;
+  const double* qprev;
+  const double* a;              // [n]  (device)
+  const double* b;              // [n]
+  const int* active;            // [n]
+  double* partials;             // [n][nbx][4]
+  unsigned* counter;
+  double* red;                  // [n][4]
+  int64_t D;
+  int nbx, n;
+};
+hipError_t launch_block_lanczos_update(const BlockLanczosArgs& a, hipStream_t st);
+int lanczos_nbx(int64_t D, int n);     // workgroups per vector of the block update
+int gram_blocks(int64_t D);            // partial rows of launch_dot_many
+// q_prev <- w / b (per vector, active only); returns via pointer rotation by the host
+hipError_t launch_block_scale(const double* w, const double* b, const int* active, double* out,
+                              int64_t D, int n, hipStream_t st);
+hipError_t launch_cf_eval(const double* a, const double* b, const int* depth, int ld, const double* norm2,
+                          int n, const double* w, int n_w, double E_G, double eta, double* I,
+                          hipStream_t st);
+
+// ---- small utility kernels ---------------------------------------------------
+hipError_t launch_number_op(const TablesDev& T, int64_t D, int site, double w_up, double w_dn,
+                            int count, int x_real, const void* x, double* y, hipStream_t st);
+hipError_t launch_combine(const TablesDev& T, int64_t D, int nsys, int n, Elem e, const void* psi,
+                          const double* coef /*[nsys][4]: phase re, im, w_up, w_dn*/,
+                          const int* site /*[nsys]*/, double* phi, hipStream_t st);
+hipError_t launch_copy_slot(Elem e, const void* src, void* dst, int64_t D, int nsys,
+                            int64_t src_stride, int64_t dst_stride, hipStream_t st);
+
+}  // namespace msb
+
+// Context (opaque in the public header).
+struct msb_ctx {
+  int L = 0, n_up = 0, n_dn = 0;
+  int64_t D = 0;
+  int n_types = 0;
+  double type_amp[MSB_MAX_BOND_TYPES] = {0};
+  double U = 0;
+  msb::SpinTable up, dn;
+  int device = 0;
+  // device tables
+  uint32_t* d_conf_up = nullptr;
+  uint32_t* d_conf_dn = nullptr;
+  uint32_t* d_off_up = nullptr;
+  uint32_t* d_off_dn = nullptr;
+  uint32_t* d_hop_up = nullptr;
+  uint32_t* d_hop_dn = nullptr;
+  // scratch for small reductions (counters must start at zero)
+  unsigned* d_counters = nullptr;     // kNumCounters
+  double* d_small = nullptr;          // small reduction outputs
+  // growable workspace
+  void* ws = nullptr;
+  size_t ws_size = 0;
+  msb::TablesDev tables() const {
+    msb::TablesDev t;
+    t.conf_up = d_conf_up; t.conf_dn = d_conf_dn;
+    t.off_up = d_off_up; t.off_dn = d_off_dn;
+    t.hop_up = d_hop_up; t.hop_dn = d_hop_dn;
+    t.n_up = up.n; t.n_dn = dn.n;
+    return t;
+  }
+};

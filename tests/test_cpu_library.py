@@ -1,0 +1,41 @@
+"""The C-ABI library builds, loads and exports every entry point of include/msb.h (no GPU)."""
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def declared_symbols():
+    text = (ROOT / "include" / "msb.h").read_text()
+    return sorted(set(re.findall(r"\b(msb_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_names():
+    from paper_2506_09551_amd import _capi
+    assert sorted(_capi.exported_symbols()) == declared_symbols()
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    from paper_2506_09551_amd import _capi
+    if not _capi.LIB_PATH.exists():
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(str(_capi.LIB_PATH))
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_create_rejects_invalid_model_without_gpu():
+    """Argument validation happens on the host before any device call."""
+    from paper_2506_09551_amd import _capi
+    if not _capi.LIB_PATH.exists():
+        pytest.skip("library not built")
+    with pytest.raises(_capi.MsbError) as e:
+        _capi.msb_create(1, 1, 1, [], 4.0)
+    assert e.value.status == _capi.MSB_EINVAL
+    with pytest.raises(_capi.MsbError):
+        _capi.msb_create(6, 7, 1, [(0, 1, 1.0)], 4.0)
+    with pytest.raises(_capi.MsbError):
+        _capi.msb_create(6, 3, 3, [(0, 6, 1.0)], 4.0)
