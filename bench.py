@@ -45,7 +45,7 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(wl, iters_gpu: int, n_iter: int = 4):
+def cpu_baseline(wl, iters_gpu: int, n_iter: int = 2):
     """Oracle recurrence (one system, all shifts) for a few iterations, extrapolated."""
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -248,6 +250,15 @@ def main():
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, last["iters"])
         log(f"cpu baseline {out['cpu_baseline']['value']:.3f} shift-solves/s")
+
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 8
+        del src, dst
 
     msb.msb_destroy(ctx)
     print(json.dumps(out), flush=True)

@@ -117,8 +117,9 @@ typedef struct {
   int bank_slots;        /* residual slots kept before a flush; 0 = min(maxit + 1, 1024) */
   int batch;             /* systems iterated together (block apply); 0 = all that fit */
   int replace_every;     /* C64 only: true-residual replacement period (default 50, 0 = off) */
-  int use_graph;         /* 1 = capture the chunk in a hipGraph (default), 0 = plain launches */
+  int use_graph;         /* 0 or 1 = capture the chunk in a hipGraph (default), -1 = plain launches */
   double mem_fraction;   /* fraction of free device memory the workspace may use (default 0.9) */
+  int assembly_engine;   /* multi-shift assembly: 0 = FP64 vector ALU (default), 1 = FP64 matrix cores */
 } msb_opts;
 
 /* ---- context -------------------------------------------------------------- */

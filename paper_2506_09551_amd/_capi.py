@@ -51,7 +51,8 @@ class msb_info(ctypes.Structure):
 
 class msb_opts(ctypes.Structure):
     _fields_ = [("chunk", c_int), ("bank_slots", c_int), ("batch", c_int),
-                ("replace_every", c_int), ("use_graph", c_int), ("mem_fraction", c_double)]
+                ("replace_every", c_int), ("use_graph", c_int), ("mem_fraction", c_double),
+                ("assembly_engine", c_int)]
 
 
 _lib = None

@@ -5,9 +5,10 @@
 // One iteration m of the seed runs as three launches on `nsys` systems:
 //   apply   : v = A_s p,  sigma = r_m^T v, |v|^2           (k_apply.hip)
 //   k_cocg_r: alpha_m = rho_m / sigma,  r_{m+1} = r_m - alpha_m v  (new bank
-//             slot), rho_{m+1} = r^T r, |r_{m+1}|; the last workgroup forms
-//             beta_m = rho_{m+1}/rho_m, advances every shift's zeta and
-//             freezes converged shifts (|r_{m+1}|/|zeta_{m+1}| <= tol |E|)
+//             slot), partial rho_{m+1} = r^T r and |r_{m+1}|^2;
+//   k_cocg_book (one workgroup per system): beta_m = rho_{m+1}/rho_m, every
+//             shift's zeta, freeze of converged shifts
+//             (|r_{m+1}|/|zeta_{m+1}| <= tol |E|) and the next status;
 //   k_cocg_p: p_{m+1} = r_{m+1} + beta_m p_m
 // The x / p vectors of the shifted systems are not touched here: the
 // residuals r_m stay in the bank and the shifted solutions are assembled
@@ -54,9 +55,14 @@ __global__ __launch_bounds__(kBlock) void k_cocg_init(InitArgs a) {
       }
     }
   }
+  block_partial<3>(part, a.partials, a.nbx, s, bx);
+}
+
+// One workgroup per system: rho_0 = E^T E, |E|, initial state and shift scalars.
+__global__ __launch_bounds__(kBlock) void k_cocg_init_fin(InitArgs a) {
+  const int s = blockIdx.x;
   __shared__ double red[4];
-  if (!publish_partials<3>(part, a.partials, a.counter, nullptr, a.nbx, s, bx, red)) return;
-  // last workgroup of system s: initial state and shift scalars
+  reduce_partials<3>(a.partials, a.nbx, s, red);
   if (threadIdx.x == 0) {
     SysState st;
     st.rho_re = red[0];
@@ -125,10 +131,15 @@ __global__ __launch_bounds__(kBlock) void k_cocg_r(CocgArgs a) {
       }
     }
   }
-  __shared__ double red2[4];
-  if (!publish_partials<3>(part, a.partials, a.counter, a.red2, a.nbx, s, bx, red2)) return;
+  block_partial<3>(part, a.partials, a.nbx, s, bx);
+}
 
-  // ---- last workgroup of system s: scalar bookkeeping ---------------------
+// One workgroup per system: rho_{m+1}, |r_{m+1}|, beta_m, every shift's zeta,
+// the freeze test and the status for the next iteration.
+__global__ __launch_bounds__(kBlock) void k_cocg_book(CocgArgs a) {
+  const int s = blockIdx.x;
+  __shared__ double red2[4];
+  reduce_partials<3>(a.partials, a.nbx, s, red2);
   SysState t = a.st[s];
   if (t.status == kPaused) {                  // p was advanced once already
     if (threadIdx.x == 0) a.st[s].status = kPausedHold;
@@ -231,6 +242,9 @@ hipError_t launch_cocg_init(Elem e, const InitArgs& a, hipStream_t st) {
   if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_init<double>, grid, dim3(kBlock), 0, st, a);
   else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_init<float>, grid, dim3(kBlock), 0, st, a);
   else return hipErrorInvalidValue;
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_cocg_init_fin, dim3(a.nsys), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 
@@ -239,6 +253,9 @@ hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st) {
   if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_r<double>, grid, dim3(kBlock), 0, st, a);
   else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_r<float>, grid, dim3(kBlock), 0, st, a);
   else return hipErrorInvalidValue;
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_cocg_book, dim3(a.nsys), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 

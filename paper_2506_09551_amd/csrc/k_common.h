@@ -70,12 +70,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Coherent (agent-scope) load used when reading partial sums written by other
-// workgroups of the same launch.
-__device__ __forceinline__ double coherent_load(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Block-wide sum of NV values into thread 0 (deterministic order).
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[kBlock / kWave]) {
@@ -98,49 +92,45 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[kBlock /
   __syncthreads();
 }
 
-// Every workgroup of system `s` (workgroups bx < nbx of that system)
-// contributes NV partial sums.  The workgroup that finishes last for that
-// system -- detected with a per-system counter -- sums the system's partials
-// in index order (the result does not depend on scheduling), writes
-// red[s][0..NV) and out_sh[0..NV) (shared memory of the calling block), resets
-// the counter and returns true.  Must be called by all threads of every
-// workgroup of the launch.
+// Cross-workgroup reductions are done in two launches: every workgroup of
+// system s writes its NV partial sums to partials[s][bx][0..NV) (block_partial),
+// and a following finalize launch with one workgroup per system sums them in
+// index order (reduce_partials), so the result does not depend on scheduling.
+// Device-scope atomics and fences are avoided on purpose: on MI355X they
+// serialise across the whole device (about 50 ns each).
 template <int NV>
-__device__ bool publish_partials(double (&v)[NV], double* partials, unsigned* counters,
-                                 double* red, int nbx, int s, int bx, double* out_sh = nullptr) {
+__device__ __forceinline__ void block_partial(double (&v)[NV], double* partials, int nbx, int s,
+                                              int bx) {
   __shared__ double sh[NV][kBlock / kWave];
-  __shared__ int s_last;
   block_sum<NV>(v, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) partials[((int64_t)s * nbx + bx) * 4 + i] = v[i];
-    __threadfence();
-    const unsigned t = atomicAdd(&counters[s], 1u);
-    s_last = (t == (unsigned)nbx - 1u) ? 1 : 0;
   }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
+}
+
+// Sum of system s's partials into out[0..NV) (shared memory, all threads see it on return).
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double* partials, int nbx, int s,
+                                                double* out) {
+  __shared__ double sh[NV][kBlock / kWave];
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   for (int j = threadIdx.x; j < nbx; j += kBlock) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += coherent_load(&partials[((int64_t)s * nbx + j) * 4 + i]);
+    for (int i = 0; i < NV; ++i) acc[i] += partials[((int64_t)s * nbx + j) * 4 + i];
   }
   block_sum<NV>(acc, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      if (red) red[s * 4 + i] = acc[i];
-      if (out_sh) out_sh[i] = acc[i];
-    }
-    __hip_atomic_store(&counters[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
+    for (int i = 0; i < NV; ++i) out[i] = acc[i];
   }
   __syncthreads();
-  return true;
 }
+
+// Generic finalize: red[s][0..4) = sum_bx partials[s][bx][0..4), one workgroup per system.
+hipError_t launch_reduce(const double* partials, int nbx, int nsys, double* red, hipStream_t st);
 
 // Number of workgroups per system for the streaming kernels: about 2048
 // workgroups in flight over the whole launch, each walking its share of the

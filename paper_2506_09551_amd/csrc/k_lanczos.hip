@@ -44,8 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce(const double* part, int 
 
 // c_i = sum_e Q[i][e] w[e], i < k, into out[4 i]; partials: [k][gram_blocks(D)]
 hipError_t launch_dot_many(const double* Q, int k, const double* w, int64_t D, double* partials,
-                           unsigned* counter, double* out, hipStream_t st) {
-  (void)counter;
+                           double* out, hipStream_t st) {
   const int nb = gram_blocks(D);
   hipLaunchKernelGGL(k_gram_partial, dim3(nb), dim3(kBlock), 0, st, Q, w, D, k, nb, partials);
   hipError_t e = hipGetLastError();
@@ -90,8 +89,7 @@ hipError_t launch_gemv(const double* Q, int k, const double* c, double* out, int
 __global__ __launch_bounds__(kBlock) void k_lanczos_real_update(double* w, const double* q,
                                                                 const double* qprev,
                                                                 const double* ab, int64_t D,
-                                                                int nbx, double* partials,
-                                                                unsigned* counter, double* out) {
+                                                                int nbx, double* partials) {
   const int bx = blockIdx.x;
   const double a = ab[0], b = ab[1];
   double part[1] = {0.0};
@@ -107,15 +105,17 @@ __global__ __launch_bounds__(kBlock) void k_lanczos_real_update(double* w, const
       }
     }
   }
-  publish_partials<1>(part, partials, counter, out, nbx, 0, bx);
+  block_partial<1>(part, partials, nbx, 0, bx);
 }
 hipError_t launch_lanczos_real_update(double* w, const double* q, const double* qprev,
                                       const double* ab, int64_t D, double* partials,
-                                      unsigned* counter, double* out, hipStream_t st) {
+                                      double* out, hipStream_t st) {
   const int nbx = stream_nbx(D, 1, kPerStepL);
   hipLaunchKernelGGL(k_lanczos_real_update, dim3(nbx), dim3(kBlock), 0, st, w, q, qprev, ab, D,
-                     nbx, partials, counter, out);
-  return hipGetLastError();
+                     nbx, partials);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return launch_reduce(partials, nbx, 1, out, st);
 }
 
 // q = w * s[0]
@@ -157,11 +157,13 @@ __global__ __launch_bounds__(kBlock) void k_block_lanczos_update(BlockLanczosArg
       }
     }
   }
-  publish_partials<1>(part, a.partials, a.counter, a.red, a.nbx, j, bx);
+  block_partial<1>(part, a.partials, a.nbx, j, bx);
 }
 hipError_t launch_block_lanczos_update(const BlockLanczosArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_block_lanczos_update, dim3(a.nbx, a.n), dim3(kBlock), 0, st, a);
-  return hipGetLastError();
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return launch_reduce(a.partials, a.nbx, a.n, a.red, st);
 }
 int lanczos_nbx(int64_t D, int n) { return stream_nbx(D, n, kPerStepL); }
 

@@ -92,4 +92,17 @@ hipError_t launch_copy_slot(Elem e, const void* src, void* dst, int64_t D, int n
   return hipGetLastError();
 }
 
+// red[s][0..4) = sum over workgroups of partials[s][bx][0..4)
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int nbx, double* red) {
+  const int s = blockIdx.x;
+  __shared__ double out[4];
+  reduce_partials<4>(partials, nbx, s, out);
+  if (threadIdx.x < 4) red[s * 4 + threadIdx.x] = out[threadIdx.x];
+}
+
+hipError_t launch_reduce(const double* partials, int nbx, int nsys, double* red, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(nsys), dim3(kBlock), 0, st, partials, nbx, red);
+  return hipGetLastError();
+}
+
 }  // namespace msb

@@ -114,24 +114,28 @@ hipError_t launch_coef(const CoefArgs& a, double* scratch, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // Flush: out[s][k][i] = ow_k * out[s][k][i] + pw_k * X[s][k][i] + sum_l C[s][j][l] r_l[i]
-// One workgroup: 4 wavefronts x TS shifts (a shift tile) times 64*EPL
-// elements; the residual tile is staged through LDS and shared by the four
-// wavefronts, the coefficients are wave-uniform (scalar loads).
-// Workgroups of one element tile are issued back to back on one XCD so the
-// residual tile is read from HBM once and from that XCD's L2 afterwards.
-constexpr int kFlushTS = 8;
-constexpr int kFlushEPL = 4;
-constexpr int kFlushKT = 8;
-int flush_shifts_per_tile() { return kFlushTS * (kBlock / kWave); }
-int flush_elems_per_tile() { return kWave * kFlushEPL; }
+// The sum is a dense complex contraction (shifts x slots) . (slots x elements),
+// evaluated with FP64 matrix-core instructions: v_mfma_f64_16x16x4f64 computes
+// D(16x16) += A(16x4) B(4x16) with A[i][k] in lane i+16k, B[k][j] in lane j+16k
+// and D[i][j] in lane j+16(i%4), register i/4.  A complex product takes four
+// real products (re*re - im*im, re*im + im*re).  A wavefront owns 16 shifts x
+// 64 elements (four 16x16 tiles); the four wavefronts of a workgroup take 64
+// consecutive shift slots over the same 64 elements, so residual loads are
+// shared through L1.  Workgroups of one element tile are issued back to back on
+// one XCD so the residual tile is read from HBM once and from L2 afterwards.
+constexpr int kFlushM = 16;       // shifts per wavefront (MFMA rows / VALU shift tile)
+constexpr int kFlushNT = 4;       // 16-element MFMA tiles per wavefront
+constexpr int kFlushWaves = kBlock / kWave;
+int flush_shifts_per_tile(int engine) { return engine == 1 ? kFlushM * kFlushWaves : 8 * kFlushWaves; }
+int flush_elems_per_tile(int engine) { return engine == 1 ? 16 * kFlushNT : kWave * 4; }
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <typename SB, typename SO>
-__global__ __launch_bounds__(kBlock) void k_flush(FlushArgs a, int ow_mode) {
-  constexpr int TS = kFlushTS, EPL = kFlushEPL, KT = kFlushKT;
-  constexpr int TILE = kWave * EPL;
+__global__ __launch_bounds__(kBlock) void k_flush_mfma(FlushArgs a, int ow_mode) {
   using AB = Access<SB, true>;
   using AO = Access<SO, true>;
-  __shared__ cv<double> rt[KT][TILE];
+  constexpr int TILE = 16 * kFlushNT;
 
   const int s = blockIdx.y;
   const int b = blockIdx.x;
@@ -141,51 +145,176 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs a, int ow_mode) {
   if (et >= a.n_etiles) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
-  const int slot0 = stt * (TS * (kBlock / kWave)) + wave * TS;
+  const int li = lane % 16, lk = lane / 16;
+  const int slot0 = stt * (kFlushM * kFlushWaves) + wave * kFlushM;
   const int Kext = a.tile_k[s * a.n_stiles + stt];
   const int64_t e0 = (int64_t)et * TILE;
   const void* bank_s = AB::offset(a.bank, (int64_t)s * a.cap * a.D);
-  const double* crow = a.coef + ((int64_t)s * a.n_list + slot0) * a.K * 2;
+  // this lane's A-operand row: shift slot0 + li
+  const double* crow = a.coef + ((int64_t)s * a.n_list + slot0 + li) * a.K * 2;
 
-  cv<double> acc[TS][EPL];
+  v4d accr[kFlushNT], acci[kFlushNT];
 #pragma unroll
-  for (int t = 0; t < TS; ++t)
+  for (int t = 0; t < kFlushNT; ++t) {
+    accr[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    acci[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  // operands of one K-step (4 residual slots); the next step's operands are
+  // loaded while the matrix instructions of the current step run
+  struct Ops {
+    double ar, ai;
+    cv<double> rv[kFlushNT];
+  };
+  // Branch-free loads (so the compiler can keep the prefetch in flight): slot
+  // and element indices are clamped into written memory; a clamped slot gets a
+  // zero coefficient, a clamped element only feeds an output that is not stored.
+  const int64_t last_e = a.D - 1;
+  auto load_ops = [&](int kb, Ops& o) {
+    const int kk = kb + lk;
+    const bool kin = kk < Kext;
+    const int kc = kin ? kk : Kext - 1;
+    const double cr = crow[2 * kc], ci = crow[2 * kc + 1];
+    o.ar = kin ? cr : 0.0;
+    o.ai = kin ? ci : 0.0;
+    const void* rs = AB::offset(bank_s, (int64_t)kc * a.D);
+#pragma unroll
+    for (int t = 0; t < kFlushNT; ++t) {
+      int64_t e = e0 + t * 16 + li;
+      e = e < last_e ? e : last_e;
+      o.rv[t] = AB::template load<double>(rs, e);
+    }
+  };
+  Ops cur, nxt;
+  load_ops(0, cur);
+  for (int kb = 0; kb < Kext; kb += 4) {
+    if (kb + 4 < Kext) load_ops(kb + 4, nxt);
+#pragma unroll
+    for (int t = 0; t < kFlushNT; ++t) {
+      accr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.ar, cur.rv[t].re, accr[t], 0, 0, 0);
+      accr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-cur.ai, cur.rv[t].im, accr[t], 0, 0, 0);
+      acci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.ar, cur.rv[t].im, acci[t], 0, 0, 0);
+      acci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.ai, cur.rv[t].re, acci[t], 0, 0, 0);
+    }
+    cur = nxt;
+  }
+
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int slot = slot0 + 4 * r + lk;            // D row i = 4r + lane/16
+    const int k = a.list[s * a.n_list + slot];
+    if (k < 0) continue;
+    cv<double> ow = {0.0, 0.0}, pw = {0.0, 0.0};
+    if (ow_mode == 1) ow = {1.0, 0.0};
+    if (ow_mode == 2) {
+      const double* o = a.ow + ((int64_t)s * a.n_list + slot) * a.ow_stride;
+      ow = {o[0], o[1]};
+    }
+    if (a.pw) {
+      const double* p = a.pw + ((int64_t)s * a.n_list + slot) * a.pw_stride;
+      pw = {p[0], p[1]};
+    }
+    const int64_t obase = ((int64_t)s * a.n_shift + k) * a.D;
+#pragma unroll
+    for (int t = 0; t < kFlushNT; ++t) {
+      const int64_t i = e0 + t * 16 + li;           // D column j = lane%16
+      if (i >= a.D) continue;
+      cv<double> v = {accr[t][r], acci[t][r]};
+      if (ow_mode != 0) v = cadd(v, cmul(ow, AO::template load<double>(a.out, obase + i)));
+      if (a.X) v = cadd(v, cmul(pw, AO::template load<double>(a.X, obase + i)));
+      AO::store(a.out, obase + i, v);
+    }
+  }
+}
+
+
+// VALU form of the same contraction (the default: on MI355X FP64 FMA issues
+// faster from the vector ALUs than from the FP64 matrix instructions).  A
+// workgroup owns 32 shift slots (8 per wavefront) x 256 elements (4 per lane).
+// Each chunk of 8 residual slots is staged in LDS.  The coefficients are
+// wave-uniform and come through the scalar cache, so they cost neither LDS
+// nor vector-memory bandwidth; the next slot's coefficients are requested
+// before the current slot's FMAs so the scalar-cache misses overlap with them.
+constexpr int kValuM = 8;         // shift slots per wavefront
+constexpr int kValuEPL = 4;       // elements per lane
+constexpr int kValuKT = 8;        // residual slots per staged chunk
+
+template <typename SB, typename SO>
+__global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double* __restrict__ coef,
+                                                       int ow_mode) {
+  using AB = Access<SB, true>;
+  using AO = Access<SO, true>;
+  constexpr int EPL = kValuEPL, KT = kValuKT, M = kValuM;
+  constexpr int TILE = kWave * EPL;                       // 256 elements
+  constexpr int NS = M * kFlushWaves;                     // 32 shift slots
+  constexpr int RPT = KT;                                 // residual slots staged per thread per chunk
+  static_assert(TILE == kBlock, "one staged element per thread");
+  __shared__ cv<double> rt[KT][TILE];
+
+  const int s = blockIdx.y;
+  const int b = blockIdx.x;
+  const int xcd = b % kNumXcd, q = b / kNumXcd;
+  const int et = xcd + kNumXcd * (q / a.n_stiles);
+  const int stt = q % a.n_stiles;
+  if (et >= a.n_etiles) return;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int lane = tid % kWave;
+  const int Kext = a.tile_k[s * a.n_stiles + stt];
+  const int64_t e0 = (int64_t)et * TILE;
+  const int64_t last_e = a.D - 1;
+  const void* bank_s = AB::offset(a.bank, (int64_t)s * a.cap * a.D);
+  const int slot0 = stt * NS + wave * M;
+  // uniform address in the constant address space: read through the scalar cache
+  typedef __attribute__((address_space(4))) const double cdouble;
+  cdouble* crow = (cdouble*)(coef + ((int64_t)s * a.n_list + slot0) * a.K * 2);
+
+  cv<double> acc[M][EPL];
+#pragma unroll
+  for (int t = 0; t < M; ++t)
 #pragma unroll
     for (int e = 0; e < EPL; ++e) acc[t][e] = {0.0, 0.0};
 
-  const int64_t my_i = e0 + threadIdx.x;
-  for (int kb = 0; kb < Kext; kb += KT) {
+  // coefficients of slot l for this wavefront's M shifts (scalar registers);
+  // the next slot's are requested before the current slot's FMAs are issued
+  auto load_c = [&](int l, cv<double> (&c)[M]) {
 #pragma unroll
-    for (int kk = 0; kk < KT; ++kk) {
-      const int l = kb + kk;
-      cv<double> v = {0.0, 0.0};
-      if (l < Kext && my_i < a.D) v = AB::template load<double>(bank_s, (int64_t)l * a.D + my_i);
-      rt[kk][threadIdx.x] = v;
+    for (int t = 0; t < M; ++t) c[t] = {crow[((int64_t)t * a.K + l) * 2], crow[((int64_t)t * a.K + l) * 2 + 1]};
+  };
+  int64_t my_e = e0 + tid;
+  my_e = my_e < last_e ? my_e : last_e;                   // clamped: feeds only unstored outputs
+  for (int kb = 0; kb < Kext; kb += KT) {
+    const int kn = min(KT, Kext - kb);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int kc = kb + (j < kn ? j : kn - 1);          // clamped: its coefficient is never used
+      rt[j][tid] = AB::template load<double>(bank_s, (int64_t)kc * a.D + my_e);
     }
     __syncthreads();
-    const int kn = min(KT, Kext - kb);
+    cv<double> c_cur[M], c_nxt[M];
+    load_c(kb, c_cur);
     for (int kk = 0; kk < kn; ++kk) {
+      if (kk + 1 < kn) load_c(kb + kk + 1, c_nxt);
       cv<double> r[EPL];
 #pragma unroll
       for (int e = 0; e < EPL; ++e) r[e] = rt[kk][lane + kWave * e];
 #pragma unroll
-      for (int t = 0; t < TS; ++t) {
-        const double cr = crow[((int64_t)t * a.K + kb + kk) * 2];
-        const double ci = crow[((int64_t)t * a.K + kb + kk) * 2 + 1];
+      for (int t = 0; t < M; ++t) {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
-          acc[t][e].re = fma(cr, r[e].re, acc[t][e].re);
-          acc[t][e].re = fma(-ci, r[e].im, acc[t][e].re);
-          acc[t][e].im = fma(cr, r[e].im, acc[t][e].im);
-          acc[t][e].im = fma(ci, r[e].re, acc[t][e].im);
+          acc[t][e].re = fma(c_cur[t].re, r[e].re, acc[t][e].re);
+          acc[t][e].re = fma(-c_cur[t].im, r[e].im, acc[t][e].re);
+          acc[t][e].im = fma(c_cur[t].re, r[e].im, acc[t][e].im);
+          acc[t][e].im = fma(c_cur[t].im, r[e].re, acc[t][e].im);
         }
       }
+#pragma unroll
+      for (int t = 0; t < M; ++t) c_cur[t] = c_nxt[t];
     }
     __syncthreads();
   }
 
 #pragma unroll
-  for (int t = 0; t < TS; ++t) {
+  for (int t = 0; t < M; ++t) {
     const int slot = slot0 + t;
     const int k = a.list[s * a.n_list + slot];
     if (k < 0) continue;
@@ -212,17 +341,23 @@ __global__ __launch_bounds__(kBlock) void k_flush(FlushArgs a, int ow_mode) {
   }
 }
 
-hipError_t launch_flush(Elem eb, Elem eo, const FlushArgs& a, int ow_mode, hipStream_t st) {
+hipError_t launch_flush(Elem eb, Elem eo, const FlushArgs& a, int ow_mode, int engine,
+                        hipStream_t st) {
   const int per_xcd = (a.n_etiles + kNumXcd - 1) / kNumXcd;
   dim3 grid(per_xcd * kNumXcd * a.n_stiles, a.nsys);
-  if (eb == Elem::C128 && eo == Elem::C128)
-    hipLaunchKernelGGL((k_flush<double, double>), grid, dim3(kBlock), 0, st, a, ow_mode);
-  else if (eb == Elem::C64 && eo == Elem::C64)
-    hipLaunchKernelGGL((k_flush<float, float>), grid, dim3(kBlock), 0, st, a, ow_mode);
-  else if (eb == Elem::C64 && eo == Elem::C128)
-    hipLaunchKernelGGL((k_flush<float, double>), grid, dim3(kBlock), 0, st, a, ow_mode);
-  else
+#define MSB_FLUSH(SB, SO)                                                                      \
+  if (engine == 1) hipLaunchKernelGGL((k_flush_mfma<SB, SO>), grid, dim3(kBlock), 0, st, a, ow_mode); \
+  else hipLaunchKernelGGL((k_flush_valu<SB, SO>), grid, dim3(kBlock), 0, st, a, a.coef, ow_mode);
+  if (eb == Elem::C128 && eo == Elem::C128) {
+    MSB_FLUSH(double, double)
+  } else if (eb == Elem::C64 && eo == Elem::C64) {
+    MSB_FLUSH(float, float)
+  } else if (eb == Elem::C64 && eo == Elem::C128) {
+    MSB_FLUSH(float, double)
+  } else {
     return hipErrorInvalidValue;
+  }
+#undef MSB_FLUSH
   return hipGetLastError();
 }
 

@@ -176,8 +176,16 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   if (e == hipSuccess) e = upload(&c->d_off_dn, c->dn.off);
   if (e == hipSuccess) e = upload(&c->d_hop_up, c->up.hop);
   if (e == hipSuccess) e = upload(&c->d_hop_dn, c->dn.hop);
-  if (e == hipSuccess) e = hipMalloc(&c->d_counters, kNumCounters * sizeof(unsigned));
-  if (e == hipSuccess) e = hipMemset(c->d_counters, 0, kNumCounters * sizeof(unsigned));
+  if (e == hipSuccess) {
+    // padded, transposed copy of the down-spin hop lists: ell[k][d]
+    const int K = std::max(c->dn.max_hops, 1);
+    std::vector<uint32_t> ell((size_t)K * c->dn.n, kNoHop);
+    for (int d = 0; d < c->dn.n; ++d)
+      for (uint32_t k = c->dn.off[d]; k < c->dn.off[d + 1]; ++k)
+        ell[(size_t)(k - c->dn.off[d]) * c->dn.n + d] = c->dn.hop[k];
+    e = upload(&c->d_ell_dn, ell);
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc(&c->d_small, 4096 * sizeof(double));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -196,7 +204,8 @@ extern "C" void msb_destroy(msb_ctx* c) {
   (void)hipFree(c->d_off_dn);
   (void)hipFree(c->d_hop_up);
   (void)hipFree(c->d_hop_dn);
-  (void)hipFree(c->d_counters);
+  (void)hipFree(c->d_ell_dn);
+  if (c->solve_stream) (void)hipStreamDestroy(c->solve_stream);
   (void)hipFree(c->d_small);
   if (c->ws) (void)hipFree(c->ws);
   delete c;
@@ -322,12 +331,11 @@ extern "C" msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, cons
   double* partials = ar.take<double>(part_doubles * sizeof(double));
   double* red = ar.take<double>((size_t)(kmax + 2) * 4 * sizeof(double));
   double* coef = ar.take<double>((size_t)(kmax + 2) * sizeof(double));
-  unsigned* cnt = ctx->d_counters;
   if (ar.overflow()) return fail(MSB_EINVAL, "internal: ground-state workspace layout");
   MSB_HIP(hipMemcpyAsync(dsys, &hs, sizeof(SysDev), hipMemcpyHostToDevice, st));
 
   auto dot = [&](const double* a, const double* b, double& outv) -> msb_status {
-    MSB_HIP(launch_dot_many(a, 1, b, D, partials, cnt, red, st));
+    MSB_HIP(launch_dot_many(a, 1, b, D, partials, red, st));
     MSB_HIP(hipMemcpyAsync(&outv, red, sizeof(double), hipMemcpyDeviceToHost, st));
     MSB_HIP(hipStreamSynchronize(st));
     return MSB_OK;
@@ -354,7 +362,6 @@ extern "C" msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, cons
     double* qk = Q + (size_t)k * D;
     ApplyArgs aa = apply_args(ctx, dsys, 1, qk, w);
     aa.partials = partials;
-    aa.counter = cnt;
     aa.red = red;
     MSB_HIP(launch_apply(Elem::R64, kModeHerm, aa, st));
     double red_h[4];
@@ -366,9 +373,9 @@ extern "C" msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, cons
     double ab[2] = {ak, bk};
     MSB_HIP(hipMemcpyAsync(coef, ab, 2 * sizeof(double), hipMemcpyHostToDevice, st));
     MSB_HIP(launch_lanczos_real_update(w, qk, k > 0 ? Q + (size_t)(k - 1) * D : nullptr, coef, D,
-                                       partials, cnt, red, st));
+                                       partials, red, st));
     for (int pass = 0; pass < 2; ++pass) {
-      MSB_HIP(launch_dot_many(Q, k + 1, w, D, partials, cnt, red, st));
+      MSB_HIP(launch_dot_many(Q, k + 1, w, D, partials, red, st));
       MSB_HIP(launch_gemv_sub(Q, k + 1, red, w, D, st));
     }
     double bb = 0;
@@ -473,7 +480,7 @@ struct SolveBufs {
     alog = c.take<double>((size_t)B * maxit * 2 * sizeof(double));
     blog = c.take<double>((size_t)B * maxit * 2 * sizeof(double));
     rlog = c.take<double>((size_t)B * (maxit + 1) * sizeof(double));
-    const int n_stiles = n_list / flush_shifts_per_tile();
+    const int n_stiles = n_list / flush_shifts_per_tile(0) + 1;   // bound for either engine
     dlist = c.take<int>((size_t)B * n_list * sizeof(int));
     dlend = c.take<int>((size_t)B * n_list * sizeof(int));
     dtile = c.take<int>((size_t)B * (n_stiles + 1) * sizeof(int));
@@ -514,7 +521,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   const Elem eo = ev;
   const int64_t D = ctx->D;
   const int mx = std::max(maxit, 1);
-  const int tile_s = flush_shifts_per_tile();
+  const int engine = (opts && opts->assembly_engine == 1) ? 1 : 0;
+  const int tile_s = flush_shifts_per_tile(engine);
   const int n_list = ((n_shift + tile_s - 1) / tile_s) * tile_s;
   const size_t s_el = elem_bytes(ev), s_out = elem_bytes(eo);
   const bool want_true = info && info->resid_true;
@@ -570,9 +578,12 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   }
   if (planB == 0) return fail(MSB_ENOMEM, "msb_solve: workspace does not fit in device memory");
 
+  // inputs are complete on the caller's stream; the solve runs on the
+  // context's own stream (needed for graph capture) and is finished on return
   hipStream_t ust = (hipStream_t)stream;
   MSB_HIP(hipStreamSynchronize(ust));
-  hipStream_t st = ust;
+  hipStream_t st = ctx->solve_stream;
+  const bool use_graph = !(opts && opts->use_graph < 0);
 
   const int B = planB, cap = plancap;
   const int n_stiles = n_list / tile_s;
@@ -609,7 +620,6 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   double* gcoef = bf.gcoef;
   double* cscr = bf.cscr;
   double* ab = bf.ab;
-  unsigned* cnt = ctx->d_counters;
 
   std::vector<double> hw(n_shift);
   for (int k = 0; k < n_shift; ++k) hw[k] = w_in[k] - seed_shift;
@@ -647,7 +657,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
 
     MSB_HIP(hipEventRecord(ev0, st));
     InitArgs ia;
-    ia.E = Eb; ia.bank = bank; ia.pvec = pvec; ia.st = dst; ia.partials = partials; ia.counter = cnt;
+    ia.E = Eb; ia.bank = bank; ia.pvec = pvec; ia.st = dst; ia.partials = partials;
     ia.cap = cap; ia.D = D; ia.nbx = cocg_nbx(D, nb); ia.nsys = nb; ia.n_shift = n_shift; ia.zeta = zeta;
     ia.zeta_prev = zeta_prev; ia.conv_iter = conv; ia.rnorm_log = rlog; ia.maxit = mx;
     MSB_HIP(launch_cocg_init(ev, ia, st));
@@ -655,7 +665,6 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ApplyArgs aa = apply_args(ctx, dsys, nb, pvec, vvec);
     aa.aux = bank;
     aa.partials = partials;
-    aa.counter = cnt;
     aa.red = red1;
     aa.status = &dst[0].status;
     aa.status_stride = (int)(sizeof(SysState) / sizeof(int));
@@ -664,7 +673,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     aa.aux_cap = cap;
 
     CocgArgs ca;
-    ca.st = dst; ca.red1 = red1; ca.partials = partials; ca.counter = cnt; ca.red2 = red2;
+    ca.st = dst; ca.red1 = red1; ca.partials = partials; ca.red2 = red2;
     ca.bank = bank; ca.vvec = vvec; ca.pvec = pvec; ca.base = dbase; ca.cap = cap; ca.D = D;
     ca.nbx = cocg_nbx(D, nb); ca.nsys = nb; ca.n_shift = n_shift; ca.wshift = wshift; ca.zeta = zeta;
     ca.zeta_prev = zeta_prev; ca.conv_iter = conv; ca.tol = tol; ca.maxit = mx;
@@ -715,14 +724,14 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       fa.bank = bank; fa.cap = cap; fa.coef = coef; fa.pw = nullptr; fa.ow = nullptr;
       fa.pw_stride = 4; fa.ow_stride = 4; fa.list = dlist; fa.tile_k = dtile; fa.out = psib;
       fa.X = nullptr; fa.D = D; fa.n_shift = n_shift; fa.n_list = n_list; fa.K = Kc; fa.nsys = nb;
-      fa.n_etiles = (int)((D + flush_elems_per_tile() - 1) / flush_elems_per_tile());
+      fa.n_etiles = (int)((D + flush_elems_per_tile(engine) - 1) / flush_elems_per_tile(engine));
       fa.n_stiles = n_stiles;
       if (!first_flush && Pc) {
         fa.pw = ab;          // Psi += (bw_base S_base) p_{base-1}
         fa.X = Pc;
       }
       MSB_HIP(hipEventRecord(eg0, st));
-      MSB_HIP(launch_flush(ev, eo, fa, first_flush ? 0 : 1, st));
+      MSB_HIP(launch_flush(ev, eo, fa, first_flush ? 0 : 1, engine, st));
       MSB_HIP(hipEventRecord(eg1, st));
       ++n_gemm;
       // algorithmic work: every (system, shift) range reads its residual slots
@@ -739,7 +748,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
         fp.pw = nullptr;
         fp.X = nullptr;
         fp.ow = ab + 2;      // p_{end-1} = (bw_base G_base) p_{base-1} + ...
-        MSB_HIP(launch_flush(ev, eo, fp, first_flush ? 0 : 2, st));
+        MSB_HIP(launch_flush(ev, eo, fp, first_flush ? 0 : 2, engine, st));
       }
       MSB_HIP(hipEventRecord(ev1, st));
       msb_status r = elapsed(t_flush);
@@ -754,13 +763,48 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       return MSB_OK;
     };
 
+    // one chunk of seed iterations; kernels skip systems that are not active.
+    // The chunk is captured once per batch into a hipGraph and replayed.
+    hipGraphExec_t gexec = nullptr;
+    auto enqueue_chunk = [&]() -> hipError_t {
+      for (int c = 0; c < chunk; ++c) {
+        hipError_t e = launch_apply(ev, kModeBilinear, aa, st);
+        if (e == hipSuccess) e = launch_cocg_r(ev, ca, st);
+        if (e == hipSuccess) e = launch_cocg_p(ev, ca, st);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    auto run_chunk = [&]() -> msb_status {
+      if (!use_graph) {
+        MSB_HIP(enqueue_chunk());
+        return MSB_OK;
+      }
+      if (!gexec) {
+        MSB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const hipError_t e_launch = enqueue_chunk();
+        hipGraph_t g = nullptr;
+        const hipError_t e_end = hipStreamEndCapture(st, &g);
+        hipError_t e_inst = hipSuccess;
+        if (e_launch == hipSuccess && e_end == hipSuccess) e_inst = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        MSB_HIP(e_launch);
+        MSB_HIP(e_end);
+        MSB_HIP(e_inst);
+      }
+      MSB_HIP(hipGraphLaunch(gexec, st));
+      return MSB_OK;
+    };
+    struct GraphGuard {
+      hipGraphExec_t* g;
+      ~GraphGuard() { if (*g) (void)hipGraphExecDestroy(*g); }
+    } graph_guard{&gexec};
+
     int it_done = 0;
     while (true) {
-      // one chunk of seed iterations; kernels skip systems that are not active
-      for (int c = 0; c < chunk; ++c) {
-        MSB_HIP(launch_apply(ev, kModeBilinear, aa, st));
-        MSB_HIP(launch_cocg_r(ev, ca, st));
-        MSB_HIP(launch_cocg_p(ev, ca, st));
+      {
+        msb_status r = run_chunk();
+        if (r != MSB_OK) return r;
       }
       it_done += chunk;
       MSB_HIP(hipMemcpyAsync(hst.data(), dst, nb * sizeof(SysState), hipMemcpyDeviceToHost, st));
@@ -857,7 +901,6 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       ta.aux = Eb;
       ta.aux_div = n_shift;
       ta.partials = bf.tpart;
-      ta.counter = cnt;
       ta.red = bf.tred;
       MSB_HIP(launch_apply(ev == Elem::C128 ? Elem::C128 : Elem::C64, kModeResid, ta, st));
       MSB_HIP(hipEventRecord(ev1, st));
@@ -985,7 +1028,6 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
   double* dw = ar.take<double>((size_t)n_w * sizeof(double));
   double* dI = ar.take<double>((size_t)n * n_w * sizeof(double));
   if (ar.overflow()) return fail(MSB_EINVAL, "internal: spectrum workspace layout");
-  unsigned* cnt = ctx->d_counters;
 
   MSB_HIP(hipMemcpyAsync(dsys, hsys.data(), n * sizeof(SysDev), hipMemcpyHostToDevice, st));
   MSB_HIP(hipMemcpyAsync(dw, w, n_w * sizeof(double), hipMemcpyHostToDevice, st));
@@ -998,7 +1040,7 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
   MSB_HIP(hipMemcpyAsync(bufW, phi, (size_t)n * D * 16, hipMemcpyDeviceToDevice, st));
   BlockLanczosArgs bl;
   bl.w = bufW; bl.q = bufW; bl.qprev = bufW; bl.a = reda; bl.b = dzero; bl.active = dactive;
-  bl.partials = partials; bl.counter = cnt; bl.red = redb; bl.D = D; bl.nbx = nbx_l; bl.n = n;
+  bl.partials = partials; bl.red = redb; bl.D = D; bl.nbx = nbx_l; bl.n = n;
   MSB_HIP(hipMemsetAsync(reda, 0, (size_t)n * 4 * sizeof(double), st));
   MSB_HIP(launch_block_lanczos_update(bl, st));
   std::vector<double> hred((size_t)n * 4), norm2(n), bcur(n, 0.0);
@@ -1042,7 +1084,6 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
     if (!any) break;
     ApplyArgs aa = apply_args(ctx, dsys, n, q, wv);
     aa.partials = partials;
-    aa.counter = cnt;
     aa.red = reda;
     aa.status = dactive;
     aa.status_stride = 1;

@@ -19,7 +19,6 @@ namespace msb {
 constexpr int kBlock = 256;            // threads per block of the streaming kernels
 constexpr int kWave = 64;              // CDNA wavefront
 constexpr int kNumXcd = 8;             // MI355X: 8 XCDs, workgroups dispatched round-robin
-constexpr int kNumCounters = 65536;    // per-system last-block counters (grid.y <= 65535)
 
 // ---- error handling ---------------------------------------------------------
 void set_error(const std::string& msg);
@@ -69,8 +68,10 @@ struct TablesDev {
   const uint32_t* off_dn;
   const uint32_t* hop_up;
   const uint32_t* hop_dn;
-  int n_up, n_dn;
+  const uint32_t* ell_dn;     // [k_dn][n_dn] padded transposed hop list, kNoHop = empty
+  int n_up, n_dn, k_dn;
 };
+constexpr uint32_t kNoHop = 0xFFFFFFFFu;
 
 // Apply kernel modes (fused reductions).
 enum ApplyMode : int {
@@ -93,12 +94,12 @@ struct ApplyArgs {
   const int* status;          // optional: per-system status stride, skip if != 0
   int status_stride;          // in ints
   double* partials;           // [nsys][nbx][4]
-  unsigned* counter;          // per-system last-block counters (zero on entry, reset by last block)
   double* red;                // [nsys][4] reduced sums
   int64_t D;
-  int nbx;                    // blocks per system (rows, XCD-padded)
+  int nbx;                    // workgroups along the rows (XCD-padded row count)
   int rows_per_xcd;
   int nsys;
+  int nvec;                   // vectors (systems) per workgroup
 };
 
 enum class Elem { R64, C128, C64 };   // real float64, complex128, complex64 storage
@@ -130,7 +131,6 @@ struct CocgArgs {
   SysState* st;                 // [nsys]
   const double* red1;           // [nsys][4] from the apply (sigma re, im, |v|^2)
   double* partials;             // [nsys][nbx][4]
-  unsigned* counter;
   double* red2;                 // [nsys][4]
   void* bank;                   // [nsys][cap][D] residual bank
   const void* vvec;             // [nsys][D]
@@ -164,7 +164,6 @@ struct InitArgs {
   void* pvec;
   SysState* st;
   double* partials;
-  unsigned* counter;
   int cap;
   int64_t D;
   int nbx;
@@ -210,15 +209,17 @@ struct FlushArgs {
   int n_etiles, n_stiles;
 };
 // ow_mode: 0 = old output ignored, 1 = weight 1, 2 = per-shift weights from ow
-hipError_t launch_flush(Elem bank, Elem out, const FlushArgs& a, int ow_mode, hipStream_t st);
-int flush_shifts_per_tile();
-int flush_elems_per_tile();
+// engine: 0 = FP64 vector-ALU kernel, 1 = FP64 matrix-core kernel
+hipError_t launch_flush(Elem bank, Elem out, const FlushArgs& a, int ow_mode, int engine,
+                        hipStream_t st);
+int flush_shifts_per_tile(int engine);
+int flush_elems_per_tile(int engine);
 
 // ---- Lanczos helpers (k_lanczos.hip) -----------------------------------------
 // Generic last-block reductions and axpy-style updates used by the ground
 // state and the continued fraction.
 hipError_t launch_dot_many(const double* Q, int k, const double* w, int64_t D,
-                           double* partials, unsigned* counter, double* out, hipStream_t st);
+                           double* partials, double* out, hipStream_t st);
 hipError_t launch_gemv_sub(const double* Q, int k, const double* c, double* w, int64_t D,
                            hipStream_t st);
 hipError_t launch_gemv(const double* Q, int k, const double* c, double* out, int64_t D,
@@ -226,7 +227,7 @@ hipError_t launch_gemv(const double* Q, int k, const double* c, double* out, int
 // real FP64: w -= a q + b qprev ; partial |w|^2
 hipError_t launch_lanczos_real_update(double* w, const double* q, const double* qprev,
                                       const double* ab /*host-visible device pair*/, int64_t D,
-                                      double* partials, unsigned* counter, double* out,
+                                      double* partials, double* out,
                                       hipStream_t st);
 hipError_t launch_scale_real(const double* w, const double* s, double* q, int64_t D,
                              hipStream_t st);
@@ -241,7 +242,6 @@ struct BlockLanczosArgs {
   const double* b;              // [n]
   const int* active;            // [n]
   double* partials;             // [n][nbx][4]
-  unsigned* counter;
   double* red;                  // [n][4]
   int64_t D;
   int nbx, n;
@@ -283,8 +283,9 @@ struct msb_ctx {
   uint32_t* d_off_dn = nullptr;
   uint32_t* d_hop_up = nullptr;
   uint32_t* d_hop_dn = nullptr;
-  // scratch for small reductions (counters must start at zero)
-  unsigned* d_counters = nullptr;     // kNumCounters
+  uint32_t* d_ell_dn = nullptr;
+  // private stream for the captured seed iterations (default priority)
+  hipStream_t solve_stream = nullptr;
   double* d_small = nullptr;          // small reduction outputs
   // growable workspace
   void* ws = nullptr;
@@ -294,7 +295,8 @@ struct msb_ctx {
     t.conf_up = d_conf_up; t.conf_dn = d_conf_dn;
     t.off_up = d_off_up; t.off_dn = d_off_dn;
     t.hop_up = d_hop_up; t.hop_dn = d_hop_dn;
-    t.n_up = up.n; t.n_dn = dn.n;
+    t.ell_dn = d_ell_dn;
+    t.n_up = up.n; t.n_dn = dn.n; t.k_dn = dn.max_hops;
     return t;
   }
 };

@@ -178,3 +178,22 @@ def test_other_models(gpu, name):
         assert err <= 1e-9, f"{name}: {err:.3e}"
     finally:
         msb.msb_destroy(ctx)
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_assembly_engines_match_direct_solve(tiny, engine):
+    """Vector-ALU and matrix-core forms of the multi-shift assembly, with and without carry."""
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E = W.random_complex(D, 41)
+    E_G = -2.6661474201323485
+    sysd = [msb.make_system(core_site=j, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma) for j in (0, 2)]
+    w = np.linspace(-9.0, 9.0, 70)                 # more than one 64-shift tile, ragged
+    refs = [osolve.direct_solve(oracle_H(m, core_site=s.core_site, Uc=wl.Uc), E, E_G, wl.Gamma, w,
+                                method="eig") for s in sysd]
+    for slots in (0, 41):
+        st, info, psi = _run(msb, ctx, sysd, np.stack([E, E]), w, 1e-12, 3000, msb.MSB_C128,
+                             opts={"assembly_engine": engine, "bank_slots": slots})
+        for j in range(2):
+            err = _rel(psi[j], refs[j])
+            assert err <= 1e-9, f"engine {engine} slots {slots} system {j}: {err:.3e}"
