@@ -79,6 +79,70 @@ def cpu_baseline(wl, iters_gpu: int, n_iter: int = 2):
     }
 
 
+def precision_extras(msb, ctx, wl, systems, E, E_G, box, info64, ms64, tol, n_sub=16):
+    """complex64 form against complex128: final FP64 true residual per shift,
+    the speedup of the whole solve, and the continued-fraction spectrum error
+    on `n_sub` incident energies spread over the shift list."""
+    import numpy as np
+    import torch
+
+    psi64 = box.pop()
+    dev = psi64.device
+    D = msb.msb_dim(ctx)
+    n_shift = len(wl.w_in)
+    sub = np.unique(np.linspace(0, n_shift - 1, n_sub).round().astype(int))
+    rt = info64["resid_true"]
+    res = {
+        "c64_true_residual": {"max": float(rt.max()), "median": float(np.median(rt)),
+                              "min": float(rt.min())},
+        "c64_replacements": int(info64["replacements"]),
+        "c64_iters": int(info64["iters"]),
+        "c64_ms": round(ms64, 3),
+    }
+
+    def spectrum(psi_all):
+        ps = psi_all[:, torch.as_tensor(sub, device=dev)].contiguous()
+        phi = torch.empty(len(sub), D, dtype=torch.complex128, device=dev)
+        msb.msb_combine(ctx, ps, wl.nrhs, len(sub), msb.MSB_C64 if ps.dtype == torch.complex64
+                        else msb.MSB_C128, wl.phases, phi)
+        I, _ = msb.msb_spectrum(ctx, msb.make_system(E_G=E_G), phi, wl.w_loss, wl.eta, 1500, 1e-12)
+        return np.asarray(I)
+
+    I64 = spectrum(psi64)
+    del psi64
+    torch.cuda.empty_cache()
+    psi128 = torch.empty(wl.nrhs, n_shift, D, dtype=torch.complex128, device=dev)
+    torch.cuda.synchronize()
+    msb.msb_solve(ctx, systems, E, wl.w_in, wl.seed_shift, tol, wl.maxit, msb.MSB_C128, psi128,
+                  want_true=True)   # warm-up: sizes the workspace the timed call reuses
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info128 = msb.msb_solve(ctx, systems, E, wl.w_in, wl.seed_shift, tol, wl.maxit, msb.MSB_C128,
+                               psi128, want_true=True)
+    torch.cuda.synchronize()
+    ms128 = (time.perf_counter() - t0) * 1e3
+    I128 = spectrum(psi128)
+    del psi128
+    torch.cuda.empty_cache()
+    peak = np.max(np.abs(I128), axis=1)
+    err = np.max(np.abs(I64 - I128), axis=1) / peak
+    res.update({
+        "c128_ms": round(ms128, 3),
+        "c128_iters": int(info128["iters"]),
+        "c128_split_ms": {"seed": round(info128["t_iter_ms"], 2), "assembly": round(info128["t_flush_ms"], 2),
+                          "true_residual": round(info128["t_true_ms"], 2), "flushes": int(info128["flushes"])},
+        "c64_split_ms": {"seed": round(info64["t_iter_ms"], 2), "assembly": round(info64["t_flush_ms"], 2),
+                         "true_residual": round(info64["t_true_ms"], 2), "flushes": int(info64["flushes"])},
+        "c128_true_residual_max": float(np.max(info128["resid_true"])),
+        "speedup_c64_vs_c128": round(ms128 / ms64, 3),
+        "spectrum_rel_err_vs_c128": {"max": float(err.max()), "median": float(np.median(err)),
+                                     "shifts": [float(wl.w_in[k]) for k in sub],
+                                     "norm": "max_w |I64 - I128| / max_w I128 per w_in"},
+    })
+    log(f"precision {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,7 +269,11 @@ def main():
         "ground_state": {"E_G": E_G, "lanczos_steps": gs_iters, "ms": round(gs_ms, 2)},
     }
 
-    if not args.no_extras:
+    if not args.no_extras and prec == msb.MSB_C64:
+        box = [psi]       # hand the only reference over so the c64 result can be freed
+        del psi
+        out["precision"] = precision_extras(msb, ctx, wl, systems, E, E_G, box, last, ms_per_step, args.tol)
+    elif not args.no_extras:
         # H-apply bandwidth: algorithmic bytes 2 D s per vector
         happly = {}
         x = torch.randn(D, dtype=cdt, device=dev)
@@ -246,7 +314,7 @@ def main():
         log(f"spectrum {out['spectrum']}")
         del phi
 
-    if not args.no_cpu:
+    if not args.no_cpu and prec == msb.MSB_C128:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, last["iters"])
         log(f"cpu baseline {out['cpu_baseline']['value']:.3f} shift-solves/s")

@@ -109,6 +109,7 @@ typedef struct {
   int n_gemm;            /* number of dense assembly launches */
   double gemm_flops;     /* algorithmic flops of those launches: 8 D sum(range lengths) */
   double gemm_bytes;     /* algorithmic bytes: residual slots read + outputs written (+read) */
+  int replacements;      /* residual replacements performed (MSB_C64 only) */
 } msb_info;
 
 /* Tuning knobs of msb_solve; pass NULL for defaults. */
@@ -116,7 +117,11 @@ typedef struct {
   int chunk;             /* seed iterations per captured graph launch (default 16) */
   int bank_slots;        /* residual slots kept before a flush; 0 = min(maxit + 1, 1024) */
   int batch;             /* systems iterated together (block apply); 0 = all that fit */
-  int replace_every;     /* C64 only: true-residual replacement period (default 50, 0 = off) */
+  int replace_every;     /* MSB_C64 only: the seed residual is replaced by E - A_s x_m (x_m and the
+                            product in complex128) at the first chunk boundary at least
+                            `replace_every` iterations after the previous replacement (a bank
+                            restart moves the boundaries); 0 = default 50, < 0 = off.  When it is
+                            on and `chunk` is 0, the chunk is min(replace_every, 64). */
   int use_graph;         /* 0 or 1 = capture the chunk in a hipGraph (default), -1 = plain launches */
   double mem_fraction;   /* fraction of free device memory the workspace may use (default 0.9) */
   int assembly_engine;   /* multi-shift assembly: 0 = FP64 vector ALU (default), 1 = FP64 matrix cores */

@@ -46,7 +46,7 @@ class msb_info(ctypes.Structure):
                 ("resid_rec", POINTER(c_double)), ("resid_true", POINTER(c_double)),
                 ("t_iter_ms", c_double), ("t_flush_ms", c_double), ("t_true_ms", c_double),
                 ("t_gemm_ms", c_double), ("n_gemm", c_int), ("gemm_flops", c_double),
-                ("gemm_bytes", c_double)]
+                ("gemm_bytes", c_double), ("replacements", c_int)]
 
 
 class msb_opts(ctypes.Structure):
@@ -277,7 +277,7 @@ def msb_solve(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit: int, 
                        if want_true else None),
         "t_iter_ms": info.t_iter_ms, "t_flush_ms": info.t_flush_ms, "t_true_ms": info.t_true_ms,
         "t_gemm_ms": info.t_gemm_ms, "n_gemm": info.n_gemm, "gemm_flops": info.gemm_flops,
-        "gemm_bytes": info.gemm_bytes,
+        "gemm_bytes": info.gemm_bytes, "replacements": info.replacements,
     }
     if raise_on_fail and st != MSB_OK:
         raise MsbError(st, lib().msb_last_error().decode())

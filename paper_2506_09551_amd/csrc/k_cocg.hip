@@ -2,14 +2,14 @@
 // Algorithm 1, in the reading: bilinear products r^T r (Appendix A,
 // r~ = r*), zeta recurrence with (1 - alpha_m w) and beta_{m-1}).
 //
-// One iteration m of the seed runs as three launches on `nsys` systems:
+// One iteration m of the seed runs as these launches on `nsys` systems:
+//   k_cocg_p: p_m = r_m + beta_{m-1} p_{m-1}  (beta_{-1} = 0 gives p_0 = r_0)
 //   apply   : v = A_s p,  sigma = r_m^T v, |v|^2           (k_apply.hip)
 //   k_cocg_r: alpha_m = rho_m / sigma,  r_{m+1} = r_m - alpha_m v  (new bank
 //             slot), partial rho_{m+1} = r^T r and |r_{m+1}|^2;
 //   k_cocg_book (one workgroup per system): beta_m = rho_{m+1}/rho_m, every
 //             shift's zeta, freeze of converged shifts
-//             (|r_{m+1}|/|zeta_{m+1}| <= tol |E|) and the next status;
-//   k_cocg_p: p_{m+1} = r_{m+1} + beta_m p_m
+//             (|r_{m+1}|/|zeta_{m+1}| <= tol |E|) and the next status.
 // The x / p vectors of the shifted systems are not touched here: the
 // residuals r_m stay in the bank and the shifted solutions are assembled
 // from them in k_shift.hip.
@@ -49,6 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_init(InitArgs a) {
         const cv<double> xs = {(double)(S)x.re, (double)(S)x.im};
         Ax::store(r0, i, xs);
         Ax::store(p, i, xs);
+        if (a.xseed) A64::store(a.xseed, (int64_t)s * a.D + i, cv<double>{0.0, 0.0});
         part[0] += xs.re * xs.re - xs.im * xs.im;
         part[1] += 2.0 * xs.re * xs.im;
         part[2] += xs.re * xs.re + xs.im * xs.im;
@@ -118,6 +119,13 @@ __global__ __launch_bounds__(kBlock) void k_cocg_r(CocgArgs a) {
           if (i < a.D) {
             const cv<double> ri = Ax::template load<double>(r, i);
             const cv<double> vi = Ax::template load<double>(v, i);
+            if (a.xseed) {          // seed solution for residual replacement: x += alpha p
+              using A64 = Access<double, true>;
+              const cv<double> pi = Ax::template load<double>(Ax::offset((const void*)a.pvec, (int64_t)s * a.D), i);
+              cv<double> xs = A64::template load<double>(a.xseed, (int64_t)s * a.D + i);
+              xs = cadd(xs, cmul(alpha, pi));
+              A64::store(a.xseed, (int64_t)s * a.D + i, xs);
+            }
             cv<double> x = {ri.re - (alpha.re * vi.re - alpha.im * vi.im),
                             ri.im - (alpha.re * vi.im + alpha.im * vi.re)};
             x.re = (double)(S)x.re;
@@ -141,10 +149,6 @@ __global__ __launch_bounds__(kBlock) void k_cocg_book(CocgArgs a) {
   __shared__ double red2[4];
   reduce_partials<3>(a.partials, a.nbx, s, red2);
   SysState t = a.st[s];
-  if (t.status == kPaused) {                  // p was advanced once already
-    if (threadIdx.x == 0) a.st[s].status = kPausedHold;
-    return;
-  }
   if (t.status != kActive) return;
   cv<double> alpha;
   if (sigma_breakdown(t, a.red1, s, alpha)) {
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_book(CocgArgs a) {
     } else if (t.m >= a.maxit) {
       t.status = kMaxit;
     } else if (t.m + 1 - base >= a.cap) {
-      t.status = kPaused;               // no bank slot for r_{m+2}: host flushes
+      t.status = kPaused;               // no bank slot for r_{m+1} of the next iteration
     }
     a.st[s] = t;
   }
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
   using Ax = Access<S, true>;
   const int s = blockIdx.y, bx = blockIdx.x;
   const SysState st = a.st[s];
-  if (st.status != kActive && st.status != kPaused) return;
+  if (st.status != kActive) return;
   const int slot = st.m - *a.base;
   const void* r = Ax::offset((const void*)a.bank, ((int64_t)s * a.cap + slot) * a.D);
   void* p = Ax::offset(a.pvec, (int64_t)s * a.D);
@@ -235,6 +239,65 @@ __global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
       }
     }
   }
+}
+
+
+// r_m <- E - w for active systems (w = A_s x_m in complex128); partial rho, |r|^2
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_cocg_replace(CocgArgs a, const double* E, const double* w) {
+  using Ax = Access<S, true>;
+  using A64 = Access<double, true>;
+  const int s = blockIdx.y, bx = blockIdx.x;
+  double part[3] = {0.0, 0.0, 0.0};
+  const SysState st = a.st[s];
+  if (st.status == kActive) {
+    void* r = Ax::offset(a.bank, ((int64_t)s * a.cap + (st.m - *a.base)) * a.D);
+    for (int64_t base = (int64_t)bx * kPerStep; base < a.D; base += (int64_t)a.nbx * kPerStep) {
+#pragma unroll
+      for (int e = 0; e < kEptStream; ++e) {
+        const int64_t i = base + e * kBlock + threadIdx.x;
+        if (i < a.D) {
+          const cv<double> ei = A64::template load<double>(E, (int64_t)s * a.D + i);
+          const cv<double> wi = A64::template load<double>(w, (int64_t)s * a.D + i);
+          cv<double> x = csub(ei, wi);
+          x.re = (double)(S)x.re;
+          x.im = (double)(S)x.im;
+          Ax::store(r, i, x);
+          part[0] += x.re * x.re - x.im * x.im;
+          part[1] += 2.0 * x.re * x.im;
+          part[2] += x.re * x.re + x.im * x.im;
+        }
+      }
+    }
+  }
+  block_partial<3>(part, a.partials, a.nbx, s, bx);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cocg_replace_fin(CocgArgs a) {
+  const int s = blockIdx.x;
+  __shared__ double red[4];
+  reduce_partials<3>(a.partials, a.nbx, s, red);
+  if (threadIdx.x != 0) return;
+  SysState t = a.st[s];
+  if (t.status != kActive || t.m == 0) return;
+  const cv<double> rho_new = {red[0], red[1]};
+  const double rn = sqrt(red[2]);
+  // beta_{m-1} = rho_m / rho_{m-1}: rescale by rho_m(new) / rho_m(old)
+  const cv<double> ratio = cdiv(rho_new, {t.rho_re, t.rho_im});
+  const cv<double> beta = cmul({t.be_re, t.be_im}, ratio);
+  t.be_re = t.bp_re = beta.re;
+  t.be_im = t.bp_im = beta.im;
+  a.beta_log[((int64_t)s * a.maxit + t.m - 1) * 2] = beta.re;
+  a.beta_log[((int64_t)s * a.maxit + t.m - 1) * 2 + 1] = beta.im;
+  t.rho_re = rho_new.re;
+  t.rho_im = rho_new.im;
+  t.rnorm = rn;
+  a.rnorm_log[(int64_t)s * (a.maxit + 1) + t.m] = rn;
+  if (!(cabs(rho_new) > 1e-14 * rn * rn)) {
+    t.status = kBreakdown;
+    t.breakdown_iter = t.m;
+  }
+  a.st[s] = t;
 }
 
 hipError_t launch_cocg_init(Elem e, const InitArgs& a, hipStream_t st) {
@@ -267,4 +330,18 @@ hipError_t launch_cocg_p(Elem e, const CocgArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+}  // namespace msb
+
+namespace msb {
+hipError_t launch_cocg_replace(Elem e, const CocgArgs& a, const double* E, const double* w,
+                               hipStream_t st) {
+  dim3 grid(a.nbx, a.nsys);
+  if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_replace<double>, grid, dim3(kBlock), 0, st, a, E, w);
+  else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_replace<float>, grid, dim3(kBlock), 0, st, a, E, w);
+  else return hipErrorInvalidValue;
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_cocg_replace_fin, dim3(a.nsys), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
 }  // namespace msb

@@ -453,12 +453,14 @@ struct SolveBufs {
   double* gcoef = nullptr;
   double* cscr = nullptr;
   double* ab = nullptr;
+  double* xseed = nullptr;      // residual replacement: seed solution [B][D] c128
+  double* wrep = nullptr;       // residual replacement: A_s x [B][D] c128
   SysDev* tsys = nullptr;       // true-residual systems
   double* tpart = nullptr;
   double* tred = nullptr;
 
   void carve(Carver& c, const msb_ctx* ctx, int B, int cap, int n_shift, int n_list, int maxit,
-             size_t s_el, size_t s_out, bool carry, bool want_true) {
+             size_t s_el, size_t s_out, bool carry, bool want_true, bool replace) {
     const int64_t D = ctx->D;
     size_t part_n = 0;   // largest nsys * nbx over the batch sizes that can occur
     for (int n = 1; n <= B; ++n)
@@ -488,6 +490,10 @@ struct SolveBufs {
     gcoef = carry ? c.take<double>((size_t)B * n_list * cap * 2 * sizeof(double)) : nullptr;
     cscr = c.take<double>((size_t)B * n_list * cap * 4 * sizeof(double));
     ab = c.take<double>((size_t)B * n_list * 4 * sizeof(double));
+    if (replace) {
+      xseed = c.take<double>((size_t)B * D * 16);
+      wrep = c.take<double>((size_t)B * D * 16);
+    }
     if (want_true) {
       const size_t nt = (size_t)B * n_shift;
       tsys = c.take<SysDev>(nt * sizeof(SysDev));
@@ -515,7 +521,14 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   if (!std::isfinite(seed_shift)) return fail(MSB_EINVAL, "msb_solve: seed_shift must be finite");
   for (int k = 0; k < n_shift; ++k)
     if (!std::isfinite(w_in[k])) return fail(MSB_EINVAL, "msb_solve: non-finite shift");
-  const int chunk = (opts && opts->chunk > 0) ? opts->chunk : 16;
+  // residual replacement (complex64 only): 0 = default period 50, < 0 = off
+  int replace_every = 0;
+  if (prec == MSB_C64) {
+    replace_every = (opts && opts->replace_every != 0) ? opts->replace_every : 50;
+    if (replace_every < 0) replace_every = 0;
+  }
+  int chunk = (opts && opts->chunk > 0) ? opts->chunk : 16;
+  if (replace_every > 0 && !(opts && opts->chunk > 0)) chunk = std::min(replace_every, 64);
   const double memfrac = (opts && opts->mem_fraction > 0) ? std::min(opts->mem_fraction, 0.98) : 0.9;
   const Elem ev = (prec == MSB_C128) ? Elem::C128 : Elem::C64;
   const Elem eo = ev;
@@ -540,7 +553,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   auto need_bytes = [&](int B, int cap, bool carry) {
     Carver c(nullptr);
     SolveBufs b;
-    b.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, carry, want_true);
+    b.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, carry, want_true, replace_every > 0);
     return c.used();
   };
   int planB = 0, plancap = 0;
@@ -594,7 +607,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   SolveBufs bf;
   {
     Carver c(ctx->ws);
-    bf.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, plancarry, want_true);
+    bf.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, plancarry, want_true, replace_every > 0);
   }
   void* bank = bf.bank;
   void* pvec = bf.pvec;
@@ -641,7 +654,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   };
 
   msb_status result = MSB_OK;
-  int max_iters = 0, total_mvms = 0, brk_iter = -1, flushes = 0;
+  int max_iters = 0, total_mvms = 0, brk_iter = -1, flushes = 0, n_replace = 0;
   std::vector<SysState> hst(B);
   std::vector<int> hconv((size_t)B * n_shift);
   std::vector<double> hz((size_t)B * n_shift * 2);
@@ -660,6 +673,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ia.E = Eb; ia.bank = bank; ia.pvec = pvec; ia.st = dst; ia.partials = partials;
     ia.cap = cap; ia.D = D; ia.nbx = cocg_nbx(D, nb); ia.nsys = nb; ia.n_shift = n_shift; ia.zeta = zeta;
     ia.zeta_prev = zeta_prev; ia.conv_iter = conv; ia.rnorm_log = rlog; ia.maxit = mx;
+    ia.xseed = bf.xseed;
     MSB_HIP(launch_cocg_init(ev, ia, st));
 
     ApplyArgs aa = apply_args(ctx, dsys, nb, pvec, vvec);
@@ -678,6 +692,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ca.nbx = cocg_nbx(D, nb); ca.nsys = nb; ca.n_shift = n_shift; ca.wshift = wshift; ca.zeta = zeta;
     ca.zeta_prev = zeta_prev; ca.conv_iter = conv; ca.tol = tol; ca.maxit = mx;
     ca.alpha_log = alog; ca.beta_log = blog; ca.rnorm_log = rlog;
+    ca.xseed = bf.xseed;
 
     int base = 0;
     bool first_flush = true;
@@ -768,9 +783,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     hipGraphExec_t gexec = nullptr;
     auto enqueue_chunk = [&]() -> hipError_t {
       for (int c = 0; c < chunk; ++c) {
-        hipError_t e = launch_apply(ev, kModeBilinear, aa, st);
+        hipError_t e = launch_cocg_p(ev, ca, st);
+        if (e == hipSuccess) e = launch_apply(ev, kModeBilinear, aa, st);
         if (e == hipSuccess) e = launch_cocg_r(ev, ca, st);
-        if (e == hipSuccess) e = launch_cocg_p(ev, ca, st);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
@@ -800,6 +815,11 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       ~GraphGuard() { if (*g) (void)hipGraphExecDestroy(*g); }
     } graph_guard{&gexec};
 
+    ApplyArgs ra = apply_args(ctx, dsys, nb, bf.xseed, bf.wrep);
+    ra.status = &dst[0].status;
+    ra.status_stride = (int)(sizeof(SysState) / sizeof(int));
+    int last_rep = 0;   // iteration of the last residual replacement
+
     int it_done = 0;
     while (true) {
       {
@@ -812,7 +832,20 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       bool any_active = false, any_paused = false;
       for (int s = 0; s < nb; ++s) {
         any_active |= hst[s].status == kActive;
-        any_paused |= hst[s].status == kPaused || hst[s].status == kPausedHold;
+        any_paused |= hst[s].status == kPaused;
+      }
+      if (any_active && replace_every > 0) {
+        // active systems advance in step, so one iteration count serves the batch
+        int m_now = 0;
+        for (int s = 0; s < nb; ++s)
+          if (hst[s].status == kActive) m_now = std::max(m_now, hst[s].m);
+        if (m_now - last_rep >= replace_every) {
+          // r_m <- E - A_s x_m with x_m and the product in complex128
+          MSB_HIP(launch_apply(Elem::C128, kModePlain, ra, st));
+          MSB_HIP(launch_cocg_replace(ev, ca, Eb, bf.wrep, st));
+          last_rep = m_now;
+          ++n_replace;
+        }
       }
       if (any_active) continue;
       if (any_paused) {
@@ -825,7 +858,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
         // restart the bank at the current residual r_m
         int m = -1;
         for (int s = 0; s < nb; ++s)
-          if (hst[s].status == kPaused || hst[s].status == kPausedHold) {
+          if (hst[s].status == kPaused) {
             if (m >= 0 && hst[s].m != m) return fail(MSB_EINVAL, "internal: paused systems out of step");
             m = hst[s].m;
           }
@@ -834,7 +867,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
         base = m;
         MSB_HIP(hipMemcpyAsync(dbase, &base, sizeof(int), hipMemcpyHostToDevice, st));
         for (int s = 0; s < nb; ++s)
-          if (hst[s].status == kPaused || hst[s].status == kPausedHold) hst[s].status = kActive;
+          if (hst[s].status == kPaused) hst[s].status = kActive;
         MSB_HIP(hipMemcpyAsync(dst, hst.data(), nb * sizeof(SysState), hipMemcpyHostToDevice, st));
         MSB_HIP(hipEventRecord(ev0, st));
         continue;
@@ -931,6 +964,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     info->mvms = total_mvms;
     info->breakdown_iter = brk_iter;
     info->flushes = flushes;
+    info->replacements = n_replace;
     info->t_iter_ms = t_iter;
     info->t_flush_ms = t_flush;
     info->t_true_ms = t_true;

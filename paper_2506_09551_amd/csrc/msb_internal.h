@@ -110,9 +110,11 @@ int apply_rows_per_xcd(int n_up);
 
 // ---- COCG seed step kernels (k_cocg.hip) -----------------------------------
 // Per-system state.  status codes:
-// kPaused: the bank is full after this iteration; p is still updated once.
-// kPausedHold: set by the next residual launch so that p is not updated again.
-enum : int { kActive = 0, kDone = 1, kBreakdown = 2, kMaxit = 3, kPaused = 4, kPausedHold = 5 };
+// One iteration runs p-update, apply, r-update (+ bookkeeping) in that order,
+// so a chunk boundary falls between the bookkeeping of iteration m-1 and the
+// p-update of iteration m (where the residual may be replaced).
+// kPaused: the bank has no slot for the next residual; the host flushes it.
+enum : int { kActive = 0, kDone = 1, kBreakdown = 2, kMaxit = 3, kPaused = 4 };
 struct SysState {
   double rho_re, rho_im;        // rho_m = r_m^T r_m
   double ap_re, ap_im;          // alpha_{m-1}
@@ -151,10 +153,15 @@ struct CocgArgs {
   double* alpha_log;            // [nsys][maxit][2]
   double* beta_log;             // [nsys][maxit][2]
   double* rnorm_log;            // [nsys][maxit+1]
+  double* xseed;                // optional [nsys][D] complex128 seed solution (x += alpha p)
 };
 
 hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st);   // r_{m+1} = r_m - alpha v
-hipError_t launch_cocg_p(Elem e, const CocgArgs& a, hipStream_t st);   // p = r_{m+1} + beta p
+hipError_t launch_cocg_p(Elem e, const CocgArgs& a, hipStream_t st);   // p_m = r_m + beta_{m-1} p_{m-1}
+// Residual replacement: r_m <- E - w (w = A_s x_m in complex128, computed by the
+// apply), rho_m and |r_m| recomputed in FP64, beta_{m-1} rescaled accordingly.
+hipError_t launch_cocg_replace(Elem e, const CocgArgs& a, const double* E, const double* w,
+                               hipStream_t st);
 int cocg_nbx(int64_t D, int nsys);
 
 // Initialisation: bank slot 0 = p = E (converted to Elem), rho_0 = E^T E, |E|.
@@ -174,6 +181,7 @@ struct InitArgs {
   int* conv_iter;
   double* rnorm_log;
   int maxit;
+  double* xseed;                // optional: zeroed
 };
 hipError_t launch_cocg_init(Elem e, const InitArgs& a, hipStream_t st);
 

@@ -123,6 +123,36 @@ def test_c64_form_accuracy(tiny):
     assert err <= 5e-5, f"c64 rel err {err:.3e}"
 
 
+@pytest.mark.parametrize("opts", [None, {"replace_every": 7, "chunk": 3},
+                                  {"replace_every": 20, "bank_slots": 33}])
+def test_c64_residual_replacement(tiny, opts):
+    """complex64 vectors with residual replacement r_m <- E - A_s x_m (complex128):
+    same accuracy as the plain form, replacements counted, and with a small
+    bank the replacement survives the flush / bank restart."""
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E = W.random_vector(D, 4).astype(np.complex128)
+    E_G = -2.6661474201323485
+    ref = osolve.direct_solve(oracle_H(m, core_site=0, Uc=wl.Uc), E, E_G, wl.Gamma, wl.w_in,
+                              method="eig")
+    sysd = msb.make_system(core_site=0, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma)
+    st, info, psi = _run(msb, ctx, [sysd], E, wl.w_in, 1e-6, 3000, msb.MSB_C64, opts=opts)
+    # replacement happens at the first chunk boundary at least `period`
+    # iterations after the previous one: at most period + chunk apart
+    period = (opts or {}).get("replace_every", 50)
+    chunk = (opts or {}).get("chunk", min(period, 64))
+    assert info["replacements"] >= max(info["iters"] // (period + chunk) - 1, 1)
+    assert info["replacements"] <= info["iters"] // period
+    err = _rel(psi[0], ref)
+    assert err <= 5e-5, f"c64 rel err {err:.3e}"
+    # after a replacement the recurrence residual tracks the true one
+    assert np.max(info["resid_true"]) <= 20 * 1e-6
+    st0, info0, psi0 = _run(msb, ctx, [sysd], E, wl.w_in, 1e-6, 3000, msb.MSB_C64,
+                            opts={"replace_every": -1})
+    assert info0["replacements"] == 0
+    assert _rel(psi0[0], ref) <= 5e-5
+
+
 def test_breakdown_reported(tiny):
     """E = e_0 + i e_1 has E^T E = 0: COCG cannot start (rho_0 = 0)."""
     msb, ctx, wl, m = tiny
