@@ -143,6 +143,44 @@ def precision_extras(msb, ctx, wl, systems, E, E_G, box, info64, ms64, tol, n_su
     return res
 
 
+def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec):
+    """Batched form against the same right-hand sides solved one at a time, and
+    the block apply's rate for the whole batch and for one vector."""
+    import torch
+
+    D = msb.msb_dim(ctx)
+    n = wl.nrhs
+
+    def separate():
+        for j in range(n):
+            st, _ = msb.msb_solve(ctx, [systems[j]], E[j:j + 1], wl.w_in, wl.seed_shift, tol, wl.maxit,
+                                  prec, psi[j:j + 1], want_true=True, raise_on_fail=False)
+            if st not in (msb.MSB_OK, msb.MSB_FLOOR):
+                raise msb.MsbError(st, msb.lib().msb_last_error().decode())
+
+    separate()                     # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    separate()
+    torch.cuda.synchronize()
+    ms_sep = (time.perf_counter() - t0) * 1e3
+    dt = psi.dtype
+    x = torch.randn(n, D, dtype=dt, device=psi.device)
+    y = torch.empty_like(x)
+    ms_blk = msb.msb_apply_timed(ctx, systems, 0.0, prec, x, y, 20)
+    ms_one = msb.msb_apply_timed(ctx, systems[0], 0.0, prec, x[0], y[0], 20)
+    el = x.element_size()
+    res = {
+        "separate_ms": round(ms_sep, 3), "batched_ms": round(ms_batched, 3),
+        "speedup_batched_vs_separate": round(ms_sep / ms_batched, 3),
+        "apply_block_ms": round(ms_blk, 4), "apply_one_ms": round(ms_one, 4),
+        "apply_block_GBs": round(2 * n * D * el / (ms_blk * 1e-3) / 1e9, 1),
+        "apply_one_GBs": round(2 * D * el / (ms_one * 1e-3) / 1e9, 1),
+    }
+    log(f"batched {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,17 +230,28 @@ def main():
         msb.msb_number_op(ctx, site, wu, wd, G, E[j])
     systems = [msb.make_system(core_site=c, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma) for c in wl.core_sites]
     n_shift = len(wl.w_in)
+    # apply launch shape: the autotuner's table for this batch (the solve reuses the winner)
+    tune_table = msb.msb_autotune(ctx, wl.nrhs, prec)
+    log("autotune " + " ".join(f"{t[0]}x{t[1]}/nv{t[2]}:{t[3]:.4f}ms" for t in tune_table))
     psi = torch.empty(wl.nrhs, n_shift, D, dtype=cdt, device=dev)
     torch.cuda.synchronize()
 
+    ok = (msb.MSB_OK, msb.MSB_FLOOR) if prec == msb.MSB_C64 else (msb.MSB_OK,)
+
     def step():
-        return msb.msb_solve(ctx, systems, E, wl.w_in, wl.seed_shift, args.tol, wl.maxit, prec, psi,
-                             want_true=True)
+        st, info = msb.msb_solve(ctx, systems, E, wl.w_in, wl.seed_shift, args.tol, wl.maxit, prec, psi,
+                                 want_true=True, raise_on_fail=False)
+        if st not in ok:
+            raise msb.MsbError(st, msb.lib().msb_last_error().decode())
+        info["status_name"] = msb.STATUS[st]
+        return st, info
 
     for i in range(args.warmup):
         _, info = step()
         log(f"warmup {i}: iters={info['iters']} t_iter={info['t_iter_ms']:.1f} ms "
-            f"t_flush={info['t_flush_ms']:.1f} ms t_true={info['t_true_ms']:.1f} ms")
+            f"t_flush={info['t_flush_ms']:.1f} ms t_true={info['t_true_ms']:.1f} ms "
+            f"setup={info['t_setup_ms']:.1f} alloc={info['t_alloc_ms']:.1f} wall={info['t_wall_ms']:.1f} ms "
+            f"flushes={info['flushes']}")
     torch.cuda.synchronize()
     infos = []
     start = torch.cuda.Event(enable_timing=True)
@@ -221,7 +270,9 @@ def main():
     value = wl.nrhs * n_shift / (ms_per_step / 1e3)
     last = infos[-1]
     max_true = float(np.max(last["resid_true"]))
-    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, max true residual {max_true:.2e}")
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, max true residual {max_true:.2e}; last: "
+        f"setup={last['t_setup_ms']:.1f} alloc={last['t_alloc_ms']:.1f} wall={last['t_wall_ms']:.1f} ms "
+        f"flushes={last['flushes']}")
 
     # ---- dominant kernel roofline: the dense multi-shift assembly ----------
     gemm_ms = sum(i["t_gemm_ms"] for i in infos) / max(1, sum(i["n_gemm"] for i in infos))
@@ -262,6 +313,10 @@ def main():
             "tol": args.tol, "Gamma": wl.Gamma, "U": wl.U, "Uc": wl.Uc,
         },
         "iters": last["iters"],
+        "solve_status": last["status_name"],
+        "apply_shape": {"threads": last["apply_shape"][0], "elems_per_thread": last["apply_shape"][1],
+                        "systems_per_workgroup": last["apply_shape"][2]},
+        "autotune_ms": {f"{t[0]}x{t[1]}/nv{t[2]}": round(t[3], 5) for t in tune_table},
         "mvms_per_step": last["mvms"],
         "max_true_residual": max_true,
         "split_ms": {k: round(v, 3) for k, v in split.items()},
@@ -269,7 +324,9 @@ def main():
         "ground_state": {"E_G": E_G, "lanczos_steps": gs_iters, "ms": round(gs_ms, 2)},
     }
 
-    if not args.no_extras and prec == msb.MSB_C64:
+    if not args.no_extras and wl.nrhs > 1 and prec == msb.MSB_C64:
+        out["batched"] = batched_extras(msb, ctx, wl, systems, E, psi, ms_per_step, args.tol, prec)
+    elif not args.no_extras and prec == msb.MSB_C64:
         box = [psi]       # hand the only reference over so the c64 result can be freed
         del psi
         out["precision"] = precision_extras(msb, ctx, wl, systems, E, E_G, box, last, ms_per_step, args.tol)

@@ -55,7 +55,10 @@ typedef enum {
   MSB_ENOMEM = 2,         /* device memory footprint exceeds what is free */
   MSB_EHIP = 3,           /* a HIP runtime call failed */
   MSB_BREAKDOWN = 4,      /* |r^T A p| fell below 1e-14 |r||Ap| (COCG breakdown) */
-  MSB_NOT_CONVERGED = 5   /* iteration cap reached before every shift converged */
+  MSB_NOT_CONVERGED = 5,  /* iteration cap reached before every shift converged */
+  MSB_FLOOR = 6           /* MSB_C64: a residual replacement found the recurrence residual more than
+                             10x below the true one, i.e. the complex64 recurrence reached its
+                             attainable accuracy before every shift met tol; that system stops there */
 } msb_status;
 
 typedef enum { MSB_C128 = 0, MSB_C64 = 1 } msb_prec;
@@ -109,8 +112,25 @@ typedef struct {
   int n_gemm;            /* number of dense assembly launches */
   double gemm_flops;     /* algorithmic flops of those launches: 8 D sum(range lengths) */
   double gemm_bytes;     /* algorithmic bytes: residual slots read + outputs written (+read) */
-  int replacements;      /* residual replacements performed (MSB_C64 only) */
+  int replacements;      /* residual replacements performed, summed over systems (MSB_C64 only) */
+  double* seed_hist;     /* optional [nsys*hist_len]: |r_m| / |E| of the seed for m < hist_len
+                            (the replaced value at a replacement), NaN after the last iteration */
+  int hist_len;
+  int apply_threads;     /* launch shape of the seed apply: threads per workgroup, */
+  int apply_ept;         /*   elements of a row per thread, */
+  int apply_nv;          /*   systems per workgroup */
+  double t_setup_ms;     /* host wall time before the workspace: validation, apply tuning, planning */
+  double t_alloc_ms;     /* host wall time of (re)allocating the workspace (0 when reused) */
+  double t_wall_ms;      /* host wall time of the whole call */
 } msb_info;
+
+/* One launch shape of the Hamiltonian apply and its measured time. */
+typedef struct {
+  int threads;           /* threads per workgroup (one workgroup per up-spin row) */
+  int elems_per_thread;  /* threads * elems_per_thread >= number of down-spin states */
+  int vectors;           /* systems handled by one workgroup (they share the hop tables) */
+  double ms;             /* mean time of one apply of min(nsys, 16) vectors (msb_autotune) */
+} msb_shape;
 
 /* Tuning knobs of msb_solve; pass NULL for defaults. */
 typedef struct {
@@ -120,17 +140,24 @@ typedef struct {
   int replace_every;     /* MSB_C64 only: the seed residual is replaced by E - A_s x_m (x_m and the
                             product in complex128) at the first chunk boundary at least
                             `replace_every` iterations after the previous replacement (a bank
-                            restart moves the boundaries); 0 = default 50, < 0 = off.  When it is
-                            on and `chunk` is 0, the chunk is min(replace_every, 64). */
+                            restart moves the boundaries), while |r_m| > max(tol, 1e-12) |E|;
+                            0 = default 50, < 0 = off.  When it is on and `chunk` is 0, the
+                            chunk is min(replace_every, 64). */
   int use_graph;         /* 0 or 1 = capture the chunk in a hipGraph (default), -1 = plain launches */
   double mem_fraction;   /* fraction of free device memory the workspace may use (default 0.9) */
   int assembly_engine;   /* multi-shift assembly: 0 = FP64 vector ALU (default), 1 = FP64 matrix cores */
+  int autotune;          /* 0 = tune the apply shape on first use (default), -1 = default shape
+                            unless one was tuned or pinned before */
 } msb_opts;
 
 /* ---- context -------------------------------------------------------------- */
 
 /* Builds the basis and the per-spin hopping tables (Jordan-Wigner signs of
  * Eq. Hubbard) on the host and uploads them to the current device.
+ * Limits: 2 <= n_sites <= 20; one down-spin row (C(n_sites, n_dn) states) is
+ * staged in one workgroup's LDS, so 8 * C(n_sites, n_dn) bytes must fit it
+ * (160 KB on gfx950: up to 20480 states; complex128 applies need 16 bytes per
+ * state, up to 10240 states, and return MSB_EINVAL beyond).
  * Errors: MSB_EINVAL for sizes outside the limits; MSB_EHIP on upload failure. */
 msb_status msb_create(const msb_model* model, msb_ctx** out);
 void msb_destroy(msb_ctx* ctx);
@@ -185,14 +212,31 @@ msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, const double* x
  * |r_m| / |zeta_m(w_k)| <= tol |E_s|.  MSB_C64 runs the vectors in complex64
  * with FP64 reductions and scalars, and replaces the seed residual by the
  * FP64 true residual every opts->replace_every iterations.
- * Returns MSB_NOT_CONVERGED (psi holds the last iterates) or MSB_BREAKDOWN
- * (psi holds the iterates before the breakdown) on failure.
+ * Returns MSB_NOT_CONVERGED (psi holds the last iterates), MSB_FLOOR (MSB_C64
+ * only; psi holds the iterates at the attainable accuracy, shifts that had not
+ * met tol have shift_iters = -1 and their resid_true says what was reached) or
+ * MSB_BREAKDOWN (psi holds the iterates before the breakdown).  Precedence when
+ * systems end differently: BREAKDOWN, NOT_CONVERGED, FLOOR.
  * Footprint (checked before launching): about (bank_slots + 6) * D * s * batch
  * (+ 2 n_shift D s batch when the bank must be flushed mid-solve). */
 msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, const void* E,
                      const double* w_in, int n_shift, double seed_shift, double tol,
                      int maxit, msb_prec prec, void* psi, msb_info* info,
                      const msb_opts* opts, void* stream);
+
+/* Autotuner of the Hamiltonian apply (the block SpMM of the batched form).
+ * Times every compiled launch shape usable for this context's row length with
+ * min(nsys, 16) systems in `prec` on scratch vectors (5 timed applies each,
+ * HIP events), keeps the fastest in the context for every later apply of that
+ * (nsys class, prec), and reports the table (out may be NULL).  msb_solve,
+ * msb_apply, msb_apply_timed, msb_ground_state and msb_spectrum tune on their
+ * first use of a (nsys class, precision) unless opts->autotune = -1.
+ * Errors: MSB_ENOMEM if the scratch vectors do not fit. */
+msb_status msb_autotune(msb_ctx* ctx, int nsys, msb_prec prec, msb_shape* out, int max_out,
+                        int* n_out, void* stream);
+/* Pins the apply shape for (min(nsys, 16), prec); shape->threads == 0 returns
+ * to the default shape.  Errors: MSB_EINVAL if the shape is not usable here. */
+msb_status msb_set_shape(msb_ctx* ctx, int nsys, msb_prec prec, const msb_shape* shape);
 
 /* phi[k] = sum_s phase_s * O1_s psi[s][k]  for k < n_shift, with
  * O1_s = (w_up n_{site up} + w_dn n_{site dn}) or identity when o1_site[s] < 0.

@@ -15,8 +15,8 @@ from pathlib import Path
 
 MSB_MAX_BOND_TYPES = 8
 STATUS = {0: "MSB_OK", 1: "MSB_EINVAL", 2: "MSB_ENOMEM", 3: "MSB_EHIP",
-          4: "MSB_BREAKDOWN", 5: "MSB_NOT_CONVERGED"}
-MSB_OK, MSB_EINVAL, MSB_ENOMEM, MSB_EHIP, MSB_BREAKDOWN, MSB_NOT_CONVERGED = range(6)
+          4: "MSB_BREAKDOWN", 5: "MSB_NOT_CONVERGED", 6: "MSB_FLOOR"}
+MSB_OK, MSB_EINVAL, MSB_ENOMEM, MSB_EHIP, MSB_BREAKDOWN, MSB_NOT_CONVERGED, MSB_FLOOR = range(7)
 MSB_C128, MSB_C64 = 0, 1
 
 LIB_PATH = Path(__file__).resolve().parent / "libmsb.so"
@@ -46,13 +46,20 @@ class msb_info(ctypes.Structure):
                 ("resid_rec", POINTER(c_double)), ("resid_true", POINTER(c_double)),
                 ("t_iter_ms", c_double), ("t_flush_ms", c_double), ("t_true_ms", c_double),
                 ("t_gemm_ms", c_double), ("n_gemm", c_int), ("gemm_flops", c_double),
-                ("gemm_bytes", c_double), ("replacements", c_int)]
+                ("gemm_bytes", c_double), ("replacements", c_int),
+                ("seed_hist", POINTER(c_double)), ("hist_len", c_int),
+                ("apply_threads", c_int), ("apply_ept", c_int), ("apply_nv", c_int),
+                ("t_setup_ms", c_double), ("t_alloc_ms", c_double), ("t_wall_ms", c_double)]
+
+
+class msb_shape(ctypes.Structure):
+    _fields_ = [("threads", c_int), ("elems_per_thread", c_int), ("vectors", c_int), ("ms", c_double)]
 
 
 class msb_opts(ctypes.Structure):
     _fields_ = [("chunk", c_int), ("bank_slots", c_int), ("batch", c_int),
                 ("replace_every", c_int), ("use_graph", c_int), ("mem_fraction", c_double),
-                ("assembly_engine", c_int)]
+                ("assembly_engine", c_int), ("autotune", c_int)]
 
 
 _lib = None
@@ -64,6 +71,9 @@ def lib():
     if _lib is None:
         if not LIB_PATH.exists():
             raise OSError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()     # torch's HIP runtime must claim the device before the library's
         L = ctypes.CDLL(str(LIB_PATH))
         L.msb_last_error.restype = ctypes.c_char_p
         L.msb_device_ok.restype = c_int
@@ -99,6 +109,11 @@ def lib():
                                    c_int, c_double, c_int, c_double, POINTER(c_double),
                                    POINTER(c_int), c_void_p]
         L.msb_spectrum.restype = c_int
+        L.msb_autotune.argtypes = [c_void_p, c_int, c_int, POINTER(msb_shape), c_int, POINTER(c_int),
+                                   c_void_p]
+        L.msb_autotune.restype = c_int
+        L.msb_set_shape.argtypes = [c_void_p, c_int, c_int, POINTER(msb_shape)]
+        L.msb_set_shape.restype = c_int
         _lib = L
     return _lib
 
@@ -107,7 +122,7 @@ def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["msb_create", "msb_destroy", "msb_dim", "msb_sector_info", "msb_last_error",
             "msb_device_ok", "msb_apply", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
-            "msb_combine", "msb_spectrum"]
+            "msb_combine", "msb_spectrum", "msb_autotune", "msb_set_shape"]
 
 
 def _check(status: int):
@@ -116,10 +131,17 @@ def _check(status: int):
 
 
 def _stream_ptr(stream):
+    """Order the call after the work queued on torch's stream, then let the
+    library run on its own default stream.
+
+    torch ships its own HIP runtime, separate from the one the library links,
+    so a torch stream handle means nothing to the library (device pointers
+    are shared: both runtimes map into the same process address space).
+    Every library call is blocking, so its outputs are complete on return.
+    """
     import torch
-    if stream is None:
-        stream = torch.cuda.current_stream()
-    return c_void_p(stream.cuda_stream)
+    (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+    return c_void_p(0)
 
 
 def _ptr(t, dtype=None, numel=None, name="tensor"):
@@ -243,7 +265,8 @@ def msb_ground_state(ctx, system, x0, tol: float, maxit: int, G, stream=None):
 
 
 def msb_solve(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit: int, prec: int, psi,
-              want_true: bool = False, opts: dict | None = None, stream=None, raise_on_fail=True):
+              want_true: bool = False, opts: dict | None = None, stream=None, raise_on_fail=True,
+              hist_len: int = 0):
     """Multi-shift solve; returns (status, info dict)."""
     import numpy as np
     import torch
@@ -260,6 +283,10 @@ def msb_solve(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit: int, 
     info.shift_iters = shift_iters
     info.resid_rec = resid_rec
     info.resid_true = ctypes.cast(resid_true, POINTER(c_double)) if want_true else None
+    seed_hist = (c_double * (n * hist_len))() if hist_len > 0 else None
+    if hist_len > 0:
+        info.seed_hist = ctypes.cast(seed_hist, POINTER(c_double))
+        info.hist_len = int(hist_len)
     o = msb_opts()
     for k, v in (opts or {}).items():
         setattr(o, k, v)
@@ -278,6 +305,10 @@ def msb_solve(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit: int, 
         "t_iter_ms": info.t_iter_ms, "t_flush_ms": info.t_flush_ms, "t_true_ms": info.t_true_ms,
         "t_gemm_ms": info.t_gemm_ms, "n_gemm": info.n_gemm, "gemm_flops": info.gemm_flops,
         "gemm_bytes": info.gemm_bytes, "replacements": info.replacements,
+        "seed_hist": (np.frombuffer(seed_hist, dtype=np.float64).reshape(n, hist_len).copy()
+                      if hist_len > 0 else None),
+        "apply_shape": (info.apply_threads, info.apply_ept, info.apply_nv),
+        "t_setup_ms": info.t_setup_ms, "t_alloc_ms": info.t_alloc_ms, "t_wall_ms": info.t_wall_ms,
     }
     if raise_on_fail and st != MSB_OK:
         raise MsbError(st, lib().msb_last_error().decode())
@@ -316,3 +347,19 @@ def msb_spectrum(ctx, system, phi, w, eta: float, lanczos_max: int, cf_tol: floa
                               int(lanczos_max), float(cf_tol), I.ctypes.data_as(POINTER(c_double)),
                               depth.ctypes.data_as(POINTER(c_int)), _stream_ptr(stream)))
     return I, depth
+
+
+def msb_autotune(ctx, nsys: int, prec: int, stream=None):
+    """Time every usable apply shape; returns [(threads, elems_per_thread, vectors, ms), ...]."""
+    tab = (msb_shape * 64)()
+    n = c_int(0)
+    _check(lib().msb_autotune(ctx, int(nsys), int(prec), tab, 64, ctypes.byref(n), _stream_ptr(stream)))
+    return [(t.threads, t.elems_per_thread, t.vectors, t.ms) for t in tab[:min(n.value, 64)]]
+
+
+def msb_set_shape(ctx, nsys: int, prec: int, shape):
+    """Pin the apply shape (threads, elems_per_thread, vectors); None returns to the default."""
+    sh = msb_shape()
+    if shape is not None:
+        sh.threads, sh.elems_per_thread, sh.vectors = (int(v) for v in shape[:3])
+    _check(lib().msb_set_shape(ctx, int(nsys), int(prec), ctypes.byref(sh)))

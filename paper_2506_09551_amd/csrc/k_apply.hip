@@ -20,8 +20,8 @@
 
 namespace msb {
 
-template <typename S, typename Tc, bool CPLX, int EPT, int MODE, int NV>
-__global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
+template <typename S, typename Tc, bool CPLX, int EPT, int MODE, int NV, int BLK>
+__global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
   using Ax = Access<S, CPLX>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cv<Tc>* rows = reinterpret_cast<cv<Tc>*>(smem_raw);    // [NV][nd]
@@ -58,6 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
       if (tid < MSB_MAX_BOND_TYPES) s_amp[v][tid] = (Tc)sd->amp[tid];
     }
   }
+  __syncthreads();   // s_amp is read before the staging barrier
   bool any = false;
 #pragma unroll
   for (int v = 0; v < NV; ++v) any |= act[v];
@@ -68,44 +69,88 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
 
   if (any) {
     const int64_t row0 = (int64_t)u * nd;
+    // own row elements d = tid + e * BLK in registers (diagonal, staging)
+    cv<Tc> xs[NV][EPT];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      if (!act[v]) continue;
       const void* x = Ax::offset(a.x, (int64_t)(s0 + v) * a.D);
-#pragma unroll 4
-      for (int i = tid; i < nd; i += kBlock) rows[v * nd + i] = Ax::template load<Tc>(x, row0 + i);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int d = tid + e * BLK;
+        xs[v][e] = (act[v] && d < nd) ? Ax::template load<Tc>(x, row0 + d) : cv<Tc>{(Tc)0, (Tc)0};
+      }
     }
-    __syncthreads();
-
     const uint32_t cu = a.T.conf_up[u];
     cv<Tc> acc[NV][EPT];
     // diagonal
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const int d = tid + e * kBlock;
+      const int d = tid + e * BLK;
       const uint32_t cd = (d < nd) ? a.T.conf_dn[d] : 0u;
       const Tc pc = (Tc)__builtin_popcount(cu & cd);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        acc[v][e] = {(Tc)0, (Tc)0};
-        if (d < nd && act[v]) {
-          Tc dg = Uv[v] * pc + dre[v];
-          if (core[v] >= 0) dg += Ucv[v] * (Tc)(((cu >> core[v]) & 1u) + ((cd >> core[v]) & 1u));
-          const cv<Tc> xd = rows[v * nd + d];
-          acc[v][e].re = dg * xd.re - dim[v] * xd.im;
-          acc[v][e].im = dg * xd.im + dim[v] * xd.re;
-        }
+        Tc dg = Uv[v] * pc + dre[v];
+        if (core[v] >= 0) dg += Ucv[v] * (Tc)(((cu >> core[v]) & 1u) + ((cd >> core[v]) & 1u));
+        acc[v][e].re = dg * xs[v][e].re - dim[v] * xs[v][e].im;
+        acc[v][e].im = dg * xs[v][e].im + dim[v] * xs[v][e].re;
+        if (d < nd) rows[v * nd + d] = xs[v][e];
       }
     }
-    // I (x) H_dn: padded transposed hop table, one entry for all NV vectors
+    // H_up (x) I: whole neighbour rows from global memory, HG hops in flight
+    // per group (the hop list of u is uniform across the workgroup)
+    constexpr int HG = (EPT * NV >= 8) ? 1 : 8 / (EPT * NV);
+    const uint32_t h0 = a.T.off_up[u], h1 = a.T.off_up[u + 1];
+    for (uint32_t k = h0; k < h1; k += HG) {
+      cv<Tc> xn[HG][NV][EPT];
+      Tc cf[HG][NV];
+#pragma unroll
+      for (int j = 0; j < HG; ++j) {
+        const bool hv = k + j < h1;
+        const uint32_t h = hv ? a.T.hop_up[k + j] : 0u;
+        const uint32_t ty = (h >> 1) & 127u;
+        const bool neg = (h & 1u) == 0u;
+        const int64_t nrow = (int64_t)(h >> 16) * nd;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          Tc c = s_amp[v][ty];
+          cf[j][v] = (hv && act[v]) ? (neg ? -c : c) : (Tc)0;
+          const void* x = Ax::offset(a.x, (int64_t)(s0 + v) * a.D);
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const int d = tid + e * BLK;
+            xn[j][v][e] = (hv && act[v] && d < nd) ? Ax::template load<Tc>(x, nrow + d)
+                                                   : cv<Tc>{(Tc)0, (Tc)0};
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < HG; ++j)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            acc[v][e].re += cf[j][v] * xn[j][v][e].re;
+            acc[v][e].im += cf[j][v] * xn[j][v][e].im;
+          }
+    }
+    __syncthreads();   // staged rows complete
+    // I (x) H_dn: padded transposed hop table (next entry prefetched), one
+    // entry for all NV vectors
     const int kdn = a.T.k_dn;
-#pragma unroll 2
+    uint32_t hn[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int d = tid + e * BLK;
+      hn[e] = (d < nd && kdn > 0) ? a.T.ell_dn[d] : kNoHop;
+    }
     for (int k = 0; k < kdn; ++k) {
       uint32_t h[EPT];
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        const int d = tid + e * kBlock;
-        h[e] = (d < nd) ? a.T.ell_dn[(int64_t)k * nd + d] : kNoHop;
+        h[e] = hn[e];
+        const int d = tid + e * BLK;
+        hn[e] = (d < nd && k + 1 < kdn) ? a.T.ell_dn[(int64_t)(k + 1) * nd + d] : kNoHop;
       }
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
@@ -117,33 +162,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
           if (!act[v]) continue;
           Tc c = s_amp[v][ty];
           c = neg ? -c : c;
-          const cv<Tc> xn = rows[v * nd + tgt];
-          acc[v][e].re += c * xn.re;
-          acc[v][e].im += c * xn.im;
-        }
-      }
-    }
-    // H_up (x) I: whole neighbour rows from global memory
-    const uint32_t h0 = a.T.off_up[u], h1 = a.T.off_up[u + 1];
-    for (uint32_t k = h0; k < h1; ++k) {
-      const uint32_t h = a.T.hop_up[k];
-      const uint32_t ty = (h >> 1) & 127u;
-      const bool neg = (h & 1u) == 0u;
-      const int64_t nrow = (int64_t)(h >> 16) * nd;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        if (!act[v]) continue;
-        Tc c = s_amp[v][ty];
-        c = neg ? -c : c;
-        const void* x = Ax::offset(a.x, (int64_t)(s0 + v) * a.D);
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          const int d = tid + e * kBlock;
-          if (d < nd) {
-            const cv<Tc> xn = Ax::template load<Tc>(x, nrow + d);
-            acc[v][e].re += c * xn.re;
-            acc[v][e].im += c * xn.im;
-          }
+          const cv<Tc> xv = rows[v * nd + tgt];
+          acc[v][e].re += c * xv.re;
+          acc[v][e].im += c * xv.im;
         }
       }
     }
@@ -154,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
       const int64_t vbase = (int64_t)(s0 + v) * a.D;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        const int d = tid + e * kBlock;
+        const int d = tid + e * BLK;
         if (d >= nd) continue;
         const int64_t gi = row0 + d;
         const cv<Tc> vv = acc[v][e];
@@ -167,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
           part[v][1] += r.re * vs.im + r.im * vs.re;
           part[v][2] += vs.re * vs.re + vs.im * vs.im;
         } else if constexpr (MODE == kModeHerm) {
-          const cv<Tc> qv = rows[v * nd + d];
+          const cv<Tc> qv = xs[v][e];
           part[v][0] += (double)qv.re * (double)vv.re + (double)qv.im * (double)vv.im;
           part[v][1] += (double)qv.re * (double)vv.im - (double)qv.im * (double)vv.re;
           part[v][2] += (double)vv.re * (double)vv.re + (double)vv.im * (double)vv.im;
@@ -181,13 +202,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
   }
   if constexpr (MODE != kModePlain) {
     // every workgroup writes the partials of all its vectors (zeros if idle)
-    __shared__ double sh[3 * NV][kBlock / kWave];
+    __shared__ double sh[3 * NV][BLK / kWave];
     double flat[3 * NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int i = 0; i < 3; ++i) flat[3 * v + i] = part[v][i];
-    block_sum<3 * NV>(flat, sh);
+    block_sum<3 * NV, BLK>(flat, sh);
     if (tid == 0) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -205,58 +226,136 @@ int apply_nbx(int n_up, int nsys) {
   return apply_rows_per_xcd(n_up) * kNumXcd;   // one row per workgroup
 }
 
-// Vectors per workgroup: as many as keep the staged rows within 40 KB of LDS
-// (four workgroups per CU), at most 4 and at most the number of systems.
-static int pick_nv(int nd, size_t elem, int nsys, int ept) {
-  if (ept > 8) return 1;
-  int nv = 4;
-  while (nv > 1 && ((size_t)nv * nd * elem > 40 * 1024 || nv > nsys)) nv /= 2;
-  return nv;
+// Compiled launch shapes (threads per workgroup, elements per thread,
+// vectors per workgroup).  A row of n_dn elements needs BLK * EPT >= n_dn.
+// Large workgroups put more waves on one staged row: with a 55 KB row only
+// two workgroups fit a CU's LDS, and 1024 threads each give 32 waves per CU
+// instead of 8, which is what hides the latency of the neighbour-row loads.
+#define MSB_APPLY_SHAPES(X)                                              \
+  X(256, 1, 4) X(256, 1, 2) X(256, 1, 1)                                 \
+  X(256, 2, 4) X(256, 2, 2) X(256, 2, 1)                                 \
+  X(256, 4, 4) X(256, 4, 2) X(256, 4, 1)                                 \
+  X(256, 8, 4) X(256, 8, 2) X(256, 8, 1)                                 \
+  X(256, 16, 1) X(256, 24, 1)                                            \
+  X(1024, 1, 2) X(1024, 1, 1)                                            \
+  X(1024, 4, 4) X(1024, 4, 2) X(1024, 4, 1)                              \
+  X(1024, 5, 4) X(1024, 5, 2) X(1024, 5, 1) X(1024, 8, 1) X(1024, 16, 1)
+
+static const ApplyShape kShapes[] = {
+#define MSB_SHAPE_ENTRY(B, E, N) {B, E, N},
+    MSB_APPLY_SHAPES(MSB_SHAPE_ENTRY)
+#undef MSB_SHAPE_ENTRY
+};
+static constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+
+static bool compiled(const ApplyShape& sh) {
+  for (int i = 0; i < kNumShapes; ++i)
+    if (kShapes[i].blk == sh.blk && kShapes[i].ept == sh.ept && kShapes[i].nv == sh.nv) return true;
+  return false;
+}
+
+// Shape usable for rows of nd elements of `row_bytes` bytes each: the row
+// fits, the staged rows fit the workgroup's LDS limit, and EPT is the
+// smallest compiled one for this (BLK, NV) (larger ones only add idle lanes).
+static bool usable(const ApplyShape& sh, int nd, size_t row_bytes, int nsys, size_t lds_max) {
+  if (!compiled(sh)) return false;
+  if ((int64_t)sh.blk * sh.ept < nd) return false;
+  if ((size_t)sh.nv * nd * row_bytes > lds_max) return false;
+  if (sh.nv > 1 && sh.nv > nsys) return false;
+  for (int i = 0; i < kNumShapes; ++i) {
+    const ApplyShape& o = kShapes[i];
+    if (o.blk == sh.blk && o.nv == sh.nv && o.ept < sh.ept && (int64_t)o.blk * o.ept >= nd) return false;
+  }
+  if (sh.blk > 256 && 2 * nd < sh.blk * sh.ept) return false;   // mostly idle lanes
+  return true;
+}
+
+int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, ApplyShape* out, int max_out) {
+  int n = 0;
+  for (int i = 0; i < kNumShapes && n < max_out; ++i)
+    if (usable(kShapes[i], nd, row_bytes, nsys, lds_max)) out[n++] = kShapes[i];
+  return n;
+}
+
+// Default shape when nothing was tuned: 256 threads (1024 if no 256-thread
+// shape covers the row), as many vectors per workgroup as keep the staged
+// rows within 40 KB (at most 4).  ept == 0: no shape fits.
+static ApplyShape default_shape(int nd, size_t row_bytes, int nsys, size_t lds_max) {
+  for (int blk : {256, 1024}) {
+    ApplyShape sh{blk, 0, 1};
+    for (int i = 0; i < kNumShapes; ++i) {
+      const ApplyShape& o = kShapes[i];
+      if (o.blk == blk && o.nv == 1 && (int64_t)o.blk * o.ept >= nd && (sh.ept == 0 || o.ept < sh.ept)) sh.ept = o.ept;
+    }
+    if (sh.ept == 0 || (size_t)nd * row_bytes > lds_max) continue;
+    for (int nv = 4; nv > 1; nv /= 2) {
+      ApplyShape c{blk, sh.ept, nv};
+      if (compiled(c) && nv <= nsys && (size_t)nv * nd * row_bytes <= 40 * 1024) return c;
+    }
+    return sh;
+  }
+  return ApplyShape{256, 0, 1};
+}
+
+// The requested shape if usable for this kernel's row type, else the same
+// shape with fewer vectors per workgroup, else the default.
+static ApplyShape resolve_shape(const ApplyArgs& a, size_t row_bytes) {
+  const int nd = a.T.n_dn;
+  ApplyShape sh = a.shape;
+  if (sh.blk > 0) {
+    for (; sh.nv >= 1; sh.nv /= 2)
+      if (usable(sh, nd, row_bytes, a.nsys, a.lds_max)) return sh;
+  }
+  return default_shape(nd, row_bytes, a.nsys, a.lds_max);
 }
 
 template <typename S, typename Tc, bool CPLX, int MODE>
-static hipError_t launch_ept(const ApplyArgs& a0, hipStream_t st) {
+static hipError_t launch_mode(const ApplyArgs& a0, hipStream_t st) {
   ApplyArgs a = a0;
   const int nd = a.T.n_dn;
-  const int need = (nd + kBlock - 1) / kBlock;
-  const int nv = pick_nv(nd, sizeof(cv<Tc>), a.nsys, need);
-  a.nvec = nv;
-  dim3 grid(a.nbx, (a.nsys + nv - 1) / nv);
-  const size_t lds = (size_t)nv * nd * sizeof(cv<Tc>);
+  const ApplyShape sh = resolve_shape(a, sizeof(cv<Tc>));
+  if (sh.ept == 0 || (int64_t)sh.blk * sh.ept < nd || (size_t)sh.nv * nd * sizeof(cv<Tc>) > a.lds_max)
+    return hipErrorInvalidValue;
+  a.nvec = sh.nv;
+  dim3 grid(a.nbx, (a.nsys + sh.nv - 1) / sh.nv);
+  const size_t lds = (size_t)sh.nv * nd * sizeof(cv<Tc>);
   hipError_t err = hipErrorInvalidValue;
-#define MSB_EPT_CASE(E, NVV)                                                              \
-  else if (need <= E && nv == NVV) {                                                      \
-    hipLaunchKernelGGL((k_apply<S, Tc, CPLX, E, MODE, NVV>), grid, dim3(kBlock), lds, st, a); \
-    err = hipGetLastError();                                                              \
+#define MSB_SHAPE_CASE(B, E, N)                                                             \
+  else if (sh.blk == B && sh.ept == E && sh.nv == N) {                                      \
+    hipLaunchKernelGGL((k_apply<S, Tc, CPLX, E, MODE, N, B>), grid, dim3(B), lds, st, a);     \
+    err = hipGetLastError();                                                                \
   }
   if (false) {}
-  MSB_EPT_CASE(1, 4) MSB_EPT_CASE(1, 2) MSB_EPT_CASE(1, 1)
-  MSB_EPT_CASE(2, 4) MSB_EPT_CASE(2, 2) MSB_EPT_CASE(2, 1)
-  MSB_EPT_CASE(4, 4) MSB_EPT_CASE(4, 2) MSB_EPT_CASE(4, 1)
-  MSB_EPT_CASE(8, 4) MSB_EPT_CASE(8, 2) MSB_EPT_CASE(8, 1)
-  MSB_EPT_CASE(16, 1)
-  MSB_EPT_CASE(24, 1)
-#undef MSB_EPT_CASE
+  MSB_APPLY_SHAPES(MSB_SHAPE_CASE)
+#undef MSB_SHAPE_CASE
   if (err != hipSuccess || MODE == kModePlain) return err;
   return launch_reduce(a.partials, a.nbx, a.nsys, a.red, st);
+}
+
+ApplyShape apply_shape_used(Elem e, int mode, const ApplyArgs& a) {
+  // bytes of one staged element: complex64 residual mode accumulates in FP64
+  size_t b = 16;
+  if (e == Elem::R64) b = 8;
+  else if (e == Elem::C64) b = (mode == kModeResid) ? 16 : 8;
+  return resolve_shape(a, b);
 }
 
 hipError_t launch_apply(Elem e, int mode, const ApplyArgs& a, hipStream_t st) {
   switch (e) {
     case Elem::R64:
-      if (mode == kModePlain) return launch_ept<double, double, false, kModePlain>(a, st);
-      if (mode == kModeHerm) return launch_ept<double, double, false, kModeHerm>(a, st);
+      if (mode == kModePlain) return launch_mode<double, double, false, kModePlain>(a, st);
+      if (mode == kModeHerm) return launch_mode<double, double, false, kModeHerm>(a, st);
       break;
     case Elem::C128:
-      if (mode == kModePlain) return launch_ept<double, double, true, kModePlain>(a, st);
-      if (mode == kModeBilinear) return launch_ept<double, double, true, kModeBilinear>(a, st);
-      if (mode == kModeHerm) return launch_ept<double, double, true, kModeHerm>(a, st);
-      if (mode == kModeResid) return launch_ept<double, double, true, kModeResid>(a, st);
+      if (mode == kModePlain) return launch_mode<double, double, true, kModePlain>(a, st);
+      if (mode == kModeBilinear) return launch_mode<double, double, true, kModeBilinear>(a, st);
+      if (mode == kModeHerm) return launch_mode<double, double, true, kModeHerm>(a, st);
+      if (mode == kModeResid) return launch_mode<double, double, true, kModeResid>(a, st);
       break;
     case Elem::C64:
-      if (mode == kModePlain) return launch_ept<float, float, true, kModePlain>(a, st);
-      if (mode == kModeBilinear) return launch_ept<float, float, true, kModeBilinear>(a, st);
-      if (mode == kModeResid) return launch_ept<float, double, true, kModeResid>(a, st);
+      if (mode == kModePlain) return launch_mode<float, float, true, kModePlain>(a, st);
+      if (mode == kModeBilinear) return launch_mode<float, float, true, kModeBilinear>(a, st);
+      if (mode == kModeResid) return launch_mode<float, double, true, kModeResid>(a, st);
       break;
   }
   return hipErrorInvalidValue;

@@ -74,6 +74,9 @@ __global__ __launch_bounds__(kBlock) void k_cocg_init_fin(InitArgs a) {
     st.bp_re = 0.0; st.bp_im = 0.0;     // beta_{-1} = 0
     st.al_re = st.al_im = st.be_re = st.be_im = 0.0;
     st.m = 0;
+    st.rbest = st.normE;
+    st.n_stall = 0;
+    st.pad = 0;
     st.n_active = a.n_shift;
     st.breakdown_iter = -1;
     if (st.normE == 0.0) {
@@ -242,7 +245,15 @@ __global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
 }
 
 
-// r_m <- E - w for active systems (w = A_s x_m in complex128); partial rho, |r|^2
+// A system's residual is replaced while it is iterating and its recurrence
+// residual is above rep_floor |E|.  Below that the seed is as accurate as the
+// FP64 product can show (or already at tol), and the shifted systems, whose
+// residuals are r_m / zeta_m, need the recurrence to go on unperturbed.
+__device__ __forceinline__ bool wants_replace(const SysState& t, const CocgArgs& a) {
+  return t.status == kActive && t.m > 0 && t.rnorm > a.rep_floor * t.normE;
+}
+
+// r_m <- E - w for the systems that want it (w = A_s x_m in complex128); partial rho, |r|^2
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_cocg_replace(CocgArgs a, const double* E, const double* w) {
   using Ax = Access<S, true>;
@@ -250,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_replace(CocgArgs a, const doubl
   const int s = blockIdx.y, bx = blockIdx.x;
   double part[3] = {0.0, 0.0, 0.0};
   const SysState st = a.st[s];
-  if (st.status == kActive) {
+  if (wants_replace(st, a)) {
     void* r = Ax::offset(a.bank, ((int64_t)s * a.cap + (st.m - *a.base)) * a.D);
     for (int64_t base = (int64_t)bx * kPerStep; base < a.D; base += (int64_t)a.nbx * kPerStep) {
 #pragma unroll
@@ -279,9 +290,10 @@ __global__ __launch_bounds__(kBlock) void k_cocg_replace_fin(CocgArgs a) {
   reduce_partials<3>(a.partials, a.nbx, s, red);
   if (threadIdx.x != 0) return;
   SysState t = a.st[s];
-  if (t.status != kActive || t.m == 0) return;
+  if (!wants_replace(t, a)) return;
   const cv<double> rho_new = {red[0], red[1]};
   const double rn = sqrt(red[2]);
+  const double rn_rec = t.rnorm;    // recurrence residual before the replacement
   // beta_{m-1} = rho_m / rho_{m-1}: rescale by rho_m(new) / rho_m(old)
   const cv<double> ratio = cdiv(rho_new, {t.rho_re, t.rho_im});
   const cv<double> beta = cmul({t.be_re, t.be_im}, ratio);
@@ -296,6 +308,13 @@ __global__ __launch_bounds__(kBlock) void k_cocg_replace_fin(CocgArgs a) {
   if (!(cabs(rho_new) > 1e-14 * rn * rn)) {
     t.status = kBreakdown;
     t.breakdown_iter = t.m;
+  } else if (rn > kFloorGap * rn_rec) {
+    t.status = kFloor;                // the recurrence went below what its precision can attain
+  } else if (rn < kStall * t.rbest) {
+    t.rbest = rn;                     // real progress
+    t.n_stall = 0;
+  } else if (rn_rec < kStall * t.rbest) {
+    if (++t.n_stall >= kStallMax) t.status = kFloor;   // claimed progress that the truth does not show
   }
   a.st[s] = t;
 }

@@ -71,8 +71,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Block-wide sum of NV values into thread 0 (deterministic order).
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[kBlock / kWave]) {
+template <int NV, int BLK = kBlock>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[BLK / kWave]) {
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
@@ -85,7 +85,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[kBlock /
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       double t = 0.0;
-      for (int w = 0; w < kBlock / kWave; ++w) t += sh[i][w];
+      for (int w = 0; w < BLK / kWave; ++w) t += sh[i][w];
       v[i] = t;
     }
   }

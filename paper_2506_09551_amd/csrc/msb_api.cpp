@@ -3,6 +3,7 @@
 // spectrum.  Host code only; every vector operation runs in the HIP kernels of
 // the k_*.hip files.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -84,6 +85,89 @@ static msb_status make_sysdev(const msb_ctx* ctx, const msb_system& s, double d_
   return MSB_OK;
 }
 
+// ---- apply launch-shape autotuner -------------------------------------------
+// Shapes are tuned per system count up to kTuneMaxSys (the grid and the L2
+// footprint change with it); larger batches share the kTuneMaxSys entry.
+constexpr int kTuneMaxSys = 16;
+static int shape_class(int nsys) { return std::max(1, std::min(nsys, kTuneMaxSys)); }
+
+struct DevBuf {               // scratch device memory released on scope exit
+  void* p = nullptr;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+static ApplyArgs apply_args(const msb_ctx* ctx, const SysDev* sys, int nsys, const void* x, void* v);
+
+// Times every usable shape for (e, shape_class(nsys)) on zero vectors and keeps
+// the fastest in the context.  `table` (optional) receives every measurement.
+static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
+                              std::vector<std::pair<ApplyShape, double>>* table) {
+  const int n = shape_class(nsys);
+  const size_t eb = elem_bytes(e);
+  ApplyShape cand[64];
+  const int nc = apply_candidates(ctx->dn.n, eb, n, ctx->lds_max, cand, 64);
+  if (nc == 0) return fail(MSB_EINVAL, "autotune: no compiled apply shape covers a row");
+  const size_t vb = (size_t)n * ctx->D * eb;
+  DevBuf x, y, ds;
+  if (hipMalloc(&x.p, vb) != hipSuccess || hipMalloc(&y.p, vb) != hipSuccess ||
+      hipMalloc(&ds.p, n * sizeof(SysDev)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MSB_ENOMEM, "autotune: scratch vectors do not fit");
+  }
+  msb_system dflt;
+  std::memset(&dflt, 0, sizeof(dflt));
+  dflt.core_site = -1;
+  dflt.U = std::numeric_limits<double>::quiet_NaN();
+  SysDev hs;
+  msb_status r = make_sysdev(ctx, dflt, 0.0, -1.0, false, hs);
+  if (r != MSB_OK) return r;
+  std::vector<SysDev> h(n, hs);
+  MSB_HIP(hipMemcpyAsync(ds.p, h.data(), n * sizeof(SysDev), hipMemcpyHostToDevice, st));
+  MSB_HIP(hipMemsetAsync(x.p, 0, vb, st));
+  ApplyArgs a = apply_args(ctx, (const SysDev*)ds.p, n, x.p, y.p);
+  hipEvent_t e0, e1;
+  MSB_HIP(hipEventCreate(&e0));
+  MSB_HIP(hipEventCreate(&e1));
+  ApplyShape best{0, 0, 0};
+  double best_ms = 0;
+  hipError_t err = hipSuccess;
+  for (int i = 0; i < nc && err == hipSuccess; ++i) {
+    a.shape = cand[i];
+    for (int w = 0; w < 2 && err == hipSuccess; ++w) err = launch_apply(e, kModePlain, a, st);
+    if (err == hipSuccess) err = hipEventRecord(e0, st);
+    for (int k = 0; k < 5 && err == hipSuccess; ++k) err = launch_apply(e, kModePlain, a, st);
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err != hipSuccess) break;
+    const double m = ms / 5.0;
+    if (table) table->push_back({cand[i], m});
+    if (best.blk == 0 || m < best_ms) {
+      best = cand[i];
+      best_ms = m;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  MSB_HIP(err);
+  ctx->shapes[{(int)e, n}] = best;
+  return MSB_OK;
+}
+
+// Shape to use for an apply of nsys systems: the tuned or pinned one, tuning
+// now if allowed; {0,0,0} (the default shape) if tuning is off or failed.
+static ApplyShape shape_for(msb_ctx* ctx, Elem e, int nsys, hipStream_t st, bool tune) {
+  const auto key = std::make_pair((int)e, shape_class(nsys));
+  auto it = ctx->shapes.find(key);
+  if (it != ctx->shapes.end()) return it->second;
+  if (!tune || tune_shapes(ctx, e, nsys, st, nullptr) != MSB_OK) {
+    (void)hipGetLastError();
+    return ApplyShape{0, 0, 0};
+  }
+  return ctx->shapes[key];
+}
+
 static ApplyArgs apply_args(const msb_ctx* ctx, const SysDev* sys, int nsys, const void* x, void* v) {
   ApplyArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -96,6 +180,7 @@ static ApplyArgs apply_args(const msb_ctx* ctx, const SysDev* sys, int nsys, con
   a.status = nullptr;
   a.status_stride = 0;
   a.D = ctx->D;
+  a.lds_max = ctx->lds_max;
   a.rows_per_xcd = apply_rows_per_xcd(ctx->up.n);
   a.nbx = apply_nbx(ctx->up.n, nsys);
   a.nsys = nsys;
@@ -163,6 +248,17 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   }
   c->D = (int64_t)c->up.n * c->dn.n;
   hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) {
+    int lds = 0;
+    e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+    if (e == hipSuccess && lds > 0) c->lds_max = (size_t)lds;
+  }
+  if (e == hipSuccess && (size_t)c->dn.n * 8 > c->lds_max) {
+    const int c_dn_n = c->dn.n;
+    delete c;
+    return fail(MSB_EINVAL, "msb_create: a down-spin row of " + std::to_string(c_dn_n) +
+                                " states does not fit one workgroup's LDS");
+  }
   auto upload = [&](uint32_t** dst, const std::vector<uint32_t>& src) -> hipError_t {
     const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(uint32_t);
     hipError_t r = hipMalloc(dst, bytes);
@@ -240,7 +336,9 @@ extern "C" msb_status msb_apply(msb_ctx* ctx, const msb_system* sys, int nsys, d
   SysDev* dsys = ar.take<SysDev>(sizeof(SysDev) * nsys);
   MSB_HIP(hipMemcpyAsync(dsys, h.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, st));
   ApplyArgs a = apply_args(ctx, dsys, nsys, x, y);
-  MSB_HIP(launch_apply(prec == MSB_C128 ? Elem::C128 : Elem::C64, kModePlain, a, st));
+  const Elem e = prec == MSB_C128 ? Elem::C128 : Elem::C64;
+  a.shape = shape_for(ctx, e, nsys, st, true);
+  MSB_HIP(launch_apply(e, kModePlain, a, st));
   MSB_HIP(hipStreamSynchronize(st));
   return MSB_OK;
 }
@@ -266,6 +364,7 @@ extern "C" msb_status msb_apply_timed(msb_ctx* ctx, const msb_system* sys, int n
   MSB_HIP(hipMemcpyAsync(dsys, h.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, st));
   ApplyArgs a = apply_args(ctx, dsys, nsys, x, y);
   const Elem e = prec == MSB_C128 ? Elem::C128 : Elem::C64;
+  a.shape = shape_for(ctx, e, nsys, st, true);
   MSB_HIP(launch_apply(e, kModePlain, a, st));     // warm-up
   hipEvent_t e0, e1;
   MSB_HIP(hipEventCreate(&e0));
@@ -310,6 +409,7 @@ extern "C" msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, cons
   SysDev hs;
   msb_status r = make_sysdev(ctx, *sys, 0.0, 0.0, false, hs);
   if (r != MSB_OK) return r;
+  const ApplyShape shp = shape_for(ctx, Elem::R64, 1, st, true);
 
   const size_t part_doubles = std::max<size_t>(
       {(size_t)apply_nbx(ctx->up.n, 1) * 4, (size_t)gram_blocks(D) * (kmax + 1),
@@ -361,6 +461,7 @@ extern "C" msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, cons
   for (k = 0; k < kmax; ++k) {
     double* qk = Q + (size_t)k * D;
     ApplyArgs aa = apply_args(ctx, dsys, 1, qk, w);
+    aa.shape = shp;
     aa.partials = partials;
     aa.red = red;
     MSB_HIP(launch_apply(Elem::R64, kModeHerm, aa, st));
@@ -512,6 +613,11 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
                                 int maxit, msb_prec prec, void* psi, msb_info* info,
                                 const msb_opts* opts, void* stream) {
   (void)hipGetLastError();   // do not report an earlier call's failure
+  using clk = std::chrono::steady_clock;
+  const auto t_entry = clk::now();
+  auto ms_since = [](clk::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  };
   if (!ctx || !sys || !E || !w_in || !psi) return fail(MSB_EINVAL, "msb_solve: null argument");
   if (nsys <= 0) return fail(MSB_EINVAL, "msb_solve: nsys must be positive");
   if (n_shift <= 0 || n_shift > 65535) return fail(MSB_EINVAL, "msb_solve: n_shift out of range");
@@ -546,10 +652,20 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     if (r != MSB_OK) return r;
   }
 
+  // apply launch shapes: tuned on first use, before the workspace is sized
+  hipStream_t ust = (hipStream_t)stream;
+  const bool tune = !(opts && opts->autotune < 0);
+  (void)shape_for(ctx, ev, nsys, ust, tune);
+  if (replace_every > 0) (void)shape_for(ctx, Elem::C128, nsys, ust, tune);
+  if (want_true) (void)shape_for(ctx, ev, (int)std::min<int64_t>((int64_t)nsys * n_shift, kTuneMaxSys), ust, tune);
+
   // ---- plan: batch size and bank capacity from the memory that is free ----
   size_t fr = 0, tot = 0;
   MSB_HIP(hipMemGetInfo(&fr, &tot));
-  const size_t budget = (size_t)((double)(fr + ctx->ws_size) * memfrac);
+  size_t budget = (size_t)((double)(fr + ctx->ws_size) * memfrac);
+  // Keep a workspace that already holds most of the budget: re-allocating a
+  // few hundred GB costs seconds, more than a slightly smaller bank does.
+  if (ctx->ws_size > 0 && (double)ctx->ws_size >= 0.85 * (double)budget) budget = ctx->ws_size;
   auto need_bytes = [&](int B, int cap, bool carry) {
     Carver c(nullptr);
     SolveBufs b;
@@ -579,6 +695,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       const int mid = lo + (hi - lo) / 2;
       if (need_bytes(B, mid, true) <= budget) lo = mid; else hi = mid;
     }
+    // whole multiples of 32 slots, so that small changes of the free memory
+    // give the same plan (and the same workspace) on the next call
+    if (lo > min_cap) lo = std::max(min_cap, lo - lo % 32);
     planB = B; plancap = lo; plancarry = true;
   }
   if (planB == 0) {
@@ -593,7 +712,6 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
 
   // inputs are complete on the caller's stream; the solve runs on the
   // context's own stream (needed for graph capture) and is finished on return
-  hipStream_t ust = (hipStream_t)stream;
   MSB_HIP(hipStreamSynchronize(ust));
   hipStream_t st = ctx->solve_stream;
   const bool use_graph = !(opts && opts->use_graph < 0);
@@ -601,9 +719,12 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   const int B = planB, cap = plancap;
   const int n_stiles = n_list / tile_s;
 
+  const double t_tune_plan = ms_since(t_entry);
+  const auto t_a0 = clk::now();
   Arena ar(ctx);
   ar.reserve(need_bytes(B, cap, plancarry));
   MSB_HIP(ar.commit());
+  const double t_alloc = ms_since(t_a0);
   SolveBufs bf;
   {
     Carver c(ctx->ws);
@@ -655,6 +776,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
 
   msb_status result = MSB_OK;
   int max_iters = 0, total_mvms = 0, brk_iter = -1, flushes = 0, n_replace = 0;
+  ApplyShape seed_shape{0, 0, 0};
   std::vector<SysState> hst(B);
   std::vector<int> hconv((size_t)B * n_shift);
   std::vector<double> hz((size_t)B * n_shift * 2);
@@ -677,6 +799,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     MSB_HIP(launch_cocg_init(ev, ia, st));
 
     ApplyArgs aa = apply_args(ctx, dsys, nb, pvec, vvec);
+    aa.shape = shape_for(ctx, ev, nb, st, tune);
+    seed_shape = apply_shape_used(ev, kModeBilinear, aa);
     aa.aux = bank;
     aa.partials = partials;
     aa.red = red1;
@@ -693,6 +817,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ca.zeta_prev = zeta_prev; ca.conv_iter = conv; ca.tol = tol; ca.maxit = mx;
     ca.alpha_log = alog; ca.beta_log = blog; ca.rnorm_log = rlog;
     ca.xseed = bf.xseed;
+    ca.rep_floor = std::max(tol, kReplaceFloor);
 
     int base = 0;
     bool first_flush = true;
@@ -816,6 +941,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     } graph_guard{&gexec};
 
     ApplyArgs ra = apply_args(ctx, dsys, nb, bf.xseed, bf.wrep);
+    ra.shape = shape_for(ctx, Elem::C128, nb, st, tune);
     ra.status = &dst[0].status;
     ra.status_stride = (int)(sizeof(SysState) / sizeof(int));
     int last_rep = 0;   // iteration of the last residual replacement
@@ -836,15 +962,18 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       }
       if (any_active && replace_every > 0) {
         // active systems advance in step, so one iteration count serves the batch
-        int m_now = 0;
+        int m_now = 0, n_want = 0;
         for (int s = 0; s < nb; ++s)
-          if (hst[s].status == kActive) m_now = std::max(m_now, hst[s].m);
-        if (m_now - last_rep >= replace_every) {
+          if (hst[s].status == kActive) {
+            m_now = std::max(m_now, hst[s].m);
+            if (hst[s].m > 0 && hst[s].rnorm > ca.rep_floor * hst[s].normE) ++n_want;   // as wants_replace()
+          }
+        if (n_want > 0 && m_now - last_rep >= replace_every) {
           // r_m <- E - A_s x_m with x_m and the product in complex128
           MSB_HIP(launch_apply(Elem::C128, kModePlain, ra, st));
           MSB_HIP(launch_cocg_replace(ev, ca, Eb, bf.wrep, st));
           last_rep = m_now;
-          ++n_replace;
+          n_replace += n_want;
         }
       }
       if (any_active) continue;
@@ -898,10 +1027,16 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       if (t.status == kBreakdown) {
         result = MSB_BREAKDOWN;
         if (brk_iter < 0 || t.breakdown_iter < brk_iter) brk_iter = t.breakdown_iter;
-      } else if (t.status == kMaxit && result == MSB_OK) {
+      } else if (t.status == kMaxit && (result == MSB_OK || result == MSB_FLOOR)) {
         result = MSB_NOT_CONVERGED;
+      } else if (t.status == kFloor && result == MSB_OK) {
+        result = MSB_FLOOR;
       }
       if (info && info->sys_iters) info->sys_iters[b0 + s] = t.m;
+      if (info && info->seed_hist && info->hist_len > 0)
+        for (int j = 0; j < info->hist_len; ++j)
+          info->seed_hist[(size_t)(b0 + s) * info->hist_len + j] =
+              (j <= t.m && j <= mx && t.normE > 0) ? hrlog[(size_t)s * (mx + 1) + j] / t.normE : NAN;
       for (int k = 0; k < n_shift; ++k) {
         const size_t idx = (size_t)s * n_shift + k;
         const size_t oidx = (size_t)(b0 + s) * n_shift + k;
@@ -931,6 +1066,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       MSB_HIP(hipMemcpyAsync(bf.tsys, tsys.data(), need_sys, hipMemcpyHostToDevice, st));
       MSB_HIP(hipEventRecord(ev0, st));
       ApplyArgs ta = apply_args(ctx, bf.tsys, nt, psib, nullptr);
+      ta.shape = shape_for(ctx, ev, nt, st, tune);
       ta.aux = Eb;
       ta.aux_div = n_shift;
       ta.partials = bf.tpart;
@@ -965,12 +1101,20 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     info->breakdown_iter = brk_iter;
     info->flushes = flushes;
     info->replacements = n_replace;
+    info->apply_threads = seed_shape.blk;
+    info->apply_ept = seed_shape.ept;
+    info->apply_nv = seed_shape.nv;
     info->t_iter_ms = t_iter;
     info->t_flush_ms = t_flush;
     info->t_true_ms = t_true;
+    info->t_setup_ms = t_tune_plan;
+    info->t_alloc_ms = t_alloc;
+    info->t_wall_ms = ms_since(t_entry);
   }
   if (result == MSB_BREAKDOWN) return fail(MSB_BREAKDOWN, "msb_solve: COCG breakdown (r^T A p or r^T r vanished)");
   if (result == MSB_NOT_CONVERGED) return fail(MSB_NOT_CONVERGED, "msb_solve: iteration cap reached");
+  if (result == MSB_FLOOR)
+    return fail(MSB_FLOOR, "msb_solve: complex64 recurrence reached its attainable accuracy before tol");
   return MSB_OK;
 }
 
@@ -1025,6 +1169,7 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
   SysDev hs;
   msb_status r = make_sysdev(ctx, *sys, 0.0, 0.0, false, hs);
   if (r != MSB_OK) return r;
+  const ApplyShape shp = shape_for(ctx, Elem::C128, n, st, true);
   std::vector<SysDev> hsys(n, hs);
   const int nbx_l = lanczos_nbx(D, n);
   const size_t part_doubles =
@@ -1117,6 +1262,7 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
     for (int j = 0; j < n; ++j) any |= active[j] == 0;
     if (!any) break;
     ApplyArgs aa = apply_args(ctx, dsys, n, q, wv);
+    aa.shape = shp;
     aa.partials = partials;
     aa.red = reda;
     aa.status = dactive;
@@ -1167,4 +1313,50 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
   if (depth_out)
     for (int j = 0; j < n; ++j) depth_out[j] = depth[j];
   return MSB_OK;
+}
+
+// =============================================================================
+// Apply launch-shape autotuner (public entry points).
+extern "C" msb_status msb_autotune(msb_ctx* ctx, int nsys, msb_prec prec, msb_shape* out, int max_out,
+                                   int* n_out, void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx) return fail(MSB_EINVAL, "msb_autotune: null context");
+  if (nsys <= 0) return fail(MSB_EINVAL, "msb_autotune: nsys must be positive");
+  if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_autotune: invalid precision");
+  if (max_out < 0 || (max_out > 0 && !out)) return fail(MSB_EINVAL, "msb_autotune: bad output table");
+  const Elem e = prec == MSB_C128 ? Elem::C128 : Elem::C64;
+  std::vector<std::pair<ApplyShape, double>> table;
+  msb_status r = tune_shapes(ctx, e, nsys, (hipStream_t)stream, &table);
+  if (r != MSB_OK) return r;
+  const int n = std::min<int>((int)table.size(), max_out);
+  for (int i = 0; i < n; ++i) {
+    out[i].threads = table[i].first.blk;
+    out[i].elems_per_thread = table[i].first.ept;
+    out[i].vectors = table[i].first.nv;
+    out[i].ms = table[i].second;
+  }
+  if (n_out) *n_out = (int)table.size();
+  return MSB_OK;
+}
+
+extern "C" msb_status msb_set_shape(msb_ctx* ctx, int nsys, msb_prec prec, const msb_shape* shape) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx || !shape) return fail(MSB_EINVAL, "msb_set_shape: null argument");
+  if (nsys <= 0) return fail(MSB_EINVAL, "msb_set_shape: nsys must be positive");
+  if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_set_shape: invalid precision");
+  const Elem e = prec == MSB_C128 ? Elem::C128 : Elem::C64;
+  const auto key = std::make_pair((int)e, shape_class(nsys));
+  if (shape->threads == 0) {
+    ctx->shapes.erase(key);
+    return MSB_OK;
+  }
+  ApplyShape cand[64];
+  const int nc = apply_candidates(ctx->dn.n, elem_bytes(e), shape_class(nsys), ctx->lds_max, cand, 64);
+  for (int i = 0; i < nc; ++i)
+    if (cand[i].blk == shape->threads && cand[i].ept == shape->elems_per_thread &&
+        cand[i].nv == shape->vectors) {
+      ctx->shapes[key] = cand[i];
+      return MSB_OK;
+    }
+  return fail(MSB_EINVAL, "msb_set_shape: shape not compiled or not usable for this row length");
 }

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -81,6 +82,12 @@ enum ApplyMode : int {
   kModeResid = 3        // no v;     partial (sum |aux - A x|^2)           -- true residual
 };
 
+// Launch shape of the apply kernel: threads per workgroup, elements per
+// thread, vectors (systems) per workgroup.  blk == 0 selects the default.
+struct ApplyShape {
+  int blk, ept, nv;
+};
+
 struct ApplyArgs {
   TablesDev T;
   const SysDev* sys;          // [nsys]
@@ -99,7 +106,9 @@ struct ApplyArgs {
   int nbx;                    // workgroups along the rows (XCD-padded row count)
   int rows_per_xcd;
   int nsys;
-  int nvec;                   // vectors (systems) per workgroup
+  int nvec;                   // vectors (systems) per workgroup (set by the launcher)
+  ApplyShape shape;           // requested launch shape ({0,0,0} = default)
+  size_t lds_max;             // LDS bytes one workgroup may use (device limit)
 };
 
 enum class Elem { R64, C128, C64 };   // real float64, complex128, complex64 storage
@@ -107,6 +116,11 @@ enum class Elem { R64, C128, C64 };   // real float64, complex128, complex64 sto
 hipError_t launch_apply(Elem e, int mode, const ApplyArgs& a, hipStream_t st);
 int apply_nbx(int n_up, int nsys);  // grid.x (workgroups per system) for the apply kernel
 int apply_rows_per_xcd(int n_up);
+// Compiled shapes usable for rows of nd elements (row_bytes per element of the
+// staged row) and nsys systems; returns how many were written to out.
+int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, ApplyShape* out, int max_out);
+// The shape launch_apply(e, mode, a) will use.
+ApplyShape apply_shape_used(Elem e, int mode, const ApplyArgs& a);
 
 // ---- COCG seed step kernels (k_cocg.hip) -----------------------------------
 // Per-system state.  status codes:
@@ -114,7 +128,18 @@ int apply_rows_per_xcd(int n_up);
 // so a chunk boundary falls between the bookkeeping of iteration m-1 and the
 // p-update of iteration m (where the residual may be replaced).
 // kPaused: the bank has no slot for the next residual; the host flushes it.
-enum : int { kActive = 0, kDone = 1, kBreakdown = 2, kMaxit = 3, kPaused = 4 };
+// kFloor: complex64 attainable accuracy reached, seen at a residual
+// replacement either as a recurrence residual more than kFloorGap times below
+// the true one, or as kStallMax replacements in a row where the recurrence
+// claimed to have cut the best true residual by kStall but the true residual
+// did not follow.
+enum : int { kActive = 0, kDone = 1, kBreakdown = 2, kMaxit = 3, kPaused = 4, kFloor = 5 };
+constexpr double kFloorGap = 10.0;
+// Residual replacement stops once |r_m| <= max(tol, kReplaceFloor) |E|: the FP64
+// product E - A x cannot resolve much less (about 1e-15 relative was measured).
+constexpr double kReplaceFloor = 1e-12;
+constexpr double kStall = 0.5;
+constexpr int kStallMax = 3;
 struct SysState {
   double rho_re, rho_im;        // rho_m = r_m^T r_m
   double ap_re, ap_im;          // alpha_{m-1}
@@ -127,6 +152,9 @@ struct SysState {
   int status;
   int n_active;                 // shifts still iterating
   int breakdown_iter;
+  double rbest;                 // smallest true residual seen at a replacement (|E| at start)
+  int n_stall;                  // replacements in a row that exposed a false improvement
+  int pad;
 };
 
 struct CocgArgs {
@@ -154,6 +182,7 @@ struct CocgArgs {
   double* beta_log;             // [nsys][maxit][2]
   double* rnorm_log;            // [nsys][maxit+1]
   double* xseed;                // optional [nsys][D] complex128 seed solution (x += alpha p)
+  double rep_floor;             // residual replacement only while |r_m| > rep_floor |E|
 };
 
 hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st);   // r_{m+1} = r_m - alpha v
@@ -284,6 +313,7 @@ struct msb_ctx {
   double U = 0;
   msb::SpinTable up, dn;
   int device = 0;
+  size_t lds_max = 64 * 1024;         // LDS per workgroup (queried from the device)
   // device tables
   uint32_t* d_conf_up = nullptr;
   uint32_t* d_conf_dn = nullptr;
@@ -298,6 +328,8 @@ struct msb_ctx {
   // growable workspace
   void* ws = nullptr;
   size_t ws_size = 0;
+  // apply launch shapes chosen by the autotuner (or pinned), key (Elem, min(nsys, 4))
+  std::map<std::pair<int, int>, msb::ApplyShape> shapes;
   msb::TablesDev tables() const {
     msb::TablesDev t;
     t.conf_up = d_conf_up; t.conf_dn = d_conf_dn;

@@ -87,3 +87,56 @@ def test_apply_full_size_sampled_rows(gpu, wl_name):
         assert err <= tol, f"{wl_name}: sampled rel err {err:.3e}"
     finally:
         msb.msb_destroy(ctx)
+
+
+WIDE = {
+    # long down-spin rows (n_dn = 924, 3432, 4368) with few up-spin rows,
+    # so the 1024-thread shapes are exercised at sizes the oracle builds quickly
+    "chain12_2_6": dict(L=12, nu=2, nd=6, bonds=W.chain_bonds(12, 1.0), U=8.0),
+    "chain14_1_7_tp": dict(L=14, nu=1, nd=7, bonds=W.chain_bonds(14, 1.0, -0.2), U=8.0),
+    "square4x4_1_5": dict(L=16, nu=1, nd=5, bonds=W.square_bonds(4, 4, 1.0, -0.25), U=8.0),
+    "chain8": dict(L=8, nu=4, nd=4, bonds=W.chain_bonds(8, 1.0), U=8.0),
+}
+
+
+@pytest.mark.parametrize("name", list(WIDE))
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_every_apply_shape_matches_oracle(gpu, name, prec):
+    """Every launch shape the autotuner may pick gives the oracle's H x (1, 3
+    and 4 systems per call: full and ragged system groups)."""
+    import torch
+    msb = gpu
+    m = WIDE[name]
+    ctx = msb.msb_create(m["L"], m["nu"], m["nd"], m["bonds"], m["U"])
+    p = msb.MSB_C128 if prec == "c128" else msb.MSB_C64
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    try:
+        D = msb.msb_dim(ctx)
+        all_sys = [msb.make_system(core_site=j % m["L"], Uc=-4.0 + 0.5 * j, E_G=-3.0 + j, Gamma=1.0 + 0.1 * j)
+                   for j in range(4)]
+        shift = 0.25
+        x = np.stack([W.random_complex(D, seed=300 + s) for s in range(4)])
+        xr = x.astype(np.complex64).astype(np.complex128) if prec == "c64" else x
+        expect = np.stack([oracle_H(m, core_site=s.core_site, Uc=s.Uc) @ xr[j]
+                           - (s.E_G + shift + 1j * s.Gamma) * xr[j] for j, s in enumerate(all_sys)])
+        tol = 1e-14 if prec == "c128" else 2e-6
+        seen = set()
+        for nsys in (1, 3, 4):
+            table = msb.msb_autotune(ctx, nsys, p)
+            assert table and all(t[3] > 0 for t in table)
+            for shape in table:
+                msb.msb_set_shape(ctx, nsys, p, shape)
+                xt = torch.from_numpy(x[:nsys]).to(dt).cuda().contiguous()
+                yt = torch.full_like(xt, float("nan"))
+                msb.msb_apply(ctx, all_sys[:nsys], shift, p, xt, yt)
+                torch.cuda.synchronize()
+                y = yt.cpu().numpy().astype(np.complex128)
+                err = np.max(np.abs(y - expect[:nsys])) / np.max(np.abs(expect[:nsys]))
+                assert err <= tol, f"{name} {prec} nsys={nsys} shape={shape[:3]}: {err:.3e}"
+                seen.add(shape[:3])
+            msb.msb_set_shape(ctx, nsys, p, None)
+        assert len(seen) >= 2
+        with pytest.raises(msb.MsbError):
+            msb.msb_set_shape(ctx, 1, p, (512, 3, 1))      # not a compiled shape
+    finally:
+        msb.msb_destroy(ctx)

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _run(msb, ctx, systems, E, w, tol, maxit, prec, seed_shift=0.0, opts=None, want_true=True,
-         raise_on_fail=True):
+         raise_on_fail=True, hist_len=0):
     import torch
     D = msb.msb_dim(ctx)
     n = len(systems)
@@ -23,7 +23,8 @@ def _run(msb, ctx, systems, E, w, tol, maxit, prec, seed_shift=0.0, opts=None, w
     dt = torch.complex128 if prec == msb.MSB_C128 else torch.complex64
     psi = torch.empty(n, len(w), D, dtype=dt, device="cuda")
     st, info = msb.msb_solve(ctx, systems, Et, w, seed_shift, tol, maxit, prec, psi,
-                             want_true=want_true, opts=opts, raise_on_fail=raise_on_fail)
+                             want_true=want_true, opts=opts, raise_on_fail=raise_on_fail,
+                             hist_len=hist_len)
     torch.cuda.synchronize()
     return st, info, psi.cpu().numpy().astype(np.complex128)
 
@@ -136,13 +137,18 @@ def test_c64_residual_replacement(tiny, opts):
     ref = osolve.direct_solve(oracle_H(m, core_site=0, Uc=wl.Uc), E, E_G, wl.Gamma, wl.w_in,
                               method="eig")
     sysd = msb.make_system(core_site=0, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma)
-    st, info, psi = _run(msb, ctx, [sysd], E, wl.w_in, 1e-6, 3000, msb.MSB_C64, opts=opts)
+    st, info, psi = _run(msb, ctx, [sysd], E, wl.w_in, 1e-6, 3000, msb.MSB_C64, opts=opts,
+                         hist_len=3001)
     # replacement happens at the first chunk boundary at least `period`
-    # iterations after the previous one: at most period + chunk apart
+    # iterations after the previous one (at most period + chunk apart), while
+    # the seed residual is above tol |E|
     period = (opts or {}).get("replace_every", 50)
     chunk = (opts or {}).get("chunk", min(period, 64))
-    assert info["replacements"] >= max(info["iters"] // (period + chunk) - 1, 1)
-    assert info["replacements"] <= info["iters"] // period
+    hist = info["seed_hist"][0]
+    m_seed = int(np.argmax(hist <= 1e-6))
+    assert 0 < m_seed < info["iters"]
+    assert info["replacements"] >= max(m_seed // (period + chunk) - 1, 1)
+    assert info["replacements"] <= m_seed // period + 1
     err = _rel(psi[0], ref)
     assert err <= 5e-5, f"c64 rel err {err:.3e}"
     # after a replacement the recurrence residual tracks the true one
@@ -151,6 +157,27 @@ def test_c64_residual_replacement(tiny, opts):
                             opts={"replace_every": -1})
     assert info0["replacements"] == 0
     assert _rel(psi0[0], ref) <= 5e-5
+
+
+def test_c64_replacement_tight_tol(tiny):
+    """tol far below complex64 resolution: replacements pull the seed down to
+    FP64 accuracy (the replaced residual is the FP64 true one), then stop, and
+    the shifted systems converge on the unperturbed recurrence as in the plain
+    form; Psi keeps complex64 accuracy."""
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E = W.random_vector(D, 4).astype(np.complex128)
+    E_G = -2.6661474201323485
+    ref = osolve.direct_solve(oracle_H(m, core_site=0, Uc=wl.Uc), E, E_G, wl.Gamma, wl.w_in,
+                              method="eig")
+    sysd = msb.make_system(core_site=0, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma)
+    st, info, psi = _run(msb, ctx, [sysd], E, wl.w_in, 1e-13, 3000, msb.MSB_C64)
+    st0, info0, _ = _run(msb, ctx, [sysd], E, wl.w_in, 1e-13, 3000, msb.MSB_C64,
+                         opts={"replace_every": -1})
+    assert st == msb.MSB_OK and info["replacements"] >= 4
+    assert info["iters"] <= 1.3 * info0["iters"]
+    assert _rel(psi[0], ref) <= 5e-5
+    assert np.max(info["resid_true"]) <= 2e-5
 
 
 def test_breakdown_reported(tiny):
