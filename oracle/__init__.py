@@ -18,10 +18,12 @@ paper's definitions in float64 / complex128 with NumPy and SciPy:
   (Algorithm 1) in the corrected reading.
 * ``spectrum`` -- the Kramers-Heisenberg intensity of Eq. ``kramers1`` by the
   Lehmann sum, by a Lanczos continued fraction, and by correction vectors.
-* ``mlp`` -- float64 forward/backward of the surrogate network (learned form).
+* ``mlp`` -- float64 forward/backward, Adam and the ensemble fallback rule of
+  the surrogate network of the learned form (textbook definitions; the paper
+  has no network), with an option that applies the GPU's bfloat16 roundings.
 
 Parity status of each function is stated in its docstring; every function is
 pinned by ``tests/test_oracle_*.py`` against closed forms, invariants or brute
 force, except where a docstring says "parity unpinned".
 """
-from . import hubbard, groundstate, solve, spectrum  # noqa: F401
+from . import hubbard, groundstate, solve, spectrum, mlp  # noqa: F401
