@@ -258,6 +258,52 @@ msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const void* phi, in
                         const double* w, int n_w, double eta, int lanczos_max,
                         double cf_tol, double* I, int* depth, void* stream);
 
+/* ---- learned form: ensemble surrogate I(U, t', U_c, Gamma, w_in, w) --------
+ * Not part of the paper's method: a regression network beside the solver,
+ * trained on spectra the solver produced, with the solver as fallback.
+ * Each member is a perceptron 6 -> 512 -> 512 -> 512 -> 1 with GELU
+ * (x Phi(x), exact normal CDF) between the layers.  Inputs are normalised
+ * as (x - in_shift) * in_scale feature by feature; the network output is
+ * out_scale * I.  The two 512 x 512 layers run on bfloat16 matrix cores with
+ * float32 accumulation; their operands (weights, activations, back-propagated
+ * gradients) are rounded to bfloat16, all other arithmetic and the master
+ * weights are float32.  Parameters of one member are a flat float32 vector of
+ * msb_mlp_num_params() values: W1[6][512] b1[512] W2[512][512] b2[512]
+ * W3[512][512] b3[512] W4[512] b4 (weights [in][out]).  Device arrays are
+ * caller-owned; every call is blocking. */
+typedef struct msb_mlp msb_mlp;
+int64_t msb_mlp_num_params(void);
+/* members in [1, 64]; parameters start at zero (set them before use).
+ * Errors: MSB_EINVAL for bad arguments, MSB_EHIP on allocation failure. */
+msb_status msb_mlp_create(int members, const double in_shift[6], const double in_scale[6],
+                          double out_scale, msb_mlp** out);
+void msb_mlp_destroy(msb_mlp* mlp);
+/* Host float32 [msb_mlp_num_params()] in/out; set also clears Adam's moments
+ * and step count. */
+msb_status msb_mlp_set_params(msb_mlp* mlp, int member, const float* params);
+msb_status msb_mlp_get_params(const msb_mlp* mlp, int member, float* params);
+/* Loss mean((out - out_scale T)^2) over n points and its gradient (host float32
+ * [msb_mlp_num_params()]) for one member.  X: device float32 [n][6]; T: device
+ * float32 [n]; 1 <= n <= 131072. */
+msb_status msb_mlp_grad(msb_mlp* mlp, int member, const float* X, const float* T, int n,
+                        double* loss, float* grad);
+/* `steps` Adam steps (lr; beta 0.9, 0.999; eps 1e-8) of every member at once.
+ * Step s of member m uses the points perm[m][s * batch ... (s + 1) * batch)
+ * (device int32 [members][steps * batch], indices < n_points).  batch: a
+ * multiple of 128 up to 131072.  loss_hist (optional host [members][steps])
+ * receives each step's loss.  One step is captured in a hipGraph and replayed. */
+msb_status msb_mlp_train(msb_mlp* mlp, const float* X, const float* T, int64_t n_points,
+                         const int* perm, int batch, int steps, double lr, double* loss_hist,
+                         void* stream);
+/* Ensemble mean and standard deviation (over members, population) of I at n
+ * points.  X: device float32 [n][6]; mean, sd: device float32 [n]. */
+msb_status msb_mlp_predict(msb_mlp* mlp, const float* X, int64_t n, float* mean, float* sd,
+                           void* stream);
+/* Solver fallback rule (host arrays): row r of an [n_rows][n_cols] (w_in, w)
+ * grid falls back when sd exceeds frac * max(mean) anywhere in the row. */
+msb_status msb_mlp_fallback(const float* mean, const float* sd, int n_rows, int n_cols, double frac,
+                            int* row_mask);
+
 #ifdef __cplusplus
 }
 #endif

@@ -114,6 +114,24 @@ def lib():
         L.msb_autotune.restype = c_int
         L.msb_set_shape.argtypes = [c_void_p, c_int, c_int, POINTER(msb_shape)]
         L.msb_set_shape.restype = c_int
+        L.msb_mlp_num_params.restype = c_int64
+        L.msb_mlp_create.argtypes = [c_int, POINTER(c_double), POINTER(c_double), c_double, POINTER(c_void_p)]
+        L.msb_mlp_create.restype = c_int
+        L.msb_mlp_destroy.argtypes = [c_void_p]
+        L.msb_mlp_destroy.restype = None
+        L.msb_mlp_set_params.argtypes = [c_void_p, c_int, c_void_p]
+        L.msb_mlp_set_params.restype = c_int
+        L.msb_mlp_get_params.argtypes = [c_void_p, c_int, c_void_p]
+        L.msb_mlp_get_params.restype = c_int
+        L.msb_mlp_grad.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_int, POINTER(c_double), c_void_p]
+        L.msb_mlp_grad.restype = c_int
+        L.msb_mlp_train.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int, c_int, c_double,
+                                    c_void_p, c_void_p]
+        L.msb_mlp_train.restype = c_int
+        L.msb_mlp_predict.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+        L.msb_mlp_predict.restype = c_int
+        L.msb_mlp_fallback.argtypes = [c_void_p, c_void_p, c_int, c_int, c_double, c_void_p]
+        L.msb_mlp_fallback.restype = c_int
         _lib = L
     return _lib
 
@@ -122,7 +140,9 @@ def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["msb_create", "msb_destroy", "msb_dim", "msb_sector_info", "msb_last_error",
             "msb_device_ok", "msb_apply", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
-            "msb_combine", "msb_spectrum", "msb_autotune", "msb_set_shape"]
+            "msb_combine", "msb_spectrum", "msb_autotune", "msb_set_shape",
+            "msb_mlp_num_params", "msb_mlp_create", "msb_mlp_destroy", "msb_mlp_set_params",
+            "msb_mlp_get_params", "msb_mlp_grad", "msb_mlp_train", "msb_mlp_predict", "msb_mlp_fallback"]
 
 
 def _check(status: int):
@@ -363,3 +383,84 @@ def msb_set_shape(ctx, nsys: int, prec: int, shape):
     if shape is not None:
         sh.threads, sh.elems_per_thread, sh.vectors = (int(v) for v in shape[:3])
     _check(lib().msb_set_shape(ctx, int(nsys), int(prec), ctypes.byref(sh)))
+
+
+# ---- learned form: ensemble surrogate --------------------------------------
+
+def msb_mlp_num_params() -> int:
+    return int(lib().msb_mlp_num_params())
+
+
+def msb_mlp_create(members: int, in_shift, in_scale, out_scale: float) -> c_void_p:
+    sh = (c_double * 6)(*[float(v) for v in in_shift])
+    sc = (c_double * 6)(*[float(v) for v in in_scale])
+    h = c_void_p()
+    _check(lib().msb_mlp_create(int(members), sh, sc, float(out_scale), ctypes.byref(h)))
+    return h
+
+
+def msb_mlp_destroy(mlp):
+    lib().msb_mlp_destroy(mlp)
+
+
+def msb_mlp_set_params(mlp, member: int, params):
+    """params: host float32 array of msb_mlp_num_params() values."""
+    import numpy as np
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    if p.size != msb_mlp_num_params():
+        raise ValueError("wrong parameter count")
+    _check(lib().msb_mlp_set_params(mlp, int(member), p.ctypes.data_as(c_void_p)))
+
+
+def msb_mlp_get_params(mlp, member: int):
+    import numpy as np
+    p = np.empty(msb_mlp_num_params(), dtype=np.float32)
+    _check(lib().msb_mlp_get_params(mlp, int(member), p.ctypes.data_as(c_void_p)))
+    return p
+
+
+def msb_mlp_grad(mlp, member: int, X, T):
+    """(loss, grad) of one member on device float32 X [n][6], T [n]."""
+    import numpy as np
+    import torch
+    n = T.numel()
+    _stream_ptr(None)
+    g = np.empty(msb_mlp_num_params(), dtype=np.float32)
+    loss = c_double()
+    _check(lib().msb_mlp_grad(mlp, int(member), _ptr(X, torch.float32, n * 6, "X"), _ptr(T, torch.float32, n, "T"),
+                              int(n), ctypes.byref(loss), g.ctypes.data_as(c_void_p)))
+    return loss.value, g
+
+
+def msb_mlp_train(mlp, X, T, perm, batch: int, steps: int, lr: float, members: int):
+    """Adam steps on device X [n][6], T [n] with device int32 perm [members][steps*batch];
+    returns the loss history [members][steps]."""
+    import numpy as np
+    import torch
+    n = T.numel()
+    hist = np.empty((members, steps), dtype=np.float64)
+    _check(lib().msb_mlp_train(mlp, _ptr(X, torch.float32, n * 6, "X"), _ptr(T, torch.float32, n, "T"), int(n),
+                               _ptr(perm, torch.int32, members * steps * batch, "perm"), int(batch), int(steps),
+                               float(lr), hist.ctypes.data_as(c_void_p), _stream_ptr(None)))
+    return hist
+
+
+def msb_mlp_predict(mlp, X, mean, sd):
+    """Ensemble mean / standard deviation at device X [n][6] into device float32 [n] tensors."""
+    import torch
+    n = mean.numel()
+    _check(lib().msb_mlp_predict(mlp, _ptr(X, torch.float32, n * 6, "X"), int(n), _ptr(mean, torch.float32, n, "mean"),
+                                 _ptr(sd, torch.float32, n, "sd"), _stream_ptr(None)))
+
+
+def msb_mlp_fallback(mean, sd, frac: float):
+    """Row mask of a host [n_rows][n_cols] prediction grid (numpy float32)."""
+    import numpy as np
+    mu = np.ascontiguousarray(np.asarray(mean, dtype=np.float32))
+    s = np.ascontiguousarray(np.asarray(sd, dtype=np.float32))
+    if mu.ndim != 2 or mu.shape != s.shape:
+        raise ValueError("mean and sd must be matching 2-D grids")
+    mask = np.empty(mu.shape[0], dtype=np.int32)
+    _check(lib().msb_mlp_fallback(mu.ctypes.data_as(c_void_p), s.ctypes.data_as(c_void_p), mu.shape[0], mu.shape[1],
+                                  float(frac), mask.ctypes.data_as(c_void_p)))
+    return mask.astype(bool)

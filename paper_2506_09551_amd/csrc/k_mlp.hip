@@ -1,0 +1,394 @@
+// Surrogate network of the learned form: an ensemble of multilayer
+// perceptrons 6 -> 512 -> 512 -> 512 -> 1 with GELU, trained with Adam.
+//
+// Precision: the two 512 x 512 layers (forward, input-gradient and
+// weight-gradient products) run on the bfloat16 matrix cores with float32
+// accumulation (gfx950 v_mfma_f32_32x32x16_bf16); the activations and the
+// back-propagated gradients that feed those products are stored in
+// bfloat16, everything else (first and last layer, biases, loss, Adam, the
+// master weights) is float32.  Every member of the ensemble is one
+// blockIdx.z slice of the same launches.
+#include "k_common.h"
+#include "mlp_internal.h"
+
+namespace msb {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// ---- matrix-core product --------------------------------------------------
+// C[M][N] = sum_k A(m,k) B(k,n) with
+//   A(m,k) = A[m lda + k] (TA = false) or A[k lda + m] (TA = true),
+//   B(k,n) = B[k ldb + n] (TB = false) or B[n ldb + k] (TB = true).
+// A 256-thread workgroup computes a 128 x 128 tile; each wave a 64 x 64
+// quarter as 2 x 2 blocks of 32 x 32 matrix-core products; K advances 32 at
+// a time through LDS tiles stored k-contiguous ([m][k] and [n][k]).
+constexpr int kGM = 128, kGN = 128, kGK = 32, kGPad = 8;
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  __shared__ __align__(16) __bf16 sa[kGM][kGK + kGPad];
+  __shared__ __align__(16) __bf16 sb[kGN][kGK + kGPad];
+  const int mem = blockIdx.z;
+  const __bf16* A = g.A + (int64_t)mem * g.sA;
+  const __bf16* B = g.B + (int64_t)mem * g.sB;
+  const int m0 = blockIdx.y * kGM, n0 = blockIdx.x * kGN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  for (int k0 = 0; k0 < g.K; k0 += kGK) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int idx = tid + it * 256;
+      if constexpr (!TA) {          // rows of A are k-contiguous
+        const int r = idx >> 2, c = (idx & 3) * 8;
+        *reinterpret_cast<bf16x8*>(&sa[r][c]) =
+            *reinterpret_cast<const bf16x8*>(A + (int64_t)(m0 + r) * g.lda + k0 + c);
+      } else {                      // columns of A are m-contiguous: transpose into LDS
+        const int kk = idx >> 4, c = (idx & 15) * 8;
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(A + (int64_t)(k0 + kk) * g.lda + m0 + c);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) sa[c + t][kk] = v[t];
+      }
+      if constexpr (TB) {           // B(k,n) = B[n ldb + k]: k-contiguous
+        const int r = idx >> 2, c = (idx & 3) * 8;
+        *reinterpret_cast<bf16x8*>(&sb[r][c]) =
+            *reinterpret_cast<const bf16x8*>(B + (int64_t)(n0 + r) * g.ldb + k0 + c);
+      } else {                      // B(k,n) = B[k ldb + n]: n-contiguous, transpose
+        const int kk = idx >> 4, c = (idx & 15) * 8;
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(B + (int64_t)(k0 + kk) * g.ldb + n0 + c);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) sb[c + t][kk] = v[t];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 16) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf16x8*>(&sa[wm + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf16x8*>(&sb[wn + j * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // accumulator lane layout: column lane % 32, row 8 (r / 4) + 4 (lane / 32) + r % 4
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = n0 + wn + j * 32 + (lane & 31);
+        const float v = acc[i][j][r];
+        if constexpr (EPI == kEpiFwd) {
+          const float z = v + g.bias[(int64_t)mem * g.sBias + col];
+          g.C[(int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = z;
+          g.H[(int64_t)mem * g.sH + (int64_t)row * g.ldh + col] = (__bf16)gelu_f(z);
+        } else if constexpr (EPI == kEpiDh) {
+          const float zp = g.Zp[(int64_t)mem * g.sZ + (int64_t)row * g.ldz + col];
+          g.H[(int64_t)mem * g.sH + (int64_t)row * g.ldh + col] = (__bf16)(v * gelu_grad_f(zp));
+        } else {
+          g.C[(int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = v;
+        }
+      }
+}
+
+hipError_t launch_gemm(bool ta, bool tb, int epi, const GemmArgs& g, int members, hipStream_t st) {
+  if (g.M % kGM || g.N % kGN || g.K % kGK) return hipErrorInvalidValue;
+  dim3 grid(g.N / kGN, g.M / kGM, members);
+#define MSB_GEMM(TA_, TB_, E_)                                                        \
+  if (ta == TA_ && tb == TB_ && epi == E_) {                                          \
+    hipLaunchKernelGGL((k_gemm<TA_, TB_, E_>), grid, dim3(256), 0, st, g);           \
+    return hipGetLastError();                                                         \
+  }
+  MSB_GEMM(false, false, kEpiFwd)      // z = h W + b (forward)
+  MSB_GEMM(false, true, kEpiDh)        // dz = (dz' W^T) * gelu'(z) (input gradient)
+  MSB_GEMM(true, false, kEpiStore)     // dW = h^T dz (weight gradient)
+#undef MSB_GEMM
+  return hipErrorInvalidValue;
+}
+
+// ---- first layer: z1 = ((x - shift) * scale) W1 + b1, h1 = gelu(z1) ---------
+// Row b of the batch is point perm[b] (perm == nullptr: point b).
+__global__ __launch_bounds__(256) void k_layer1_fwd(MlpFwdArgs a) {
+  const int mem = blockIdx.z;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;   // over batch * 512
+  if (i >= (int64_t)a.batch * kMlpH) return;
+  const int b = (int)(i / kMlpH), n = (int)(i % kMlpH);
+  const float* W1 = a.params + (int64_t)mem * a.pstride + kOffW1;
+  float z = a.params[(int64_t)mem * a.pstride + kOffB1 + n];
+  if (b < a.valid) {            // padding rows see zero inputs
+    const int* perm = a.perm ? a.perm + (int64_t)mem * a.perm_stride + (int64_t)(*a.step) * a.batch : nullptr;
+    const int64_t pt = a.base + (perm ? perm[b] : b);
+#pragma unroll
+    for (int k = 0; k < kMlpIn; ++k) z += (a.X[pt * kMlpIn + k] - a.in_shift[k]) * a.in_scale[k] * W1[k * kMlpH + n];
+  }
+  a.z1[(int64_t)mem * a.act_stride + i] = z;
+  a.h1[(int64_t)mem * a.act_stride + i] = (__bf16)gelu_f(z);
+}
+
+// ---- output layer: y = h3 W4 + b4; loss gradient g = 2 (y - t) / batch ------
+// One wave per batch row; per-workgroup loss partials (deterministic sum).
+__global__ __launch_bounds__(256) void k_layer4_fwd(MlpFwdArgs a) {
+  const int mem = blockIdx.z;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 4 + wave;
+  const float* W4 = a.params + (int64_t)mem * a.pstride + kOffW4;
+  float s = 0.0f;
+  if (b < a.batch) {
+    const __bf16* h = a.h3 + (int64_t)mem * a.act_stride + (int64_t)b * kMlpH;
+#pragma unroll
+    for (int t = 0; t < kMlpH / 64; ++t) s += (float)h[lane + 64 * t] * W4[lane + 64 * t];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  __shared__ double part[4];
+  double l2 = 0.0;
+  if (b < a.batch && lane == 0) {
+    const float y = s + a.params[(int64_t)mem * a.pstride + kOffB4];
+    a.y[(int64_t)mem * a.y_stride + b] = y;
+    if (a.T) {
+      float gv = 0.0f;
+      if (b < a.valid) {
+        const int* perm = a.perm ? a.perm + (int64_t)mem * a.perm_stride + (int64_t)(*a.step) * a.batch : nullptr;
+        const int64_t pt = a.base + (perm ? perm[b] : b);
+        const float d = y - a.out_scale * a.T[pt];
+        gv = 2.0f * d / (float)a.valid;
+        l2 = (double)d * (double)d;
+      }
+      a.g[(int64_t)mem * a.y_stride + b] = gv;
+    }
+  }
+  if (lane == 0) part[wave] = l2;
+  __syncthreads();
+  if (threadIdx.x == 0 && a.loss_part)
+    a.loss_part[(int64_t)mem * gridDim.x + blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+__global__ __launch_bounds__(64) void k_loss_record(const double* loss_part, int nparts, const int* step,
+                                                    double* hist, int64_t hist_stride, int valid) {
+  const int mem = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += loss_part[(int64_t)mem * nparts + p];
+  hist[(int64_t)mem * hist_stride + *step] = s / valid;
+}
+
+hipError_t launch_loss_record(const MlpFwdArgs& a, double* loss_hist, int64_t hist_stride, int members,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_loss_record, dim3(members), dim3(64), 0, st, a.loss_part, (a.batch + 3) / 4, a.step,
+                     loss_hist, hist_stride, a.valid);
+  return hipGetLastError();
+}
+
+// ---- output-layer backward: dz3 = g W4^T * gelu'(z3) (bf16) ----------------
+__global__ __launch_bounds__(256) void k_layer4_bwd(MlpFwdArgs a) {
+  const int mem = blockIdx.z;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)a.batch * kMlpH) return;
+  const int b = (int)(i / kMlpH), n = (int)(i % kMlpH);
+  const float gv = a.g[(int64_t)mem * a.y_stride + b];
+  const float w = a.params[(int64_t)mem * a.pstride + kOffW4 + n];
+  const float zp = a.z3[(int64_t)mem * a.act_stride + i];
+  a.dz3[(int64_t)mem * a.act_stride + i] = (__bf16)(gv * w * gelu_grad_f(zp));
+}
+
+// ---- column sums over the batch --------------------------------------------
+// out[n] = sum_b w_b * src(b, n) for the bias gradients (src = dz, bf16), the
+// output-layer weight gradient (src = h3, weights g) and its bias (src = g).
+// Each workgroup sums a 256-column strip over a slice of rows; a second
+// launch adds the slices in order.
+__global__ __launch_bounds__(256) void k_colsum_part(ColSumArgs a) {
+  const int mem = blockIdx.z;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= a.ncols) return;
+  const int r0 = blockIdx.y * a.rows_per_part, r1 = min(a.nrows, r0 + a.rows_per_part);
+  float s = 0.0f;
+  for (int b = r0; b < r1; ++b) {
+    float v = a.src_bf16 ? (float)a.src_bf16[(int64_t)mem * a.src_stride + (int64_t)b * a.ld + n]
+                         : a.src_f32[(int64_t)mem * a.src_stride + (int64_t)b * a.ld + n];
+    if (a.wgt) v *= a.wgt[(int64_t)mem * a.wgt_stride + b];
+    s += v;
+  }
+  a.part[((int64_t)mem * gridDim.y + blockIdx.y) * a.ncols + n] = s;
+}
+
+__global__ __launch_bounds__(256) void k_colsum_fin(ColSumArgs a, int nparts) {
+  const int mem = blockIdx.z;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= a.ncols) return;
+  float s = 0.0f;
+  for (int p = 0; p < nparts; ++p) s += a.part[((int64_t)mem * nparts + p) * a.ncols + n];
+  a.out[(int64_t)mem * a.out_stride + n] = s;
+}
+
+hipError_t launch_colsum(const ColSumArgs& a, int members, hipStream_t st) {
+  const int nparts = (a.nrows + a.rows_per_part - 1) / a.rows_per_part;
+  if (nparts > a.max_parts) return hipErrorInvalidValue;
+  dim3 grid((a.ncols + 255) / 256, nparts, members);
+  hipLaunchKernelGGL(k_colsum_part, grid, dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum_fin, dim3((a.ncols + 255) / 256, 1, members), dim3(256), 0, st, a, nparts);
+  return hipGetLastError();
+}
+
+// ---- first-layer weight gradient: dW1[k][n] = sum_b xn(b, k) dz1(b, n) -------
+__global__ __launch_bounds__(256) void k_layer1_bwd_part(MlpFwdArgs a, float* part, int rows_per_part) {
+  const int mem = blockIdx.z;
+  const int n = blockIdx.x * 256 + threadIdx.x;   // < 512
+  const int r0 = blockIdx.y * rows_per_part, r1 = min(a.valid, r0 + rows_per_part);
+  const int* perm = a.perm ? a.perm + (int64_t)mem * a.perm_stride + (int64_t)(*a.step) * a.batch : nullptr;
+  float s[kMlpIn] = {0, 0, 0, 0, 0, 0};
+  for (int b = r0; b < r1; ++b) {
+    const int64_t pt = a.base + (perm ? perm[b] : b);
+    const float d = (float)a.dz1[(int64_t)mem * a.act_stride + (int64_t)b * kMlpH + n];
+#pragma unroll
+    for (int k = 0; k < kMlpIn; ++k) s[k] += (a.X[pt * kMlpIn + k] - a.in_shift[k]) * a.in_scale[k] * d;
+  }
+#pragma unroll
+  for (int k = 0; k < kMlpIn; ++k) part[(((int64_t)mem * gridDim.y + blockIdx.y) * kMlpIn + k) * kMlpH + n] = s[k];
+}
+
+__global__ __launch_bounds__(256) void k_layer1_bwd_fin(float* grads, int64_t gstride, const float* part, int nparts) {
+  const int mem = blockIdx.z;
+  const int i = blockIdx.x * 256 + threadIdx.x;   // over 6 * 512
+  if (i >= kMlpIn * kMlpH) return;
+  float s = 0.0f;
+  for (int p = 0; p < nparts; ++p) s += part[((int64_t)mem * nparts + p) * kMlpIn * kMlpH + i];
+  grads[(int64_t)mem * gstride + kOffW1 + i] = s;
+}
+
+hipError_t launch_layer1_bwd(const MlpFwdArgs& a, float* part, int max_parts, float* grads, int64_t gstride,
+                             int members, hipStream_t st) {
+  const int rows_per_part = 256;
+  const int nparts = (a.batch + rows_per_part - 1) / rows_per_part;
+  if (nparts > max_parts) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_layer1_bwd_part, dim3(kMlpH / 256, nparts, members), dim3(256), 0, st, a, part,
+                     rows_per_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_layer1_bwd_fin, dim3((kMlpIn * kMlpH + 255) / 256, 1, members), dim3(256), 0, st,
+                     grads, gstride, part, nparts);
+  return hipGetLastError();
+}
+
+hipError_t launch_layer1_fwd(const MlpFwdArgs& a, int members, hipStream_t st) {
+  const int64_t n = (int64_t)a.batch * kMlpH;
+  hipLaunchKernelGGL(k_layer1_fwd, dim3((unsigned)((n + 255) / 256), 1, members), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_layer4_fwd(const MlpFwdArgs& a, int members, hipStream_t st) {
+  hipLaunchKernelGGL(k_layer4_fwd, dim3((a.batch + 3) / 4, 1, members), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_layer4_bwd(const MlpFwdArgs& a, int members, hipStream_t st) {
+  const int64_t n = (int64_t)a.batch * kMlpH;
+  hipLaunchKernelGGL(k_layer4_bwd, dim3((unsigned)((n + 255) / 256), 1, members), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---- Adam (float32 master weights) and the bfloat16 operand copies ---------
+// The step number lives on the device (advanced here) so that a captured
+// training step replays unchanged.
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+  const int mem = blockIdx.z;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int k = *a.step + 1;
+  if (i < kMlpParams) {
+    const int64_t o = (int64_t)mem * a.pstride + i;
+    const float g = a.grads[o];
+    const float m = a.b1 * a.m[o] + (1.0f - a.b1) * g;
+    const float v = a.b2 * a.v[o] + (1.0f - a.b2) * g * g;
+    a.m[o] = m;
+    a.v[o] = v;
+    const float mh = m / (1.0f - powf(a.b1, (float)k));
+    const float vh = v / (1.0f - powf(a.b2, (float)k));
+    const float p = a.params[o] - a.lr * mh / (sqrtf(vh) + a.eps);
+    a.params[o] = p;
+    if (i >= kOffW2 && i < kOffW2 + kMlpH * kMlpH)
+      a.w2b[(int64_t)mem * kMlpH * kMlpH + (i - kOffW2)] = (__bf16)p;
+    else if (i >= kOffW3 && i < kOffW3 + kMlpH * kMlpH)
+      a.w3b[(int64_t)mem * kMlpH * kMlpH + (i - kOffW3)] = (__bf16)p;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_step_advance(int* step, int* call_step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *step += 1;
+    *call_step += 1;
+  }
+}
+
+hipError_t launch_adam(const AdamArgs& a, int members, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3((kMlpParams + 255) / 256, 1, members), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, st, a.step, a.call_step);
+  return hipGetLastError();
+}
+
+// bfloat16 copies of W2 and W3 from the float32 master weights
+__global__ __launch_bounds__(256) void k_weights_bf16(const float* params, int64_t pstride, __bf16* w2b, __bf16* w3b) {
+  const int mem = blockIdx.z;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= kMlpH * kMlpH) return;
+  w2b[(int64_t)mem * kMlpH * kMlpH + i] = (__bf16)params[(int64_t)mem * pstride + kOffW2 + i];
+  w3b[(int64_t)mem * kMlpH * kMlpH + i] = (__bf16)params[(int64_t)mem * pstride + kOffW3 + i];
+}
+
+hipError_t launch_weights_bf16(const float* params, int64_t pstride, __bf16* w2b, __bf16* w3b, int members,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_weights_bf16, dim3(kMlpH * kMlpH / 256, 1, members), dim3(256), 0, st, params, pstride,
+                     w2b, w3b);
+  return hipGetLastError();
+}
+
+// ---- ensemble statistics: mean and standard deviation over members ---------
+__global__ __launch_bounds__(256) void k_ensemble_stats(const float* y, int64_t y_stride, int members, int n,
+                                                        float inv_scale, float* mean, float* sd) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0, s2 = 0.0;
+  for (int m = 0; m < members; ++m) {
+    const double v = (double)y[(int64_t)m * y_stride + i] * inv_scale;
+    s += v;
+    s2 += v * v;
+  }
+  const double mu = s / members;
+  const double var = members > 1 ? fmax(s2 / members - mu * mu, 0.0) : 0.0;
+  mean[i] = (float)mu;
+  sd[i] = (float)sqrt(var);
+}
+
+hipError_t launch_ensemble_stats(const float* y, int64_t y_stride, int members, int n, float inv_scale,
+                                 float* mean, float* sd, hipStream_t st) {
+  hipLaunchKernelGGL(k_ensemble_stats, dim3((n + 255) / 256), dim3(256), 0, st, y, y_stride, members, n,
+                     inv_scale, mean, sd);
+  return hipGetLastError();
+}
+
+}  // namespace msb

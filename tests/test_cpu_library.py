@@ -39,3 +39,20 @@ def test_create_rejects_invalid_model_without_gpu():
         _capi.msb_create(6, 7, 1, [(0, 1, 1.0)], 4.0)
     with pytest.raises(_capi.MsbError):
         _capi.msb_create(6, 3, 3, [(0, 6, 1.0)], 4.0)
+
+
+def test_surrogate_fallback_rule_matches_oracle():
+    """The fallback rule is host code: checked here against the oracle's rule."""
+    import numpy as np
+    from oracle import mlp as omlp
+    msb = pytest.importorskip("paper_2506_09551_amd")
+    try:
+        msb.lib()
+    except OSError:
+        pytest.skip("library not built")
+    assert msb.msb_mlp_num_params() == omlp.num_params()
+    rng = np.random.default_rng(4)
+    mean = rng.uniform(0, 1, (16, 40)).astype(np.float32)
+    sd = rng.uniform(0, 0.06, (16, 40)).astype(np.float32)
+    for frac in (0.02, 0.05, 0.1):
+        assert np.array_equal(msb.msb_mlp_fallback(mean, sd, frac), omlp.fallback_rows(mean, sd, frac))

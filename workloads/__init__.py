@@ -225,3 +225,46 @@ def sobol_params(n: int, seed: int = 7, skip: int = 0) -> np.ndarray:
     lo = np.array([4.0, -0.4, -6.0, 0.5])
     hi = np.array([12.0, 0.0, -2.0, 2.0])
     return lo + u * (hi - lo)
+
+
+# ---- learned form: inputs of the surrogate network -------------------------
+# Feature order (U, t', U_c, Gamma, w_in, w) and the box each feature spans.
+SURROGATE_LO = np.array([4.0, -0.4, -6.0, 0.5, -10.0, 0.0])
+SURROGATE_HI = np.array([12.0, 0.0, -2.0, 2.0, 10.0, 10.0])
+
+
+def surrogate_normalisation():
+    """(shift, scale) mapping every feature's box onto [-1, 1]."""
+    shift = 0.5 * (SURROGATE_LO + SURROGATE_HI)
+    scale = 2.0 / (SURROGATE_HI - SURROGATE_LO)
+    return shift, scale
+
+
+def mlp_init(seed: int, widths=(6, 512, 512, 512, 1)) -> np.ndarray:
+    """Seeded initial parameters (flat float32, layout W1 b1 W2 b2 ...): weights
+    uniform in +-sqrt(6 / fan_in) (He), the output layer scaled by 0.1, biases 0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    L = len(widths) - 1
+    for i in range(L):
+        lim = np.sqrt(6.0 / widths[i]) * (0.1 if i == L - 1 else 1.0)
+        parts.append(rng.uniform(-lim, lim, widths[i] * widths[i + 1]))
+        parts.append(np.zeros(widths[i + 1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def permutations(members: int, steps: int, batch: int, n_points: int, seed: int) -> np.ndarray:
+    """[members][steps * batch] int32 point indices: each member walks its own
+    shuffled passes over the n_points training points."""
+    rng = np.random.default_rng(seed)
+    need = steps * batch
+    out = np.empty((members, need), dtype=np.int32)
+    for m in range(members):
+        idx = []
+        have = 0
+        while have < need:
+            p = rng.permutation(n_points)
+            idx.append(p)
+            have += n_points
+        out[m] = np.concatenate(idx)[:need]
+    return out
