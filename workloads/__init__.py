@@ -268,3 +268,21 @@ def permutations(members: int, steps: int, batch: int, n_points: int, seed: int)
             have += n_points
         out[m] = np.concatenate(idx)[:need]
     return out
+
+
+def permutations_device(members: int, steps: int, batch: int, n_points: int, seed: int, device):
+    """As ``permutations`` but drawn on the device with torch's seeded
+    generator (for training sets of 10^8 points): [members][steps * batch] int32."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    need = steps * batch
+    out = torch.empty((members, need), dtype=torch.int32, device=device)
+    for m in range(members):
+        have = 0
+        while have < need:
+            p = torch.randperm(n_points, generator=g, device=device, dtype=torch.int64)
+            k = min(n_points, need - have)
+            out[m, have:have + k] = p[:k].to(torch.int32)
+            have += k
+    return out
