@@ -29,6 +29,30 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
+# HBM counters of the assembly kernel on the scale step (one launch), from
+# profiles/solve_scale_L12_hbm_counters.md: raw FETCH_SIZE / WRITE_SIZE in KiB
+# and the copy-calibrated factors; valid while the kernel source is unchanged.
+FLUSH_COUNTERS = {
+    "source": "paper_2506_09551_amd/csrc/k_shift.hip", "sha256_16": "43c9b817d20a01cd",
+    "fetch_kib": 79030301.4, "write_kib": 32016600.0, "fetch_factor": 2.0, "write_factor": 1.0,
+    "workload": "scale_L12_N6",
+}
+
+
+def flush_traffic_gb(wl_name):
+    """Counter-measured HBM bytes (GB) of one assembly launch, or None."""
+    import hashlib
+    c = FLUSH_COUNTERS
+    if wl_name != c["workload"]:
+        return None
+    try:
+        h = hashlib.sha256(open(os.path.join(ROOT, c["source"]), "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if h != c["sha256_16"]:
+        return None
+    return 1024.0 * (c["fetch_factor"] * c["fetch_kib"] + c["write_factor"] * c["write_kib"]) / 1e9
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -181,6 +205,42 @@ def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec):
     return res
 
 
+def mlp_train_main(args):
+    """Training throughput of the surrogate alone: 5 members, batch 8192,
+    `--mlp-train-steps` Adam steps on 2^20 seeded random points (targets
+    uniform), after one warm-up call; reports the matrix-core rate of the
+    six 8192 x 512 x 512 products per member and step."""
+    import numpy as np
+    import torch
+
+    from paper_2506_09551_amd import surrogate as S
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    members, batch, steps = 5, 8192, args.mlp_train_steps
+    shift, scale = W.surrogate_normalisation()
+    ens = S.Ensemble(members, shift, scale, 1.0, [W.mlp_init(100 + m) for m in range(members)])
+    n = 1 << 20
+    rng = np.random.default_rng(0)
+    X = torch.from_numpy((W.SURROGATE_LO + rng.uniform(0, 1, (n, 6)) * (W.SURROGATE_HI - W.SURROGATE_LO))
+                         .astype(np.float32)).to(dev)
+    T = torch.from_numpy(rng.uniform(0, 1, n).astype(np.float32)).to(dev)
+    perm = W.permutations_device(members, steps, batch, n, seed=1, device=dev)
+    ens.train(X, T, perm, batch, steps, 1e-3)            # warm-up (graph capture, buffers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = ens.train(X, T, perm, batch, steps, 1e-3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ens.close()
+    flops = members * steps * batch * 6 * 2 * 512 * 512
+    out = {"metric": "surrogate training step", "value": round(dt / steps * 1e3, 4), "unit": "ms/step",
+           "higher_is_better": False, "n_gpus": 1, "steps": steps, "members": members, "batch": batch,
+           "matrix_core_TFLOPs": round(flops / dt / 1e12, 2), "peak_TFLOPs": 2500.0,
+           "loss_first_last": [float(hist[:, 0].mean()), float(hist[:, -1].mean())], "data": "synthetic"}
+    print(json.dumps(out), flush=True)
+
+
 def learned_main(args):
     """Learned form: the ensemble surrogate against the plain solver.
 
@@ -309,10 +369,15 @@ def main():
     ap.add_argument("--train-spectra", type=int, default=4096, help="learned form: training spectra")
     ap.add_argument("--heldout-spectra", type=int, default=256, help="learned form: held-out spectra")
     ap.add_argument("--epochs", type=float, default=2.0, help="learned form: passes over the training set")
+    ap.add_argument("--mlp-train-steps", type=int, default=0,
+                    help="learned form: only time this many training steps on seeded random points")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
+    if args.workload == "learned" and args.mlp_train_steps > 0:
+        mlp_train_main(args)
+        return
     if args.workload == "learned":
         learned_main(args)
         return
@@ -352,7 +417,7 @@ def main():
     n_shift = len(wl.w_in)
     # apply launch shape: the autotuner's table for this batch (the solve reuses the winner)
     tune_table = msb.msb_autotune(ctx, wl.nrhs, prec)
-    log("autotune " + " ".join(f"{t[0]}x{t[1]}/nv{t[2]}:{t[3]:.4f}ms" for t in tune_table))
+    log("autotune " + " ".join(f"{t[0]}x{t[1]}/nv{t[2]}/p{t[3]}:{t[4]:.4f}ms" for t in tune_table))
     psi = torch.empty(wl.nrhs, n_shift, D, dtype=cdt, device=dev)
     torch.cuda.synchronize()
 
@@ -410,7 +475,8 @@ def main():
         "peak": FP64_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(gemm_tflops / FP64_VECTOR_PEAK_TFLOPS, 4),
-        "traffic": None,
+        "traffic": (None if flush_traffic_gb(wl.name) is None else round(flush_traffic_gb(wl.name), 2)),
+        "traffic_unit": "GB per launch (HBM, rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
         "per_launch": {"flops": gemm_flops, "avg_ms": gemm_ms,
                        "alg_bytes": last["gemm_bytes"] / max(1, last["n_gemm"])},
     }
@@ -435,8 +501,8 @@ def main():
         "iters": last["iters"],
         "solve_status": last["status_name"],
         "apply_shape": {"threads": last["apply_shape"][0], "elems_per_thread": last["apply_shape"][1],
-                        "systems_per_workgroup": last["apply_shape"][2]},
-        "autotune_ms": {f"{t[0]}x{t[1]}/nv{t[2]}": round(t[3], 5) for t in tune_table},
+                        "systems_per_workgroup": last["apply_shape"][2], "passes": last["apply_shape"][3]},
+        "autotune_ms": {f"{t[0]}x{t[1]}/nv{t[2]}/passes{t[3]}": round(t[4], 5) for t in tune_table},
         "mvms_per_step": last["mvms"],
         "max_true_residual": max_true,
         "split_ms": {k: round(v, 3) for k, v in split.items()},

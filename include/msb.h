@@ -118,7 +118,8 @@ typedef struct {
   int hist_len;
   int apply_threads;     /* launch shape of the seed apply: threads per workgroup, */
   int apply_ept;         /*   elements of a row per thread, */
-  int apply_nv;          /*   systems per workgroup */
+  int apply_nv;          /*   systems per workgroup, */
+  int apply_passes;      /*   1, or 2 when the up-spin hops ran as a separate column-panel pass */
   double t_setup_ms;     /* host wall time before the workspace: validation, apply tuning, planning */
   double t_alloc_ms;     /* host wall time of (re)allocating the workspace (0 when reused) */
   double t_wall_ms;      /* host wall time of the whole call */
@@ -129,6 +130,9 @@ typedef struct {
   int threads;           /* threads per workgroup (one workgroup per up-spin row) */
   int elems_per_thread;  /* threads * elems_per_thread >= number of down-spin states */
   int vectors;           /* systems handled by one workgroup (they share the hop tables) */
+  int passes;            /* 1: one row kernel; 2: diagonal and up-spin hops first, on column
+                            panels that stay in one XCD's L2, then the row kernel adds the
+                            down-spin hops in place (not used by the residual check) */
   double ms;             /* mean time of one apply of min(nsys, 16) vectors (msb_autotune) */
 } msb_shape;
 

@@ -82,6 +82,7 @@ __global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
     }
     const uint32_t cu = a.T.conf_up[u];
     cv<Tc> acc[NV][EPT];
+    const bool second_pass = a.vin != nullptr;   // diagonal and up-spin hops already in vin
     // diagonal
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -90,17 +91,23 @@ __global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
       const Tc pc = (Tc)__builtin_popcount(cu & cd);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Tc dg = Uv[v] * pc + dre[v];
-        if (core[v] >= 0) dg += Ucv[v] * (Tc)(((cu >> core[v]) & 1u) + ((cd >> core[v]) & 1u));
-        acc[v][e].re = dg * xs[v][e].re - dim[v] * xs[v][e].im;
-        acc[v][e].im = dg * xs[v][e].im + dim[v] * xs[v][e].re;
+        if (second_pass) {
+          acc[v][e] = (act[v] && d < nd)
+                          ? Ax::template load<Tc>(Ax::offset(a.vin, (int64_t)(s0 + v) * a.D), row0 + d)
+                          : cv<Tc>{(Tc)0, (Tc)0};
+        } else {
+          Tc dg = Uv[v] * pc + dre[v];
+          if (core[v] >= 0) dg += Ucv[v] * (Tc)(((cu >> core[v]) & 1u) + ((cd >> core[v]) & 1u));
+          acc[v][e].re = dg * xs[v][e].re - dim[v] * xs[v][e].im;
+          acc[v][e].im = dg * xs[v][e].im + dim[v] * xs[v][e].re;
+        }
         if (d < nd) rows[v * nd + d] = xs[v][e];
       }
     }
     // H_up (x) I: whole neighbour rows from global memory, HG hops in flight
     // per group (the hop list of u is uniform across the workgroup)
     constexpr int HG = (EPT * NV >= 8) ? 1 : 8 / (EPT * NV);
-    const uint32_t h0 = a.T.off_up[u], h1 = a.T.off_up[u + 1];
+    const uint32_t h0 = a.T.off_up[u], h1 = second_pass ? h0 : a.T.off_up[u + 1];
     for (uint32_t k = h0; k < h1; k += HG) {
       cv<Tc> xn[HG][NV][EPT];
       Tc cf[HG][NV];
@@ -179,10 +186,10 @@ __global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
         if (d >= nd) continue;
         const int64_t gi = row0 + d;
         const cv<Tc> vv = acc[v][e];
-        if constexpr (MODE != kModeResid) Ax::store(a.v, vbase + gi, vv);
+        if constexpr (MODE != kModeResid) Ax::store_nt(a.v, vbase + gi, vv);
         if constexpr (MODE == kModeBilinear) {
           // sigma = sum r_i v_i (unconjugated, r^T v) with r the stored residual
-          const cv<double> r = Ax::template load<double>(a.aux, aux_off[v] + gi);
+          const cv<double> r = Ax::template load_nt<double>(a.aux, aux_off[v] + gi);
           const cv<double> vs = {(double)(S)vv.re, (double)(S)vv.im};   // value as stored
           part[v][0] += r.re * vs.re - r.im * vs.im;
           part[v][1] += r.re * vs.im + r.im * vs.re;
@@ -193,7 +200,7 @@ __global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
           part[v][1] += (double)qv.re * (double)vv.im - (double)qv.im * (double)vv.re;
           part[v][2] += (double)vv.re * (double)vv.re + (double)vv.im * (double)vv.im;
         } else if constexpr (MODE == kModeResid) {
-          const cv<double> ee = Access<double, true>::template load<double>(a.aux, aux_off[v] + gi);
+          const cv<double> ee = Access<double, true>::template load_nt<double>(a.aux, aux_off[v] + gi);
           const double dr = ee.re - (double)vv.re, di = ee.im - (double)vv.im;
           part[v][2] += dr * dr + di * di;
         }
@@ -220,6 +227,76 @@ __global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
   }
 }
 
+// ---- first pass of the two-pass apply: diagonal and H_up (x) I ------------
+// v[u][d] = diag(u, d) x[u][d] + sum_u' T_up[u][u'] x[u'][d] on column panels
+// of kPanel down-spin states.  The panels are dealt to the XCDs round robin
+// (panel p on XCD p % 8) and one XCD works through a panel before the next, so
+// the panel (n_up x kPanel elements, 2.2 MB for 4368 rows in complex64) stays
+// in that XCD's L2 while every row gathers its up-spin neighbours from it; the
+// single-pass kernel fetches those neighbour rows from the Infinity Cache.
+// One wave handles one row of a panel (one element per lane), a workgroup
+// kRowsPerWg consecutive rows.  The row kernel then adds I (x) H_dn in place
+// (ApplyArgs::vin).
+constexpr int kPanel = 64, kRowsPerWg = 16;
+
+int panel_nbx(int n_up, int n_dn) {
+  const int n_panels = (n_dn + kPanel - 1) / kPanel;
+  const int chunks = (n_up + kRowsPerWg - 1) / kRowsPerWg;
+  return kNumXcd * ((n_panels + kNumXcd - 1) / kNumXcd) * chunks;
+}
+
+template <typename S, typename Tc, bool CPLX>
+__global__ __launch_bounds__(256) void k_apply_up(ApplyArgs a) {
+  using Ax = Access<S, CPLX>;
+  const int s = blockIdx.y;
+  const int nd = a.T.n_dn, nu = a.T.n_up;
+  const int chunks = (nu + kRowsPerWg - 1) / kRowsPerWg;
+  const int x = blockIdx.x % kNumXcd, l = blockIdx.x / kNumXcd;
+  const int panel = x + kNumXcd * (l / chunks), chunk = l % chunks;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int d = panel * kPanel + lane;
+  if (panel * kPanel >= nd) return;
+  if (a.status && a.status[(int64_t)s * a.status_stride] != kActive) return;
+  const SysDev sd = a.sys[s];
+  const Tc U = (Tc)sd.U, Uc = (Tc)sd.Uc, dre = (Tc)sd.d_re, dim = (Tc)sd.d_im;
+  Tc amp[MSB_MAX_BOND_TYPES];
+#pragma unroll
+  for (int t = 0; t < MSB_MAX_BOND_TYPES; ++t) amp[t] = (Tc)sd.amp[t];
+  const void* xv = Ax::offset(a.x, (int64_t)s * a.D);
+  void* vv = Ax::offset(a.v, (int64_t)s * a.D);
+  const bool ok = d < nd;
+  const uint32_t cd = ok ? a.T.conf_dn[d] : 0u;
+  for (int r = wave; r < kRowsPerWg; r += 4) {
+    const int u = chunk * kRowsPerWg + r;
+    if (u >= nu) break;
+    const uint32_t cu = a.T.conf_up[u];
+    const cv<Tc> xo = ok ? Ax::template load<Tc>(xv, (int64_t)u * nd + d) : cv<Tc>{(Tc)0, (Tc)0};
+    Tc dg = U * (Tc)__builtin_popcount(cu & cd) + dre;
+    if (sd.core >= 0) dg += Uc * (Tc)(((cu >> sd.core) & 1u) + ((cd >> sd.core) & 1u));
+    cv<Tc> acc = {dg * xo.re - dim * xo.im, dg * xo.im + dim * xo.re};
+    const uint32_t h0 = a.T.off_up[u], h1 = a.T.off_up[u + 1];
+    constexpr int HG = 8;
+    for (uint32_t k = h0; k < h1; k += HG) {
+      cv<Tc> xn[HG];
+      Tc cf[HG];
+#pragma unroll
+      for (int j = 0; j < HG; ++j) {
+        const bool hv = k + j < h1;
+        const uint32_t h = hv ? a.T.hop_up[k + j] : 0u;
+        const Tc c = amp[(h >> 1) & (MSB_MAX_BOND_TYPES - 1)];
+        cf[j] = hv ? (((h & 1u) == 0u) ? -c : c) : (Tc)0;
+        xn[j] = (hv && ok) ? Ax::template load<Tc>(xv, (int64_t)(h >> 16) * nd + d) : cv<Tc>{(Tc)0, (Tc)0};
+      }
+#pragma unroll
+      for (int j = 0; j < HG; ++j) {
+        acc.re += cf[j] * xn[j].re;
+        acc.im += cf[j] * xn[j].im;
+      }
+    }
+    if (ok) Ax::store(vv, (int64_t)u * nd + d, acc);
+  }
+}
+
 int apply_rows_per_xcd(int n_up) { return (n_up + kNumXcd - 1) / kNumXcd; }
 int apply_nbx(int n_up, int nsys) {
   (void)nsys;
@@ -242,7 +319,7 @@ int apply_nbx(int n_up, int nsys) {
   X(1024, 5, 4) X(1024, 5, 2) X(1024, 5, 1) X(1024, 8, 1) X(1024, 16, 1)
 
 static const ApplyShape kShapes[] = {
-#define MSB_SHAPE_ENTRY(B, E, N) {B, E, N},
+#define MSB_SHAPE_ENTRY(B, E, N) {B, E, N, 1},
     MSB_APPLY_SHAPES(MSB_SHAPE_ENTRY)
 #undef MSB_SHAPE_ENTRY
 };
@@ -258,7 +335,7 @@ static bool compiled(const ApplyShape& sh) {
 // fits, the staged rows fit the workgroup's LDS limit, and EPT is the
 // smallest compiled one for this (BLK, NV) (larger ones only add idle lanes).
 static bool usable(const ApplyShape& sh, int nd, size_t row_bytes, int nsys, size_t lds_max) {
-  if (!compiled(sh)) return false;
+  if (!compiled(sh) || (sh.passes != 1 && sh.passes != 2)) return false;
   if ((int64_t)sh.blk * sh.ept < nd) return false;
   if ((size_t)sh.nv * nd * row_bytes > lds_max) return false;
   if (sh.nv > 1 && sh.nv > nsys) return false;
@@ -272,8 +349,12 @@ static bool usable(const ApplyShape& sh, int nd, size_t row_bytes, int nsys, siz
 
 int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, ApplyShape* out, int max_out) {
   int n = 0;
-  for (int i = 0; i < kNumShapes && n < max_out; ++i)
-    if (usable(kShapes[i], nd, row_bytes, nsys, lds_max)) out[n++] = kShapes[i];
+  for (int passes = 1; passes <= 2; ++passes)
+    for (int i = 0; i < kNumShapes && n < max_out; ++i) {
+      ApplyShape sh = kShapes[i];
+      sh.passes = passes;
+      if (usable(sh, nd, row_bytes, nsys, lds_max)) out[n++] = sh;
+    }
   return n;
 }
 
@@ -282,27 +363,30 @@ int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, ApplySh
 // rows within 40 KB (at most 4).  ept == 0: no shape fits.
 static ApplyShape default_shape(int nd, size_t row_bytes, int nsys, size_t lds_max) {
   for (int blk : {256, 1024}) {
-    ApplyShape sh{blk, 0, 1};
+    ApplyShape sh{blk, 0, 1, 1};
     for (int i = 0; i < kNumShapes; ++i) {
       const ApplyShape& o = kShapes[i];
       if (o.blk == blk && o.nv == 1 && (int64_t)o.blk * o.ept >= nd && (sh.ept == 0 || o.ept < sh.ept)) sh.ept = o.ept;
     }
     if (sh.ept == 0 || (size_t)nd * row_bytes > lds_max) continue;
     for (int nv = 4; nv > 1; nv /= 2) {
-      ApplyShape c{blk, sh.ept, nv};
+      ApplyShape c{blk, sh.ept, nv, 1};
       if (compiled(c) && nv <= nsys && (size_t)nv * nd * row_bytes <= 40 * 1024) return c;
     }
     return sh;
   }
-  return ApplyShape{256, 0, 1};
+  return ApplyShape{256, 0, 1, 1};
 }
 
 // The requested shape if usable for this kernel's row type, else the same
 // shape with fewer vectors per workgroup, else the default.
-static ApplyShape resolve_shape(const ApplyArgs& a, size_t row_bytes) {
+// The residual mode writes no v, so it has no buffer for the first pass and
+// runs the single-pass form of the requested shape.
+static ApplyShape resolve_shape(const ApplyArgs& a, size_t row_bytes, bool allow_two) {
   const int nd = a.T.n_dn;
   ApplyShape sh = a.shape;
   if (sh.blk > 0) {
+    if (sh.passes == 2 && !allow_two) sh.passes = 1;
     for (; sh.nv >= 1; sh.nv /= 2)
       if (usable(sh, nd, row_bytes, a.nsys, a.lds_max)) return sh;
   }
@@ -313,10 +397,17 @@ template <typename S, typename Tc, bool CPLX, int MODE>
 static hipError_t launch_mode(const ApplyArgs& a0, hipStream_t st) {
   ApplyArgs a = a0;
   const int nd = a.T.n_dn;
-  const ApplyShape sh = resolve_shape(a, sizeof(cv<Tc>));
+  const ApplyShape sh = resolve_shape(a, sizeof(cv<Tc>), MODE != kModeResid);
   if (sh.ept == 0 || (int64_t)sh.blk * sh.ept < nd || (size_t)sh.nv * nd * sizeof(cv<Tc>) > a.lds_max)
     return hipErrorInvalidValue;
   a.nvec = sh.nv;
+  a.vin = nullptr;
+  if (sh.passes == 2) {
+    hipLaunchKernelGGL((k_apply_up<S, Tc, CPLX>), dim3(panel_nbx(a.T.n_up, nd), a.nsys), dim3(256), 0, st, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    a.vin = a.v;   // the row kernel adds the down-spin hops in place
+  }
   dim3 grid(a.nbx, (a.nsys + sh.nv - 1) / sh.nv);
   const size_t lds = (size_t)sh.nv * nd * sizeof(cv<Tc>);
   hipError_t err = hipErrorInvalidValue;
@@ -337,7 +428,7 @@ ApplyShape apply_shape_used(Elem e, int mode, const ApplyArgs& a) {
   size_t b = 16;
   if (e == Elem::R64) b = 8;
   else if (e == Elem::C64) b = (mode == kModeResid) ? 16 : 8;
-  return resolve_shape(a, b);
+  return resolve_shape(a, b, mode != kModeResid);
 }
 
 hipError_t launch_apply(Elem e, int mode, const ApplyArgs& a, hipStream_t st) {

@@ -55,6 +55,29 @@ struct Access {
       reinterpret_cast<S*>(base)[i] = (S)v.re;
     }
   }
+  // Streaming variants (non-temporal hint): for data touched once, so that it
+  // does not evict the re-read neighbour rows from the caches.
+  using N2 = S __attribute__((ext_vector_type(2)));
+  template <typename Tc>
+  static __device__ __forceinline__ cv<Tc> load_nt(const void* base, int64_t i) {
+    if constexpr (CPLX) {
+      const N2 t = __builtin_nontemporal_load(reinterpret_cast<const N2*>(base) + i);
+      return {(Tc)t.x, (Tc)t.y};
+    } else {
+      return {(Tc)__builtin_nontemporal_load(reinterpret_cast<const S*>(base) + i), (Tc)0};
+    }
+  }
+  template <typename Tc>
+  static __device__ __forceinline__ void store_nt(void* base, int64_t i, cv<Tc> v) {
+    if constexpr (CPLX) {
+      N2 t;
+      t.x = (S)v.re;
+      t.y = (S)v.im;
+      __builtin_nontemporal_store(t, reinterpret_cast<N2*>(base) + i);
+    } else {
+      __builtin_nontemporal_store((S)v.re, reinterpret_cast<S*>(base) + i);
+    }
+  }
   static constexpr int64_t kBytes = (int64_t)sizeof(S) * (CPLX ? 2 : 1);
   static __device__ __forceinline__ const void* offset(const void* base, int64_t elems) {
     return reinterpret_cast<const char*>(base) + elems * kBytes;

@@ -22,18 +22,19 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
 }
 
 // ---- matrix-core product --------------------------------------------------
-// C[M][N] = sum_k A(m,k) B(k,n) with
-//   A(m,k) = A[m lda + k] (TA = false) or A[k lda + m] (TA = true),
-//   B(k,n) = B[k ldb + n] (TB = false) or B[n ldb + k] (TB = true).
-// A 256-thread workgroup computes a 128 x 128 tile; each wave a 64 x 64
-// quarter as 2 x 2 blocks of 32 x 32 matrix-core products; K advances 32 at
-// a time through LDS tiles stored k-contiguous ([m][k] and [n][k]).
-constexpr int kGM = 128, kGN = 128, kGK = 32, kGPad = 8;
+// C[M][N] = sum_k A[m][k] B[n][k]: both operands are stored k-contiguous (the
+// layers keep bfloat16 copies of W and W^T, and the activations that feed a
+// weight gradient are also written transposed), so every tile moves with
+// 16-byte loads and stores.  A 256-thread workgroup computes a 128 x 128
+// tile, each wave a 64 x 64 quarter as 2 x 2 blocks of 32 x 32 matrix-core
+// products.  K advances 64 at a time through two LDS buffers: the next tile
+// is loaded into registers while the current one is multiplied.
+constexpr int kGM = 128, kGN = 128, kGK = 64, kGPad = 8;
 
-template <bool TA, bool TB, int EPI>
+template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ __align__(16) __bf16 sa[kGM][kGK + kGPad];
-  __shared__ __align__(16) __bf16 sb[kGN][kGK + kGPad];
+  __shared__ __align__(16) __bf16 sa[2][kGM][kGK + kGPad];
+  __shared__ __align__(16) __bf16 sb[2][kGN][kGK + kGPad];
   const int mem = blockIdx.z;
   const __bf16* A = g.A + (int64_t)mem * g.sA;
   const __bf16* B = g.B + (int64_t)mem * g.sB;
@@ -48,46 +49,46 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  for (int k0 = 0; k0 < g.K; k0 += kGK) {
+  // tile chunk c = tid + 256 it: row c / 8, k offset (c % 8) * 8
+  bf16x8 ra[4], rb[4];
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int idx = tid + it * 256;
-      if constexpr (!TA) {          // rows of A are k-contiguous
-        const int r = idx >> 2, c = (idx & 3) * 8;
-        *reinterpret_cast<bf16x8*>(&sa[r][c]) =
-            *reinterpret_cast<const bf16x8*>(A + (int64_t)(m0 + r) * g.lda + k0 + c);
-      } else {                      // columns of A are m-contiguous: transpose into LDS
-        const int kk = idx >> 4, c = (idx & 15) * 8;
-        const bf16x8 v = *reinterpret_cast<const bf16x8*>(A + (int64_t)(k0 + kk) * g.lda + m0 + c);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) sa[c + t][kk] = v[t];
-      }
-      if constexpr (TB) {           // B(k,n) = B[n ldb + k]: k-contiguous
-        const int r = idx >> 2, c = (idx & 3) * 8;
-        *reinterpret_cast<bf16x8*>(&sb[r][c]) =
-            *reinterpret_cast<const bf16x8*>(B + (int64_t)(n0 + r) * g.ldb + k0 + c);
-      } else {                      // B(k,n) = B[k ldb + n]: n-contiguous, transpose
-        const int kk = idx >> 4, c = (idx & 15) * 8;
-        const bf16x8 v = *reinterpret_cast<const bf16x8*>(B + (int64_t)(k0 + kk) * g.ldb + n0 + c);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) sb[c + t][kk] = v[t];
-      }
+    for (int it = 0; it < 4; ++it) {
+      const int c = tid + it * 256, r = c >> 3, kc = (c & 7) * 8;
+      ra[it] = *reinterpret_cast<const bf16x8*>(A + (int64_t)(m0 + r) * g.lda + k0 + kc);
+      rb[it] = *reinterpret_cast<const bf16x8*>(B + (int64_t)(n0 + r) * g.ldb + k0 + kc);
     }
-    __syncthreads();
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int c = tid + it * 256, r = c >> 3, kc = (c & 7) * 8;
+      *reinterpret_cast<bf16x8*>(&sa[buf][r][kc]) = ra[it];
+      *reinterpret_cast<bf16x8*>(&sb[buf][r][kc]) = rb[it];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int k0 = 0; k0 < g.K; k0 += kGK) {
+    const int buf = (k0 / kGK) & 1;
+    const bool more = k0 + kGK < g.K;
+    if (more) gload(k0 + kGK);
 #pragma unroll
     for (int kk = 0; kk < kGK; kk += 16) {
       bf16x8 a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        a[i] = *reinterpret_cast<const bf16x8*>(&sa[wm + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+        a[i] = *reinterpret_cast<const bf16x8*>(&sa[buf][wm + i * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        b[j] = *reinterpret_cast<const bf16x8*>(&sb[wn + j * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
+        b[j] = *reinterpret_cast<const bf16x8*>(&sb[buf][wn + j * 32 + (lane & 31)][kk + 8 * (lane >> 5)]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) sstore(buf ^ 1);   // buf ^ 1 was last read before the previous barrier
     __syncthreads();
   }
 
@@ -97,55 +98,82 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      for (int q = 0; q < 4; ++q) {
+        const int row0 = m0 + wm + i * 32 + 8 * q + 4 * (lane >> 5);
         const int col = n0 + wn + j * 32 + (lane & 31);
-        const float v = acc[i][j][r];
-        if constexpr (EPI == kEpiFwd) {
-          const float z = v + g.bias[(int64_t)mem * g.sBias + col];
-          g.C[(int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = z;
-          g.H[(int64_t)mem * g.sH + (int64_t)row * g.ldh + col] = (__bf16)gelu_f(z);
-        } else if constexpr (EPI == kEpiDh) {
-          const float zp = g.Zp[(int64_t)mem * g.sZ + (int64_t)row * g.ldz + col];
-          g.H[(int64_t)mem * g.sH + (int64_t)row * g.ldh + col] = (__bf16)(v * gelu_grad_f(zp));
-        } else {
-          g.C[(int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = v;
+        __bf16 hv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + r;
+          const float v = acc[i][j][4 * q + r];
+          if constexpr (EPI == kEpiFwd) {
+            const float z = v + g.bias[(int64_t)mem * g.sBias + col];
+            g.C[(int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = z;
+            hv[r] = (__bf16)gelu_f(z);
+            g.H[(int64_t)mem * g.sH + (int64_t)row * g.ldh + col] = hv[r];
+          } else if constexpr (EPI == kEpiDh) {
+            const float zp = g.Zp[(int64_t)mem * g.sZ + (int64_t)row * g.ldz + col];
+            hv[r] = (__bf16)(v * gelu_grad_f(zp));
+            g.H[(int64_t)mem * g.sH + (int64_t)row * g.ldh + col] = hv[r];
+          } else {
+            g.C[(int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = v;
+          }
+        }
+        if constexpr (EPI != kEpiStore) {
+          if (g.HT) {   // transposed copy: four consecutive rows are one 8-byte store
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            bf16x4 t4 = {hv[0], hv[1], hv[2], hv[3]};
+            *reinterpret_cast<bf16x4*>(g.HT + (int64_t)mem * g.sHT + (int64_t)col * g.ldht + row0) = t4;
+          }
         }
       }
 }
 
-hipError_t launch_gemm(bool ta, bool tb, int epi, const GemmArgs& g, int members, hipStream_t st) {
+hipError_t launch_gemm(int epi, const GemmArgs& g, int members, hipStream_t st) {
   if (g.M % kGM || g.N % kGN || g.K % kGK) return hipErrorInvalidValue;
   dim3 grid(g.N / kGN, g.M / kGM, members);
-#define MSB_GEMM(TA_, TB_, E_)                                                        \
-  if (ta == TA_ && tb == TB_ && epi == E_) {                                          \
-    hipLaunchKernelGGL((k_gemm<TA_, TB_, E_>), grid, dim3(256), 0, st, g);           \
-    return hipGetLastError();                                                         \
-  }
-  MSB_GEMM(false, false, kEpiFwd)      // z = h W + b (forward)
-  MSB_GEMM(false, true, kEpiDh)        // dz = (dz' W^T) * gelu'(z) (input gradient)
-  MSB_GEMM(true, false, kEpiStore)     // dW = h^T dz (weight gradient)
-#undef MSB_GEMM
-  return hipErrorInvalidValue;
+  if (epi == kEpiFwd) hipLaunchKernelGGL(k_gemm<kEpiFwd>, grid, dim3(256), 0, st, g);
+  else if (epi == kEpiDh) hipLaunchKernelGGL(k_gemm<kEpiDh>, grid, dim3(256), 0, st, g);
+  else if (epi == kEpiStore) hipLaunchKernelGGL(k_gemm<kEpiStore>, grid, dim3(256), 0, st, g);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 // ---- first layer: z1 = ((x - shift) * scale) W1 + b1, h1 = gelu(z1) ---------
-// Row b of the batch is point perm[b] (perm == nullptr: point b).
+// Row b of the batch is point perm[b] (perm == nullptr: point base + b).
+// A workgroup computes a 64 x 64 tile and writes h1 both row-major and
+// transposed (through LDS, so both stores are coalesced).
 __global__ __launch_bounds__(256) void k_layer1_fwd(MlpFwdArgs a) {
+  __shared__ __bf16 tile[64][66];
   const int mem = blockIdx.z;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;   // over batch * 512
-  if (i >= (int64_t)a.batch * kMlpH) return;
-  const int b = (int)(i / kMlpH), n = (int)(i % kMlpH);
+  const int n = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int b0 = blockIdx.y * 64;
   const float* W1 = a.params + (int64_t)mem * a.pstride + kOffW1;
-  float z = a.params[(int64_t)mem * a.pstride + kOffB1 + n];
-  if (b < a.valid) {            // padding rows see zero inputs
-    const int* perm = a.perm ? a.perm + (int64_t)mem * a.perm_stride + (int64_t)(*a.step) * a.batch : nullptr;
-    const int64_t pt = a.base + (perm ? perm[b] : b);
+  const float bias = a.params[(int64_t)mem * a.pstride + kOffB1 + n];
+  float w[kMlpIn];
 #pragma unroll
-    for (int k = 0; k < kMlpIn; ++k) z += (a.X[pt * kMlpIn + k] - a.in_shift[k]) * a.in_scale[k] * W1[k * kMlpH + n];
+  for (int k = 0; k < kMlpIn; ++k) w[k] = W1[k * kMlpH + n] * a.in_scale[k];
+  const int* perm = a.perm ? a.perm + (int64_t)mem * a.perm_stride + (int64_t)(*a.step) * a.batch : nullptr;
+  for (int r = threadIdx.x >> 6; r < 64; r += 4) {
+    const int b = b0 + r;
+    float z = bias;
+    if (b < a.valid) {            // padding rows see zero inputs
+      const int64_t pt = a.base + (perm ? perm[b] : b);
+#pragma unroll
+      for (int k = 0; k < kMlpIn; ++k) z += (a.X[pt * kMlpIn + k] - a.in_shift[k]) * w[k];
+    }
+    const int64_t i = (int64_t)mem * a.act_stride + (int64_t)b * kMlpH + n;
+    a.z1[i] = z;
+    const __bf16 h = (__bf16)gelu_f(z);
+    a.h1[i] = h;
+    tile[threadIdx.x & 63][r] = h;
   }
-  a.z1[(int64_t)mem * a.act_stride + i] = z;
-  a.h1[(int64_t)mem * a.act_stride + i] = (__bf16)gelu_f(z);
+  __syncthreads();
+  // transposed: h1T[n][b], 4 threads per column, 16 rows each
+  const int c = threadIdx.x >> 2, r0 = (threadIdx.x & 3) * 16;
+  __bf16* dst = a.h1T + (int64_t)mem * a.actT_stride + (int64_t)(blockIdx.x * 64 + c) * a.ldT + b0 + r0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) dst[j] = tile[c][r0 + j];
 }
 
 // ---- output layer: y = h3 W4 + b4; loss gradient g = 2 (y - t) / batch ------
@@ -186,32 +214,43 @@ __global__ __launch_bounds__(256) void k_layer4_fwd(MlpFwdArgs a) {
     a.loss_part[(int64_t)mem * gridDim.x + blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
-__global__ __launch_bounds__(64) void k_loss_record(const double* loss_part, int nparts, const int* step,
-                                                    double* hist, int64_t hist_stride, int valid) {
+__global__ __launch_bounds__(kBlock) void k_loss_record(const double* loss_part, int nparts, const int* step,
+                                                        double* hist, int64_t hist_stride, int valid) {
   const int mem = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += loss_part[(int64_t)mem * nparts + p];
-  hist[(int64_t)mem * hist_stride + *step] = s / valid;
+  double s[1] = {0.0};
+  for (int p = threadIdx.x; p < nparts; p += kBlock) s[0] += loss_part[(int64_t)mem * nparts + p];
+  __shared__ double sh[1][kBlock / kWave];
+  block_sum<1>(s, sh);
+  if (threadIdx.x == 0) hist[(int64_t)mem * hist_stride + *step] = s[0] / valid;
 }
 
 hipError_t launch_loss_record(const MlpFwdArgs& a, double* loss_hist, int64_t hist_stride, int members,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_loss_record, dim3(members), dim3(64), 0, st, a.loss_part, (a.batch + 3) / 4, a.step,
+  hipLaunchKernelGGL(k_loss_record, dim3(members), dim3(kBlock), 0, st, a.loss_part, (a.batch + 3) / 4, a.step,
                      loss_hist, hist_stride, a.valid);
   return hipGetLastError();
 }
 
 // ---- output-layer backward: dz3 = g W4^T * gelu'(z3) (bf16) ----------------
 __global__ __launch_bounds__(256) void k_layer4_bwd(MlpFwdArgs a) {
+  __shared__ __bf16 tile[64][66];
   const int mem = blockIdx.z;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (int64_t)a.batch * kMlpH) return;
-  const int b = (int)(i / kMlpH), n = (int)(i % kMlpH);
-  const float gv = a.g[(int64_t)mem * a.y_stride + b];
+  const int n = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int b0 = blockIdx.y * 64;
   const float w = a.params[(int64_t)mem * a.pstride + kOffW4 + n];
-  const float zp = a.z3[(int64_t)mem * a.act_stride + i];
-  a.dz3[(int64_t)mem * a.act_stride + i] = (__bf16)(gv * w * gelu_grad_f(zp));
+  for (int r = threadIdx.x >> 6; r < 64; r += 4) {
+    const int b = b0 + r;
+    const int64_t i = (int64_t)mem * a.act_stride + (int64_t)b * kMlpH + n;
+    const float gv = a.g[(int64_t)mem * a.y_stride + b];
+    const __bf16 d = (__bf16)(gv * w * gelu_grad_f(a.z3[i]));
+    a.dz3[i] = d;
+    tile[threadIdx.x & 63][r] = d;
+  }
+  __syncthreads();
+  const int c = threadIdx.x >> 2, r0 = (threadIdx.x & 3) * 16;
+  __bf16* dst = a.dz3T + (int64_t)mem * a.actT_stride + (int64_t)(blockIdx.x * 64 + c) * a.ldT + b0 + r0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) dst[j] = tile[c][r0 + j];
 }
 
 // ---- column sums over the batch --------------------------------------------
@@ -282,7 +321,7 @@ __global__ __launch_bounds__(256) void k_layer1_bwd_fin(float* grads, int64_t gs
 
 hipError_t launch_layer1_bwd(const MlpFwdArgs& a, float* part, int max_parts, float* grads, int64_t gstride,
                              int members, hipStream_t st) {
-  const int rows_per_part = 256;
+  const int rows_per_part = kRowsPerPart;
   const int nparts = (a.batch + rows_per_part - 1) / rows_per_part;
   if (nparts > max_parts) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_layer1_bwd_part, dim3(kMlpH / 256, nparts, members), dim3(256), 0, st, a, part,
@@ -295,8 +334,8 @@ hipError_t launch_layer1_bwd(const MlpFwdArgs& a, float* part, int max_parts, fl
 }
 
 hipError_t launch_layer1_fwd(const MlpFwdArgs& a, int members, hipStream_t st) {
-  const int64_t n = (int64_t)a.batch * kMlpH;
-  hipLaunchKernelGGL(k_layer1_fwd, dim3((unsigned)((n + 255) / 256), 1, members), dim3(256), 0, st, a);
+  if (a.batch % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_layer1_fwd, dim3(kMlpH / 64, a.batch / 64, members), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -306,8 +345,8 @@ hipError_t launch_layer4_fwd(const MlpFwdArgs& a, int members, hipStream_t st) {
 }
 
 hipError_t launch_layer4_bwd(const MlpFwdArgs& a, int members, hipStream_t st) {
-  const int64_t n = (int64_t)a.batch * kMlpH;
-  hipLaunchKernelGGL(k_layer4_bwd, dim3((unsigned)((n + 255) / 256), 1, members), dim3(256), 0, st, a);
+  if (a.batch % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_layer4_bwd, dim3(kMlpH / 64, a.batch / 64, members), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -329,10 +368,15 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
     const float vh = v / (1.0f - powf(a.b2, (float)k));
     const float p = a.params[o] - a.lr * mh / (sqrtf(vh) + a.eps);
     a.params[o] = p;
-    if (i >= kOffW2 && i < kOffW2 + kMlpH * kMlpH)
-      a.w2b[(int64_t)mem * kMlpH * kMlpH + (i - kOffW2)] = (__bf16)p;
-    else if (i >= kOffW3 && i < kOffW3 + kMlpH * kMlpH)
-      a.w3b[(int64_t)mem * kMlpH * kMlpH + (i - kOffW3)] = (__bf16)p;
+    if (i >= kOffW2 && i < kOffW2 + kMlpH * kMlpH) {
+      const int64_t e = i - kOffW2;     // W2[in][out]: copies [in][out] and [out][in]
+      a.w2b[(int64_t)mem * kMlpH * kMlpH + e] = (__bf16)p;
+      a.w2t[(int64_t)mem * kMlpH * kMlpH + (e % kMlpH) * kMlpH + e / kMlpH] = (__bf16)p;
+    } else if (i >= kOffW3 && i < kOffW3 + kMlpH * kMlpH) {
+      const int64_t e = i - kOffW3;
+      a.w3b[(int64_t)mem * kMlpH * kMlpH + e] = (__bf16)p;
+      a.w3t[(int64_t)mem * kMlpH * kMlpH + (e % kMlpH) * kMlpH + e / kMlpH] = (__bf16)p;
+    }
   }
 }
 
@@ -352,18 +396,24 @@ hipError_t launch_adam(const AdamArgs& a, int members, hipStream_t st) {
 }
 
 // bfloat16 copies of W2 and W3 from the float32 master weights
-__global__ __launch_bounds__(256) void k_weights_bf16(const float* params, int64_t pstride, __bf16* w2b, __bf16* w3b) {
+__global__ __launch_bounds__(256) void k_weights_bf16(const float* params, int64_t pstride, __bf16* w2b,
+                                                      __bf16* w3b, __bf16* w2t, __bf16* w3t) {
   const int mem = blockIdx.z;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= kMlpH * kMlpH) return;
-  w2b[(int64_t)mem * kMlpH * kMlpH + i] = (__bf16)params[(int64_t)mem * pstride + kOffW2 + i];
-  w3b[(int64_t)mem * kMlpH * kMlpH + i] = (__bf16)params[(int64_t)mem * pstride + kOffW3 + i];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= kMlpH * kMlpH) return;
+  const int64_t o = (int64_t)mem * kMlpH * kMlpH, t = (e % kMlpH) * kMlpH + e / kMlpH;
+  const __bf16 v2 = (__bf16)params[(int64_t)mem * pstride + kOffW2 + e];
+  const __bf16 v3 = (__bf16)params[(int64_t)mem * pstride + kOffW3 + e];
+  w2b[o + e] = v2;
+  w3b[o + e] = v3;
+  w2t[o + t] = v2;
+  w3t[o + t] = v3;
 }
 
-hipError_t launch_weights_bf16(const float* params, int64_t pstride, __bf16* w2b, __bf16* w3b, int members,
-                               hipStream_t st) {
+hipError_t launch_weights_bf16(const float* params, int64_t pstride, __bf16* w2b, __bf16* w3b, __bf16* w2t,
+                               __bf16* w3t, int members, hipStream_t st) {
   hipLaunchKernelGGL(k_weights_bf16, dim3(kMlpH * kMlpH / 256, 1, members), dim3(256), 0, st, params, pstride,
-                     w2b, w3b);
+                     w2b, w3b, w2t, w3t);
   return hipGetLastError();
 }
 

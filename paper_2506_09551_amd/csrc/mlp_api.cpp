@@ -22,8 +22,10 @@ struct msb_mlp {
   float* grads = nullptr;
   float* adam_m = nullptr;
   float* adam_v = nullptr;
-  __bf16* w2b = nullptr;          // [members][512][512] bfloat16 operand copies
+  __bf16* w2b = nullptr;          // [members][512][512] bfloat16 operand copies [in][out]
   __bf16* w3b = nullptr;
+  __bf16* w2t = nullptr;          // and [out][in]
+  __bf16* w3t = nullptr;
   int* step = nullptr;            // device Adam step counter (since the last set_params)
   int* call_step = nullptr;       // device step within the current training call
   int* zero_step = nullptr;       // device 0 (offset for calls without a permutation)
@@ -36,11 +38,12 @@ struct msb_mlp {
 
 namespace {
 
-constexpr int kMaxParts = 512;   // column-sum partial slices (rows / 256)
+int max_parts(int cap) { return (cap + kRowsPerPart - 1) / kRowsPerPart; }
 
 struct ActView {
   float *z1, *z2, *z3, *y, *g, *part;
   __bf16 *h1, *h2, *h3, *dz1, *dz2, *dz3;
+  __bf16 *h1T, *h2T, *dz2T, *dz3T;
   double* loss_part;
   int64_t act_stride, y_stride;
 };
@@ -51,9 +54,9 @@ size_t act_need(int members, int cap) {
   const size_t a = (size_t)cap * kMlpH;
   size_t n = 0;
   n += 3 * align256(members * a * sizeof(float));        // z1..z3
-  n += 6 * align256(members * a * sizeof(__bf16));       // h1..h3, dz1..dz3
+  n += 10 * align256(members * a * sizeof(__bf16));      // h1..h3, dz1..dz3, four transposed copies
   n += 2 * align256((size_t)members * cap * sizeof(float));   // y, g
-  n += align256((size_t)members * kMaxParts * kMlpIn * kMlpH * sizeof(float));   // partials
+  n += align256((size_t)members * max_parts(cap) * kMlpIn * kMlpH * sizeof(float));   // partials
   n += align256((size_t)members * (cap / 4 + 1) * sizeof(double));
   return n;
 }
@@ -72,9 +75,13 @@ ActView carve(msb_mlp* m) {
   v.dz1 = (__bf16*)take(m->members * a * sizeof(__bf16));
   v.dz2 = (__bf16*)take(m->members * a * sizeof(__bf16));
   v.dz3 = (__bf16*)take(m->members * a * sizeof(__bf16));
+  v.h1T = (__bf16*)take(m->members * a * sizeof(__bf16));
+  v.h2T = (__bf16*)take(m->members * a * sizeof(__bf16));
+  v.dz2T = (__bf16*)take(m->members * a * sizeof(__bf16));
+  v.dz3T = (__bf16*)take(m->members * a * sizeof(__bf16));
   v.y = (float*)take((size_t)m->members * m->cap * sizeof(float));
   v.g = (float*)take((size_t)m->members * m->cap * sizeof(float));
-  v.part = (float*)take((size_t)m->members * kMaxParts * kMlpIn * kMlpH * sizeof(float));
+  v.part = (float*)take((size_t)m->members * max_parts(m->cap) * kMlpIn * kMlpH * sizeof(float));
   v.loss_part = (double*)take((size_t)m->members * (m->cap / 4 + 1) * sizeof(double));
   v.act_stride = (int64_t)a;
   v.y_stride = m->cap;
@@ -117,6 +124,9 @@ MlpFwdArgs fwd_args(msb_mlp* m, const ActView& v, const float* X, const float* T
   a.h1 = v.h1; a.h2 = v.h2; a.h3 = v.h3;
   a.dz1 = v.dz1; a.dz2 = v.dz2; a.dz3 = v.dz3;
   a.act_stride = v.act_stride;
+  a.h1T = v.h1T; a.h2T = v.h2T; a.dz2T = v.dz2T; a.dz3T = v.dz3T;
+  a.actT_stride = v.act_stride;
+  a.ldT = m->cap;
   a.y = v.y; a.g = v.g; a.y_stride = v.y_stride;
   a.loss_part = v.loss_part;
   return a;
@@ -137,17 +147,20 @@ hipError_t forward(msb_mlp* m, int mem0, int members, const MlpFwdArgs& a0, hipS
   const __bf16* hin[2] = {a.h1, a.h2};
   float* zout[2] = {a.z2, a.z3};
   __bf16* hout[2] = {a.h2, a.h3};
-  const __bf16* wb[2] = {m->w2b + (int64_t)mem0 * kMlpH * kMlpH, m->w3b + (int64_t)mem0 * kMlpH * kMlpH};
+  // B[n][k] = W[k][n]: the [out][in] copies
+  const __bf16* wt[2] = {m->w2t + (int64_t)mem0 * kMlpH * kMlpH, m->w3t + (int64_t)mem0 * kMlpH * kMlpH};
+  __bf16* hT[2] = {a.h2T, nullptr};             // h2 feeds the layer-3 weight gradient
   const int64_t boff[2] = {kOffB2, kOffB3};
   for (int l = 0; l < 2 && e == hipSuccess; ++l) {
     GemmArgs g = gemm_base();
     g.A = hin[l]; g.lda = kMlpH; g.sA = a.act_stride;
-    g.B = wb[l]; g.ldb = kMlpH; g.sB = (int64_t)kMlpH * kMlpH;
+    g.B = wt[l]; g.ldb = kMlpH; g.sB = (int64_t)kMlpH * kMlpH;
     g.M = a.batch; g.N = kMlpH; g.K = kMlpH;
     g.C = zout[l]; g.ldc = kMlpH; g.sC = a.act_stride;
     g.bias = a.params + boff[l]; g.sBias = ps;
     g.H = hout[l]; g.ldh = kMlpH; g.sH = a.act_stride;
-    e = launch_gemm(false, false, kEpiFwd, g, members, st);
+    g.HT = hT[l]; g.ldht = a.ldT; g.sHT = a.actT_stride;
+    e = launch_gemm(kEpiFwd, g, members, st);
   }
   if (e == hipSuccess) e = launch_layer4_fwd(a, members, st);
   return e;
@@ -165,7 +178,7 @@ hipError_t backward(msb_mlp* m, int mem0, int members, const MlpFwdArgs& a0, con
   std::memset(&c, 0, sizeof(c));
   c.src_bf16 = a.h3; c.src_stride = a.act_stride; c.ld = kMlpH;
   c.wgt = a.g; c.wgt_stride = a.y_stride;
-  c.nrows = a.valid; c.ncols = kMlpH; c.rows_per_part = 256; c.max_parts = kMaxParts;
+  c.nrows = a.valid; c.ncols = kMlpH; c.rows_per_part = kRowsPerPart; c.max_parts = max_parts(m->cap);
   c.part = v.part; c.out = grads + kOffW4; c.out_stride = ps;
   if (e == hipSuccess) e = launch_colsum(c, members, st);
   ColSumArgs cb = c;
@@ -173,37 +186,40 @@ hipError_t backward(msb_mlp* m, int mem0, int members, const MlpFwdArgs& a0, con
   cb.wgt = nullptr; cb.ncols = 1; cb.out = grads + kOffB4;
   if (e == hipSuccess) e = launch_colsum(cb, members, st);
   // hidden layers 3 and 2: dW = h^T dz, db = sum dz, dz_prev = (dz W^T) * gelu'(z_prev)
-  const __bf16* hin[2] = {a.h2, a.h1};
+  const __bf16* hinT[2] = {a.h2T, a.h1T};
   const __bf16* dzs[2] = {a.dz3, a.dz2};
+  const __bf16* dzsT[2] = {a.dz3T, a.dz2T};
   __bf16* dzp[2] = {a.dz2, a.dz1};
+  __bf16* dzpT[2] = {a.dz2T, nullptr};
   const float* zp[2] = {a.z2, a.z1};
   const __bf16* wb[2] = {m->w3b + (int64_t)mem0 * kMlpH * kMlpH, m->w2b + (int64_t)mem0 * kMlpH * kMlpH};
   const int64_t woff[2] = {kOffW3, kOffW2}, boff[2] = {kOffB3, kOffB2};
   for (int l = 0; l < 2 && e == hipSuccess; ++l) {
     GemmArgs g = gemm_base();
-    g.A = hin[l]; g.lda = kMlpH; g.sA = a.act_stride;      // A(m,k) = h[k][m]
-    g.B = dzs[l]; g.ldb = kMlpH; g.sB = a.act_stride;      // B(k,n) = dz[k][n]
+    g.A = hinT[l]; g.lda = a.ldT; g.sA = a.actT_stride;    // A[in][b] = h^T
+    g.B = dzsT[l]; g.ldb = a.ldT; g.sB = a.actT_stride;    // B[out][b] = dz^T
     g.M = kMlpH; g.N = kMlpH; g.K = a.batch;
     g.C = grads + woff[l]; g.ldc = kMlpH; g.sC = ps;
-    e = launch_gemm(true, false, kEpiStore, g, members, st);
+    e = launch_gemm(kEpiStore, g, members, st);
     ColSumArgs cz = c;
     cz.src_bf16 = dzs[l]; cz.src_f32 = nullptr; cz.src_stride = a.act_stride; cz.ld = kMlpH;
     cz.wgt = nullptr; cz.ncols = kMlpH; cz.out = grads + boff[l];
     if (e == hipSuccess) e = launch_colsum(cz, members, st);
     GemmArgs d = gemm_base();
-    d.A = dzs[l]; d.lda = kMlpH; d.sA = a.act_stride;      // A(m,k) = dz[m][k]
-    d.B = wb[l]; d.ldb = kMlpH; d.sB = (int64_t)kMlpH * kMlpH;   // B(k,n) = W[n][k]
+    d.A = dzs[l]; d.lda = kMlpH; d.sA = a.act_stride;      // A[b][out] = dz
+    d.B = wb[l]; d.ldb = kMlpH; d.sB = (int64_t)kMlpH * kMlpH;   // B[in][out] = W
     d.M = a.batch; d.N = kMlpH; d.K = kMlpH;
     d.H = dzp[l]; d.ldh = kMlpH; d.sH = a.act_stride;
+    d.HT = dzpT[l]; d.ldht = a.ldT; d.sHT = a.actT_stride;
     d.Zp = zp[l]; d.ldz = kMlpH; d.sZ = a.act_stride;
-    if (e == hipSuccess) e = launch_gemm(false, true, kEpiDh, d, members, st);
+    if (e == hipSuccess) e = launch_gemm(kEpiDh, d, members, st);
   }
   // first layer
   ColSumArgs c1 = c;
   c1.src_bf16 = a.dz1; c1.src_stride = a.act_stride; c1.ld = kMlpH; c1.wgt = nullptr; c1.ncols = kMlpH;
   c1.out = grads + kOffB1;
   if (e == hipSuccess) e = launch_colsum(c1, members, st);
-  if (e == hipSuccess) e = launch_layer1_bwd(a, v.part, kMaxParts, grads, ps, members, st);
+  if (e == hipSuccess) e = launch_layer1_bwd(a, v.part, max_parts(m->cap), grads, ps, members, st);
   return e;
 }
 
@@ -244,6 +260,8 @@ extern "C" msb_status msb_mlp_create(int members, const double* in_shift, const 
   if (e == hipSuccess) e = hipMalloc(&m->adam_v, pb);
   if (e == hipSuccess) e = hipMalloc(&m->w2b, wb);
   if (e == hipSuccess) e = hipMalloc(&m->w3b, wb);
+  if (e == hipSuccess) e = hipMalloc(&m->w2t, wb);
+  if (e == hipSuccess) e = hipMalloc(&m->w3t, wb);
   if (e == hipSuccess) e = hipMalloc(&m->step, sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&m->zero_step, sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&m->call_step, sizeof(int));
@@ -256,7 +274,7 @@ extern "C" msb_status msb_mlp_create(int members, const double* in_shift, const 
   if (e == hipSuccess) e = hipMemset(m->zero_step, 0, sizeof(int));
   if (e == hipSuccess) e = hipMemset(m->call_step, 0, sizeof(int));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = launch_weights_bf16(m->params, m->pstride, m->w2b, m->w3b, members, m->stream);
+  if (e == hipSuccess) e = launch_weights_bf16(m->params, m->pstride, m->w2b, m->w3b, m->w2t, m->w3t, members, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) {
     msb_mlp_destroy(m);
@@ -270,7 +288,7 @@ extern "C" void msb_mlp_destroy(msb_mlp* m) {
   if (!m) return;
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   for (void* p : {(void*)m->d_in, (void*)m->params, (void*)m->grads, (void*)m->adam_m, (void*)m->adam_v,
-                  (void*)m->w2b, (void*)m->w3b, (void*)m->step, (void*)m->zero_step, (void*)m->call_step,
+                  (void*)m->w2b, (void*)m->w3b, (void*)m->w2t, (void*)m->w3t, (void*)m->step, (void*)m->zero_step, (void*)m->call_step,
                   m->act})
     if (p) (void)hipFree(p);
   if (m->stream) (void)hipStreamDestroy(m->stream);
@@ -287,7 +305,7 @@ extern "C" msb_status msb_mlp_set_params(msb_mlp* m, int member, const float* pa
   MSB_HIP(hipMemset(m->adam_m + o, 0, kMlpParams * sizeof(float)));
   MSB_HIP(hipMemset(m->adam_v + o, 0, kMlpParams * sizeof(float)));
   MSB_HIP(hipMemset(m->step, 0, sizeof(int)));
-  MSB_HIP(launch_weights_bf16(m->params, m->pstride, m->w2b, m->w3b, m->members, m->stream));
+  MSB_HIP(launch_weights_bf16(m->params, m->pstride, m->w2b, m->w3b, m->w2t, m->w3t, m->members, m->stream));
   MSB_HIP(hipStreamSynchronize(m->stream));
   return MSB_OK;
 }
@@ -306,7 +324,7 @@ extern "C" msb_status msb_mlp_grad(msb_mlp* m, int member, const float* X, const
   (void)hipGetLastError();
   if (!m || !X || !T || !grad) return fail(MSB_EINVAL, "msb_mlp_grad: null argument");
   if (member < 0 || member >= m->members) return fail(MSB_EINVAL, "msb_mlp_grad: member out of range");
-  if (n < 1 || n > kMaxParts * 256) return fail(MSB_EINVAL, "msb_mlp_grad: n out of range");
+  if (n < 1 || n > kMaxRows) return fail(MSB_EINVAL, "msb_mlp_grad: n out of range");
   const int rows = (n + 127) / 128 * 128;
   msb_status r = ensure_cap(m, rows);
   if (r != MSB_OK) return r;
@@ -333,7 +351,7 @@ extern "C" msb_status msb_mlp_train(msb_mlp* m, const float* X, const float* T, 
                                     void* stream) {
   (void)hipGetLastError();
   if (!m || !X || !T || !perm) return fail(MSB_EINVAL, "msb_mlp_train: null argument");
-  if (batch < 128 || batch % 128 || batch > kMaxParts * 256)
+  if (batch < 128 || batch % 128 || batch > kMaxRows)
     return fail(MSB_EINVAL, "msb_mlp_train: batch must be a multiple of 128 in [128, 131072]");
   if (steps < 1 || n_points < 1) return fail(MSB_EINVAL, "msb_mlp_train: steps and n_points must be positive");
   if (!(lr > 0) || !std::isfinite(lr)) return fail(MSB_EINVAL, "msb_mlp_train: lr must be positive");
@@ -355,7 +373,8 @@ extern "C" msb_status msb_mlp_train(msb_mlp* m, const float* X, const float* T, 
   } free_hist{d_hist};
   AdamArgs ad;
   ad.params = m->params; ad.grads = m->grads; ad.m = m->adam_m; ad.v = m->adam_v; ad.pstride = m->pstride;
-  ad.w2b = m->w2b; ad.w3b = m->w3b; ad.step = m->step; ad.call_step = m->call_step;
+  ad.w2b = m->w2b; ad.w3b = m->w3b; ad.w2t = m->w2t; ad.w3t = m->w3t;
+  ad.step = m->step; ad.call_step = m->call_step;
   ad.lr = (float)lr; ad.b1 = 0.9f; ad.b2 = 0.999f; ad.eps = 1e-8f;
   auto enqueue_step = [&]() -> hipError_t {
     hipError_t e = forward(m, 0, m->members, a, st);

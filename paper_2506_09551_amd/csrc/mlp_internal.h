@@ -21,17 +21,21 @@ constexpr int64_t kOffB4 = kOffW4 + kMlpH;
 constexpr int64_t kMlpParams = kOffB4 + 1;
 
 enum { kEpiFwd = 0, kEpiDh = 1, kEpiStore = 2 };
+constexpr int kRowsPerPart = 32;     // batch rows per partial sum of the column reductions
+constexpr int kMaxRows = 131072;     // largest batch
 
+// C[M][N] = sum_k A[m][k] B[n][k] (both operands k-contiguous, bfloat16)
 struct GemmArgs {
   const __bf16* A; int64_t lda, sA;     // s*: stride between ensemble members (elements)
   const __bf16* B; int64_t ldb, sB;
-  int M, N, K;
+  int M, N, K;                          // multiples of 128, 128, 64
   float* C; int64_t ldc, sC;            // float32 output (z or dW)
   const float* bias; int64_t sBias;     // forward epilogue
   __bf16* H; int64_t ldh, sH;           // bfloat16 output (h or dz)
+  __bf16* HT; int64_t ldht, sHT;        // optional transposed bfloat16 output [n][m]
   const float* Zp; int64_t ldz, sZ;     // pre-activations for gelu' (input-gradient epilogue)
 };
-hipError_t launch_gemm(bool ta, bool tb, int epi, const GemmArgs& g, int members, hipStream_t st);
+hipError_t launch_gemm(int epi, const GemmArgs& g, int members, hipStream_t st);
 
 struct MlpFwdArgs {
   const float* X;          // [points][6] raw inputs
@@ -49,6 +53,8 @@ struct MlpFwdArgs {
   __bf16 *h1, *h2, *h3;
   __bf16 *dz1, *dz2, *dz3;
   int64_t act_stride;
+  __bf16 *h1T, *h2T, *dz2T, *dz3T;  // transposed copies [members][512][ldT] (weight-gradient operands)
+  int64_t actT_stride, ldT;
   float* y; float* g; int64_t y_stride;          // [members][batch]
   double* loss_part;       // [members][batch / 4]
 };
@@ -73,14 +79,15 @@ hipError_t launch_colsum(const ColSumArgs& a, int members, hipStream_t st);
 
 struct AdamArgs {
   float* params; float* grads; float* m; float* v; int64_t pstride;
-  __bf16* w2b; __bf16* w3b;
+  __bf16* w2b; __bf16* w3b;   // bfloat16 copies [in][out]
+  __bf16* w2t; __bf16* w3t;   // and [out][in]
   int* step;                // Adam step (advanced after the update)
   int* call_step;           // step within the training call (advanced too)
   float lr, b1, b2, eps;
 };
 hipError_t launch_adam(const AdamArgs& a, int members, hipStream_t st);
-hipError_t launch_weights_bf16(const float* params, int64_t pstride, __bf16* w2b, __bf16* w3b, int members,
-                               hipStream_t st);
+hipError_t launch_weights_bf16(const float* params, int64_t pstride, __bf16* w2b, __bf16* w3b, __bf16* w2t,
+                               __bf16* w3t, int members, hipStream_t st);
 hipError_t launch_ensemble_stats(const float* y, int64_t y_stride, int members, int n, float inv_scale,
                                  float* mean, float* sd, hipStream_t st);
 

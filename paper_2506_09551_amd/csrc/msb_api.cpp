@@ -128,7 +128,7 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   hipEvent_t e0, e1;
   MSB_HIP(hipEventCreate(&e0));
   MSB_HIP(hipEventCreate(&e1));
-  ApplyShape best{0, 0, 0};
+  ApplyShape best{0, 0, 0, 0};
   double best_ms = 0;
   hipError_t err = hipSuccess;
   for (int i = 0; i < nc && err == hipSuccess; ++i) {
@@ -163,7 +163,7 @@ static ApplyShape shape_for(msb_ctx* ctx, Elem e, int nsys, hipStream_t st, bool
   if (it != ctx->shapes.end()) return it->second;
   if (!tune || tune_shapes(ctx, e, nsys, st, nullptr) != MSB_OK) {
     (void)hipGetLastError();
-    return ApplyShape{0, 0, 0};
+    return ApplyShape{0, 0, 0, 0};
   }
   return ctx->shapes[key];
 }
@@ -776,7 +776,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
 
   msb_status result = MSB_OK;
   int max_iters = 0, total_mvms = 0, brk_iter = -1, flushes = 0, n_replace = 0;
-  ApplyShape seed_shape{0, 0, 0};
+  ApplyShape seed_shape{0, 0, 0, 0};
   std::vector<SysState> hst(B);
   std::vector<int> hconv((size_t)B * n_shift);
   std::vector<double> hz((size_t)B * n_shift * 2);
@@ -1104,6 +1104,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     info->apply_threads = seed_shape.blk;
     info->apply_ept = seed_shape.ept;
     info->apply_nv = seed_shape.nv;
+    info->apply_passes = seed_shape.passes;
     info->t_iter_ms = t_iter;
     info->t_flush_ms = t_flush;
     info->t_true_ms = t_true;
@@ -1333,6 +1334,7 @@ extern "C" msb_status msb_autotune(msb_ctx* ctx, int nsys, msb_prec prec, msb_sh
     out[i].threads = table[i].first.blk;
     out[i].elems_per_thread = table[i].first.ept;
     out[i].vectors = table[i].first.nv;
+    out[i].passes = table[i].first.passes;
     out[i].ms = table[i].second;
   }
   if (n_out) *n_out = (int)table.size();
@@ -1354,7 +1356,7 @@ extern "C" msb_status msb_set_shape(msb_ctx* ctx, int nsys, msb_prec prec, const
   const int nc = apply_candidates(ctx->dn.n, elem_bytes(e), shape_class(nsys), ctx->lds_max, cand, 64);
   for (int i = 0; i < nc; ++i)
     if (cand[i].blk == shape->threads && cand[i].ept == shape->elems_per_thread &&
-        cand[i].nv == shape->vectors) {
+        cand[i].nv == shape->vectors && cand[i].passes == (shape->passes == 2 ? 2 : 1)) {
       ctx->shapes[key] = cand[i];
       return MSB_OK;
     }

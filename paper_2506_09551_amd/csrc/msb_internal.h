@@ -83,9 +83,11 @@ enum ApplyMode : int {
 };
 
 // Launch shape of the apply kernel: threads per workgroup, elements per
-// thread, vectors (systems) per workgroup.  blk == 0 selects the default.
+// thread, vectors (systems) per workgroup of the row kernel, and whether the
+// diagonal and the up-spin hops run first in a separate column-panel pass
+// (passes = 2).  blk == 0 selects the default.
 struct ApplyShape {
-  int blk, ept, nv;
+  int blk, ept, nv, passes;
 };
 
 struct ApplyArgs {
@@ -107,8 +109,9 @@ struct ApplyArgs {
   int rows_per_xcd;
   int nsys;
   int nvec;                   // vectors (systems) per workgroup (set by the launcher)
-  ApplyShape shape;           // requested launch shape ({0,0,0} = default)
+  ApplyShape shape;           // requested launch shape ({0,0,0,0} = default)
   size_t lds_max;             // LDS bytes one workgroup may use (device limit)
+  const void* vin;            // set by the launcher for the second pass: v holds diag + up-spin hops
 };
 
 enum class Elem { R64, C128, C64 };   // real float64, complex128, complex64 storage
