@@ -35,9 +35,11 @@ template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ __align__(16) __bf16 sa[2][kGM][kGK + kGPad];
   __shared__ __align__(16) __bf16 sb[2][kGN][kGK + kGPad];
-  const int mem = blockIdx.z;
-  const __bf16* A = g.A + (int64_t)mem * g.sA;
-  const __bf16* B = g.B + (int64_t)mem * g.sB;
+  const int splits = g.splitk > 1 ? g.splitk : 1;
+  const int mem = blockIdx.z / splits, ks = blockIdx.z % splits;
+  const int klen = g.K / splits, kbeg = ks * klen;
+  const __bf16* A = g.A + (int64_t)mem * g.sA + kbeg;
+  const __bf16* B = g.B + (int64_t)mem * g.sB + kbeg;
   const int m0 = blockIdx.y * kGM, n0 = blockIdx.x * kGN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -70,9 +72,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   gload(0);
   sstore(0);
   __syncthreads();
-  for (int k0 = 0; k0 < g.K; k0 += kGK) {
+  for (int k0 = 0; k0 < klen; k0 += kGK) {
     const int buf = (k0 / kGK) & 1;
-    const bool more = k0 + kGK < g.K;
+    const bool more = k0 + kGK < klen;
     if (more) gload(k0 + kGK);
 #pragma unroll
     for (int kk = 0; kk < kGK; kk += 16) {
@@ -115,8 +117,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             const float zp = g.Zp[(int64_t)mem * g.sZ + (int64_t)row * g.ldz + col];
             hv[r] = (__bf16)(v * gelu_grad_f(zp));
             g.H[(int64_t)mem * g.sH + (int64_t)row * g.ldh + col] = hv[r];
-          } else {
-            g.C[(int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = v;
+          } else {    // float32 output; a K slice writes its own partial copy
+            g.C[(int64_t)ks * g.sCk + (int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = v;
           }
         }
         if constexpr (EPI != kEpiStore) {
@@ -130,8 +132,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 }
 
 hipError_t launch_gemm(int epi, const GemmArgs& g, int members, hipStream_t st) {
-  if (g.M % kGM || g.N % kGN || g.K % kGK) return hipErrorInvalidValue;
-  dim3 grid(g.N / kGN, g.M / kGM, members);
+  const int splits = g.splitk > 1 ? g.splitk : 1;
+  if (g.M % kGM || g.N % kGN || g.K % (kGK * splits)) return hipErrorInvalidValue;
+  if (splits > 1 && epi != kEpiStore) return hipErrorInvalidValue;
+  dim3 grid(g.N / kGN, g.M / kGM, members * splits);
   if (epi == kEpiFwd) hipLaunchKernelGGL(k_gemm<kEpiFwd>, grid, dim3(256), 0, st, g);
   else if (epi == kEpiDh) hipLaunchKernelGGL(k_gemm<kEpiDh>, grid, dim3(256), 0, st, g);
   else if (epi == kEpiStore) hipLaunchKernelGGL(k_gemm<kEpiStore>, grid, dim3(256), 0, st, g);
@@ -256,21 +260,28 @@ __global__ __launch_bounds__(256) void k_layer4_bwd(MlpFwdArgs a) {
 // ---- column sums over the batch --------------------------------------------
 // out[n] = sum_b w_b * src(b, n) for the bias gradients (src = dz, bf16), the
 // output-layer weight gradient (src = h3, weights g) and its bias (src = g).
-// Each workgroup sums a 256-column strip over a slice of rows; a second
-// launch adds the slices in order.
+// A workgroup owns 64 columns and a slice of kRowsPerPart rows: its four
+// waves take every fourth row (coalesced 64-column rows) and meet in LDS; a
+// second launch adds the slices in order.
 __global__ __launch_bounds__(256) void k_colsum_part(ColSumArgs a) {
+  __shared__ float red[4][64];
   const int mem = blockIdx.z;
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= a.ncols) return;
+  const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
   const int r0 = blockIdx.y * a.rows_per_part, r1 = min(a.nrows, r0 + a.rows_per_part);
   float s = 0.0f;
-  for (int b = r0; b < r1; ++b) {
-    float v = a.src_bf16 ? (float)a.src_bf16[(int64_t)mem * a.src_stride + (int64_t)b * a.ld + n]
-                         : a.src_f32[(int64_t)mem * a.src_stride + (int64_t)b * a.ld + n];
-    if (a.wgt) v *= a.wgt[(int64_t)mem * a.wgt_stride + b];
-    s += v;
+  if (n < a.ncols) {
+    for (int b = r0 + grp; b < r1; b += 4) {
+      float v = a.src_bf16 ? (float)a.src_bf16[(int64_t)mem * a.src_stride + (int64_t)b * a.ld + n]
+                           : a.src_f32[(int64_t)mem * a.src_stride + (int64_t)b * a.ld + n];
+      if (a.wgt) v *= a.wgt[(int64_t)mem * a.wgt_stride + b];
+      s += v;
+    }
   }
-  a.part[((int64_t)mem * gridDim.y + blockIdx.y) * a.ncols + n] = s;
+  red[grp][c] = s;
+  __syncthreads();
+  if (grp == 0 && n < a.ncols)
+    a.part[((int64_t)mem * gridDim.y + blockIdx.y) * a.ncols + n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
 __global__ __launch_bounds__(256) void k_colsum_fin(ColSumArgs a, int nparts) {
@@ -285,7 +296,7 @@ __global__ __launch_bounds__(256) void k_colsum_fin(ColSumArgs a, int nparts) {
 hipError_t launch_colsum(const ColSumArgs& a, int members, hipStream_t st) {
   const int nparts = (a.nrows + a.rows_per_part - 1) / a.rows_per_part;
   if (nparts > a.max_parts) return hipErrorInvalidValue;
-  dim3 grid((a.ncols + 255) / 256, nparts, members);
+  dim3 grid((a.ncols + 63) / 64, nparts, members);
   hipLaunchKernelGGL(k_colsum_part, grid, dim3(256), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -294,20 +305,30 @@ hipError_t launch_colsum(const ColSumArgs& a, int members, hipStream_t st) {
 }
 
 // ---- first-layer weight gradient: dW1[k][n] = sum_b xn(b, k) dz1(b, n) -------
+// Same decomposition as the column sums, six sums per column.
 __global__ __launch_bounds__(256) void k_layer1_bwd_part(MlpFwdArgs a, float* part, int rows_per_part) {
+  __shared__ float red[4][kMlpIn][64];
   const int mem = blockIdx.z;
-  const int n = blockIdx.x * 256 + threadIdx.x;   // < 512
+  const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;   // < 512
   const int r0 = blockIdx.y * rows_per_part, r1 = min(a.valid, r0 + rows_per_part);
   const int* perm = a.perm ? a.perm + (int64_t)mem * a.perm_stride + (int64_t)(*a.step) * a.batch : nullptr;
   float s[kMlpIn] = {0, 0, 0, 0, 0, 0};
-  for (int b = r0; b < r1; ++b) {
+  for (int b = r0 + grp; b < r1; b += 4) {
     const int64_t pt = a.base + (perm ? perm[b] : b);
     const float d = (float)a.dz1[(int64_t)mem * a.act_stride + (int64_t)b * kMlpH + n];
 #pragma unroll
     for (int k = 0; k < kMlpIn; ++k) s[k] += (a.X[pt * kMlpIn + k] - a.in_shift[k]) * a.in_scale[k] * d;
   }
 #pragma unroll
-  for (int k = 0; k < kMlpIn; ++k) part[(((int64_t)mem * gridDim.y + blockIdx.y) * kMlpIn + k) * kMlpH + n] = s[k];
+  for (int k = 0; k < kMlpIn; ++k) red[grp][k][c] = s[k];
+  __syncthreads();
+  if (grp == 0) {
+#pragma unroll
+    for (int k = 0; k < kMlpIn; ++k)
+      part[(((int64_t)mem * gridDim.y + blockIdx.y) * kMlpIn + k) * kMlpH + n] =
+          ((red[0][k][c] + red[1][k][c]) + red[2][k][c]) + red[3][k][c];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_layer1_bwd_fin(float* grads, int64_t gstride, const float* part, int nparts) {
@@ -324,12 +345,30 @@ hipError_t launch_layer1_bwd(const MlpFwdArgs& a, float* part, int max_parts, fl
   const int rows_per_part = kRowsPerPart;
   const int nparts = (a.batch + rows_per_part - 1) / rows_per_part;
   if (nparts > max_parts) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_layer1_bwd_part, dim3(kMlpH / 256, nparts, members), dim3(256), 0, st, a, part,
+  hipLaunchKernelGGL(k_layer1_bwd_part, dim3(kMlpH / 64, nparts, members), dim3(256), 0, st, a, part,
                      rows_per_part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_layer1_bwd_fin, dim3((kMlpIn * kMlpH + 255) / 256, 1, members), dim3(256), 0, st,
                      grads, gstride, part, nparts);
+  return hipGetLastError();
+}
+
+// ---- split-K reduction of the weight-gradient product ----------------------
+__global__ __launch_bounds__(256) void k_splitk_sum(const float* part, int64_t split_stride, int splits,
+                                                    float* out, int64_t out_stride, int64_t n) {
+  const int mem = blockIdx.z;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int k = 0; k < splits; ++k) s += part[(int64_t)k * split_stride + (int64_t)mem * n + i];
+  out[(int64_t)mem * out_stride + i] = s;
+}
+
+hipError_t launch_splitk_sum(const float* part, int64_t split_stride, int splits, float* out, int64_t out_stride,
+                             int64_t n, int members, hipStream_t st) {
+  hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((n + 255) / 256), 1, members), dim3(256), 0, st, part,
+                     split_stride, splits, out, out_stride, n);
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ namespace {
 int max_parts(int cap) { return (cap + kRowsPerPart - 1) / kRowsPerPart; }
 
 struct ActView {
-  float *z1, *z2, *z3, *y, *g, *part;
+  float *z1, *z2, *z3, *y, *g, *part, *splitk;
   __bf16 *h1, *h2, *h3, *dz1, *dz2, *dz3;
   __bf16 *h1T, *h2T, *dz2T, *dz3T;
   double* loss_part;
@@ -58,6 +58,7 @@ size_t act_need(int members, int cap) {
   n += 2 * align256((size_t)members * cap * sizeof(float));   // y, g
   n += align256((size_t)members * max_parts(cap) * kMlpIn * kMlpH * sizeof(float));   // partials
   n += align256((size_t)members * (cap / 4 + 1) * sizeof(double));
+  n += align256((size_t)kMaxSplitK * members * kMlpH * kMlpH * sizeof(float));   // split-K partials
   return n;
 }
 
@@ -83,6 +84,7 @@ ActView carve(msb_mlp* m) {
   v.g = (float*)take((size_t)m->members * m->cap * sizeof(float));
   v.part = (float*)take((size_t)m->members * max_parts(m->cap) * kMlpIn * kMlpH * sizeof(float));
   v.loss_part = (double*)take((size_t)m->members * (m->cap / 4 + 1) * sizeof(double));
+  v.splitk = (float*)take((size_t)kMaxSplitK * m->members * kMlpH * kMlpH * sizeof(float));
   v.act_stride = (int64_t)a;
   v.y_stride = m->cap;
   return v;
@@ -199,8 +201,20 @@ hipError_t backward(msb_mlp* m, int mem0, int members, const MlpFwdArgs& a0, con
     g.A = hinT[l]; g.lda = a.ldT; g.sA = a.actT_stride;    // A[in][b] = h^T
     g.B = dzsT[l]; g.ldb = a.ldT; g.sB = a.actT_stride;    // B[out][b] = dz^T
     g.M = kMlpH; g.N = kMlpH; g.K = a.batch;
-    g.C = grads + woff[l]; g.ldc = kMlpH; g.sC = ps;
-    e = launch_gemm(kEpiStore, g, members, st);
+    // the 512 x 512 output has only 16 tiles per member: split K so that
+    // enough workgroups run, then add the slices
+    int splits = 1;
+    while (splits < kMaxSplitK && a.batch % (2 * splits * 64) == 0 && a.batch / (2 * splits) >= 512) splits *= 2;
+    g.splitk = splits;
+    if (splits > 1) {
+      g.C = v.splitk; g.ldc = kMlpH; g.sC = (int64_t)kMlpH * kMlpH; g.sCk = (int64_t)members * kMlpH * kMlpH;
+      e = launch_gemm(kEpiStore, g, members, st);
+      if (e == hipSuccess)
+        e = launch_splitk_sum(v.splitk, g.sCk, splits, grads + woff[l], ps, (int64_t)kMlpH * kMlpH, members, st);
+    } else {
+      g.C = grads + woff[l]; g.ldc = kMlpH; g.sC = ps;
+      e = launch_gemm(kEpiStore, g, members, st);
+    }
     ColSumArgs cz = c;
     cz.src_bf16 = dzs[l]; cz.src_f32 = nullptr; cz.src_stride = a.act_stride; cz.ld = kMlpH;
     cz.wgt = nullptr; cz.ncols = kMlpH; cz.out = grads + boff[l];

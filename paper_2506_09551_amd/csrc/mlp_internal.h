@@ -21,15 +21,17 @@ constexpr int64_t kOffB4 = kOffW4 + kMlpH;
 constexpr int64_t kMlpParams = kOffB4 + 1;
 
 enum { kEpiFwd = 0, kEpiDh = 1, kEpiStore = 2 };
-constexpr int kRowsPerPart = 32;     // batch rows per partial sum of the column reductions
+constexpr int kRowsPerPart = 256;    // batch rows per partial sum of the column reductions
+constexpr int kMaxSplitK = 8;        // K slices of the weight-gradient product
 constexpr int kMaxRows = 131072;     // largest batch
 
 // C[M][N] = sum_k A[m][k] B[n][k] (both operands k-contiguous, bfloat16)
 struct GemmArgs {
   const __bf16* A; int64_t lda, sA;     // s*: stride between ensemble members (elements)
   const __bf16* B; int64_t ldb, sB;
-  int M, N, K;                          // multiples of 128, 128, 64
-  float* C; int64_t ldc, sC;            // float32 output (z or dW)
+  int M, N, K;                          // multiples of 128, 128, 64 * splitk
+  int splitk;                           // K slices (weight gradient only; 0 or 1 = none)
+  float* C; int64_t ldc, sC, sCk;       // float32 output (z or dW); sCk: stride between K slices
   const float* bias; int64_t sBias;     // forward epilogue
   __bf16* H; int64_t ldh, sH;           // bfloat16 output (h or dz)
   __bf16* HT; int64_t ldht, sHT;        // optional transposed bfloat16 output [n][m]
@@ -76,6 +78,9 @@ struct ColSumArgs {
   float* out; int64_t out_stride;
 };
 hipError_t launch_colsum(const ColSumArgs& a, int members, hipStream_t st);
+// out[m][i] = sum_k part[k][m][i] for i < n (part stride split_stride per slice)
+hipError_t launch_splitk_sum(const float* part, int64_t split_stride, int splits, float* out, int64_t out_stride,
+                             int64_t n, int members, hipStream_t st);
 
 struct AdamArgs {
   float* params; float* grads; float* m; float* v; int64_t pstride;

@@ -657,7 +657,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   const bool tune = !(opts && opts->autotune < 0);
   (void)shape_for(ctx, ev, nsys, ust, tune);
   if (replace_every > 0) (void)shape_for(ctx, Elem::C128, nsys, ust, tune);
-  if (want_true) (void)shape_for(ctx, ev, (int)std::min<int64_t>((int64_t)nsys * n_shift, kTuneMaxSys), ust, tune);
+  // the residual check stages FP64 rows whatever the storage: tune it as complex128
+  if (want_true)
+    (void)shape_for(ctx, Elem::C128, (int)std::min<int64_t>((int64_t)nsys * n_shift, kTuneMaxSys), ust, tune);
 
   // ---- plan: batch size and bank capacity from the memory that is free ----
   size_t fr = 0, tot = 0;
@@ -1066,7 +1068,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       MSB_HIP(hipMemcpyAsync(bf.tsys, tsys.data(), need_sys, hipMemcpyHostToDevice, st));
       MSB_HIP(hipEventRecord(ev0, st));
       ApplyArgs ta = apply_args(ctx, bf.tsys, nt, psib, nullptr);
-      ta.shape = shape_for(ctx, ev, nt, st, tune);
+      ta.shape = shape_for(ctx, Elem::C128, nt, st, tune);   // FP64 rows, as tuned above
       ta.aux = Eb;
       ta.aux_div = n_shift;
       ta.partials = bf.tpart;
