@@ -167,6 +167,65 @@ hipError_t launch_block_lanczos_update(const BlockLanczosArgs& a, hipStream_t st
 }
 int lanczos_nbx(int64_t D, int n) { return stream_nbx(D, n, kPerStepL); }
 
+// One step of the block recurrence on unnormalised Lanczos vectors u_k
+// (q_k = u_k / beta_k, beta_k^2 = nrm[j]):
+//   a_k = <u_k|H u_k> / beta_k^2,
+//   u_{k+1} = v / beta_k - (a_k / beta_k) u_k - (beta_k / beta_{k-1}) u_{k-1},  v = H u_k,
+// written over u_{k-1}; partial |u_{k+1}|^2.  Keeping the vectors unnormalised
+// removes the separate scaling pass (6 instead of 8 vector passes per step).
+__global__ __launch_bounds__(kBlock) void k_block_lanczos_step(BlockStepArgs a) {
+  using Ax = Access<double, true>;
+  const int j = blockIdx.y, bx = blockIdx.x;
+  double part[1] = {0.0};
+  if (a.active[j] == 0) {
+    const double nrm = a.nrm[j];
+    const double inv_b = 1.0 / sqrt(nrm);
+    const double ca = a.herm[4 * j] / nrm * inv_b;
+    const double bp = a.bprev[j];
+    const double cp = bp > 0.0 ? sqrt(nrm) / bp : 0.0;
+    const int64_t off = (int64_t)j * a.D;
+    for (int64_t base = (int64_t)bx * kPerStepL; base < a.D; base += (int64_t)a.nbx * kPerStepL) {
+#pragma unroll
+      for (int e = 0; e < kEptL; ++e) {
+        const int64_t i = base + e * kBlock + threadIdx.x;
+        if (i < a.D) {
+          const cv<double> v = Ax::template load_nt<double>(a.v, off + i);
+          const cv<double> u = Ax::template load<double>(a.u, off + i);
+          cv<double> x = {v.re * inv_b - ca * u.re, v.im * inv_b - ca * u.im};
+          if (cp != 0.0) {
+            const cv<double> up = Ax::template load<double>(a.up, off + i);
+            x.re -= cp * up.re;
+            x.im -= cp * up.im;
+          }
+          Ax::store(a.up, off + i, x);
+          part[0] += x.re * x.re + x.im * x.im;
+        }
+      }
+    }
+  }
+  block_partial<1>(part, a.partials, a.nbx, j, bx);
+}
+
+// beta_{k-1} <- beta_k, beta_k^2 <- |u_{k+1}|^2 for active vectors
+__global__ __launch_bounds__(kBlock) void k_block_lanczos_rotate(const int* active, const double* red,
+                                                                 double* nrm, double* bprev, int n) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n || active[j] != 0) return;
+  bprev[j] = sqrt(nrm[j]);
+  nrm[j] = red[4 * j];
+}
+
+hipError_t launch_block_lanczos_step(const BlockStepArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_lanczos_step, dim3(a.nbx, a.n), dim3(kBlock), 0, st, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  err = launch_reduce(a.partials, a.nbx, a.n, a.red, st);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_block_lanczos_rotate, dim3((a.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a.active,
+                     a.red, a.nrm, a.bprev, a.n);
+  return hipGetLastError();
+}
+
 // out_j = w_j / b_j for active j
 __global__ __launch_bounds__(kBlock) void k_block_scale(const double* w, const double* b,
                                                         const int* active, double* out, int64_t D) {

@@ -1184,7 +1184,7 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
                           (size_t)n * sizeof(SysDev), part_doubles * sizeof(double),
                           (size_t)n * 4 * sizeof(double), (size_t)n * 4 * sizeof(double),   // reda, redb
                           (size_t)n * sizeof(double), (size_t)n * sizeof(double),
-                          (size_t)n * sizeof(double),                                    // dzero dbcur dnorm2
+                          (size_t)n * sizeof(double), (size_t)n * sizeof(double),        // dzero dbcur dnorm2 dnrm
                           (size_t)n * sizeof(int), (size_t)n * sizeof(int),             // dactive ddepth
                           (size_t)n * ld * sizeof(double), (size_t)n * ld * sizeof(double),  // logs
                           (size_t)n_w * sizeof(double), (size_t)n * n_w * sizeof(double)};
@@ -1203,6 +1203,7 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
   double* dzero = ar.take<double>((size_t)n * sizeof(double));
   double* dbcur = ar.take<double>((size_t)n * sizeof(double));
   double* dnorm2 = ar.take<double>((size_t)n * sizeof(double));
+  double* dnrm = ar.take<double>((size_t)n * sizeof(double));
   int* dactive = ar.take<int>((size_t)n * sizeof(int));
   int* ddepth = ar.take<int>((size_t)n * sizeof(int));
   double* dalog = ar.take<double>((size_t)n * ld * sizeof(double));
@@ -1239,14 +1240,13 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
   MSB_HIP(hipMemcpyAsync(dnorm2, norm2.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
   MSB_HIP(hipMemcpyAsync(dbcur, bcur.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
   MSB_HIP(hipMemcpyAsync(dactive, active.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
-  // q_0 = phi / |phi| into bufA
-  MSB_HIP(launch_block_scale(bufW, dbcur, dactive, bufA, D, n, st));
-  std::vector<double> zeros(n, 0.0);
-  MSB_HIP(hipMemcpyAsync(dbcur, zeros.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
-
-  double* q = bufA;
-  double* qp = bufB;
-  double* wv = bufW;
+  // u_0 = phi itself (unnormalised vectors, beta_0^2 = |phi|^2), u_{-1} = 0
+  MSB_HIP(hipMemcpyAsync(dnrm, norm2.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+  MSB_HIP(hipMemsetAsync(dbcur, 0, n * sizeof(double), st));      // beta_{k-1}
+  double* u = bufW;
+  double* up = bufB;
+  double* vv = bufA;
+  std::vector<double> nrm_h = norm2;
   std::vector<double> Iprev((size_t)n * n_w, 0.0), Icur((size_t)n * n_w, 0.0);
   std::vector<int> checked(n, 0);
   const int check_every = 10;
@@ -1264,25 +1264,27 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
     bool any = false;
     for (int j = 0; j < n; ++j) any |= active[j] == 0;
     if (!any) break;
-    ApplyArgs aa = apply_args(ctx, dsys, n, q, wv);
+    ApplyArgs aa = apply_args(ctx, dsys, n, u, vv);
     aa.shape = shp;
     aa.partials = partials;
     aa.red = reda;
     aa.status = dactive;
     aa.status_stride = 1;
     MSB_HIP(launch_apply(Elem::C128, kModeHerm, aa, st));
-    bl.w = wv; bl.q = q; bl.qprev = qp; bl.a = reda; bl.b = dbcur;
-    MSB_HIP(launch_block_lanczos_update(bl, st));
+    BlockStepArgs bs;
+    bs.v = vv; bs.u = u; bs.up = up; bs.herm = reda; bs.nrm = dnrm; bs.bprev = dbcur; bs.active = dactive;
+    bs.partials = partials; bs.red = redb; bs.D = D; bs.nbx = nbx_l; bs.n = n;
+    MSB_HIP(launch_block_lanczos_step(bs, st));
     std::vector<double> ha((size_t)n * 4);
     MSB_HIP(hipMemcpyAsync(ha.data(), reda, n * 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     MSB_HIP(hipMemcpyAsync(hred.data(), redb, n * 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     MSB_HIP(hipStreamSynchronize(st));
     for (int j = 0; j < n; ++j) {
       if (active[j] != 0) continue;
-      alog[(size_t)j * ld + k] = ha[4 * j];
+      alog[(size_t)j * ld + k] = ha[4 * j] / nrm_h[j];
       depth[j] = k + 1;
       const double bn = std::sqrt(hred[4 * j]);
-      bcur[j] = bn;
+      nrm_h[j] = hred[4 * j];
       if (k + 1 < ld) blog[(size_t)j * ld + k + 1] = bn;
       if (!(bn > 1e-14 * std::sqrt(norm2[j]))) active[j] = 2;   // invariant subspace reached
     }
@@ -1304,11 +1306,8 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
       }
       Iprev = Icur;
     }
-    MSB_HIP(hipMemcpyAsync(dbcur, bcur.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
     MSB_HIP(hipMemcpyAsync(dactive, active.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
-    // q_{k+1} = w / b_{k+1} into the buffer of q_{k-1}, then rotate
-    MSB_HIP(launch_block_scale(wv, dbcur, dactive, qp, D, n, st));
-    std::swap(q, qp);
+    std::swap(u, up);   // up now holds u_{k+1}
   }
   r = eval_cf(Icur);
   if (r != MSB_OK) return r;

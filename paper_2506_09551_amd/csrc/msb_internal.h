@@ -287,6 +287,20 @@ struct BlockLanczosArgs {
   int nbx, n;
 };
 hipError_t launch_block_lanczos_update(const BlockLanczosArgs& a, hipStream_t st);
+struct BlockStepArgs {
+  const double* v;              // [n][D] H u_k
+  const double* u;              // u_k
+  double* up;                   // u_{k-1} in, u_{k+1} out
+  const double* herm;           // [n][4] <u_k|H u_k> in [4 j]
+  double* nrm;                  // [n] |u_k|^2, advanced to |u_{k+1}|^2
+  double* bprev;                // [n] |u_{k-1}| (0: no previous vector), advanced
+  const int* active;            // [n]
+  double* partials;             // [n][nbx][4]
+  double* red;                  // [n][4] |u_{k+1}|^2
+  int64_t D;
+  int nbx, n;
+};
+hipError_t launch_block_lanczos_step(const BlockStepArgs& a, hipStream_t st);
 int lanczos_nbx(int64_t D, int n);     // workgroups per vector of the block update
 int gram_blocks(int64_t D);            // partial rows of launch_dot_many
 // q_prev <- w / b (per vector, active only); returns via pointer rotation by the host
