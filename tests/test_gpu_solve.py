@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from oracle import hubbard as hb
 from oracle import solve as osolve
 from tests._cases import oracle_H, small_models
 
@@ -254,3 +255,51 @@ def test_assembly_engines_match_direct_solve(tiny, engine):
         for j in range(2):
             err = _rel(psi[j], refs[j])
             assert err <= 1e-9, f"engine {engine} slots {slots} system {j}: {err:.3e}"
+
+
+@pytest.mark.parametrize("wl_name", ["scale", "precision", "batched"])
+def test_full_size_solve_sampled_rows(gpu, wl_name):
+    """The workloads at full size in the bench's configuration (all systems and
+    shifts of one msb_solve call): the equation (A - w)Psi = E checked by the
+    oracle's row-by-row operator on sampled rows of sampled (system, shift)
+    pairs, and the library's own FP64 true residuals."""
+    import torch
+    msb = gpu
+    from tests._cases import basis
+    wl = W.get(wl_name)
+    ctx = msb.msb_create(wl.n_sites, wl.n_up, wl.n_dn, wl.bonds, wl.U)
+    try:
+        D = msb.msb_dim(ctx)
+        x0 = torch.from_numpy(W.random_vector(D, wl.gs_seed)).cuda()
+        G = torch.empty(D, dtype=torch.float64, device="cuda")
+        E_G, _ = msb.msb_ground_state(ctx, msb.make_system(), x0, 1e-10, 600, G)
+        E = torch.empty(wl.nrhs, D, dtype=torch.complex128, device="cuda")
+        for j, w2 in enumerate(wl.o2_weights):
+            site, wu, wd = (-1, 1.0, 1.0) if w2 is None else (wl.core_sites[j], w2[0], w2[1])
+            msb.msb_number_op(ctx, site, wu, wd, G, E[j])
+        systems = [msb.make_system(core_site=c, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma) for c in wl.core_sites]
+        prec = msb.MSB_C128 if wl.dtype == "c128" else msb.MSB_C64
+        dt = torch.complex128 if prec == msb.MSB_C128 else torch.complex64
+        n = len(wl.w_in)
+        psi = torch.empty(wl.nrhs, n, D, dtype=dt, device="cuda")
+        tol = 1e-8
+        st, info = msb.msb_solve(ctx, systems, E, wl.w_in, wl.seed_shift, tol, wl.maxit, prec, psi,
+                                 want_true=True, raise_on_fail=False)
+        assert st in ((msb.MSB_OK,) if prec == msb.MSB_C128 else (msb.MSB_OK, msb.MSB_FLOOR))
+        floor = tol if prec == msb.MSB_C128 else 2e-5          # complex64 storage of Psi
+        assert np.max(info["resid_true"]) <= 1.01 * floor
+        B = basis(wl.n_sites, wl.n_up, wl.n_dn)
+        rng = np.random.default_rng(17)
+        rows = np.unique(np.concatenate([rng.integers(0, D, 150), [0, D - 1]]))
+        for s in sorted({0, wl.nrhs - 1}):
+            Es = E[s].cpu().numpy()
+            nE = np.linalg.norm(Es)
+            for k in sorted({0, n // 3, n // 2, n - 1}):
+                ps = psi[s, k].cpu().numpy().astype(np.complex128)
+                sysd = systems[s]
+                Ax = hb.apply_rows(B, wl.bonds, wl.U, ps, rows, core_site=sysd.core_site, Uc=sysd.Uc,
+                                   shift=E_G + wl.w_in[k] + 1j * wl.Gamma)
+                r = Es[rows] - Ax
+                assert np.max(np.abs(r)) <= 1.01 * floor * nE, (s, k, np.max(np.abs(r)) / nE)
+    finally:
+        msb.msb_destroy(ctx)
