@@ -417,7 +417,7 @@ def main():
     n_shift = len(wl.w_in)
     # apply launch shape: the autotuner's table for this batch (the solve reuses the winner)
     tune_table = msb.msb_autotune(ctx, wl.nrhs, prec)
-    log("autotune " + " ".join(f"{t[0]}x{t[1]}/nv{t[2]}/p{t[3]}:{t[4]:.4f}ms" for t in tune_table))
+    log("autotune " + " ".join(f"{t[0]}x{t[1]}/nv{t[2]}/p{t[3]}/o{t[4]}:{t[5]:.4f}ms" for t in tune_table))
     psi = torch.empty(wl.nrhs, n_shift, D, dtype=cdt, device=dev)
     torch.cuda.synchronize()
 
@@ -501,8 +501,10 @@ def main():
         "iters": last["iters"],
         "solve_status": last["status_name"],
         "apply_shape": {"threads": last["apply_shape"][0], "elems_per_thread": last["apply_shape"][1],
-                        "systems_per_workgroup": last["apply_shape"][2], "passes": last["apply_shape"][3]},
-        "autotune_ms": {f"{t[0]}x{t[1]}/nv{t[2]}/passes{t[3]}": round(t[4], 5) for t in tune_table},
+                        "systems_per_workgroup": last["apply_shape"][2], "passes": last["apply_shape"][3],
+                        "row_order": last["apply_shape"][4]},
+        "autotune_ms": {f"{t[0]}x{t[1]}/nv{t[2]}/passes{t[3]}/order{t[4]}": round(t[5], 5)
+                        for t in sorted(tune_table, key=lambda t: t[5])[:6]},   # the six fastest
         "mvms_per_step": last["mvms"],
         "max_true_residual": max_true,
         "split_ms": {k: round(v, 3) for k, v in split.items()},

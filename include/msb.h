@@ -119,7 +119,8 @@ typedef struct {
   int apply_threads;     /* launch shape of the seed apply: threads per workgroup, */
   int apply_ept;         /*   elements of a row per thread, */
   int apply_nv;          /*   systems per workgroup, */
-  int apply_passes;      /*   1, or 2 when the up-spin hops ran as a separate column-panel pass */
+  int apply_passes;      /*   1, or 2 when the up-spin hops ran as a separate column-panel pass, */
+  int apply_order;       /*   row order: 0 contiguous rank range per XCD, 1 level order */
   double t_setup_ms;     /* host wall time before the workspace: validation, apply tuning, planning */
   double t_alloc_ms;     /* host wall time of (re)allocating the workspace (0 when reused) */
   double t_wall_ms;      /* host wall time of the whole call */
@@ -133,6 +134,9 @@ typedef struct {
   int passes;            /* 1: one row kernel; 2: diagonal and up-spin hops first, on column
                             panels that stay in one XCD's L2, then the row kernel adds the
                             down-spin hops in place (not used by the residual check) */
+  int row_order;         /* 0: each XCD walks one contiguous range of up-spin ranks of every
+                            system; 1: the rows of all systems in level order (ascending sum
+                            of occupied site indices), one contiguous eighth per XCD */
   double ms;             /* mean time of one apply of min(nsys, 16) vectors (msb_autotune) */
 } msb_shape;
 

@@ -49,12 +49,12 @@ class msb_info(ctypes.Structure):
                 ("gemm_bytes", c_double), ("replacements", c_int),
                 ("seed_hist", POINTER(c_double)), ("hist_len", c_int),
                 ("apply_threads", c_int), ("apply_ept", c_int), ("apply_nv", c_int), ("apply_passes", c_int),
-                ("t_setup_ms", c_double), ("t_alloc_ms", c_double), ("t_wall_ms", c_double)]
+                ("apply_order", c_int), ("t_setup_ms", c_double), ("t_alloc_ms", c_double), ("t_wall_ms", c_double)]
 
 
 class msb_shape(ctypes.Structure):
     _fields_ = [("threads", c_int), ("elems_per_thread", c_int), ("vectors", c_int), ("passes", c_int),
-                ("ms", c_double)]
+                ("row_order", c_int), ("ms", c_double)]
 
 
 class msb_opts(ctypes.Structure):
@@ -328,7 +328,8 @@ def msb_solve(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit: int, 
         "gemm_bytes": info.gemm_bytes, "replacements": info.replacements,
         "seed_hist": (np.frombuffer(seed_hist, dtype=np.float64).reshape(n, hist_len).copy()
                       if hist_len > 0 else None),
-        "apply_shape": (info.apply_threads, info.apply_ept, info.apply_nv, info.apply_passes),
+        "apply_shape": (info.apply_threads, info.apply_ept, info.apply_nv, info.apply_passes,
+                        info.apply_order),
         "t_setup_ms": info.t_setup_ms, "t_alloc_ms": info.t_alloc_ms, "t_wall_ms": info.t_wall_ms,
     }
     if raise_on_fail and st != MSB_OK:
@@ -371,19 +372,23 @@ def msb_spectrum(ctx, system, phi, w, eta: float, lanczos_max: int, cf_tol: floa
 
 
 def msb_autotune(ctx, nsys: int, prec: int, stream=None):
-    """Time every usable apply shape; returns [(threads, elems_per_thread, vectors, passes, ms), ...]."""
-    tab = (msb_shape * 64)()
+    """Time every usable apply shape; returns
+    [(threads, elems_per_thread, vectors, passes, row_order, ms), ...]."""
+    tab = (msb_shape * 128)()
     n = c_int(0)
-    _check(lib().msb_autotune(ctx, int(nsys), int(prec), tab, 64, ctypes.byref(n), _stream_ptr(stream)))
-    return [(t.threads, t.elems_per_thread, t.vectors, t.passes, t.ms) for t in tab[:min(n.value, 64)]]
+    _check(lib().msb_autotune(ctx, int(nsys), int(prec), tab, 128, ctypes.byref(n), _stream_ptr(stream)))
+    return [(t.threads, t.elems_per_thread, t.vectors, t.passes, t.row_order, t.ms)
+            for t in tab[:min(n.value, 128)]]
 
 
 def msb_set_shape(ctx, nsys: int, prec: int, shape):
-    """Pin the apply shape (threads, elems_per_thread, vectors[, passes]); None returns to the default."""
+    """Pin the apply shape (threads, elems_per_thread, vectors[, passes[, row_order]]);
+    None returns to the default."""
     sh = msb_shape()
     if shape is not None:
         sh.threads, sh.elems_per_thread, sh.vectors = (int(v) for v in shape[:3])
         sh.passes = int(shape[3]) if len(shape) >= 4 else 1
+        sh.row_order = int(shape[4]) if len(shape) >= 5 else 0
     _check(lib().msb_set_shape(ctx, int(nsys), int(prec), ctypes.byref(sh)))
 
 

@@ -13,6 +13,10 @@
 // Rows are assigned so that each XCD (workgroups are dispatched round-robin
 // over the 8 XCDs) works on one contiguous range of u, which keeps
 // neighbouring rows u' that differ only in low sites inside that XCD's L2.
+// The ordered form instead lists the rows of all systems in level order
+// (TablesDev::order_up) and gives each XCD one contiguous eighth of that
+// list: on chains a row's up-spin neighbours lie in the adjacent levels, so
+// they are still in the XCD's L2 from the rows just before.
 // Optional fused reductions feed the COCG step (sigma = r^T A p), the
 // Lanczos coefficient a_k = <q|H q>, or the true residual |E - (A - w) Psi|;
 // their per-workgroup partials are summed by a finalize launch.
@@ -28,10 +32,20 @@ __global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
   __shared__ Tc s_amp[NV][MSB_MAX_BOND_TYPES];
 
   const int tid = threadIdx.x;
-  const int bx = blockIdx.x;
-  const int s0 = blockIdx.y * NV;
   const int nd = a.T.n_dn;
-  const int u = (bx % kNumXcd) * a.rows_per_xcd + bx / kNumXcd;
+  // (system group, row) of this workgroup and its column in the partials
+  int s0, u, bx;
+  if (a.ordered) {
+    const int per_xcd = gridDim.x / kNumXcd;            // grid.x = groups * nbx, nbx % 8 == 0
+    const int item = (blockIdx.x % kNumXcd) * per_xcd + blockIdx.x / kNumXcd;
+    bx = item % a.nbx;
+    s0 = (item / a.nbx) * NV;
+    u = bx < a.T.n_up ? (int)a.T.order_up[bx] : a.T.n_up;
+  } else {
+    bx = blockIdx.x;
+    s0 = blockIdx.y * NV;
+    u = (bx % kNumXcd) * a.rows_per_xcd + bx / kNumXcd;
+  }
   const bool row_ok = u < a.T.n_up;
 
   bool act[NV];
@@ -319,7 +333,7 @@ int apply_nbx(int n_up, int nsys) {
   X(1024, 5, 4) X(1024, 5, 2) X(1024, 5, 1) X(1024, 8, 1) X(1024, 16, 1)
 
 static const ApplyShape kShapes[] = {
-#define MSB_SHAPE_ENTRY(B, E, N) {B, E, N, 1},
+#define MSB_SHAPE_ENTRY(B, E, N) {B, E, N, 1, 0},
     MSB_APPLY_SHAPES(MSB_SHAPE_ENTRY)
 #undef MSB_SHAPE_ENTRY
 };
@@ -335,7 +349,7 @@ static bool compiled(const ApplyShape& sh) {
 // fits, the staged rows fit the workgroup's LDS limit, and EPT is the
 // smallest compiled one for this (BLK, NV) (larger ones only add idle lanes).
 static bool usable(const ApplyShape& sh, int nd, size_t row_bytes, int nsys, size_t lds_max) {
-  if (!compiled(sh) || (sh.passes != 1 && sh.passes != 2)) return false;
+  if (!compiled(sh) || (sh.passes != 1 && sh.passes != 2) || (sh.order != 0 && sh.order != 1)) return false;
   if ((int64_t)sh.blk * sh.ept < nd) return false;
   if ((size_t)sh.nv * nd * row_bytes > lds_max) return false;
   if (sh.nv > 1 && sh.nv > nsys) return false;
@@ -349,12 +363,14 @@ static bool usable(const ApplyShape& sh, int nd, size_t row_bytes, int nsys, siz
 
 int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, ApplyShape* out, int max_out) {
   int n = 0;
-  for (int passes = 1; passes <= 2; ++passes)
-    for (int i = 0; i < kNumShapes && n < max_out; ++i) {
-      ApplyShape sh = kShapes[i];
-      sh.passes = passes;
-      if (usable(sh, nd, row_bytes, nsys, lds_max)) out[n++] = sh;
-    }
+  for (int order = 0; order <= 1; ++order)
+    for (int passes = 1; passes <= 2; ++passes)
+      for (int i = 0; i < kNumShapes && n < max_out; ++i) {
+        ApplyShape sh = kShapes[i];
+        sh.passes = passes;
+        sh.order = order;
+        if (usable(sh, nd, row_bytes, nsys, lds_max)) out[n++] = sh;
+      }
   return n;
 }
 
@@ -363,19 +379,19 @@ int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, ApplySh
 // rows within 40 KB (at most 4).  ept == 0: no shape fits.
 static ApplyShape default_shape(int nd, size_t row_bytes, int nsys, size_t lds_max) {
   for (int blk : {256, 1024}) {
-    ApplyShape sh{blk, 0, 1, 1};
+    ApplyShape sh{blk, 0, 1, 1, 0};
     for (int i = 0; i < kNumShapes; ++i) {
       const ApplyShape& o = kShapes[i];
       if (o.blk == blk && o.nv == 1 && (int64_t)o.blk * o.ept >= nd && (sh.ept == 0 || o.ept < sh.ept)) sh.ept = o.ept;
     }
     if (sh.ept == 0 || (size_t)nd * row_bytes > lds_max) continue;
     for (int nv = 4; nv > 1; nv /= 2) {
-      ApplyShape c{blk, sh.ept, nv, 1};
+      ApplyShape c{blk, sh.ept, nv, 1, 0};
       if (compiled(c) && nv <= nsys && (size_t)nv * nd * row_bytes <= 40 * 1024) return c;
     }
     return sh;
   }
-  return ApplyShape{256, 0, 1, 1};
+  return ApplyShape{256, 0, 1, 1, 0};
 }
 
 // The requested shape if usable for this kernel's row type, else the same
@@ -402,13 +418,15 @@ static hipError_t launch_mode(const ApplyArgs& a0, hipStream_t st) {
     return hipErrorInvalidValue;
   a.nvec = sh.nv;
   a.vin = nullptr;
+  a.ordered = sh.order;
   if (sh.passes == 2) {
     hipLaunchKernelGGL((k_apply_up<S, Tc, CPLX>), dim3(panel_nbx(a.T.n_up, nd), a.nsys), dim3(256), 0, st, a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     a.vin = a.v;   // the row kernel adds the down-spin hops in place
   }
-  dim3 grid(a.nbx, (a.nsys + sh.nv - 1) / sh.nv);
+  const int groups = (a.nsys + sh.nv - 1) / sh.nv;
+  const dim3 grid = sh.order ? dim3(a.nbx * groups, 1) : dim3(a.nbx, groups);
   const size_t lds = (size_t)sh.nv * nd * sizeof(cv<Tc>);
   hipError_t err = hipErrorInvalidValue;
 #define MSB_SHAPE_CASE(B, E, N)                                                             \

@@ -97,6 +97,7 @@ struct DevBuf {               // scratch device memory released on scope exit
 };
 
 static ApplyArgs apply_args(const msb_ctx* ctx, const SysDev* sys, int nsys, const void* x, void* v);
+constexpr int kMaxCand = 128;   // compiled shapes x passes x row orders
 
 // Times every usable shape for (e, shape_class(nsys)) on zero vectors and keeps
 // the fastest in the context.  `table` (optional) receives every measurement.
@@ -104,8 +105,8 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
                               std::vector<std::pair<ApplyShape, double>>* table) {
   const int n = shape_class(nsys);
   const size_t eb = elem_bytes(e);
-  ApplyShape cand[64];
-  const int nc = apply_candidates(ctx->dn.n, eb, n, ctx->lds_max, cand, 64);
+  ApplyShape cand[kMaxCand];
+  const int nc = apply_candidates(ctx->dn.n, eb, n, ctx->lds_max, cand, kMaxCand);
   if (nc == 0) return fail(MSB_EINVAL, "autotune: no compiled apply shape covers a row");
   const size_t vb = (size_t)n * ctx->D * eb;
   DevBuf x, y, ds;
@@ -128,7 +129,7 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   hipEvent_t e0, e1;
   MSB_HIP(hipEventCreate(&e0));
   MSB_HIP(hipEventCreate(&e1));
-  ApplyShape best{0, 0, 0, 0};
+  ApplyShape best{0, 0, 0, 0, 0};
   double best_ms = 0;
   hipError_t err = hipSuccess;
   for (int i = 0; i < nc && err == hipSuccess; ++i) {
@@ -163,7 +164,7 @@ static ApplyShape shape_for(msb_ctx* ctx, Elem e, int nsys, hipStream_t st, bool
   if (it != ctx->shapes.end()) return it->second;
   if (!tune || tune_shapes(ctx, e, nsys, st, nullptr) != MSB_OK) {
     (void)hipGetLastError();
-    return ApplyShape{0, 0, 0, 0};
+    return ApplyShape{0, 0, 0, 0, 0};
   }
   return ctx->shapes[key];
 }
@@ -281,6 +282,7 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
         ell[(size_t)(k - c->dn.off[d]) * c->dn.n + d] = c->dn.hop[k];
     e = upload(&c->d_ell_dn, ell);
   }
+  if (e == hipSuccess) e = upload(&c->d_order_up, c->up.order);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc(&c->d_small, 4096 * sizeof(double));
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -301,6 +303,7 @@ extern "C" void msb_destroy(msb_ctx* c) {
   (void)hipFree(c->d_hop_up);
   (void)hipFree(c->d_hop_dn);
   (void)hipFree(c->d_ell_dn);
+  (void)hipFree(c->d_order_up);
   if (c->solve_stream) (void)hipStreamDestroy(c->solve_stream);
   (void)hipFree(c->d_small);
   if (c->ws) (void)hipFree(c->ws);
@@ -1107,6 +1110,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     info->apply_ept = seed_shape.ept;
     info->apply_nv = seed_shape.nv;
     info->apply_passes = seed_shape.passes;
+    info->apply_order = seed_shape.order;
     info->t_iter_ms = t_iter;
     info->t_flush_ms = t_flush;
     info->t_true_ms = t_true;
@@ -1336,6 +1340,7 @@ extern "C" msb_status msb_autotune(msb_ctx* ctx, int nsys, msb_prec prec, msb_sh
     out[i].elems_per_thread = table[i].first.ept;
     out[i].vectors = table[i].first.nv;
     out[i].passes = table[i].first.passes;
+    out[i].row_order = table[i].first.order;
     out[i].ms = table[i].second;
   }
   if (n_out) *n_out = (int)table.size();
@@ -1353,11 +1358,12 @@ extern "C" msb_status msb_set_shape(msb_ctx* ctx, int nsys, msb_prec prec, const
     ctx->shapes.erase(key);
     return MSB_OK;
   }
-  ApplyShape cand[64];
-  const int nc = apply_candidates(ctx->dn.n, elem_bytes(e), shape_class(nsys), ctx->lds_max, cand, 64);
+  ApplyShape cand[kMaxCand];
+  const int nc = apply_candidates(ctx->dn.n, elem_bytes(e), shape_class(nsys), ctx->lds_max, cand, kMaxCand);
   for (int i = 0; i < nc; ++i)
     if (cand[i].blk == shape->threads && cand[i].ept == shape->elems_per_thread &&
-        cand[i].nv == shape->vectors && cand[i].passes == (shape->passes == 2 ? 2 : 1)) {
+        cand[i].nv == shape->vectors && cand[i].passes == (shape->passes == 2 ? 2 : 1) &&
+        cand[i].order == (shape->row_order == 1 ? 1 : 0)) {
       ctx->shapes[key] = cand[i];
       return MSB_OK;
     }

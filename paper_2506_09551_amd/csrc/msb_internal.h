@@ -40,6 +40,7 @@ struct SpinTable {
   std::vector<uint32_t> conf;   // [n] ascending configs
   std::vector<uint32_t> off;    // [n + 1] CSR offsets into hop
   std::vector<uint32_t> hop;    // packed hop entries
+  std::vector<uint32_t> order;  // [n] ranks by ascending sum of occupied site indices, then rank
   int max_hops = 0;
 };
 bool build_spin_table(int L, int N, const std::vector<int>& bi, const std::vector<int>& bj,
@@ -70,6 +71,7 @@ struct TablesDev {
   const uint32_t* hop_up;
   const uint32_t* hop_dn;
   const uint32_t* ell_dn;     // [k_dn][n_dn] padded transposed hop list, kNoHop = empty
+  const uint32_t* order_up;   // [n_up] up-spin rows in level order (SpinTable::order)
   int n_up, n_dn, k_dn;
 };
 constexpr uint32_t kNoHop = 0xFFFFFFFFu;
@@ -83,11 +85,14 @@ enum ApplyMode : int {
 };
 
 // Launch shape of the apply kernel: threads per workgroup, elements per
-// thread, vectors (systems) per workgroup of the row kernel, and whether the
+// thread, vectors (systems) per workgroup of the row kernel, whether the
 // diagonal and the up-spin hops run first in a separate column-panel pass
-// (passes = 2).  blk == 0 selects the default.
+// (passes = 2), and the order in which the XCDs walk the rows (order 0: each
+// XCD one contiguous range of ranks of every system; order 1: the rows of
+// all systems in level order, one contiguous eighth per XCD).  blk == 0
+// selects the default.
 struct ApplyShape {
-  int blk, ept, nv, passes;
+  int blk, ept, nv, passes, order;
 };
 
 struct ApplyArgs {
@@ -112,6 +117,7 @@ struct ApplyArgs {
   ApplyShape shape;           // requested launch shape ({0,0,0,0} = default)
   size_t lds_max;             // LDS bytes one workgroup may use (device limit)
   const void* vin;            // set by the launcher for the second pass: v holds diag + up-spin hops
+  int ordered;                // set by the launcher: row order of the shape (ApplyShape::order)
 };
 
 enum class Elem { R64, C128, C64 };   // real float64, complex128, complex64 storage
@@ -339,6 +345,7 @@ struct msb_ctx {
   uint32_t* d_hop_up = nullptr;
   uint32_t* d_hop_dn = nullptr;
   uint32_t* d_ell_dn = nullptr;
+  uint32_t* d_order_up = nullptr;
   // private stream for the captured seed iterations (default priority)
   hipStream_t solve_stream = nullptr;
   double* d_small = nullptr;          // small reduction outputs
@@ -353,6 +360,7 @@ struct msb_ctx {
     t.off_up = d_off_up; t.off_dn = d_off_dn;
     t.hop_up = d_hop_up; t.hop_dn = d_hop_dn;
     t.ell_dn = d_ell_dn;
+    t.order_up = d_order_up;
     t.n_up = up.n; t.n_dn = dn.n; t.k_dn = dn.max_hops;
     return t;
   }

@@ -60,6 +60,19 @@ bool build_spin_table(int L, int N, const std::vector<int>& bi, const std::vecto
     out.hop.insert(out.hop.end(), row.begin(), row.end());
     out.off[r + 1] = (uint32_t)out.hop.size();
   }
+  // Level order: a hop between sites i and i+1 changes the sum of the
+  // occupied site indices by one, so on chains most hops join neighbouring
+  // levels; walking the rows level by level keeps a row's neighbours close
+  // in time (the apply kernel can use it for cache reuse).
+  std::vector<std::pair<int, uint32_t>> lev(out.n);
+  for (int r = 0; r < out.n; ++r) {
+    int s = 0;
+    for (int i = 0; i < L; ++i) s += ((out.conf[r] >> i) & 1u) ? i : 0;
+    lev[r] = {s, (uint32_t)r};
+  }
+  std::sort(lev.begin(), lev.end());
+  out.order.resize(out.n);
+  for (int r = 0; r < out.n; ++r) out.order[r] = lev[r].second;
   return true;
 }
 

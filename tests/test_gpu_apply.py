@@ -123,8 +123,9 @@ def test_every_apply_shape_matches_oracle(gpu, name, prec):
         seen = set()
         for nsys in (1, 3, 4):
             table = msb.msb_autotune(ctx, nsys, p)
-            assert table and all(t[4] > 0 for t in table)
+            assert table and all(t[5] > 0 for t in table)
             assert {t[3] for t in table} == {1, 2}          # single- and two-pass forms
+            assert {t[4] for t in table} == {0, 1}          # both row orders
             for shape in table:
                 msb.msb_set_shape(ctx, nsys, p, shape)
                 xt = torch.from_numpy(x[:nsys]).to(dt).cuda().contiguous()
@@ -133,8 +134,8 @@ def test_every_apply_shape_matches_oracle(gpu, name, prec):
                 torch.cuda.synchronize()
                 y = yt.cpu().numpy().astype(np.complex128)
                 err = np.max(np.abs(y - expect[:nsys])) / np.max(np.abs(expect[:nsys]))
-                assert err <= tol, f"{name} {prec} nsys={nsys} shape={shape[:4]}: {err:.3e}"
-                seen.add(shape[:4])
+                assert err <= tol, f"{name} {prec} nsys={nsys} shape={shape[:5]}: {err:.3e}"
+                seen.add(shape[:5])
             msb.msb_set_shape(ctx, nsys, p, None)
         assert len(seen) >= 2
         with pytest.raises(msb.MsbError):
