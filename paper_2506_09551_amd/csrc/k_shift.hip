@@ -264,6 +264,9 @@ __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double
   const int64_t last_e = a.D - 1;
   const void* bank_s = AB::offset(a.bank, (int64_t)s * a.cap * a.D);
   const int slot0 = stt * NS + wave * M;
+  // the list is sorted by descending range, so the wavefront's first slot has
+  // its longest one: chunks beyond it are staged for the other wavefronts only
+  const int Kw = a.lend ? __builtin_amdgcn_readfirstlane(a.lend[s * a.n_list + slot0]) : Kext;
   // uniform address in the constant address space: read through the scalar cache
   typedef __attribute__((address_space(4))) const double cdouble;
   cdouble* crow = (cdouble*)(coef + ((int64_t)s * a.n_list + slot0) * a.K * 2);
@@ -291,9 +294,10 @@ __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double
     }
     __syncthreads();
     cv<double> c_cur[M], c_nxt[M];
-    load_c(kb, c_cur);
-    for (int kk = 0; kk < kn; ++kk) {
-      if (kk + 1 < kn) load_c(kb + kk + 1, c_nxt);
+    const int kw = min(kn, Kw - kb);                      // wave-uniform; may be <= 0
+    if (kw > 0) load_c(kb, c_cur);
+    for (int kk = 0; kk < kw; ++kk) {
+      if (kk + 1 < kw) load_c(kb + kk + 1, c_nxt);
       cv<double> r[EPL];
 #pragma unroll
       for (int e = 0; e < EPL; ++e) r[e] = rt[kk][lane + kWave * e];

@@ -586,7 +586,7 @@ struct SolveBufs {
     alog = c.take<double>((size_t)B * maxit * 2 * sizeof(double));
     blog = c.take<double>((size_t)B * maxit * 2 * sizeof(double));
     rlog = c.take<double>((size_t)B * (maxit + 1) * sizeof(double));
-    const int n_stiles = n_list / flush_shifts_per_tile(0) + 1;   // bound for either engine
+    const int n_stiles = n_list;   // bound on the shift tiles of every engine (tiles hold >= 1 shift)
     dlist = c.take<int>((size_t)B * n_list * sizeof(int));
     dlend = c.take<int>((size_t)B * n_list * sizeof(int));
     dtile = c.take<int>((size_t)B * (n_stiles + 1) * sizeof(int));
@@ -867,7 +867,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       MSB_HIP(launch_coef(cf, cscr, st));
       FlushArgs fa;
       fa.bank = bank; fa.cap = cap; fa.coef = coef; fa.pw = nullptr; fa.ow = nullptr;
-      fa.pw_stride = 4; fa.ow_stride = 4; fa.list = dlist; fa.tile_k = dtile; fa.out = psib;
+      fa.pw_stride = 4; fa.ow_stride = 4; fa.list = dlist; fa.tile_k = dtile; fa.lend = dlend; fa.out = psib;
       fa.X = nullptr; fa.D = D; fa.n_shift = n_shift; fa.n_list = n_list; fa.K = Kc; fa.nsys = nb;
       fa.n_etiles = (int)((D + flush_elems_per_tile(engine) - 1) / flush_elems_per_tile(engine));
       fa.n_stiles = n_stiles;

@@ -248,6 +248,7 @@ struct FlushArgs {
   int pw_stride, ow_stride;     // doubles between consecutive entries of pw / ow
   const int* list;              // [nsys][n_list]
   const int* tile_k;            // [nsys][n_tiles] K extent of each shift tile
+  const int* lend;              // [nsys][n_list] slots of each listed shift (descending), or null
   void* out;                    // [nsys][n_shift][D]   (Psi, or P in place)
   const void* X;                // [nsys][n_shift][D]   p_prev (or null)
   int64_t D;
