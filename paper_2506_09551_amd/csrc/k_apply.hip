@@ -24,15 +24,26 @@
 
 namespace msb {
 
+// Amplitude with its sign flipped when bit 31 of `sb` is set (sign bits of
+// the hop entries; no branch and no select).
+__device__ __forceinline__ float flip_sign(float a, uint32_t sb) {
+  return __int_as_float(__float_as_int(a) ^ (int)sb);
+}
+__device__ __forceinline__ double flip_sign(double a, uint32_t sb) {
+  return __longlong_as_double(__double_as_longlong(a) ^ ((long long)sb << 32));
+}
+
+// 1024-thread shapes with few elements per thread ask for 8 waves per SIMD
+// (at most 64 VGPRs), so that two workgroups share a CU.
 template <typename S, typename Tc, bool CPLX, int EPT, int MODE, int NV, int BLK>
-__global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
+__global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k_apply(ApplyArgs a) {
   using Ax = Access<S, CPLX>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cv<Tc>* rows = reinterpret_cast<cv<Tc>*>(smem_raw);    // [NV][nd]
-  __shared__ Tc s_amp[NV][MSB_MAX_BOND_TYPES];
+  cv<Tc>* rows = reinterpret_cast<cv<Tc>*>(smem_raw);    // [NV][nd + 1], element nd = 0
 
   const int tid = threadIdx.x;
   const int nd = a.T.n_dn;
+  const int ldr = nd + 1;
   // (system group, row) of this workgroup and its column in the partials
   int s0, u, bx;
   if (a.ordered) {
@@ -69,10 +80,8 @@ __global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
       dre[v] = (Tc)sd->d_re;
       dim[v] = (Tc)sd->d_im;
       core[v] = sd->core;
-      if (tid < MSB_MAX_BOND_TYPES) s_amp[v][tid] = (Tc)sd->amp[tid];
     }
   }
-  __syncthreads();   // s_amp is read before the staging barrier
   bool any = false;
 #pragma unroll
   for (int v = 0; v < NV; ++v) any |= act[v];
@@ -83,15 +92,22 @@ __global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
 
   if (any) {
     const int64_t row0 = (int64_t)u * nd;
-    // own row elements d = tid + e * BLK in registers (diagonal, staging)
+    // columns d = tid + e * BLK; idle lanes (d >= nd) read column nd - 1 and
+    // store nothing, so every load below is unconditional
+    uint32_t voff[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int d = tid + e * BLK;
+      voff[e] = (uint32_t)(d < nd ? d : nd - 1);
+    }
+    // own row elements in registers (diagonal, staging)
     cv<Tc> xs[NV][EPT];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const void* x = Ax::offset(a.x, (int64_t)(s0 + v) * a.D);
+      const void* x = Ax::offset(a.x, (int64_t)(s0 + v) * a.D + row0);
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        const int d = tid + e * BLK;
-        xs[v][e] = (act[v] && d < nd) ? Ax::template load<Tc>(x, row0 + d) : cv<Tc>{(Tc)0, (Tc)0};
+        xs[v][e] = act[v] ? Ax::template load<Tc>(x, voff[e]) : cv<Tc>{(Tc)0, (Tc)0};
       }
     }
     const uint32_t cu = a.T.conf_up[u];
@@ -101,52 +117,53 @@ __global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int d = tid + e * BLK;
-      const uint32_t cd = (d < nd) ? a.T.conf_dn[d] : 0u;
+      const uint32_t cd = a.T.conf_dn[voff[e]];
       const Tc pc = (Tc)__builtin_popcount(cu & cd);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if (second_pass) {
-          acc[v][e] = (act[v] && d < nd)
-                          ? Ax::template load<Tc>(Ax::offset(a.vin, (int64_t)(s0 + v) * a.D), row0 + d)
-                          : cv<Tc>{(Tc)0, (Tc)0};
+          acc[v][e] = act[v] ? Ax::template load<Tc>(Ax::offset(a.vin, (int64_t)(s0 + v) * a.D + row0), voff[e])
+                             : cv<Tc>{(Tc)0, (Tc)0};
         } else {
           Tc dg = Uv[v] * pc + dre[v];
           if (core[v] >= 0) dg += Ucv[v] * (Tc)(((cu >> core[v]) & 1u) + ((cd >> core[v]) & 1u));
           acc[v][e].re = dg * xs[v][e].re - dim[v] * xs[v][e].im;
           acc[v][e].im = dg * xs[v][e].im + dim[v] * xs[v][e].re;
         }
-        if (d < nd) rows[v * nd + d] = xs[v][e];
+        if (d < nd) rows[v * ldr + d] = xs[v][e];
       }
     }
-    // H_up (x) I: whole neighbour rows from global memory, HG hops in flight
-    // per group (the hop list of u is uniform across the workgroup)
-    constexpr int HG = (EPT * NV >= 8) ? 1 : 8 / (EPT * NV);
-    const uint32_t h0 = a.T.off_up[u], h1 = second_pass ? h0 : a.T.off_up[u + 1];
-    for (uint32_t k = h0; k < h1; k += HG) {
-      cv<Tc> xn[HG][NV][EPT];
-      Tc cf[HG][NV];
+    if (tid < NV) rows[tid * ldr + nd] = cv<Tc>{(Tc)0, (Tc)0};
+    // H_up (x) I: whole neighbour rows from global memory.  The hop list of u
+    // is uniform across the workgroup (scalar loads; the coefficient is a
+    // scalar), and HG hops are loaded before their FMAs are issued.
+    constexpr int kLoadsInFlight = sizeof(Tc) == 4 ? 12 : 8;
+    constexpr int HG = (EPT * NV >= kLoadsInFlight) ? 1 : kLoadsInFlight / (EPT * NV);
+    const int h0 = second_pass ? 0 : (int)a.T.off_up[u];
+    const int nh = second_pass ? 0 : (int)a.T.off_up[u + 1] - h0;
+    auto up_hops = [&](auto G, int k) {
+      constexpr int NG = decltype(G)::value;
+      cv<Tc> xn[NG][NV][EPT];
+      Tc cf[NG][NV];
 #pragma unroll
-      for (int j = 0; j < HG; ++j) {
-        const bool hv = k + j < h1;
-        const uint32_t h = hv ? a.T.hop_up[k + j] : 0u;
-        const uint32_t ty = (h >> 1) & 127u;
-        const bool neg = (h & 1u) == 0u;
+      for (int j = 0; j < NG; ++j) {
+        const uint32_t h = a.T.hop_up[h0 + k + j];
+        const uint32_t ty = (h >> 1) & (MSB_MAX_BOND_TYPES - 1);
+        const uint32_t sb = (h & 1u) ? 0u : 0x80000000u;      // parity 0: -t
         const int64_t nrow = (int64_t)(h >> 16) * nd;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          Tc c = s_amp[v][ty];
-          cf[j][v] = (hv && act[v]) ? (neg ? -c : c) : (Tc)0;
-          const void* x = Ax::offset(a.x, (int64_t)(s0 + v) * a.D);
+          cf[j][v] = act[v] ? flip_sign((Tc)a.sys[s0 + v].amp[ty], sb) : (Tc)0;
+          // a ragged last group has slots past the last system: they read
+          // system s0 (always present) and add it with coefficient 0
+          const int sv = (s0 + v < a.nsys) ? s0 + v : s0;
+          const void* x = Ax::offset(a.x, (int64_t)sv * a.D + nrow);
 #pragma unroll
-          for (int e = 0; e < EPT; ++e) {
-            const int d = tid + e * BLK;
-            xn[j][v][e] = (hv && act[v] && d < nd) ? Ax::template load<Tc>(x, nrow + d)
-                                                   : cv<Tc>{(Tc)0, (Tc)0};
-          }
+          for (int e = 0; e < EPT; ++e) xn[j][v][e] = Ax::template load<Tc>(x, voff[e]);
         }
       }
 #pragma unroll
-      for (int j = 0; j < HG; ++j)
+      for (int j = 0; j < NG; ++j)
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -154,40 +171,48 @@ __global__ __launch_bounds__(BLK) void k_apply(ApplyArgs a) {
             acc[v][e].re += cf[j][v] * xn[j][v][e].re;
             acc[v][e].im += cf[j][v] * xn[j][v][e].im;
           }
-    }
+    };
+    int k = 0;
+    for (; k + HG <= nh; k += HG) up_hops(std::integral_constant<int, HG>{}, k);
+    for (; k < nh; ++k) up_hops(std::integral_constant<int, 1>{}, k);
     __syncthreads();   // staged rows complete
-    // I (x) H_dn: padded transposed hop table (next entry prefetched), one
-    // entry for all NV vectors
-    const int kdn = a.T.k_dn;
-    uint32_t hn[EPT];
+    // I (x) H_dn: one padded, transposed hop table per bond type; an entry is
+    // the target column with the parity-0 sign in bit 31, padding points at
+    // the zero element nd.  The next entry is prefetched.
+    const uint32_t* ell = a.T.ell_dn;
+    for (int t = 0; t < a.T.n_types; ++t) {
+      const int kt = a.T.k_type[t];
+      Tc amp[NV];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int d = tid + e * BLK;
-      hn[e] = (d < nd && kdn > 0) ? a.T.ell_dn[d] : kNoHop;
-    }
-    for (int k = 0; k < kdn; ++k) {
-      uint32_t h[EPT];
+      for (int v = 0; v < NV; ++v) amp[v] = act[v] ? (Tc)a.sys[s0 + v].amp[t] : (Tc)0;
+      uint32_t hn[EPT];
+      if (kt > 0) {
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        h[e] = hn[e];
-        const int d = tid + e * BLK;
-        hn[e] = (d < nd && k + 1 < kdn) ? a.T.ell_dn[(int64_t)(k + 1) * nd + d] : kNoHop;
+        for (int e = 0; e < EPT; ++e) hn[e] = ell[voff[e]];
       }
+      for (int kk = 0; kk < kt; ++kk) {
+        uint32_t h[EPT];
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        if (h[e] == kNoHop) continue;
-        const uint32_t tgt = h[e] >> 16, ty = (h[e] >> 1) & 127u;
-        const bool neg = (h[e] & 1u) == 0u;
+        for (int e = 0; e < EPT; ++e) h[e] = hn[e];
+        if (kk + 1 < kt) {
+          const uint32_t* nxt = ell + (int64_t)(kk + 1) * nd;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          if (!act[v]) continue;
-          Tc c = s_amp[v][ty];
-          c = neg ? -c : c;
-          const cv<Tc> xv = rows[v * nd + tgt];
-          acc[v][e].re += c * xv.re;
-          acc[v][e].im += c * xv.im;
+          for (int e = 0; e < EPT; ++e) hn[e] = nxt[voff[e]];
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const uint32_t sb = h[e] & 0x80000000u;
+          const int tgt = (int)(h[e] & 0xFFFFu);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const Tc c = flip_sign(amp[v], sb);
+            const cv<Tc> xv = rows[v * ldr + tgt];
+            acc[v][e].re += c * xv.re;
+            acc[v][e].im += c * xv.im;
+          }
         }
       }
+      ell += (int64_t)kt * nd;
     }
     // outputs
 #pragma unroll
@@ -267,46 +292,49 @@ __global__ __launch_bounds__(256) void k_apply_up(ApplyArgs a) {
   const int chunks = (nu + kRowsPerWg - 1) / kRowsPerWg;
   const int x = blockIdx.x % kNumXcd, l = blockIdx.x / kNumXcd;
   const int panel = x + kNumXcd * (l / chunks), chunk = l % chunks;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int d = panel * kPanel + lane;
   if (panel * kPanel >= nd) return;
   if (a.status && a.status[(int64_t)s * a.status_stride] != kActive) return;
-  const SysDev sd = a.sys[s];
-  const Tc U = (Tc)sd.U, Uc = (Tc)sd.Uc, dre = (Tc)sd.d_re, dim = (Tc)sd.d_im;
-  Tc amp[MSB_MAX_BOND_TYPES];
-#pragma unroll
-  for (int t = 0; t < MSB_MAX_BOND_TYPES; ++t) amp[t] = (Tc)sd.amp[t];
-  const void* xv = Ax::offset(a.x, (int64_t)s * a.D);
+  const SysDev* sd = a.sys + s;
+  const Tc U = (Tc)sd->U, Uc = (Tc)sd->Uc, dre = (Tc)sd->d_re, dim = (Tc)sd->d_im;
+  const int core = sd->core;
   void* vv = Ax::offset(a.v, (int64_t)s * a.D);
   const bool ok = d < nd;
-  const uint32_t cd = ok ? a.T.conf_dn[d] : 0u;
+  const uint32_t dc = (uint32_t)(ok ? d : nd - 1);        // idle lanes read a valid column
+  const uint32_t cd = a.T.conf_dn[dc];
   for (int r = wave; r < kRowsPerWg; r += 4) {
     const int u = chunk * kRowsPerWg + r;
     if (u >= nu) break;
     const uint32_t cu = a.T.conf_up[u];
-    const cv<Tc> xo = ok ? Ax::template load<Tc>(xv, (int64_t)u * nd + d) : cv<Tc>{(Tc)0, (Tc)0};
+    const cv<Tc> xo = Ax::template load<Tc>(Ax::offset(a.x, (int64_t)s * a.D + (int64_t)u * nd), dc);
     Tc dg = U * (Tc)__builtin_popcount(cu & cd) + dre;
-    if (sd.core >= 0) dg += Uc * (Tc)(((cu >> sd.core) & 1u) + ((cd >> sd.core) & 1u));
+    if (core >= 0) dg += Uc * (Tc)(((cu >> core) & 1u) + ((cd >> core) & 1u));
     cv<Tc> acc = {dg * xo.re - dim * xo.im, dg * xo.im + dim * xo.re};
-    const uint32_t h0 = a.T.off_up[u], h1 = a.T.off_up[u + 1];
-    constexpr int HG = 8;
-    for (uint32_t k = h0; k < h1; k += HG) {
-      cv<Tc> xn[HG];
-      Tc cf[HG];
+    const int h0 = (int)a.T.off_up[u], nh = (int)a.T.off_up[u + 1] - h0;
+    // the hop list is uniform per wavefront: scalar loads, scalar coefficients
+    auto hops = [&](auto G, int k) {
+      constexpr int NG = decltype(G)::value;
+      cv<Tc> xn[NG];
+      Tc cf[NG];
 #pragma unroll
-      for (int j = 0; j < HG; ++j) {
-        const bool hv = k + j < h1;
-        const uint32_t h = hv ? a.T.hop_up[k + j] : 0u;
-        const Tc c = amp[(h >> 1) & (MSB_MAX_BOND_TYPES - 1)];
-        cf[j] = hv ? (((h & 1u) == 0u) ? -c : c) : (Tc)0;
-        xn[j] = (hv && ok) ? Ax::template load<Tc>(xv, (int64_t)(h >> 16) * nd + d) : cv<Tc>{(Tc)0, (Tc)0};
+      for (int j = 0; j < NG; ++j) {
+        const uint32_t h = a.T.hop_up[h0 + k + j];
+        const uint32_t sb = (h & 1u) ? 0u : 0x80000000u;   // parity 0: -t
+        cf[j] = flip_sign((Tc)sd->amp[(h >> 1) & (MSB_MAX_BOND_TYPES - 1)], sb);
+        xn[j] = Ax::template load<Tc>(Ax::offset(a.x, (int64_t)s * a.D + (int64_t)(h >> 16) * nd), dc);
       }
 #pragma unroll
-      for (int j = 0; j < HG; ++j) {
+      for (int j = 0; j < NG; ++j) {
         acc.re += cf[j] * xn[j].re;
         acc.im += cf[j] * xn[j].im;
       }
-    }
+    };
+    constexpr int HG = 8;
+    int k = 0;
+    for (; k + HG <= nh; k += HG) hops(std::integral_constant<int, HG>{}, k);
+    for (; k < nh; ++k) hops(std::integral_constant<int, 1>{}, k);
     if (ok) Ax::store(vv, (int64_t)u * nd + d, acc);
   }
 }
@@ -351,7 +379,7 @@ static bool compiled(const ApplyShape& sh) {
 static bool usable(const ApplyShape& sh, int nd, size_t row_bytes, int nsys, size_t lds_max) {
   if (!compiled(sh) || (sh.passes != 1 && sh.passes != 2) || (sh.order != 0 && sh.order != 1)) return false;
   if ((int64_t)sh.blk * sh.ept < nd) return false;
-  if ((size_t)sh.nv * nd * row_bytes > lds_max) return false;
+  if ((size_t)sh.nv * (nd + 1) * row_bytes > lds_max) return false;
   if (sh.nv > 1 && sh.nv > nsys) return false;
   for (int i = 0; i < kNumShapes; ++i) {
     const ApplyShape& o = kShapes[i];
@@ -384,10 +412,10 @@ static ApplyShape default_shape(int nd, size_t row_bytes, int nsys, size_t lds_m
       const ApplyShape& o = kShapes[i];
       if (o.blk == blk && o.nv == 1 && (int64_t)o.blk * o.ept >= nd && (sh.ept == 0 || o.ept < sh.ept)) sh.ept = o.ept;
     }
-    if (sh.ept == 0 || (size_t)nd * row_bytes > lds_max) continue;
+    if (sh.ept == 0 || (size_t)(nd + 1) * row_bytes > lds_max) continue;
     for (int nv = 4; nv > 1; nv /= 2) {
       ApplyShape c{blk, sh.ept, nv, 1, 0};
-      if (compiled(c) && nv <= nsys && (size_t)nv * nd * row_bytes <= 40 * 1024) return c;
+      if (compiled(c) && nv <= nsys && (size_t)nv * (nd + 1) * row_bytes <= 40 * 1024) return c;
     }
     return sh;
   }
@@ -414,7 +442,7 @@ static hipError_t launch_mode(const ApplyArgs& a0, hipStream_t st) {
   ApplyArgs a = a0;
   const int nd = a.T.n_dn;
   const ApplyShape sh = resolve_shape(a, sizeof(cv<Tc>), MODE != kModeResid);
-  if (sh.ept == 0 || (int64_t)sh.blk * sh.ept < nd || (size_t)sh.nv * nd * sizeof(cv<Tc>) > a.lds_max)
+  if (sh.ept == 0 || (int64_t)sh.blk * sh.ept < nd || (size_t)sh.nv * (nd + 1) * sizeof(cv<Tc>) > a.lds_max)
     return hipErrorInvalidValue;
   a.nvec = sh.nv;
   a.vin = nullptr;
@@ -427,7 +455,7 @@ static hipError_t launch_mode(const ApplyArgs& a0, hipStream_t st) {
   }
   const int groups = (a.nsys + sh.nv - 1) / sh.nv;
   const dim3 grid = sh.order ? dim3(a.nbx * groups, 1) : dim3(a.nbx, groups);
-  const size_t lds = (size_t)sh.nv * nd * sizeof(cv<Tc>);
+  const size_t lds = (size_t)sh.nv * (nd + 1) * sizeof(cv<Tc>);
   hipError_t err = hipErrorInvalidValue;
 #define MSB_SHAPE_CASE(B, E, N)                                                             \
   else if (sh.blk == B && sh.ept == E && sh.nv == N) {                                      \

@@ -254,7 +254,7 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
     e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
     if (e == hipSuccess && lds > 0) c->lds_max = (size_t)lds;
   }
-  if (e == hipSuccess && (size_t)c->dn.n * 8 > c->lds_max) {
+  if (e == hipSuccess && (size_t)(c->dn.n + 1) * 8 > c->lds_max) {
     const int c_dn_n = c->dn.n;
     delete c;
     return fail(MSB_EINVAL, "msb_create: a down-spin row of " + std::to_string(c_dn_n) +
@@ -274,12 +274,32 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   if (e == hipSuccess) e = upload(&c->d_hop_up, c->up.hop);
   if (e == hipSuccess) e = upload(&c->d_hop_dn, c->dn.hop);
   if (e == hipSuccess) {
-    // padded, transposed copy of the down-spin hop lists: ell[k][d]
-    const int K = std::max(c->dn.max_hops, 1);
-    std::vector<uint32_t> ell((size_t)K * c->dn.n, kNoHop);
-    for (int d = 0; d < c->dn.n; ++d)
-      for (uint32_t k = c->dn.off[d]; k < c->dn.off[d + 1]; ++k)
-        ell[(size_t)(k - c->dn.off[d]) * c->dn.n + d] = c->dn.hop[k];
+    // padded, transposed copies of the down-spin hop lists, one per bond
+    // type: ell[t][k][d] = target | (even parity ? 1 << 31 : 0), padding n_dn
+    const int nd = c->dn.n;
+    std::vector<std::vector<uint32_t>> per(c->n_types);
+    for (int t = 0; t < c->n_types; ++t) {
+      int kt = 0;
+      for (int d = 0; d < nd; ++d) {
+        int cnt = 0;
+        for (uint32_t k = c->dn.off[d]; k < c->dn.off[d + 1]; ++k)
+          cnt += ((c->dn.hop[k] >> 1) & 127u) == (uint32_t)t;
+        kt = std::max(kt, cnt);
+      }
+      c->k_type_dn[t] = kt;
+      per[t].assign((size_t)kt * nd, (uint32_t)nd);
+      for (int d = 0; d < nd; ++d) {
+        int j = 0;
+        for (uint32_t k = c->dn.off[d]; k < c->dn.off[d + 1]; ++k) {
+          const uint32_t h = c->dn.hop[k];
+          if (((h >> 1) & 127u) != (uint32_t)t) continue;
+          per[t][(size_t)j * nd + d] = (h >> 16) | ((h & 1u) ? 0u : 0x80000000u);
+          ++j;
+        }
+      }
+    }
+    std::vector<uint32_t> ell;
+    for (int t = 0; t < c->n_types; ++t) ell.insert(ell.end(), per[t].begin(), per[t].end());
     e = upload(&c->d_ell_dn, ell);
   }
   if (e == hipSuccess) e = upload(&c->d_order_up, c->up.order);

@@ -70,9 +70,14 @@ struct TablesDev {
   const uint32_t* off_dn;
   const uint32_t* hop_up;
   const uint32_t* hop_dn;
-  const uint32_t* ell_dn;     // [k_dn][n_dn] padded transposed hop list, kNoHop = empty
+  // down-spin hops, one padded transposed table per bond type t (types in
+  // order, k_type[t] rows of n_dn entries each): entry = target column, with
+  // bit 31 set where the matrix element is -t (even parity); padding = n_dn
+  const uint32_t* ell_dn;
   const uint32_t* order_up;   // [n_up] up-spin rows in level order (SpinTable::order)
-  int n_up, n_dn, k_dn;
+  int n_up, n_dn, k_dn;       // k_dn: sum of k_type
+  int n_types;
+  int k_type[MSB_MAX_BOND_TYPES];
 };
 constexpr uint32_t kNoHop = 0xFFFFFFFFu;
 
@@ -347,6 +352,7 @@ struct msb_ctx {
   uint32_t* d_hop_dn = nullptr;
   uint32_t* d_ell_dn = nullptr;
   uint32_t* d_order_up = nullptr;
+  int k_type_dn[MSB_MAX_BOND_TYPES] = {0};   // rows of each bond type's down-spin hop table
   // private stream for the captured seed iterations (default priority)
   hipStream_t solve_stream = nullptr;
   double* d_small = nullptr;          // small reduction outputs
@@ -362,7 +368,12 @@ struct msb_ctx {
     t.hop_up = d_hop_up; t.hop_dn = d_hop_dn;
     t.ell_dn = d_ell_dn;
     t.order_up = d_order_up;
-    t.n_up = up.n; t.n_dn = dn.n; t.k_dn = dn.max_hops;
+    t.n_up = up.n; t.n_dn = dn.n; t.k_dn = 0;
+    t.n_types = n_types;
+    for (int i = 0; i < MSB_MAX_BOND_TYPES; ++i) {
+      t.k_type[i] = i < n_types ? k_type_dn[i] : 0;
+      t.k_dn += t.k_type[i];
+    }
     return t;
   }
 };
