@@ -167,13 +167,22 @@ def precision_extras(msb, ctx, wl, systems, E, E_G, box, info64, ms64, tol, n_su
     return res
 
 
-def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec):
-    """Batched form against the same right-hand sides solved one at a time, and
-    the block apply's rate for the whole batch and for one vector."""
+def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec, E_G, n_sub=4):
+    """Batched form against the same right-hand sides solved one at a time (in
+    its own precision, and in the plain complex128 form), the continued-fraction
+    spectrum error of the batched solution against the complex128 one on
+    `n_sub` incident energies per right-hand side, and the block apply's rate
+    for the whole batch and for one vector."""
+    import numpy as np
     import torch
 
     D = msb.msb_dim(ctx)
     n = wl.nrhs
+    # the batched solution's rows for the spectrum check (psi is reused below)
+    n_shift = len(wl.w_in)
+    sub_k = np.unique(np.linspace(0, n_shift - 1, n_sub).round().astype(int))
+    kk = torch.as_tensor(sub_k, device=psi.device)
+    phi_b = psi[:, kk].to(torch.complex128).reshape(n * len(sub_k), D)
 
     def separate():
         for j in range(n):
@@ -188,6 +197,29 @@ def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec):
     separate()
     torch.cuda.synchronize()
     ms_sep = (time.perf_counter() - t0) * 1e3
+    # plain complex128 multi-shift solves, one right-hand side at a time
+    phi_p = torch.empty_like(phi_b)
+    psi128 = torch.empty(1, n_shift, D, dtype=torch.complex128, device=psi.device)
+    msb.msb_solve(ctx, [systems[0]], E[0:1], wl.w_in, wl.seed_shift, tol, wl.maxit, msb.MSB_C128, psi128,
+                  want_true=True)   # warm-up: sizes the workspace
+    ms128 = 0.0
+    for j in range(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        msb.msb_solve(ctx, [systems[j]], E[j:j + 1], wl.w_in, wl.seed_shift, tol, wl.maxit, msb.MSB_C128,
+                      psi128, want_true=True)
+        torch.cuda.synchronize()
+        ms128 += (time.perf_counter() - t0) * 1e3
+        phi_p[j * len(sub_k):(j + 1) * len(sub_k)] = psi128[0, kk]
+    del psi128
+    torch.cuda.empty_cache()
+    gs = msb.make_system(E_G=E_G)
+    I_b, _ = msb.msb_spectrum(ctx, gs, phi_b, wl.w_loss, wl.eta, 1500, 1e-10)
+    I_p, _ = msb.msb_spectrum(ctx, gs, phi_p, wl.w_loss, wl.eta, 1500, 1e-10)
+    del phi_b, phi_p
+    torch.cuda.empty_cache()
+    peak = np.max(np.abs(I_p), axis=1)
+    err = np.max(np.abs(np.asarray(I_b) - np.asarray(I_p)), axis=1) / peak
     dt = psi.dtype
     x = torch.randn(n, D, dtype=dt, device=psi.device)
     y = torch.empty_like(x)
@@ -197,6 +229,11 @@ def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec):
     res = {
         "separate_ms": round(ms_sep, 3), "batched_ms": round(ms_batched, 3),
         "speedup_batched_vs_separate": round(ms_sep / ms_batched, 3),
+        "plain_c128_separate_ms": round(ms128, 3),
+        "speedup_batched_vs_plain_c128": round(ms128 / ms_batched, 3),
+        "spectrum_rel_err_vs_c128": {"max": float(err.max()), "median": float(np.median(err)),
+                                     "shifts": [float(wl.w_in[k]) for k in sub_k],
+                                     "norm": "max_w |I_batched - I_c128| / max_w I_c128 per (RHS, w_in)"},
         "apply_block_ms": round(ms_blk, 4), "apply_one_ms": round(ms_one, 4),
         "apply_block_GBs": round(2 * n * D * el / (ms_blk * 1e-3) / 1e9, 1),
         "apply_one_GBs": round(2 * D * el / (ms_one * 1e-3) / 1e9, 1),
@@ -513,7 +550,7 @@ def main():
     }
 
     if not args.no_extras and wl.nrhs > 1 and prec == msb.MSB_C64:
-        out["batched"] = batched_extras(msb, ctx, wl, systems, E, psi, ms_per_step, args.tol, prec)
+        out["batched"] = batched_extras(msb, ctx, wl, systems, E, psi, ms_per_step, args.tol, prec, E_G)
     elif not args.no_extras and prec == msb.MSB_C64:
         box = [psi]       # hand the only reference over so the c64 result can be freed
         del psi

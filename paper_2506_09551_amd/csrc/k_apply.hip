@@ -110,6 +110,24 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
         xs[v][e] = act[v] ? Ax::template load<Tc>(x, voff[e]) : cv<Tc>{(Tc)0, (Tc)0};
       }
     }
+    // the operand of the fused reduction (r for sigma, E for the residual) is
+    // requested now, so that its latency hides behind the hops
+    constexpr bool kAuxEarly = (MODE == kModeBilinear || MODE == kModeResid) && EPT * NV <= 8 && BLK < 1024;
+    cv<double> auxv[kAuxEarly ? NV : 1][kAuxEarly ? EPT : 1];
+    if constexpr (kAuxEarly) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          auxv[v][e] = {0.0, 0.0};
+          if (act[v]) {
+            if constexpr (MODE == kModeBilinear)
+              auxv[v][e] = Ax::template load_nt<double>(a.aux, aux_off[v] + row0 + voff[e]);
+            else
+              auxv[v][e] = Access<double, true>::template load_nt<double>(a.aux, aux_off[v] + row0 + voff[e]);
+          }
+        }
+    }
     const uint32_t cu = a.T.conf_up[u];
     cv<Tc> acc[NV][EPT];
     const bool second_pass = a.vin != nullptr;   // diagonal and up-spin hops already in vin
@@ -137,7 +155,8 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
     // H_up (x) I: whole neighbour rows from global memory.  The hop list of u
     // is uniform across the workgroup (scalar loads; the coefficient is a
     // scalar), and HG hops are loaded before their FMAs are issued.
-    constexpr int kLoadsInFlight = sizeof(Tc) == 4 ? 12 : 8;
+    // (256-thread shapes have the registers for twice as many)
+    constexpr int kLoadsInFlight = (sizeof(Tc) == 4 ? 12 : 8) * (BLK >= 1024 ? 1 : 2);
     constexpr int HG = (EPT * NV >= kLoadsInFlight) ? 1 : kLoadsInFlight / (EPT * NV);
     const int h0 = second_pass ? 0 : (int)a.T.off_up[u];
     const int nh = second_pass ? 0 : (int)a.T.off_up[u + 1] - h0;
@@ -228,7 +247,9 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
         if constexpr (MODE != kModeResid) Ax::store_nt(a.v, vbase + gi, vv);
         if constexpr (MODE == kModeBilinear) {
           // sigma = sum r_i v_i (unconjugated, r^T v) with r the stored residual
-          const cv<double> r = Ax::template load_nt<double>(a.aux, aux_off[v] + gi);
+          cv<double> r;
+          if constexpr (kAuxEarly) r = auxv[v][e];
+          else r = Ax::template load_nt<double>(a.aux, aux_off[v] + gi);
           const cv<double> vs = {(double)(S)vv.re, (double)(S)vv.im};   // value as stored
           part[v][0] += r.re * vs.re - r.im * vs.im;
           part[v][1] += r.re * vs.im + r.im * vs.re;
@@ -239,7 +260,9 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
           part[v][1] += (double)qv.re * (double)vv.im - (double)qv.im * (double)vv.re;
           part[v][2] += (double)vv.re * (double)vv.re + (double)vv.im * (double)vv.im;
         } else if constexpr (MODE == kModeResid) {
-          const cv<double> ee = Access<double, true>::template load_nt<double>(a.aux, aux_off[v] + gi);
+          cv<double> ee;
+          if constexpr (kAuxEarly) ee = auxv[v][e];
+          else ee = Access<double, true>::template load_nt<double>(a.aux, aux_off[v] + gi);
           const double dr = ee.re - (double)vv.re, di = ee.im - (double)vv.im;
           part[v][2] += dr * dr + di * di;
         }
