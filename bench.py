@@ -33,8 +33,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # profiles/solve_scale_L12_hbm_counters.md: raw FETCH_SIZE / WRITE_SIZE in KiB
 # and the copy-calibrated factors; valid while the kernel source is unchanged.
 FLUSH_COUNTERS = {
-    "source": "paper_2506_09551_amd/csrc/k_shift.hip", "sha256_16": "43c9b817d20a01cd",
-    "fetch_kib": 79030301.4, "write_kib": 32016600.0, "fetch_factor": 2.0, "write_factor": 1.0,
+    "source": "paper_2506_09551_amd/csrc/k_shift.hip", "sha256_16": "a6a4b1eec48e1f46",
+    "fetch_kib": 83024170.8, "write_kib": 32016600.0, "fetch_factor": 2.0, "write_factor": 1.0,
     "workload": "scale_L12_N6",
 }
 
@@ -197,7 +197,9 @@ def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec, E_G, n_
     separate()
     torch.cuda.synchronize()
     ms_sep = (time.perf_counter() - t0) * 1e3
-    # plain complex128 multi-shift solves, one right-hand side at a time
+    # plain complex128 multi-shift solves, one right-hand side at a time (the
+    # complex64 solves' workspace is released first: it holds most of the HBM)
+    msb.msb_release_workspace(ctx)
     phi_p = torch.empty_like(phi_b)
     psi128 = torch.empty(1, n_shift, D, dtype=torch.complex128, device=psi.device)
     msb.msb_solve(ctx, [systems[0]], E[0:1], wl.w_in, wl.seed_shift, tol, wl.maxit, msb.MSB_C128, psi128,

@@ -169,6 +169,11 @@ typedef struct {
  * Errors: MSB_EINVAL for sizes outside the limits; MSB_EHIP on upload failure. */
 msb_status msb_create(const msb_model* model, msb_ctx** out);
 void msb_destroy(msb_ctx* ctx);
+/* Frees the context's solve / spectrum workspace (the next call that needs it
+ * allocates it again), e.g. before a caller allocates large buffers of its
+ * own.  Waits for the context's stream first.  Errors: MSB_EINVAL for a null
+ * context; MSB_EHIP if the wait or the free fails. */
+msb_status msb_release_workspace(msb_ctx* ctx);
 int64_t msb_dim(const msb_ctx* ctx);
 /* Per-spin sector sizes and bond-type count (any pointer may be NULL). */
 msb_status msb_sector_info(const msb_ctx* ctx, int* n_up_states, int* n_dn_states, int* n_bond_types);

@@ -82,6 +82,8 @@ def lib():
         L.msb_create.restype = c_int
         L.msb_destroy.argtypes = [c_void_p]
         L.msb_destroy.restype = None
+        L.msb_release_workspace.argtypes = [c_void_p]
+        L.msb_release_workspace.restype = c_int
         L.msb_dim.argtypes = [c_void_p]
         L.msb_dim.restype = c_int64
         L.msb_sector_info.argtypes = [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int)]
@@ -139,7 +141,7 @@ def lib():
 
 def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
-    return ["msb_create", "msb_destroy", "msb_dim", "msb_sector_info", "msb_last_error",
+    return ["msb_create", "msb_destroy", "msb_release_workspace", "msb_dim", "msb_sector_info", "msb_last_error",
             "msb_device_ok", "msb_apply", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
             "msb_combine", "msb_spectrum", "msb_autotune", "msb_set_shape",
             "msb_mlp_num_params", "msb_mlp_create", "msb_mlp_destroy", "msb_mlp_set_params",
@@ -228,6 +230,11 @@ def msb_create(n_sites: int, n_up: int, n_dn: int, bonds, U: float) -> c_void_p:
 
 def msb_destroy(ctx):
     lib().msb_destroy(ctx)
+
+
+def msb_release_workspace(ctx):
+    """Free the context's solve / spectrum workspace (reallocated on next use)."""
+    _check(lib().msb_release_workspace(ctx))
 
 
 def msb_dim(ctx) -> int:

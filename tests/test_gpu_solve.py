@@ -60,6 +60,22 @@ def test_tiny_all_shifts_match_direct_solve(tiny):
     assert np.max(info["resid_true"]) <= 1e-11
 
 
+def test_release_workspace_then_solve_again(tiny):
+    """Freeing the workspace between two identical solves changes nothing:
+    the second call allocates it again and gives the same bits."""
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E = W.random_vector(D, 4).astype(np.complex128)
+    sysd = msb.make_system(core_site=0, Uc=wl.Uc, E_G=-2.6661474201323485, Gamma=wl.Gamma)
+    _, info1, psi1 = _run(msb, ctx, [sysd], E, wl.w_in, 1e-10, 3000, msb.MSB_C128)
+    msb.msb_release_workspace(ctx)
+    msb.msb_release_workspace(ctx)          # a second release is a no-op
+    _, info2, psi2 = _run(msb, ctx, [sysd], E, wl.w_in, 1e-10, 3000, msb.MSB_C128)
+    assert info2["t_alloc_ms"] > 0.0
+    assert info1["iters"] == info2["iters"]
+    assert np.array_equal(psi1, psi2)
+
+
 def test_seed_shift_and_batched_systems(tiny):
     msb, ctx, wl, m = tiny
     D = msb.msb_dim(ctx)
