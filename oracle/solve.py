@@ -39,6 +39,17 @@ Readings of the printed algorithm (each verified against ``direct_solve`` by
 7. Breakdown.  The method is silent on it; the oracle stops when
    |r^T A p| <= 1e-14 |r| |A p| or, with shifts still open, when
    |r^T r| <= 1e-14 |r|^2 (convergence is tested first).
+8. Seed exhaustion.  Also silent: a seed far from the resonances converges
+   much faster than the shifts it carries, and once |r_{m+1}| falls below
+   1e-150 |E| its bilinear products (about |r|^2) leave the normal float64
+   range and beta = rho_{m+1}/rho_m soon turns inf or NaN.  The seed then stops and the open shifts are reported
+   unconverged (``exhausted``); Appendix E's reseeding is the remedy.
+9. Reseeding (Appendix E).  The collinearity deviation of shift w is
+   dr(w) = |r_t(w) - r(w)| with the true residual r_t = E - (A - w)Psi(w) and
+   the recurrence residual r(w) = r_M / zeta_M(w) at the shift's last
+   iteration M.  A shift is restarted when dr(w) > reseed_tol |E| or when it
+   was never frozen; the failing shift with the largest dr becomes the next
+   seed, and the failing shifts are solved again from r_0 = E with it.
 """
 from __future__ import annotations
 
@@ -91,11 +102,16 @@ class MSBiCGResult:
         self.zeta = None          # zeta history [iters+1, n_shift] (if requested)
         self.breakdown = False
         self.converged = False
+        self.exhausted = False
+        self.r_shift = None       # [n_shift, D] r_M / zeta_M at each shift's last iteration (if requested)
+
+
+SEED_FLOOR = 1e-150      # reading 8
 
 
 def msbicg_reference(A_apply, E: np.ndarray, w_in, tol: float, maxit: int,
                      seed_shift: float = 0.0, keep_zeta: bool = False,
-                     breakdown_tol: float = 1e-14) -> MSBiCGResult:
+                     breakdown_tol: float = 1e-14, keep_r: bool = False) -> MSBiCGResult:
     """Multi-shift COCG for (A - w I) Psi = E, all shifts from one seed.
 
     ``A_apply(x)`` returns A x with A = H' - E_G - i Gamma.  The seed system is
@@ -123,6 +139,7 @@ def msbicg_reference(A_apply, E: np.ndarray, w_in, tol: float, maxit: int,
     conv_iter = np.full(n, -1, dtype=np.int64)
     res.rnorm.append(np.linalg.norm(r))
     zhist = [zeta.copy()] if keep_zeta else None
+    r_shift = np.repeat(E[None, :], n, axis=0) if keep_r else None    # r_0 / zeta_0 = E
 
     if not (abs(rho) > breakdown_tol * normE * normE):
         # E = 0 is solved by Psi = 0; E^T E = 0 with E != 0 cannot start COCG
@@ -157,6 +174,8 @@ def msbicg_reference(A_apply, E: np.ndarray, w_in, tol: float, maxit: int,
         psi[a] += alpha_w[:, None] * p_w[a]
         newly = a & (rn / np.abs(zeta_next) <= tol * normE)
         conv_iter[newly] = m + 1
+        if keep_r:
+            r_shift[a] = r_new[None, :] / zeta_next[a, None]
         zeta_prev = np.where(a, zeta, zeta_prev)
         zeta = np.where(a, zeta_next, zeta)
         active = a & ~newly
@@ -174,6 +193,9 @@ def msbicg_reference(A_apply, E: np.ndarray, w_in, tol: float, maxit: int,
         if not np.any(active):
             m += 1
             break
+        if not (rn > SEED_FLOOR * normE and np.isfinite(beta)):
+            res.exhausted = True    # reading 8: stop before the products underflow
+            break
         if not (abs(rho) > breakdown_tol * rn * rn):
             res.breakdown = True        # rho_{m+1} = 0 while shifts are still open
             break
@@ -184,6 +206,7 @@ def msbicg_reference(A_apply, E: np.ndarray, w_in, tol: float, maxit: int,
     res.iters = len(res.alpha)
     res.conv_iter = conv_iter
     res.converged = not np.any(active)
+    res.r_shift = r_shift
     if keep_zeta:
         res.zeta = np.array(zhist)
     return res
@@ -208,3 +231,53 @@ def residual_polynomial(alpha, beta, x):
         out.append(P.copy())
         a_prev, b_prev = a, b
     return np.array(out)
+
+
+class ReseedResult:
+    def __init__(self):
+        self.psi = None           # [n_shift, D]
+        self.seed_of = None       # [n_shift] seed whose solve gave the final Psi of each shift
+        self.dr = None            # [n_shift] final collinearity deviation dr(w) / |E|
+        self.frozen = None        # [n_shift] bool: the final solve froze the shift
+        self.seeds = []           # seeds in the order used
+        self.iters = []           # seed iterations of every round
+
+
+def reseed_solve(A_apply, E: np.ndarray, w_in, tol: float, maxit: int, seed_shift: float,
+                 reseed_tol: float, max_rounds: int = 8) -> ReseedResult:
+    """Appendix E: MSBiCG with adaptive reseeding (readings 8 and 9).
+
+    Round 0 solves every shift from ``seed_shift``.  After each round, every
+    shift of that round gets dr(w) = |r_t(w) - r(w)| (true residual against
+    the recurrence residual r_M / zeta_M); shifts with dr > reseed_tol |E| or
+    never frozen fail, the failing shift with the largest dr is the next seed,
+    and only the failing shifts are solved again, from r_0 = E.  Stops when no
+    shift fails or after ``max_rounds`` rounds.
+    """
+    E = np.asarray(E, dtype=np.complex128)
+    w = np.asarray(w_in, dtype=np.float64)
+    n = len(w)
+    normE = np.linalg.norm(E)
+    out = ReseedResult()
+    out.psi = np.zeros((n, E.shape[0]), dtype=np.complex128)
+    out.seed_of = np.full(n, np.nan)
+    out.dr = np.full(n, np.inf)
+    out.frozen = np.zeros(n, dtype=bool)
+    todo = np.arange(n)
+    seed = float(seed_shift)
+    for _ in range(max_rounds):
+        res = msbicg_reference(A_apply, E, w[todo], tol, maxit, seed_shift=seed, keep_r=True)
+        out.seeds.append(seed)
+        out.iters.append(res.iters)
+        for j, k in enumerate(todo):
+            rt = E - (A_apply(res.psi[j]) - w[k] * res.psi[j])
+            out.psi[k] = res.psi[j]
+            out.seed_of[k] = seed
+            out.dr[k] = np.linalg.norm(rt - res.r_shift[j]) / normE
+            out.frozen[k] = res.conv_iter[j] >= 0
+        fail = todo[(out.dr[todo] > reseed_tol) | ~out.frozen[todo]]
+        if len(fail) == 0:
+            break
+        seed = float(w[fail[np.argmax(out.dr[fail])]])
+        todo = fail
+    return out

@@ -166,3 +166,65 @@ def test_rho_breakdown_detected():
     E[0], E[1] = 1.0, 1.0j
     res = so.msbicg_reference(lambda x: Hp @ x - (1 + 1j) * x, E, [0.0, 1.0], 1e-10, 10)
     assert res.breakdown and res.iters == 0
+
+
+@pytest.fixture(scope="module")
+def sharp():
+    """The L=8 ring with a narrow core-hole broadening (Gamma = 0.3): an edge
+    seed (w_in = -12) converges far faster than the resonant shifts it carries."""
+    bonds = W.chain_bonds(8, 1.0)
+    B = hb.Basis(8, 4, 4)
+    E_G, G, _ = gs.dense_ground_state(hb.hamiltonian(B, bonds, 8.0))
+    Hp = hb.hamiltonian(B, bonds, 8.0, core_site=0, Uc=-4.0)
+    Gamma = 0.3
+    w = np.linspace(-12.0, 12.0, 64)
+    E = G.astype(np.complex128)
+
+    def A(x):
+        return Hp @ x - (E_G + 1j * Gamma) * x
+    ref = so.direct_solve(Hp, E, E_G, Gamma, w, method="eig")
+    return A, E, w, ref
+
+
+def test_edge_seed_exhausts_without_nan(sharp):
+    """Reading 8: the seed stops at the float64 floor instead of producing
+    NaN; the shifts frozen before that are the direct solution."""
+    A, E, w, ref = sharp
+    res = so.msbicg_reference(A, E, w, 1e-10, 3000, seed_shift=-12.0, keep_r=True)
+    assert res.exhausted and not res.converged and not res.breakdown
+    assert res.rnorm[-1] <= so.SEED_FLOOR * np.linalg.norm(E) * 1e3
+    assert np.all(np.isfinite(res.psi))
+    frozen = res.conv_iter >= 0
+    assert 0 < frozen.sum() < len(w)
+    err = np.linalg.norm(res.psi[frozen] - ref[frozen], axis=1) / np.linalg.norm(ref[frozen], axis=1)
+    assert err.max() <= 1e-8
+    # the open shifts have not met tol, some by orders of magnitude
+    rt = np.array([np.linalg.norm(E - (A(res.psi[k]) - w[k] * res.psi[k])) for k in np.nonzero(~frozen)[0]])
+    assert rt.min() > 1e-10 * np.linalg.norm(E) and rt.max() > 1e-6 * np.linalg.norm(E)
+
+
+def test_collinearity_deviation_vanishes_for_a_good_seed(sharp):
+    """dr(w) of Appendix E is rounding-small when collinearity holds (seed 0),
+    which pins the stored recurrence residuals r_M / zeta_M."""
+    A, E, w, ref = sharp
+    out = so.reseed_solve(A, E, w, 1e-10, 3000, 0.0, 1e-9)
+    assert out.seeds == [0.0] and out.frozen.all()
+    assert out.dr.max() <= 1e-12
+    res = so.msbicg_reference(A, E, w, 1e-10, 3000, seed_shift=0.0)
+    assert np.array_equal(out.psi, res.psi)
+
+
+def test_reseeding_recovers_from_an_edge_seed(sharp):
+    """Appendix E: the failing shifts restart from the worst one and every
+    shift ends at the direct solution."""
+    A, E, w, ref = sharp
+    out = so.reseed_solve(A, E, w, 1e-10, 3000, -12.0, 1e-9)
+    assert len(out.seeds) >= 2 and out.seeds[0] == -12.0
+    assert out.frozen.all() and out.dr.max() <= 1e-9
+    assert set(out.seed_of) <= set(out.seeds)
+    assert np.all(np.isin(out.seeds[1:], w))       # later seeds are shifts of the list
+    err = np.linalg.norm(out.psi - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= 1e-8
+    # the shifts kept from round 0 are exactly those the edge seed froze
+    r0 = so.msbicg_reference(A, E, w, 1e-10, 3000, seed_shift=-12.0)
+    assert np.array_equal(out.seed_of == -12.0, r0.conv_iter >= 0)
