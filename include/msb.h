@@ -225,7 +225,11 @@ msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, const double* x
  * |r_m| / |zeta_m(w_k)| <= tol |E_s|.  MSB_C64 runs the vectors in complex64
  * with FP64 reductions and scalars, and replaces the seed residual by the
  * FP64 true residual every opts->replace_every iterations.
- * Returns MSB_NOT_CONVERGED (psi holds the last iterates), MSB_FLOOR (MSB_C64
+ * The seed also stops when its residual falls below 1e-150 |E_s| with shifts
+ * still open (its bilinear products would leave the float64 range; a seed far
+ * from the resonances converges much faster than the shifts it carries).
+ * Returns MSB_NOT_CONVERGED (psi holds the last iterates; cap reached or seed
+ * exhausted), MSB_FLOOR (MSB_C64
  * only; psi holds the iterates at the attainable accuracy, shifts that had not
  * met tol have shift_iters = -1 and their resid_true says what was reached) or
  * MSB_BREAKDOWN (psi holds the iterates before the breakdown).  Precedence when
@@ -237,10 +241,32 @@ msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, const void* 
                      int maxit, msb_prec prec, void* psi, msb_info* info,
                      const msb_opts* opts, void* stream);
 
+/* Adaptive reseeding (Appendix E) around msb_solve, one system at a time.
+ * Round 0 solves every shift of system s from seed_shift.  After each round,
+ * a shift of that round fails when its FP64 true residual |r_t(w)| / |E_s|
+ * exceeds reseed_tol or it never froze.  (For a frozen shift the paper's
+ * collinearity deviation |r_t(w) - r_m / zeta_m(w)| differs from |r_t(w)| by
+ * at most tol |E_s|, so reseed_tol should be well above tol.)  The failing
+ * shift with the largest true residual becomes the seed and only the failing
+ * shifts are solved again from r_0 = E_s; at most max_rounds rounds in all.
+ * E: [nsys][D] C128; psi: [nsys][n_shift][D] of prec (device).  Host outputs
+ * (each may be NULL): seed_of [nsys][n_shift] the seed whose solve gave each
+ * final psi row, resid_true [nsys][n_shift] the final true residuals,
+ * rounds [nsys] the rounds used.  opts applies to every inner solve.
+ * Returns MSB_OK when every shift passes, MSB_NOT_CONVERGED when some still
+ * fail after max_rounds, MSB_EINVAL for bad arguments (reseed_tol <= 0,
+ * max_rounds < 1), or the first MSB_ENOMEM / MSB_EHIP of an inner solve. */
+msb_status msb_solve_reseed(msb_ctx* ctx, const msb_system* sys, int nsys, const void* E,
+                            const double* w_in, int n_shift, double seed_shift, double tol,
+                            int maxit, msb_prec prec, double reseed_tol, int max_rounds,
+                            void* psi, double* seed_of, double* resid_true, int* rounds,
+                            const msb_opts* opts, void* stream);
+
 /* Autotuner of the Hamiltonian apply (the block SpMM of the batched form).
  * Times every compiled launch shape usable for this context's row length with
- * min(nsys, 16) systems in `prec` on scratch vectors (5 timed applies each,
- * HIP events), keeps the fastest in the context for every later apply of that
+ * min(nsys, 16) systems in `prec` on scratch vectors (HIP events: one warm-up
+ * and one timed apply each, four more for shapes within 1.5x of the best so
+ * far; the reported time is the mean of the timed ones), keeps the fastest in the context for every later apply of that
  * (nsys class, prec), and reports the table (out may be NULL).  msb_solve,
  * msb_apply, msb_apply_timed, msb_ground_state and msb_spectrum tune on their
  * first use of a (nsys class, precision) unless opts->autotune = -1.

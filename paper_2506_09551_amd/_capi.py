@@ -104,6 +104,11 @@ def lib():
                                 c_int, c_double, c_double, c_int, c_int, c_void_p,
                                 POINTER(msb_info), POINTER(msb_opts), c_void_p]
         L.msb_solve.restype = c_int
+        L.msb_solve_reseed.argtypes = [c_void_p, POINTER(msb_system), c_int, c_void_p, POINTER(c_double),
+                                       c_int, c_double, c_double, c_int, c_int, c_double, c_int, c_void_p,
+                                       POINTER(c_double), POINTER(c_double), POINTER(c_int),
+                                       POINTER(msb_opts), c_void_p]
+        L.msb_solve_reseed.restype = c_int
         L.msb_combine.argtypes = [c_void_p, c_int, c_int, c_int, c_void_p, POINTER(c_double),
                                   POINTER(c_double), POINTER(c_int), POINTER(c_double),
                                   POINTER(c_double), c_void_p, c_void_p]
@@ -143,6 +148,7 @@ def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["msb_create", "msb_destroy", "msb_release_workspace", "msb_dim", "msb_sector_info", "msb_last_error",
             "msb_device_ok", "msb_apply", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
+            "msb_solve_reseed",
             "msb_combine", "msb_spectrum", "msb_autotune", "msb_set_shape",
             "msb_mlp_num_params", "msb_mlp_create", "msb_mlp_destroy", "msb_mlp_set_params",
             "msb_mlp_get_params", "msb_mlp_grad", "msb_mlp_train", "msb_mlp_predict", "msb_mlp_fallback"]
@@ -342,6 +348,34 @@ def msb_solve(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit: int, 
     if raise_on_fail and st != MSB_OK:
         raise MsbError(st, lib().msb_last_error().decode())
     return st, out
+
+
+def msb_solve_reseed(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit: int, prec: int, psi,
+                     reseed_tol: float, max_rounds: int = 8, opts: dict | None = None, stream=None,
+                     raise_on_fail=True):
+    """Multi-shift solve with adaptive reseeding; returns (status, info dict with
+    seed_of [nsys][n_shift], resid_true [nsys][n_shift], rounds [nsys])."""
+    import numpy as np
+    import torch
+    arr, n = _systems(systems)
+    D = msb_dim(ctx)
+    w = np.ascontiguousarray(np.asarray(w_in, dtype=np.float64))
+    ns = len(w)
+    seed_of = np.empty((n, ns), dtype=np.float64)
+    rt = np.empty((n, ns), dtype=np.float64)
+    rounds = np.empty(n, dtype=np.int32)
+    o = msb_opts()
+    for k, v in (opts or {}).items():
+        setattr(o, k, v)
+    st = lib().msb_solve_reseed(ctx, arr, n, _ptr(E, torch.complex128, n * D, "E"),
+                                w.ctypes.data_as(POINTER(c_double)), ns, float(seed_shift), float(tol),
+                                int(maxit), int(prec), float(reseed_tol), int(max_rounds),
+                                _ptr(psi, _prec_dtype(prec), n * ns * D, "psi"),
+                                seed_of.ctypes.data_as(POINTER(c_double)), rt.ctypes.data_as(POINTER(c_double)),
+                                rounds.ctypes.data_as(POINTER(c_int)), ctypes.byref(o), _stream_ptr(stream))
+    if raise_on_fail and st != MSB_OK:
+        raise MsbError(st, lib().msb_last_error().decode())
+    return st, {"status": st, "seed_of": seed_of, "resid_true": rt, "rounds": rounds}
 
 
 def msb_combine(ctx, psi, nsys: int, n_shift: int, prec: int, phases, phi, o1=None, stream=None):

@@ -207,6 +207,8 @@ __global__ __launch_bounds__(kBlock) void k_cocg_book(CocgArgs a) {
     t.m = m + 1;
     if (t.n_active == 0) {
       t.status = kDone;
+    } else if (!(rn > kSeedFloor * t.normE) || !isfinite(beta.re) || !isfinite(beta.im)) {
+      t.status = kExhausted;
     } else if (!(cabs(rho_new) > 1e-14 * rn * rn)) {
       t.status = kBreakdown;            // rho_{m+1} = 0 with shifts still open
       t.breakdown_iter = m + 1;

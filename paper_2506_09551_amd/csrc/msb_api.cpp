@@ -1070,7 +1070,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       if (t.status == kBreakdown) {
         result = MSB_BREAKDOWN;
         if (brk_iter < 0 || t.breakdown_iter < brk_iter) brk_iter = t.breakdown_iter;
-      } else if (t.status == kMaxit && (result == MSB_OK || result == MSB_FLOOR)) {
+      } else if ((t.status == kMaxit || t.status == kExhausted) && (result == MSB_OK || result == MSB_FLOOR)) {
         result = MSB_NOT_CONVERGED;
       } else if (t.status == kFloor && result == MSB_OK) {
         result = MSB_FLOOR;
@@ -1164,6 +1164,85 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
 }
 
 // =============================================================================
+// Appendix E around msb_solve: per system, restart the failing shifts from
+// the worst of them until every shift passes or max_rounds is reached.
+extern "C" msb_status msb_solve_reseed(msb_ctx* ctx, const msb_system* sys, int nsys, const void* E,
+                                       const double* w_in, int n_shift, double seed_shift, double tol,
+                                       int maxit, msb_prec prec, double reseed_tol, int max_rounds,
+                                       void* psi, double* seed_of, double* resid_true, int* rounds,
+                                       const msb_opts* opts, void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx || !sys || !E || !w_in || !psi) return fail(MSB_EINVAL, "msb_solve_reseed: null argument");
+  if (nsys <= 0 || n_shift <= 0) return fail(MSB_EINVAL, "msb_solve_reseed: nsys and n_shift must be positive");
+  if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_solve_reseed: invalid precision");
+  if (!(reseed_tol > 0.0) || max_rounds < 1)
+    return fail(MSB_EINVAL, "msb_solve_reseed: need reseed_tol > 0 and max_rounds >= 1");
+  const int64_t D = ctx->D;
+  const size_t es = elem_bytes(prec == MSB_C128 ? Elem::C128 : Elem::C64);
+  bool all_pass = true;
+  for (int s = 0; s < nsys; ++s) {
+    char* psi_s = static_cast<char*>(psi) + (size_t)s * n_shift * D * es;
+    const void* E_s = static_cast<const char*>(E) + (size_t)s * D * 16;
+    std::vector<int> todo(n_shift);
+    for (int k = 0; k < n_shift; ++k) todo[k] = k;
+    std::vector<double> rt_all(n_shift, 0.0);
+    double seed = seed_shift;
+    int r = 0;
+    for (; r < max_rounds; ++r) {
+      const int n = (int)todo.size();
+      std::vector<double> w(n), rr(n), rt(n);
+      std::vector<int> it(n);
+      int si = 0;
+      for (int j = 0; j < n; ++j) w[j] = w_in[todo[j]];
+      msb_info inf;
+      std::memset(&inf, 0, sizeof(inf));
+      inf.sys_iters = &si;
+      inf.shift_iters = it.data();
+      inf.resid_rec = rr.data();
+      inf.resid_true = rt.data();
+      // round 0 solves every shift in place; later rounds into a scratch block
+      void* tmp = nullptr;
+      if (r > 0 && hipMalloc(&tmp, (size_t)n * D * es) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MSB_ENOMEM, "msb_solve_reseed: no room for the restarted shifts");
+      }
+      const msb_status st = msb_solve(ctx, sys + s, 1, E_s, w.data(), n, seed, tol, maxit, prec,
+                                      r == 0 ? (void*)psi_s : tmp, &inf, opts, stream);
+      if (st == MSB_EINVAL || st == MSB_ENOMEM || st == MSB_EHIP) {
+        if (tmp) (void)hipFree(tmp);
+        return st;
+      }
+      hipError_t e = hipSuccess;
+      for (int j = 0; j < n && r > 0 && e == hipSuccess; ++j)
+        e = hipMemcpy(psi_s + (size_t)todo[j] * D * es, static_cast<char*>(tmp) + (size_t)j * D * es,
+                      (size_t)D * es, hipMemcpyDeviceToDevice);
+      if (tmp) (void)hipFree(tmp);
+      MSB_HIP(e);
+      std::vector<int> bad;
+      for (int j = 0; j < n; ++j) {
+        const int k = todo[j];
+        rt_all[k] = rt[j];
+        if (seed_of) seed_of[(size_t)s * n_shift + k] = seed;
+        if (!(rt[j] <= reseed_tol) || it[j] < 0) bad.push_back(k);
+      }
+      if (bad.empty()) break;
+      int worst = bad[0];
+      for (int k : bad) {
+        if (std::isnan(rt_all[worst])) break;              // NaN counts as worst
+        if (std::isnan(rt_all[k]) || rt_all[k] > rt_all[worst]) worst = k;
+      }
+      seed = w_in[worst];
+      todo = bad;
+      if (r + 1 == max_rounds) all_pass = false;
+    }
+    if (rounds) rounds[s] = std::min(r + 1, max_rounds);
+    if (resid_true)
+      for (int k = 0; k < n_shift; ++k) resid_true[(size_t)s * n_shift + k] = rt_all[k];
+  }
+  if (!all_pass) return fail(MSB_NOT_CONVERGED, "msb_solve_reseed: some shifts still fail after max_rounds");
+  return MSB_OK;
+}
+
 extern "C" msb_status msb_combine(msb_ctx* ctx, int nsys, int n_shift, msb_prec prec, const void* psi,
                                   const double* phase_re, const double* phase_im, const int* o1_site,
                                   const double* o1_wup, const double* o1_wdn, void* phi, void* stream) {

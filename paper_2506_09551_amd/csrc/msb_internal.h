@@ -147,7 +147,11 @@ ApplyShape apply_shape_used(Elem e, int mode, const ApplyArgs& a);
 // the true one, or as kStallMax replacements in a row where the recurrence
 // claimed to have cut the best true residual by kStall but the true residual
 // did not follow.
-enum : int { kActive = 0, kDone = 1, kBreakdown = 2, kMaxit = 3, kPaused = 4, kFloor = 5 };
+enum : int { kActive = 0, kDone = 1, kBreakdown = 2, kMaxit = 3, kPaused = 4, kFloor = 5, kExhausted = 6 };
+// kExhausted: the seed's residual fell below kSeedFloor |E| (or beta stopped
+// being finite) with shifts still open; its bilinear products would leave the
+// normal float64 range, so it stops and the open shifts are unconverged.
+constexpr double kSeedFloor = 1e-150;
 constexpr double kFloorGap = 10.0;
 // Residual replacement stops once |r_m| <= max(tol, kReplaceFloor) |E|: the FP64
 // product E - A x cannot resolve much less (about 1e-15 relative was measured).

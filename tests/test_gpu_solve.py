@@ -319,3 +319,71 @@ def test_full_size_solve_sampled_rows(gpu, wl_name):
                 assert np.max(np.abs(r)) <= 1.01 * floor * nE, (s, k, np.max(np.abs(r)) / nE)
     finally:
         msb.msb_destroy(ctx)
+
+
+@pytest.fixture(scope="module")
+def sharp(tiny):
+    """The L=8 ring with Gamma = 0.3 and the 64 shifts of the tiny workload
+    widened to [-12, 12]: an edge seed exhausts before the resonant shifts."""
+    msb, ctx, wl, m = tiny
+    Hp = oracle_H(m, core_site=0, Uc=wl.Uc)
+    H = oracle_H(m)
+    from oracle import groundstate as ogs
+    E_G, G, _ = ogs.dense_ground_state(H)
+    w = np.linspace(-12.0, 12.0, 64)
+    Gamma = 0.3
+    E = G.astype(np.complex128)
+    ref = osolve.direct_solve(Hp, E, E_G, Gamma, w, method="eig")
+    sysd = msb.make_system(core_site=0, Uc=wl.Uc, E_G=E_G, Gamma=Gamma)
+    return msb, ctx, sysd, E, w, ref
+
+
+def test_edge_seed_exhaustion_reported(sharp):
+    msb, ctx, sysd, E, w, ref = sharp
+    st, info, psi = _run(msb, ctx, [sysd], E, w, 1e-10, 3000, msb.MSB_C128, seed_shift=-12.0,
+                         raise_on_fail=False)
+    assert st == msb.MSB_NOT_CONVERGED
+    assert np.all(np.isfinite(psi))
+    frozen = info["shift_iters"][0] >= 0
+    assert 0 < frozen.sum() < len(w)
+    err = np.linalg.norm(psi[0][frozen] - ref[frozen], axis=1) / np.linalg.norm(ref[frozen], axis=1)
+    assert err.max() <= 1e-8
+    assert np.all(info["resid_true"][0][~frozen] > 1e-10)
+
+
+def test_reseeding_recovers_from_edge_seed(sharp):
+    """Appendix E on the GPU: every shift ends at the direct solution; the
+    final seeds are the edge seed (shifts it froze) and shifts of the list."""
+    import torch
+    msb, ctx, sysd, E, w, ref = sharp
+    D = msb.msb_dim(ctx)
+    Et = torch.from_numpy(E.reshape(1, D)).cuda()
+    psi = torch.empty(1, len(w), D, dtype=torch.complex128, device="cuda")
+    st, info = msb.msb_solve_reseed(ctx, [sysd], Et, w, -12.0, 1e-10, 3000, msb.MSB_C128, psi, 1e-9, 6)
+    assert st == msb.MSB_OK
+    assert info["rounds"][0] >= 2
+    assert np.all(info["resid_true"][0] <= 1e-9)
+    seeds = set(info["seed_of"][0])
+    assert -12.0 in seeds and (seeds - {-12.0}) <= set(w)
+    got = psi[0].cpu().numpy()
+    err = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= 1e-8
+    # round 0 keeps exactly the shifts the edge seed froze
+    st0, info0, _ = _run(msb, ctx, [sysd], E, w, 1e-10, 3000, msb.MSB_C128, seed_shift=-12.0,
+                         raise_on_fail=False)
+    kept = info["seed_of"][0] == -12.0
+    assert np.array_equal(kept, (info0["shift_iters"][0] >= 0) & (info0["resid_true"][0] <= 1e-9))
+
+
+def test_reseeding_without_failures_is_the_plain_solve(sharp):
+    import torch
+    msb, ctx, sysd, E, w, ref = sharp
+    D = msb.msb_dim(ctx)
+    Et = torch.from_numpy(E.reshape(1, D)).cuda()
+    psi = torch.empty(1, len(w), D, dtype=torch.complex128, device="cuda")
+    st, info = msb.msb_solve_reseed(ctx, [sysd], Et, w, 0.0, 1e-10, 3000, msb.MSB_C128, psi, 1e-9, 6)
+    assert st == msb.MSB_OK and info["rounds"][0] == 1 and np.all(info["seed_of"] == 0.0)
+    _, _, psi0 = _run(msb, ctx, [sysd], E, w, 1e-10, 3000, msb.MSB_C128, seed_shift=0.0)
+    assert np.array_equal(psi[0].cpu().numpy(), psi0[0])
+    with pytest.raises(msb.MsbError):
+        msb.msb_solve_reseed(ctx, [sysd], Et, w, 0.0, 1e-10, 3000, msb.MSB_C128, psi, 0.0, 6)

@@ -188,12 +188,26 @@ def _learned():
         note="L=10 ring, N=5+5, D=63504; per-sample (U, t', Uc, Gamma) vary")
 
 
+def _reseed():
+    # a narrow core-hole broadening and an edge seed: the seed converges far
+    # faster than the resonant shifts it carries (Appendix E's setting)
+    L = 10
+    return Workload(
+        name="reseed_L10_N5", n_sites=L, n_up=5, n_dn=5,
+        bonds=chain_bonds(L, 1.0), U=8.0, Uc=-4.0, Gamma=0.3,
+        w_in=np.linspace(-12.0, 12.0, 128), tol=1e-10, dtype="c128",
+        core_sites=[0], o2_weights=[None], phases=[1.0 + 0j],
+        w_loss=np.linspace(0.0, 10.0, 256), eta=0.1, seed_shift=-12.0, maxit=4000,
+        note="L=10 ring, N=5+5, D=63504, Gamma=0.3, 128 shifts in [-12,12], initial seed w_in=-12")
+
+
 WORKLOADS = {
     "tiny": _tiny,
     "scale": _scale,
     "precision": _precision,
     "batched": _batched,
     "learned": _learned,
+    "reseed": _reseed,
 }
 
 
