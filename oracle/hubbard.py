@@ -173,3 +173,41 @@ def number_op(basis: Basis, site: int, w_up: float, w_dn: float) -> np.ndarray:
     u = S & mask
     d = S >> L
     return w_up * ((u >> site) & 1).astype(np.float64) + w_dn * ((d >> site) & 1).astype(np.float64)
+
+
+def site_op(src: Basis, dst: Basis, site: int, spin: int, create: bool) -> sp.csr_matrix:
+    """Matrix of c+_{site spin} (``create``) or c_{site spin} from the sector of
+    ``src`` to the sector of ``dst`` (the dipole-type operators of Sec. III that
+    change the electron number).
+
+    Spin-orbital a = site + spin * L (all up orbitals first, then all down
+    ones, the order the Hamiltonian's Jordan-Wigner signs assume); the
+    operator acting on a Fock code picks up (-1)^{number of occupied orbitals
+    with index < a}, as in ``hop_terms``.
+    """
+    L = src.L
+    if dst.L != L:
+        raise ValueError("sectors of different lattices")
+    dn_up = (1 if create else -1) if spin == 0 else 0
+    dn_dn = (1 if create else -1) if spin == 1 else 0
+    if (dst.n_up, dst.n_dn) != (src.n_up + dn_up, src.n_dn + dn_dn):
+        raise ValueError("destination sector does not match the operator")
+    a = site + spin * L
+    S = src.states()
+    occ = (S >> a) & 1
+    m = (occ == 0) if create else (occ == 1)
+    s0 = S[m]
+    sign = _parity_below(s0, a).astype(np.float64)
+    s1 = (s0 | (np.int64(1) << a)) if create else (s0 ^ (np.int64(1) << a))
+    rows = dst.index(s1)
+    cols = np.nonzero(m)[0]
+    return sp.csr_matrix((sign, (rows, cols)), shape=(dst.dim, src.dim))
+
+
+def dipole_op(src: Basis, dst: Basis, coef, spin: int, create: bool) -> sp.csr_matrix:
+    """sum_j coef[j] c+_{j spin} (or c_{j spin}): one spin species, complex coefficients per site."""
+    out = sp.csr_matrix((dst.dim, src.dim), dtype=np.complex128)
+    for j, c in enumerate(coef):
+        if c != 0:
+            out = out + complex(c) * site_op(src, dst, j, spin, create)
+    return out
