@@ -214,6 +214,21 @@ msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, const double* x
                             double tol, int maxit, double* E_G, double* G,
                             int* iters, void* stream);
 
+/* Dipole-type operators that add or remove one valence electron (Sec. III:
+ * O_2 creates the electron the x-ray promotes, O_1 removes one on emission):
+ *   y[v] = sum_j coef_j c+_{j spin} x[v]   (create = 1)
+ *   y[v] = sum_j coef_j c_{j spin} x[v]    (create = 0),   v < nvec.
+ * x lives in the sector of `src`; y in the sector of `dst`, which must be the
+ * same lattice with (N_up +- 1, N_dn) for spin 0 or (N_up, N_dn +- 1) for
+ * spin 1.  Jordan-Wigner order: all up orbitals (sites 0..L-1) before all
+ * down orbitals, so c+_{j s} on a basis state carries (-1)^{number of occupied
+ * orbitals before (j, s)} -- the order the Hamiltonian's hop signs assume.
+ * coef: host [2 * n_sites] complex (re, im); x: [nvec][D_src] C128, y:
+ * [nvec][D_dst] C128 (device; y is overwritten).  Errors: MSB_EINVAL for
+ * mismatched lattices or sectors, spin not 0/1, nvec outside 1..65535. */
+msb_status msb_dipole(const msb_ctx* src, const msb_ctx* dst, int spin, int create,
+                      const double* coef, int nvec, const void* x, void* y, void* stream);
+
 /* ---- the hot path: all shifts of every system from one Krylov space ------- */
 
 /* Multi-shift COCG (Algorithm 1, corrected reading: (1 - alpha_m w) in the

@@ -109,6 +109,9 @@ def lib():
                                        POINTER(c_double), POINTER(c_double), POINTER(c_int),
                                        POINTER(msb_opts), c_void_p]
         L.msb_solve_reseed.restype = c_int
+        L.msb_dipole.argtypes = [c_void_p, c_void_p, c_int, c_int, POINTER(c_double), c_int, c_void_p,
+                                 c_void_p, c_void_p]
+        L.msb_dipole.restype = c_int
         L.msb_combine.argtypes = [c_void_p, c_int, c_int, c_int, c_void_p, POINTER(c_double),
                                   POINTER(c_double), POINTER(c_int), POINTER(c_double),
                                   POINTER(c_double), c_void_p, c_void_p]
@@ -148,7 +151,7 @@ def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["msb_create", "msb_destroy", "msb_release_workspace", "msb_dim", "msb_sector_info", "msb_last_error",
             "msb_device_ok", "msb_apply", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
-            "msb_solve_reseed",
+            "msb_solve_reseed", "msb_dipole",
             "msb_combine", "msb_spectrum", "msb_autotune", "msb_set_shape",
             "msb_mlp_num_params", "msb_mlp_create", "msb_mlp_destroy", "msb_mlp_set_params",
             "msb_mlp_get_params", "msb_mlp_grad", "msb_mlp_train", "msb_mlp_predict", "msb_mlp_fallback"]
@@ -376,6 +379,20 @@ def msb_solve_reseed(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit
     if raise_on_fail and st != MSB_OK:
         raise MsbError(st, lib().msb_last_error().decode())
     return st, {"status": st, "seed_of": seed_of, "resid_true": rt, "rounds": rounds}
+
+
+def msb_dipole(src_ctx, dst_ctx, spin: int, create: bool, coef, x, y, stream=None):
+    """y[v] = sum_j coef[j] c+_{j spin} x[v] (create) or c_{j spin}; x, y complex128 [nvec][D]."""
+    import numpy as np
+    import torch
+    c = np.ascontiguousarray(np.asarray(coef, dtype=np.complex128))
+    if c.ndim != 1:
+        raise ValueError("coef must be one complex number per site")
+    cc = np.ascontiguousarray(np.stack([c.real, c.imag], axis=1).ravel())
+    nvec = x.shape[0] if x.dim() == 2 else 1
+    _check(lib().msb_dipole(src_ctx, dst_ctx, int(spin), int(bool(create)), cc.ctypes.data_as(POINTER(c_double)),
+                            nvec, _ptr(x, torch.complex128, nvec * msb_dim(src_ctx), "x"),
+                            _ptr(y, torch.complex128, nvec * msb_dim(dst_ctx), "y"), _stream_ptr(stream)))
 
 
 def msb_combine(ctx, psi, nsys: int, n_shift: int, prec: int, phases, phi, o1=None, stream=None):

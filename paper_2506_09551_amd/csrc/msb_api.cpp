@@ -434,6 +434,64 @@ extern "C" msb_status msb_number_op(msb_ctx* ctx, int site, double w_up, double 
   return MSB_OK;
 }
 
+// Electron-number-changing site operators (dipole-type O_1 / O_2 between two
+// sectors): host tables of input rank and Jordan-Wigner sign, then k_dipole.
+extern "C" msb_status msb_dipole(const msb_ctx* src, const msb_ctx* dst, int spin, int create,
+                                 const double* coef, int nvec, const void* x, void* y, void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!src || !dst || !coef || !x || !y) return fail(MSB_EINVAL, "msb_dipole: null argument");
+  if (spin != 0 && spin != 1) return fail(MSB_EINVAL, "msb_dipole: spin must be 0 (up) or 1 (down)");
+  if (nvec <= 0 || nvec > 65535) return fail(MSB_EINVAL, "msb_dipole: nvec out of range");
+  if (src->L != dst->L || src->L > kMaxSites) return fail(MSB_EINVAL, "msb_dipole: contexts of different lattices");
+  const int dn = create ? 1 : -1;
+  const bool ok = (spin == 0) ? (dst->n_up == src->n_up + dn && dst->n_dn == src->n_dn)
+                              : (dst->n_dn == src->n_dn + dn && dst->n_up == src->n_up);
+  if (!ok) return fail(MSB_EINVAL, "msb_dipole: destination sector does not match the operator");
+  const SpinTable& S = (spin == 0) ? src->up : src->dn;
+  const SpinTable& T = (spin == 0) ? dst->up : dst->dn;
+  const int L = src->L;
+  // orbital order: all up sites, then all down sites; a down-spin operator
+  // passes every up electron (N_up is the same in both sectors)
+  const int base_parity = (spin == 1) ? (src->n_up & 1) : 0;
+  std::vector<int> table((size_t)L * T.n, -1);
+  for (int c = 0; c < T.n; ++c) {
+    const uint32_t cf = T.conf[c];
+    for (int j = 0; j < L; ++j) {
+      const bool occ = (cf >> j) & 1u;
+      if (create != (int)occ) continue;          // c+ needs j occupied in the output, c needs it empty
+      const uint32_t ci = cf ^ (1u << j);
+      const auto it = std::lower_bound(S.conf.begin(), S.conf.end(), ci);
+      if (it == S.conf.end() || *it != ci) continue;
+      const int r = (int)(it - S.conf.begin());
+      const int par = (base_parity + __builtin_popcount(cf & ((1u << j) - 1u))) & 1;
+      table[(size_t)j * T.n + c] = (r << 1) | par;
+    }
+  }
+  DipoleArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = x;
+  a.y = y;
+  a.D_src = src->D;
+  a.D_dst = dst->D;
+  a.nd_src = src->dn.n;
+  a.nd_dst = dst->dn.n;
+  a.n_conf = T.n;
+  a.n_sites = L;
+  a.spin = spin;
+  for (int j = 0; j < L; ++j) {
+    a.coef_re[j] = coef[2 * j];
+    a.coef_im[j] = coef[2 * j + 1];
+  }
+  DevBuf tb;
+  MSB_HIP(hipMalloc(&tb.p, table.size() * sizeof(int)));
+  MSB_HIP(hipMemcpy(tb.p, table.data(), table.size() * sizeof(int), hipMemcpyHostToDevice));
+  a.table = (const int*)tb.p;
+  hipStream_t st = (hipStream_t)stream;
+  MSB_HIP(launch_dipole(a, nvec, st));
+  MSB_HIP(hipStreamSynchronize(st));
+  return MSB_OK;
+}
+
 // =============================================================================
 // Ground state: FP64 Lanczos with full reorthogonalisation (classical
 // Gram-Schmidt applied twice against every stored Lanczos vector).

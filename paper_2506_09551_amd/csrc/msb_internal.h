@@ -327,6 +327,20 @@ hipError_t launch_cf_eval(const double* a, const double* b, const int* depth, in
                           hipStream_t st);
 
 // ---- small utility kernels ---------------------------------------------------
+// Site operator c+ / c of one spin between two sectors (k_dipole.hip).
+constexpr int kMaxSites = 20;
+struct DipoleArgs {
+  const int* table;             // [n_sites][n_conf]: input rank << 1 | (sign < 0), or -1
+  const void* x;                // [nvec][D_src] complex128
+  void* y;                      // [nvec][D_dst] complex128
+  int64_t D_src, D_dst;
+  int nd_src, nd_dst;           // down-spin states of each sector (row lengths)
+  int n_conf;                   // output configurations of the operator's spin
+  int n_sites, spin;
+  double coef_re[kMaxSites], coef_im[kMaxSites];
+};
+hipError_t launch_dipole(const DipoleArgs& a, int nvec, hipStream_t st);
+
 hipError_t launch_number_op(const TablesDev& T, int64_t D, int site, double w_up, double w_dn,
                             int count, int x_real, const void* x, double* y, hipStream_t st);
 hipError_t launch_combine(const TablesDev& T, int64_t D, int nsys, int n, Elem e, const void* psi,
