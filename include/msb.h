@@ -224,10 +224,13 @@ msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, const double* x
  * down orbitals, so c+_{j s} on a basis state carries (-1)^{number of occupied
  * orbitals before (j, s)} -- the order the Hamiltonian's hop signs assume.
  * coef: host [2 * n_sites] complex (re, im); x: [nvec][D_src] C128, y:
- * [nvec][D_dst] C128 (device; y is overwritten).  Errors: MSB_EINVAL for
- * mismatched lattices or sectors, spin not 0/1, nvec outside 1..65535. */
+ * [nvec][D_dst] C128 (device; overwritten, or added to when accumulate != 0,
+ * which forms coherent site sums such as sum_j e^{iqj} c_{j s} Psi_j one site
+ * at a time).  Errors: MSB_EINVAL for mismatched lattices or sectors, spin
+ * not 0/1, nvec outside 1..65535. */
 msb_status msb_dipole(const msb_ctx* src, const msb_ctx* dst, int spin, int create,
-                      const double* coef, int nvec, const void* x, void* y, void* stream);
+                      const double* coef, int nvec, int accumulate, const void* x, void* y,
+                      void* stream);
 
 /* ---- the hot path: all shifts of every system from one Krylov space ------- */
 

@@ -109,8 +109,8 @@ def lib():
                                        POINTER(c_double), POINTER(c_double), POINTER(c_int),
                                        POINTER(msb_opts), c_void_p]
         L.msb_solve_reseed.restype = c_int
-        L.msb_dipole.argtypes = [c_void_p, c_void_p, c_int, c_int, POINTER(c_double), c_int, c_void_p,
-                                 c_void_p, c_void_p]
+        L.msb_dipole.argtypes = [c_void_p, c_void_p, c_int, c_int, POINTER(c_double), c_int, c_int,
+                                 c_void_p, c_void_p, c_void_p]
         L.msb_dipole.restype = c_int
         L.msb_combine.argtypes = [c_void_p, c_int, c_int, c_int, c_void_p, POINTER(c_double),
                                   POINTER(c_double), POINTER(c_int), POINTER(c_double),
@@ -381,8 +381,8 @@ def msb_solve_reseed(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit
     return st, {"status": st, "seed_of": seed_of, "resid_true": rt, "rounds": rounds}
 
 
-def msb_dipole(src_ctx, dst_ctx, spin: int, create: bool, coef, x, y, stream=None):
-    """y[v] = sum_j coef[j] c+_{j spin} x[v] (create) or c_{j spin}; x, y complex128 [nvec][D]."""
+def msb_dipole(src_ctx, dst_ctx, spin: int, create: bool, coef, x, y, accumulate=False, stream=None):
+    """y[v] (+)= sum_j coef[j] c+_{j spin} x[v] (create) or c_{j spin}; x, y complex128 [nvec][D]."""
     import numpy as np
     import torch
     c = np.ascontiguousarray(np.asarray(coef, dtype=np.complex128))
@@ -391,7 +391,7 @@ def msb_dipole(src_ctx, dst_ctx, spin: int, create: bool, coef, x, y, stream=Non
     cc = np.ascontiguousarray(np.stack([c.real, c.imag], axis=1).ravel())
     nvec = x.shape[0] if x.dim() == 2 else 1
     _check(lib().msb_dipole(src_ctx, dst_ctx, int(spin), int(bool(create)), cc.ctypes.data_as(POINTER(c_double)),
-                            nvec, _ptr(x, torch.complex128, nvec * msb_dim(src_ctx), "x"),
+                            nvec, int(bool(accumulate)), _ptr(x, torch.complex128, nvec * msb_dim(src_ctx), "x"),
                             _ptr(y, torch.complex128, nvec * msb_dim(dst_ctx), "y"), _stream_ptr(stream)))
 
 

@@ -29,7 +29,9 @@ __global__ __launch_bounds__(kBlock) void k_dipole(DipoleArgs a) {
     const cv<double> cf = {s * a.coef_re[j], s * a.coef_im[j]};
     acc = cadd(acc, cmul(cf, xv));
   }
-  Access<double, true>::store(Access<double, true>::offset(a.y, (int64_t)v * a.D_dst), i, acc);
+  void* y = Access<double, true>::offset(a.y, (int64_t)v * a.D_dst);
+  if (a.accumulate) acc = cadd(acc, Access<double, true>::template load<double>(y, i));
+  Access<double, true>::store(y, i, acc);
 }
 
 hipError_t launch_dipole(const DipoleArgs& a, int nvec, hipStream_t st) {

@@ -437,7 +437,8 @@ extern "C" msb_status msb_number_op(msb_ctx* ctx, int site, double w_up, double 
 // Electron-number-changing site operators (dipole-type O_1 / O_2 between two
 // sectors): host tables of input rank and Jordan-Wigner sign, then k_dipole.
 extern "C" msb_status msb_dipole(const msb_ctx* src, const msb_ctx* dst, int spin, int create,
-                                 const double* coef, int nvec, const void* x, void* y, void* stream) {
+                                 const double* coef, int nvec, int accumulate, const void* x, void* y,
+                                 void* stream) {
   (void)hipGetLastError();   // do not report an earlier call's failure
   if (!src || !dst || !coef || !x || !y) return fail(MSB_EINVAL, "msb_dipole: null argument");
   if (spin != 0 && spin != 1) return fail(MSB_EINVAL, "msb_dipole: spin must be 0 (up) or 1 (down)");
@@ -478,6 +479,7 @@ extern "C" msb_status msb_dipole(const msb_ctx* src, const msb_ctx* dst, int spi
   a.n_conf = T.n;
   a.n_sites = L;
   a.spin = spin;
+  a.accumulate = accumulate ? 1 : 0;
   for (int j = 0; j < L; ++j) {
     a.coef_re[j] = coef[2 * j];
     a.coef_im[j] = coef[2 * j + 1];

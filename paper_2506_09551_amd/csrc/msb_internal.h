@@ -337,6 +337,7 @@ struct DipoleArgs {
   int nd_src, nd_dst;           // down-spin states of each sector (row lengths)
   int n_conf;                   // output configurations of the operator's spin
   int n_sites, spin;
+  int accumulate;               // y += op x instead of y = op x
   double coef_re[kMaxSites], coef_im[kMaxSites];
 };
 hipError_t launch_dipole(const DipoleArgs& a, int nvec, hipStream_t st);

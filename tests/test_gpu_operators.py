@@ -97,6 +97,8 @@ def test_dipole_matches_oracle(ring, spin, create):
         ref = np.stack([Op @ x[k] for k in range(2)])
         got = y.cpu().numpy()
         assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+        msb.msb_dipole(ctx, ctx2, spin, create, coef, torch.from_numpy(x).cuda(), y, accumulate=True)
+        assert np.max(np.abs(y.cpu().numpy() - 2 * ref)) <= 2e-14 * np.max(np.abs(ref))
         with pytest.raises(msb.MsbError):           # wrong direction for this pair of sectors
             msb.msb_dipole(ctx, ctx2, spin, not create, coef, torch.from_numpy(x).cuda(), y)
     finally:

@@ -118,6 +118,7 @@ class Workload:
     gs_seed: int = 12345
     seed_shift: float = 0.0
     maxit: int = 2000
+    dipole_spin: int = -1       # >= 0: O2_j = c+_{j spin}, O1_j = c_{j spin} (intermediate sector N_spin + 1)
     note: str = ""
 
     @property
@@ -201,6 +202,22 @@ def _reseed():
         note="L=10 ring, N=5+5, D=63504, Gamma=0.3, 128 shifts in [-12,12], initial seed w_in=-12")
 
 
+def _dipole():
+    # direct edge with a valence electron added at the core-hole site: the
+    # ground state in (6, 6), the intermediate states in (7, 6)
+    L = 12
+    q = math.pi / 2
+    return Workload(
+        name="dipole_L12_N6", n_sites=L, n_up=6, n_dn=6,
+        bonds=chain_bonds(L, 1.0, 0.0), U=8.0, Uc=-4.0, Gamma=1.0,
+        w_in=np.linspace(-12.0, 12.0, 200), tol=1e-8, dtype="c128",
+        core_sites=list(range(L)), o2_weights=[None] * L,
+        phases=[complex(math.cos(q * j), math.sin(q * j)) for j in range(L)],
+        w_loss=np.linspace(0.0, 10.0, 256), eta=0.1, dipole_spin=0,
+        note="L=12 ring, ground state N=6+6, intermediate N=7+6 (D=731808) with O2_j = c+_{j up}, "
+             "O1_j = c_{j up}; 12 core-hole sites x 200 shifts in [-12,12], q=pi/2")
+
+
 WORKLOADS = {
     "tiny": _tiny,
     "scale": _scale,
@@ -208,6 +225,7 @@ WORKLOADS = {
     "batched": _batched,
     "learned": _learned,
     "reseed": _reseed,
+    "dipole": _dipole,
 }
 
 
