@@ -86,7 +86,10 @@ def hop_terms(basis: Basis, bonds, src_idx: np.ndarray, t_scale=None):
 
     For every bond (i, j, t), spin sigma and direction, applies
     -t * c+_{a} c_{b} (a, b the two spin-orbitals of the bond) to each source
-    state with Jordan-Wigner signs from the generic operator action.
+    state with Jordan-Wigner signs from the generic operator action.  A bond
+    (i, j, t, t_rev) is directed: -t c+_j c_i - t_rev c+_i c_j (an electron
+    hops from i to j with t and back with t_rev; non-symmetric when they
+    differ, as in non-reciprocal, dissipative models).
     Returns (dst_index, src_index, value) arrays.  ``t_scale`` optionally maps
     a bond's t to a replacement amplitude (used for per-parameter models).
     """
@@ -94,11 +97,14 @@ def hop_terms(basis: Basis, bonds, src_idx: np.ndarray, t_scale=None):
     src_idx = np.asarray(src_idx, dtype=np.int64)
     S = basis.states(src_idx)
     dst_all, src_all, val_all = [], [], []
-    for (i, j, t) in bonds:
+    for bond in bonds:
+        i, j, t = bond[0], bond[1], bond[2]
+        t_rev = bond[3] if len(bond) > 3 else t
         amp = t if t_scale is None else t_scale(t)
+        amp_rev = t_rev if t_scale is None else t_scale(t_rev)
         for sigma in (0, 1):
             oi, oj = i + sigma * L, j + sigma * L
-            for a, b in ((oi, oj), (oj, oi)):       # c+_a c_b and its conjugate
+            for a, b, am in ((oj, oi, amp), (oi, oj, amp_rev)):       # c+_j c_i, c+_i c_j
                 occ_b = (S >> b) & 1
                 occ_a = (S >> a) & 1
                 m = (occ_b == 1) & (occ_a == 0)
@@ -111,7 +117,7 @@ def hop_terms(basis: Basis, bonds, src_idx: np.ndarray, t_scale=None):
                 s2 = s1 | (np.int64(1) << a)
                 dst_all.append(basis.index(s2))
                 src_all.append(src_idx[m])
-                val_all.append(-amp * (sign1 * sign2).astype(np.float64))
+                val_all.append(-am * (sign1 * sign2).astype(np.float64))
     if not dst_all:
         z = np.zeros(0, dtype=np.int64)
         return z, z, np.zeros(0)
@@ -134,7 +140,8 @@ def diagonal(basis: Basis, U: float, core_site=None, Uc: float = 0.0, idx=None) 
 
 def hamiltonian(basis: Basis, bonds, U: float, core_site=None, Uc: float = 0.0,
                 t_scale=None) -> sp.csr_matrix:
-    """Sparse real matrix of H (core_site None) or H' (core hole on core_site)."""
+    """Sparse real matrix of H (core_site None) or H' (core hole on core_site);
+    symmetric unless some bond is directed (see ``hop_terms``)."""
     D = basis.dim
     dst, src, val = hop_terms(basis, bonds, np.arange(D, dtype=np.int64), t_scale)
     diag = diagonal(basis, U, core_site, Uc)
@@ -152,6 +159,8 @@ def apply_rows(basis: Basis, bonds, U: float, x: np.ndarray, rows, core_site=Non
     generated from source state r.  Intended for sampled checks at dimensions
     where the full sparse matrix is too large to build.
     """
+    if any(len(b) > 3 and b[3] != b[2] for b in bonds):
+        raise ValueError("apply_rows needs a symmetric Hamiltonian")
     rows = np.asarray(rows, dtype=np.int64)
     dst, src, val = hop_terms(basis, bonds, rows)
     out = (diagonal(basis, U, core_site, Uc, idx=rows) - shift) * x[rows]

@@ -42,14 +42,21 @@ Readings of the printed algorithm (each verified against ``direct_solve`` by
 8. Seed exhaustion.  Also silent: a seed far from the resonances converges
    much faster than the shifts it carries, and once |r_{m+1}| falls below
    1e-150 |E| its bilinear products (about |r|^2) leave the normal float64
-   range and beta = rho_{m+1}/rho_m soon turns inf or NaN.  The seed then stops and the open shifts are reported
-   unconverged (``exhausted``); Appendix E's reseeding is the remedy.
+   range and beta = rho_{m+1}/rho_m soon turns inf or NaN.  The seed then
+   stops and the open shifts are reported unconverged (``exhausted``);
+   Appendix E's reseeding is the remedy.
 9. Reseeding (Appendix E).  The collinearity deviation of shift w is
    dr(w) = |r_t(w) - r(w)| with the true residual r_t = E - (A - w)Psi(w) and
    the recurrence residual r(w) = r_M / zeta_M(w) at the shift's last
    iteration M.  A shift is restarted when dr(w) > reseed_tol |E| or when it
    was never frozen; the failing shift with the largest dr becomes the next
    seed, and the failing shifts are solved again from r_0 = E with it.
+10. Dual space.  For a non-symmetric A (the general case of Appendix A that
+   the method's BiCG form covers) the shadow residual is no longer r*: r~ and
+   p~ run their own recurrence with A^T (bilinear form, so no conjugates),
+   r~_0 = r_0 = E, sigma = r~^T A p, rho = r~^T r -- two products with the
+   matrix per iteration.  With A symmetric, r~ = r at every step and the
+   iteration is the complex-symmetric one above.
 """
 from __future__ import annotations
 
@@ -111,12 +118,14 @@ SEED_FLOOR = 1e-150      # reading 8
 
 def msbicg_reference(A_apply, E: np.ndarray, w_in, tol: float, maxit: int,
                      seed_shift: float = 0.0, keep_zeta: bool = False,
-                     breakdown_tol: float = 1e-14, keep_r: bool = False) -> MSBiCGResult:
+                     breakdown_tol: float = 1e-14, keep_r: bool = False,
+                     AT_apply=None) -> MSBiCGResult:
     """Multi-shift COCG for (A - w I) Psi = E, all shifts from one seed.
 
     ``A_apply(x)`` returns A x with A = H' - E_G - i Gamma.  The seed system is
     A_s = A - seed_shift I.  Follows Appendix D with readings 1-6 of the
-    module docstring.  Returns an ``MSBiCGResult``.
+    module docstring.  Returns an ``MSBiCGResult``.  ``AT_apply`` (x -> A^T x)
+    selects the dual-space form of reading 10 for a non-symmetric A.
     """
     E = np.asarray(E, dtype=np.complex128)
     w = np.asarray(w_in, dtype=np.float64) - seed_shift       # w' = w - sigma_s
@@ -125,8 +134,11 @@ def msbicg_reference(A_apply, E: np.ndarray, w_in, tol: float, maxit: int,
     res = MSBiCGResult()
 
     # Initialisation (Algorithm 1, first two lines).
+    dual = AT_apply is not None
     r = E.copy()
     p = E.copy()
+    rt = E.copy() if dual else None      # shadow residual and direction (reading 10)
+    pt = E.copy() if dual else None
     rho = r @ r                          # bilinear, reading 3
     normE = np.linalg.norm(E)
     psi = np.zeros((n, D), dtype=np.complex128)
@@ -154,13 +166,19 @@ def msbicg_reference(A_apply, E: np.ndarray, w_in, tol: float, maxit: int,
     m = 0
     for m in range(maxit):
         v = A_apply(p) - seed_shift * p                 # matrix-vector product
-        sigma = r @ v
-        if abs(sigma) <= breakdown_tol * np.linalg.norm(r) * np.linalg.norm(v):
+        lhs = rt if dual else r
+        sigma = lhs @ v
+        if abs(sigma) <= breakdown_tol * np.linalg.norm(lhs) * np.linalg.norm(v):
             res.breakdown = True
             break
         alpha = rho / sigma
         r_new = r - alpha * v
-        rho_new = r_new @ r_new
+        if dual:
+            vt = AT_apply(pt) - seed_shift * pt         # the dual product
+            rt_new = rt - alpha * vt
+            rho_new = rt_new @ r_new
+        else:
+            rho_new = r_new @ r_new
         beta = rho_new / rho
         rn = np.linalg.norm(r_new)
 
@@ -183,6 +201,9 @@ def msbicg_reference(A_apply, E: np.ndarray, w_in, tol: float, maxit: int,
         # Seed update.
         p = r_new + beta * p
         r = r_new
+        if dual:
+            pt = rt_new + beta * pt
+            rt = rt_new
         rho = rho_new
         alpha_prev, beta_prev = alpha, beta
         res.alpha.append(alpha)
@@ -196,7 +217,8 @@ def msbicg_reference(A_apply, E: np.ndarray, w_in, tol: float, maxit: int,
         if not (rn > SEED_FLOOR * normE and np.isfinite(beta)):
             res.exhausted = True    # reading 8: stop before the products underflow
             break
-        if not (abs(rho) > breakdown_tol * rn * rn):
+        rtn = np.linalg.norm(rt) if dual else rn
+        if not (abs(rho) > breakdown_tol * rn * rtn):
             res.breakdown = True        # rho_{m+1} = 0 while shifts are still open
             break
     else:

@@ -228,3 +228,76 @@ def test_reseeding_recovers_from_an_edge_seed(sharp):
     # the shifts kept from round 0 are exactly those the edge seed froze
     r0 = so.msbicg_reference(A, E, w, 1e-10, 3000, seed_shift=-12.0)
     assert np.array_equal(out.seed_of == -12.0, r0.conv_iter >= 0)
+
+
+def _directed_ring(g, open_chain=False):
+    """L=6 ring (or open chain), N=3+3, hopping e^{+g} to the right and e^{-g}
+    to the left (non-reciprocal), core hole on site 0."""
+    L = 6
+    bonds = [(i, i + 1, np.exp(g), np.exp(-g)) for i in range(L - 1)]
+    if not open_chain:
+        bonds.append((L - 1, 0, np.exp(g), np.exp(-g)))
+    return hb.Basis(L, 3, 3), bonds
+
+
+def test_directed_transpose_swaps_directions():
+    B, bonds = _directed_ring(0.3)
+    H = hb.hamiltonian(B, bonds, 8.0, core_site=0, Uc=-4.0)
+    swapped = [(i, j, tr, t) for (i, j, t, tr) in bonds]
+    HT = hb.hamiltonian(B, swapped, 8.0, core_site=0, Uc=-4.0)
+    assert abs(H - H.T).max() > 0.1                       # really non-symmetric
+    assert abs(HT - H.T).max() == 0.0
+
+
+def test_directed_open_chain_is_an_imaginary_gauge_transform():
+    """Open chain: H_g = S H_0 S^-1 with S = diag(e^{g * sum of electron
+    positions}) -- fixes which direction carries e^{+g}."""
+    g = 0.4
+    B, bonds = _directed_ring(g, open_chain=True)
+    B0, bonds0 = _directed_ring(0.0, open_chain=True)
+    Hg = hb.hamiltonian(B, bonds, 8.0).toarray()
+    H0 = hb.hamiltonian(B0, bonds0, 8.0).toarray()
+    S = B.states()
+    L = B.L
+    pos = np.zeros(B.dim)
+    for k in range(2 * L):
+        pos += ((S >> k) & 1) * (k % L)
+    sc = np.exp(g * pos)
+    assert np.allclose(Hg, sc[:, None] * H0 / sc[None, :], atol=1e-12, rtol=0)
+
+
+def test_dual_space_form_solves_nonsymmetric_systems():
+    B, bonds = _directed_ring(0.3)
+    H = hb.hamiltonian(B, bonds, 8.0, core_site=0, Uc=-4.0)
+    HT = H.T.tocsr()
+    E_G, Gamma = -3.0, 1.0
+    E = W.random_complex(B.dim, 5)
+    w = np.linspace(-6, 6, 12)
+    ref = so.direct_solve(H, E, E_G, Gamma, w, method="lu")
+
+    def A(x):
+        return H @ x - (E_G + 1j * Gamma) * x
+
+    def AT(x):
+        return HT @ x - (E_G + 1j * Gamma) * x
+    res = so.msbicg_reference(A, E, w, 1e-13, 2000, AT_apply=AT)
+    assert res.converged
+    err = np.max(np.linalg.norm(res.psi - ref, axis=1) / np.linalg.norm(ref, axis=1))
+    assert err <= 1e-10
+    # the complex-symmetric form (no dual) does not solve them
+    bad = so.msbicg_reference(A, E, w, 1e-13, 2000)
+    errb = np.max(np.linalg.norm(bad.psi - ref, axis=1) / np.linalg.norm(ref, axis=1))
+    assert errb > 1e-3
+
+
+def test_dual_space_form_reduces_to_the_symmetric_one(ring):
+    B, H, Hp, E_G, G = ring
+    E = W.random_complex(B.dim, 8)
+    w = np.linspace(-5, 5, 9)
+
+    def A(x):
+        return Hp @ x - (E_G + 1j) * x
+    a = so.msbicg_reference(A, E, w, 1e-12, 500)
+    b = so.msbicg_reference(A, E, w, 1e-12, 500, AT_apply=A)
+    assert a.iters == b.iters
+    assert np.array_equal(a.psi, b.psi)
