@@ -69,6 +69,13 @@ typedef enum { MSB_C128 = 0, MSB_C64 = 1 } msb_prec;
  * Bonds with equal t form one "bond type" (types numbered by first
  * appearance, at most MSB_MAX_BOND_TYPES); per-system amplitudes may
  * override a type's t (msb_system.t_amp).
+ * Directed bonds (bond_t_rev != NULL): the hop term of bond b is
+ *   -sum_sigma (t_b c+_{j_b sigma} c_{i_b sigma} + t_rev_b c+_{i_b sigma} c_{j_b sigma}),
+ * non-symmetric where t_rev_b != t_b (non-reciprocal, dissipative models).
+ * Every distinct pair (t, t_rev) is a class k with two types, 2k for the hop
+ * i -> j (amplitude t) and 2k + 1 for j -> i (t_rev), so at most
+ * MSB_MAX_BOND_TYPES / 2 classes; per-system t_amp may make any system
+ * non-symmetric, and msb_solve then uses the dual-space form.
  * Limits: 2 <= n_sites <= 20, C(L, N_sigma) <= 65535. */
 typedef struct {
   int n_sites, n_up, n_dn, n_bonds;
@@ -76,6 +83,7 @@ typedef struct {
   const int* bond_j;
   const double* bond_t;
   double U;
+  const double* bond_t_rev;   /* NULL: t_rev = t (symmetric hopping) */
 } msb_model;
 
 /* One linear system / Hamiltonian instance on the context's sector.
@@ -156,6 +164,8 @@ typedef struct {
   int assembly_engine;   /* multi-shift assembly: 0 = FP64 vector ALU (default), 1 = FP64 matrix cores */
   int autotune;          /* 0 = tune the apply shape on first use (default), -1 = default shape
                             unless one was tuned or pinned before */
+  int dual;              /* 0 = the dual-space (BiCG) form only when some system's A is not
+                            symmetric (default), 1 = always; MSB_C128 only */
 } msb_opts;
 
 /* ---- context -------------------------------------------------------------- */
@@ -243,6 +253,13 @@ msb_status msb_dipole(const msb_ctx* src, const msb_ctx* dst, int spin, int crea
  * |r_m| / |zeta_m(w_k)| <= tol |E_s|.  MSB_C64 runs the vectors in complex64
  * with FP64 reductions and scalars, and replaces the seed residual by the
  * FP64 true residual every opts->replace_every iterations.
+ * When some system's A is not symmetric (directed bonds with different
+ * amplitudes, msb_model) the dual-space form runs instead: a shadow residual
+ * r~ and direction p~ follow the same recurrences with A^T (a second apply per
+ * iteration), sigma = r~^T A p and rho = r~^T r; the shift recurrences are
+ * unchanged.  It needs MSB_C128 (MSB_EINVAL otherwise); opts->dual = 1 forces
+ * it for symmetric systems too (then r~ = r and the iterates are identical).
+ * msb_ground_state and msb_spectrum need symmetric systems.
  * The seed also stops when its residual falls below 1e-150 |E_s| with shifts
  * still open (its bilinear products would leave the float64 range; a seed far
  * from the resonances converges much faster than the shifts it carries).

@@ -32,7 +32,7 @@ class MsbError(RuntimeError):
 class msb_model(ctypes.Structure):
     _fields_ = [("n_sites", c_int), ("n_up", c_int), ("n_dn", c_int), ("n_bonds", c_int),
                 ("bond_i", POINTER(c_int)), ("bond_j", POINTER(c_int)),
-                ("bond_t", POINTER(c_double)), ("U", c_double)]
+                ("bond_t", POINTER(c_double)), ("U", c_double), ("bond_t_rev", POINTER(c_double))]
 
 
 class msb_system(ctypes.Structure):
@@ -60,7 +60,7 @@ class msb_shape(ctypes.Structure):
 class msb_opts(ctypes.Structure):
     _fields_ = [("chunk", c_int), ("bank_slots", c_int), ("batch", c_int),
                 ("replace_every", c_int), ("use_graph", c_int), ("mem_fraction", c_double),
-                ("assembly_engine", c_int), ("autotune", c_int)]
+                ("assembly_engine", c_int), ("autotune", c_int), ("dual", c_int)]
 
 
 _lib = None
@@ -226,12 +226,16 @@ def msb_device_ok() -> bool:
 
 
 def msb_create(n_sites: int, n_up: int, n_dn: int, bonds, U: float) -> c_void_p:
-    """Context for H on the (n_up, n_dn) sector; bonds = [(i, j, t), ...]."""
+    """Context for H on the (n_up, n_dn) sector; bonds = [(i, j, t), ...], or
+    directed [(i, j, t, t_rev), ...] (t moves an electron i -> j, t_rev back)."""
     nb = len(bonds)
     bi = (c_int * max(nb, 1))(*[int(b[0]) for b in bonds])
     bj = (c_int * max(nb, 1))(*[int(b[1]) for b in bonds])
     bt = (c_double * max(nb, 1))(*[float(b[2]) for b in bonds])
-    m = msb_model(int(n_sites), int(n_up), int(n_dn), nb, bi, bj, bt, float(U))
+    directed = any(len(b) > 3 for b in bonds)
+    btr = (c_double * max(nb, 1))(*[float(b[3] if len(b) > 3 else b[2]) for b in bonds]) if directed else None
+    m = msb_model(int(n_sites), int(n_up), int(n_dn), nb, bi, bj, bt, float(U),
+                  ctypes.cast(btr, POINTER(c_double)) if directed else None)
     ctx = c_void_p()
     _check(lib().msb_create(ctypes.byref(m), ctypes.byref(ctx)))
     return ctx

@@ -13,6 +13,10 @@
 // The x / p vectors of the shifted systems are not touched here: the
 // residuals r_m stay in the bank and the shifted solutions are assembled
 // from them in k_shift.hip.
+// Dual-space form (non-symmetric A; CocgArgs::rt set): the shadow residual
+// r~ and direction p~ follow the same recurrences with v~ = A^T p~ (a second
+// apply, plain mode), sigma = r~^T A p (the apply reads r~ instead of the bank
+// slot) and rho_{m+1} = r~_{m+1}^T r_{m+1}; the shift recurrences are unchanged.
 #include "k_common.h"
 
 namespace msb {
@@ -27,7 +31,7 @@ __device__ __forceinline__ bool sigma_breakdown(const SysState& st, const double
   const cv<double> sigma = {red1[s * 4 + 0], red1[s * 4 + 1]};
   const double vnorm = sqrt(red1[s * 4 + 2]);
   const double sabs = cabs(sigma);
-  if (!(sabs > 1e-14 * st.rnorm * vnorm)) return true;   // also catches NaN
+  if (!(sabs > 1e-14 * st.rtnorm * vnorm)) return true;   // also catches NaN (r~ = r unless dual)
   alpha = cdiv({st.rho_re, st.rho_im}, sigma);
   return false;
 }
@@ -49,6 +53,10 @@ __global__ __launch_bounds__(kBlock) void k_cocg_init(InitArgs a) {
         const cv<double> xs = {(double)(S)x.re, (double)(S)x.im};
         Ax::store(r0, i, xs);
         Ax::store(p, i, xs);
+        if (a.rt) {                     // dual-space form: r~_0 = p~_0 = E
+          Ax::store(Ax::offset(a.rt, (int64_t)s * a.D), i, xs);
+          Ax::store(Ax::offset(a.pt, (int64_t)s * a.D), i, xs);
+        }
         if (a.xseed) A64::store(a.xseed, (int64_t)s * a.D + i, cv<double>{0.0, 0.0});
         part[0] += xs.re * xs.re - xs.im * xs.im;
         part[1] += 2.0 * xs.re * xs.im;
@@ -69,6 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_init_fin(InitArgs a) {
     st.rho_re = red[0];
     st.rho_im = red[1];
     st.rnorm = sqrt(red[2]);
+    st.rtnorm = st.rnorm;
     st.normE = st.rnorm;
     st.ap_re = 1.0; st.ap_im = 0.0;     // alpha_{-1} = 1
     st.bp_re = 0.0; st.bp_im = 0.0;     // beta_{-1} = 0
@@ -106,12 +115,15 @@ template <typename S>
 __global__ __launch_bounds__(kBlock) void k_cocg_r(CocgArgs a) {
   using Ax = Access<S, true>;
   const int s = blockIdx.y, bx = blockIdx.x;
-  double part[3] = {0.0, 0.0, 0.0};
+  // rho_{m+1} (bilinear: r~^T r, or r^T r), |r_{m+1}|^2, |r~_{m+1}|^2
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
   const SysState st = a.st[s];
   if (st.status == kActive) {
     cv<double> alpha;
     if (!sigma_breakdown(st, a.red1, s, alpha)) {
       const int slot = st.m - *a.base;
+      void* rt = a.rt ? Ax::offset(a.rt, (int64_t)s * a.D) : nullptr;
+      const void* vt = a.rt ? Ax::offset(a.vt, (int64_t)s * a.D) : nullptr;
       const void* r = Ax::offset((const void*)a.bank, ((int64_t)s * a.cap + slot) * a.D);
       void* rn = Ax::offset(a.bank, ((int64_t)s * a.cap + slot + 1) * a.D);
       const void* v = Ax::offset(a.vvec, (int64_t)s * a.D);
@@ -134,15 +146,26 @@ __global__ __launch_bounds__(kBlock) void k_cocg_r(CocgArgs a) {
             x.re = (double)(S)x.re;
             x.im = (double)(S)x.im;
             Ax::store(rn, i, x);
-            part[0] += x.re * x.re - x.im * x.im;
-            part[1] += 2.0 * x.re * x.im;
+            cv<double> xt = x;
+            if (rt) {               // dual-space form: r~ <- r~ - alpha A^T p~
+              const cv<double> rti = Ax::template load<double>(rt, i);
+              const cv<double> vti = Ax::template load<double>(vt, i);
+              xt = {rti.re - (alpha.re * vti.re - alpha.im * vti.im),
+                    rti.im - (alpha.re * vti.im + alpha.im * vti.re)};
+              xt.re = (double)(S)xt.re;
+              xt.im = (double)(S)xt.im;
+              Ax::store(rt, i, xt);
+            }
+            part[0] += xt.re * x.re - xt.im * x.im;
+            part[1] += xt.re * x.im + xt.im * x.re;
             part[2] += x.re * x.re + x.im * x.im;
+            part[3] += xt.re * xt.re + xt.im * xt.im;
           }
         }
       }
     }
   }
-  block_partial<3>(part, a.partials, a.nbx, s, bx);
+  block_partial<4>(part, a.partials, a.nbx, s, bx);
 }
 
 // One workgroup per system: rho_{m+1}, |r_{m+1}|, beta_m, every shift's zeta,
@@ -150,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_r(CocgArgs a) {
 __global__ __launch_bounds__(kBlock) void k_cocg_book(CocgArgs a) {
   const int s = blockIdx.x;
   __shared__ double red2[4];
-  reduce_partials<3>(a.partials, a.nbx, s, red2);
+  reduce_partials<4>(a.partials, a.nbx, s, red2);
   SysState t = a.st[s];
   if (t.status != kActive) return;
   cv<double> alpha;
@@ -164,6 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_book(CocgArgs a) {
   const int base = *a.base;
   const cv<double> rho_new = {red2[0], red2[1]};
   const double rn = sqrt(red2[2]);
+  const double rtn = a.rt ? sqrt(red2[3]) : rn;
   const cv<double> beta = cdiv(rho_new, {t.rho_re, t.rho_im});
   // zeta_{m+1} = (1 - alpha_m w) zeta_m + (alpha_m beta_{m-1} / alpha_{m-1}) (zeta_m - zeta_{m-1})
   const cv<double> cshift = cdiv(cmul(alpha, {t.bp_re, t.bp_im}), {t.ap_re, t.ap_im});
@@ -204,12 +228,13 @@ __global__ __launch_bounds__(kBlock) void k_cocg_book(CocgArgs a) {
     t.bp_re = beta.re; t.bp_im = beta.im;
     t.rho_re = rho_new.re; t.rho_im = rho_new.im;
     t.rnorm = rn;
+    t.rtnorm = rtn;
     t.m = m + 1;
     if (t.n_active == 0) {
       t.status = kDone;
     } else if (!(rn > kSeedFloor * t.normE) || !isfinite(beta.re) || !isfinite(beta.im)) {
       t.status = kExhausted;
-    } else if (!(cabs(rho_new) > 1e-14 * rn * rn)) {
+    } else if (!(cabs(rho_new) > 1e-14 * rn * rtn)) {
       t.status = kBreakdown;            // rho_{m+1} = 0 with shifts still open
       t.breakdown_iter = m + 1;
     } else if (t.m >= a.maxit) {
@@ -231,6 +256,8 @@ __global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
   const void* r = Ax::offset((const void*)a.bank, ((int64_t)s * a.cap + slot) * a.D);
   void* p = Ax::offset(a.pvec, (int64_t)s * a.D);
   const cv<double> beta = {st.be_re, st.be_im};
+  const void* rt = a.rt ? Ax::offset((const void*)a.rt, (int64_t)s * a.D) : nullptr;
+  void* pt = a.rt ? Ax::offset(a.pt, (int64_t)s * a.D) : nullptr;
   for (int64_t base = (int64_t)bx * kPerStep; base < a.D; base += (int64_t)a.nbx * kPerStep) {
 #pragma unroll
     for (int e = 0; e < kEptStream; ++e) {
@@ -241,6 +268,13 @@ __global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
         const cv<double> x = {ri.re + beta.re * pi.re - beta.im * pi.im,
                               ri.im + beta.re * pi.im + beta.im * pi.re};
         Ax::store(p, i, x);
+        if (pt) {                       // p~ = r~ + beta p~
+          const cv<double> rti = Ax::template load<double>(rt, i);
+          const cv<double> pti = Ax::template load<double>(pt, i);
+          const cv<double> y = {rti.re + beta.re * pti.re - beta.im * pti.im,
+                                rti.im + beta.re * pti.im + beta.im * pti.re};
+          Ax::store(pt, i, y);
+        }
       }
     }
   }
@@ -306,6 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_replace_fin(CocgArgs a) {
   t.rho_re = rho_new.re;
   t.rho_im = rho_new.im;
   t.rnorm = rn;
+  t.rtnorm = rn;                      // replacement runs in the complex-symmetric form only
   a.rnorm_log[(int64_t)s * (a.maxit + 1) + t.m] = rn;
   if (!(cabs(rho_new) > 1e-14 * rn * rn)) {
     t.status = kBreakdown;

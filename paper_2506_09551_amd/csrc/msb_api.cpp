@@ -85,6 +85,21 @@ static msb_status make_sysdev(const msb_ctx* ctx, const msb_system& s, double d_
   return MSB_OK;
 }
 
+// A system's A is symmetric unless a directed bond type and its reverse have
+// different amplitudes.
+static bool sysdev_symmetric(const msb_ctx* ctx, const SysDev& s) {
+  for (int t = 0; t < ctx->n_types; ++t)
+    if (s.amp[t] != s.amp[ctx->type_partner[t]]) return false;
+  return true;
+}
+// The same system with every directed type's amplitude swapped with its
+// reverse: the apply then computes A^T x.
+static SysDev sysdev_transpose(const msb_ctx* ctx, const SysDev& s) {
+  SysDev t = s;
+  for (int q = 0; q < ctx->n_types; ++q) t.amp[q] = s.amp[ctx->type_partner[q]];
+  return t;
+}
+
 // ---- apply launch-shape autotuner -------------------------------------------
 // Shapes are tuned per system count up to kTuneMaxSys (the grid and the L2
 // footprint change with it); larger batches share the kTuneMaxSys entry.
@@ -222,25 +237,46 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   if (m->n_bonds < 0 || (m->n_bonds > 0 && (!m->bond_i || !m->bond_j || !m->bond_t)))
     return fail(MSB_EINVAL, "bond arrays missing");
   if (!std::isfinite(m->U)) return fail(MSB_EINVAL, "U must be finite");
-  std::vector<int> bi, bj, bt;
-  std::vector<double> amps;
+  std::vector<int> bi, bj, bt_f, bt_b;
+  std::vector<double> amps;                       // amplitude of each type
+  std::vector<std::pair<double, double>> classes; // directed: (t, t_rev) of class k = types 2k, 2k+1
+  const bool directed = m->bond_t_rev != nullptr;
   for (int b = 0; b < m->n_bonds; ++b) {
     const int i = m->bond_i[b], j = m->bond_j[b];
     const double t = m->bond_t[b];
+    const double tr = directed ? m->bond_t_rev[b] : t;
     if (i < 0 || j < 0 || i >= m->n_sites || j >= m->n_sites || i == j)
       return fail(MSB_EINVAL, "bond " + std::to_string(b) + " has invalid sites");
-    if (!std::isfinite(t)) return fail(MSB_EINVAL, "bond amplitude must be finite");
-    int type = -1;
-    for (size_t q = 0; q < amps.size(); ++q)
-      if (amps[q] == t) type = (int)q;
-    if (type < 0) {
-      if ((int)amps.size() >= MSB_MAX_BOND_TYPES) return fail(MSB_EINVAL, "too many distinct bond amplitudes");
-      amps.push_back(t);
-      type = (int)amps.size() - 1;
+    if (!std::isfinite(t) || !std::isfinite(tr)) return fail(MSB_EINVAL, "bond amplitude must be finite");
+    int tf = -1, tb = -1;
+    if (directed) {
+      int k = -1;
+      for (size_t q = 0; q < classes.size(); ++q)
+        if (classes[q].first == t && classes[q].second == tr) k = (int)q;
+      if (k < 0) {
+        if (2 * ((int)classes.size() + 1) > MSB_MAX_BOND_TYPES)
+          return fail(MSB_EINVAL, "too many distinct directed bond classes");
+        classes.push_back({t, tr});
+        amps.push_back(t);
+        amps.push_back(tr);
+        k = (int)classes.size() - 1;
+      }
+      tf = 2 * k;
+      tb = 2 * k + 1;
+    } else {
+      for (size_t q = 0; q < amps.size(); ++q)
+        if (amps[q] == t) tf = (int)q;
+      if (tf < 0) {
+        if ((int)amps.size() >= MSB_MAX_BOND_TYPES) return fail(MSB_EINVAL, "too many distinct bond amplitudes");
+        amps.push_back(t);
+        tf = (int)amps.size() - 1;
+      }
+      tb = tf;
     }
     bi.push_back(i);
     bj.push_back(j);
-    bt.push_back(type);
+    bt_f.push_back(tf);
+    bt_b.push_back(tb);
   }
   msb_ctx* c = new msb_ctx();
   c->L = m->n_sites;
@@ -249,9 +285,10 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   c->U = m->U;
   c->n_types = (int)amps.size();
   for (size_t q = 0; q < amps.size(); ++q) c->type_amp[q] = amps[q];
+  for (int q = 0; q < MSB_MAX_BOND_TYPES; ++q) c->type_partner[q] = directed ? (q ^ 1) : q;
   std::string err;
-  if (!build_spin_table(m->n_sites, m->n_up, bi, bj, bt, c->up, err) ||
-      !build_spin_table(m->n_sites, m->n_dn, bi, bj, bt, c->dn, err)) {
+  if (!build_spin_table(m->n_sites, m->n_up, bi, bj, bt_f, bt_b, c->up, err) ||
+      !build_spin_table(m->n_sites, m->n_dn, bi, bj, bt_f, bt_b, c->dn, err)) {
     delete c;
     return fail(MSB_EINVAL, err);
   }
@@ -510,6 +547,8 @@ extern "C" msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, cons
   SysDev hs;
   msb_status r = make_sysdev(ctx, *sys, 0.0, 0.0, false, hs);
   if (r != MSB_OK) return r;
+  if (!sysdev_symmetric(ctx, hs))
+    return fail(MSB_EINVAL, "Lanczos needs a symmetric H: give directed types equal amplitudes");
   const ApplyShape shp = shape_for(ctx, Elem::R64, 1, st, true);
 
   const size_t part_doubles = std::max<size_t>(
@@ -660,9 +699,13 @@ struct SolveBufs {
   SysDev* tsys = nullptr;       // true-residual systems
   double* tpart = nullptr;
   double* tred = nullptr;
+  void* rt = nullptr;           // dual-space form: r~, p~, A^T p~ [B][D] and the transposed systems
+  void* pt = nullptr;
+  void* vt = nullptr;
+  SysDev* dsysT = nullptr;
 
   void carve(Carver& c, const msb_ctx* ctx, int B, int cap, int n_shift, int n_list, int maxit,
-             size_t s_el, size_t s_out, bool carry, bool want_true, bool replace) {
+             size_t s_el, size_t s_out, bool carry, bool want_true, bool replace, bool dual) {
     const int64_t D = ctx->D;
     size_t part_n = 0;   // largest nsys * nbx over the batch sizes that can occur
     for (int n = 1; n <= B; ++n)
@@ -695,6 +738,12 @@ struct SolveBufs {
     if (replace) {
       xseed = c.take<double>((size_t)B * D * 16);
       wrep = c.take<double>((size_t)B * D * 16);
+    }
+    if (dual) {
+      rt = c.take<void>((size_t)B * D * s_el);
+      pt = c.take<void>((size_t)B * D * s_el);
+      vt = c.take<void>((size_t)B * D * s_el);
+      dsysT = c.take<SysDev>(B * sizeof(SysDev));
     }
     if (want_true) {
       const size_t nt = (size_t)B * n_shift;
@@ -747,10 +796,17 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   const size_t s_el = elem_bytes(ev), s_out = elem_bytes(eo);
   const bool want_true = info && info->resid_true;
 
-  std::vector<SysDev> hsys(nsys);
+  std::vector<SysDev> hsys(nsys), hsysT;
+  bool dual = opts && opts->dual == 1;
   for (int s = 0; s < nsys; ++s) {
     msb_status r = make_sysdev(ctx, sys[s], -(sys[s].E_G + seed_shift), -sys[s].Gamma, true, hsys[s]);
     if (r != MSB_OK) return r;
+    dual = dual || !sysdev_symmetric(ctx, hsys[s]);
+  }
+  if (dual) {
+    if (prec != MSB_C128) return fail(MSB_EINVAL, "msb_solve: the dual-space form runs in complex128");
+    hsysT.resize(nsys);
+    for (int s = 0; s < nsys; ++s) hsysT[s] = sysdev_transpose(ctx, hsys[s]);
   }
 
   // apply launch shapes: tuned on first use, before the workspace is sized
@@ -772,7 +828,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   auto need_bytes = [&](int B, int cap, bool carry) {
     Carver c(nullptr);
     SolveBufs b;
-    b.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, carry, want_true, replace_every > 0);
+    b.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, carry, want_true, replace_every > 0, dual);
     return c.used();
   };
   int planB = 0, plancap = 0;
@@ -831,7 +887,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   SolveBufs bf;
   {
     Carver c(ctx->ws);
-    bf.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, plancarry, want_true, replace_every > 0);
+    bf.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, plancarry, want_true, replace_every > 0, dual);
   }
   void* bank = bf.bank;
   void* pvec = bf.pvec;
@@ -890,6 +946,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     const double* Eb = (const double*)E + (size_t)b0 * D * 2;
     char* psib = (char*)psi + (size_t)b0 * n_shift * D * s_out;
     MSB_HIP(hipMemcpyAsync(dsys, hsys.data() + b0, nb * sizeof(SysDev), hipMemcpyHostToDevice, st));
+    if (dual)
+      MSB_HIP(hipMemcpyAsync(bf.dsysT, hsysT.data() + b0, nb * sizeof(SysDev), hipMemcpyHostToDevice, st));
     int zero = 0;
     MSB_HIP(hipMemcpyAsync(dbase, &zero, sizeof(int), hipMemcpyHostToDevice, st));
 
@@ -899,6 +957,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ia.cap = cap; ia.D = D; ia.nbx = cocg_nbx(D, nb); ia.nsys = nb; ia.n_shift = n_shift; ia.zeta = zeta;
     ia.zeta_prev = zeta_prev; ia.conv_iter = conv; ia.rnorm_log = rlog; ia.maxit = mx;
     ia.xseed = bf.xseed;
+    ia.rt = dual ? bf.rt : nullptr;
+    ia.pt = dual ? bf.pt : nullptr;
     MSB_HIP(launch_cocg_init(ev, ia, st));
 
     ApplyArgs aa = apply_args(ctx, dsys, nb, pvec, vvec);
@@ -912,6 +972,16 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     aa.aux_m = &dst[0].m;
     aa.aux_base = dbase;
     aa.aux_cap = cap;
+    ApplyArgs ta = apply_args(ctx, bf.dsysT, nb, bf.pt, bf.vt);   // dual: v~ = A^T p~
+    if (dual) {
+      aa.aux = bf.rt;            // sigma = r~^T A p
+      aa.aux_m = nullptr;
+      aa.aux_base = nullptr;
+      aa.aux_cap = 0;
+      ta.shape = aa.shape;
+      ta.status = aa.status;
+      ta.status_stride = aa.status_stride;
+    }
 
     CocgArgs ca;
     ca.st = dst; ca.red1 = red1; ca.partials = partials; ca.red2 = red2;
@@ -921,6 +991,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ca.alpha_log = alog; ca.beta_log = blog; ca.rnorm_log = rlog;
     ca.xseed = bf.xseed;
     ca.rep_floor = std::max(tol, kReplaceFloor);
+    ca.rt = dual ? bf.rt : nullptr;
+    ca.pt = dual ? bf.pt : nullptr;
+    ca.vt = dual ? bf.vt : nullptr;
 
     int base = 0;
     bool first_flush = true;
@@ -1013,6 +1086,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       for (int c = 0; c < chunk; ++c) {
         hipError_t e = launch_cocg_p(ev, ca, st);
         if (e == hipSuccess) e = launch_apply(ev, kModeBilinear, aa, st);
+        if (e == hipSuccess && dual) e = launch_apply(ev, kModePlain, ta, st);
         if (e == hipSuccess) e = launch_cocg_r(ev, ca, st);
         if (e != hipSuccess) return e;
       }
@@ -1126,7 +1200,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     for (int s = 0; s < nb; ++s) {
       const SysState& t = hst[s];
       max_iters = std::max(max_iters, t.m);
-      total_mvms += t.m;
+      total_mvms += dual ? 2 * t.m : t.m;
       if (t.status == kBreakdown) {
         result = MSB_BREAKDOWN;
         if (brk_iter < 0 || t.breakdown_iter < brk_iter) brk_iter = t.breakdown_iter;
@@ -1353,6 +1427,8 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
   SysDev hs;
   msb_status r = make_sysdev(ctx, *sys, 0.0, 0.0, false, hs);
   if (r != MSB_OK) return r;
+  if (!sysdev_symmetric(ctx, hs))
+    return fail(MSB_EINVAL, "Lanczos needs a symmetric H: give directed types equal amplitudes");
   const ApplyShape shp = shape_for(ctx, Elem::C128, n, st, true);
   std::vector<SysDev> hsys(n, hs);
   const int nbx_l = lanczos_nbx(D, n);

@@ -43,8 +43,11 @@ struct SpinTable {
   std::vector<uint32_t> order;  // [n] ranks by ascending sum of occupied site indices, then rank
   int max_hops = 0;
 };
+// bt_fwd[b]: type of the hop i_b -> j_b, bt_bwd[b]: of j_b -> i_b (equal for
+// symmetric bonds)
 bool build_spin_table(int L, int N, const std::vector<int>& bi, const std::vector<int>& bj,
-                      const std::vector<int>& btype, SpinTable& out, std::string& err);
+                      const std::vector<int>& bt_fwd, const std::vector<int>& bt_bwd, SpinTable& out,
+                      std::string& err);
 
 // ---- host tridiagonal eigensolver (tridiag.cpp) ------------------------------
 // Lowest eigenvalue of the symmetric tridiagonal T (diag a[0..k), offdiag b[0..k-1))
@@ -173,6 +176,7 @@ struct SysState {
   double rbest;                 // smallest true residual seen at a replacement (|E| at start)
   int n_stall;                  // replacements in a row that exposed a false improvement
   int pad;
+  double rtnorm;                // |r~_m| of the dual-space form (= rnorm otherwise)
 };
 
 struct CocgArgs {
@@ -201,6 +205,11 @@ struct CocgArgs {
   double* rnorm_log;            // [nsys][maxit+1]
   double* xseed;                // optional [nsys][D] complex128 seed solution (x += alpha p)
   double rep_floor;             // residual replacement only while |r_m| > rep_floor |E|
+  // dual-space form (null for the complex-symmetric one): shadow residual r~,
+  // direction p~ and vt = A^T p~, each [nsys][D]
+  void* rt;
+  void* pt;
+  const void* vt;
 };
 
 hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st);   // r_{m+1} = r_m - alpha v
@@ -229,6 +238,8 @@ struct InitArgs {
   double* rnorm_log;
   int maxit;
   double* xseed;                // optional: zeroed
+  void* rt;                     // optional (dual-space form): r~_0 = p~_0 = E
+  void* pt;
 };
 hipError_t launch_cocg_init(Elem e, const InitArgs& a, hipStream_t st);
 
@@ -372,6 +383,7 @@ struct msb_ctx {
   uint32_t* d_ell_dn = nullptr;
   uint32_t* d_order_up = nullptr;
   int k_type_dn[MSB_MAX_BOND_TYPES] = {0};   // rows of each bond type's down-spin hop table
+  int type_partner[MSB_MAX_BOND_TYPES] = {0}; // type of the reverse hop (itself when symmetric)
   // private stream for the captured seed iterations (default priority)
   hipStream_t solve_stream = nullptr;
   double* d_small = nullptr;          // small reduction outputs

@@ -17,7 +17,8 @@
 namespace msb {
 
 bool build_spin_table(int L, int N, const std::vector<int>& bi, const std::vector<int>& bj,
-                      const std::vector<int>& btype, SpinTable& out, std::string& err) {
+                      const std::vector<int>& bt_fwd, const std::vector<int>& bt_bwd, SpinTable& out,
+                      std::string& err) {
   if (L < 1 || L > 20 || N < 0 || N > L) {
     err = "spin table: need 1 <= L <= 20 and 0 <= N <= L";
     return false;
@@ -52,7 +53,10 @@ bool build_spin_table(int L, int N, const std::vector<int>& bi, const std::vecto
       const uint32_t between = (hi - lo > 1) ? (((1u << hi) - 1u) & ~((1u << (lo + 1)) - 1u)) : 0u;
       const uint32_t neg = __builtin_popcount(c & between) & 1u;
       const int32_t r2 = rank[c2];
-      row.push_back(((uint32_t)r2 << 16) | ((uint32_t)btype[b] << 1) | neg);
+      // row c, column c2: the electron ends on j (hop i -> j) when j is
+      // occupied in c, on i (hop j -> i) otherwise
+      const int type = oj ? bt_fwd[b] : bt_bwd[b];
+      row.push_back(((uint32_t)r2 << 16) | ((uint32_t)type << 1) | neg);
     }
     // Deterministic order: by target rank, then type.
     std::sort(row.begin(), row.end());
