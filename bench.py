@@ -621,7 +621,8 @@ def main():
     for j, w2 in enumerate(wl.o2_weights):
         site, wu, wd = (-1, 1.0, 1.0) if w2 is None else (wl.core_sites[j], w2[0], w2[1])
         msb.msb_number_op(ctx, site, wu, wd, G, E[j])
-    systems = [msb.make_system(core_site=c, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma) for c in wl.core_sites]
+    systems = [msb.make_system(core_site=c, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma, t_amp=wl.t_amp_sys)
+               for c in wl.core_sites]
     n_shift = len(wl.w_in)
     # apply launch shape: the autotuner's table for this batch (the solve reuses the winner)
     tune_table = msb.msb_autotune(ctx, wl.nrhs, prec)

@@ -119,6 +119,7 @@ class Workload:
     seed_shift: float = 0.0
     maxit: int = 2000
     dipole_spin: int = -1       # >= 0: O2_j = c+_{j spin}, O1_j = c_{j spin} (intermediate sector N_spin + 1)
+    t_amp_sys: list = None      # per-system bond-type amplitudes of H' (None: the model's)
     note: str = ""
 
     @property
@@ -218,6 +219,24 @@ def _dipole():
              "O1_j = c_{j up}; 12 core-hole sites x 200 shifts in [-12,12], q=pi/2")
 
 
+def _dual():
+    # the scale workload with non-reciprocal hopping in H' (e^{+g} to the right,
+    # e^{-g} back, g = 0.2): the ground state is the symmetric ring's, the
+    # intermediate Hamiltonians are not symmetric
+    L = 12
+    q = math.pi / 2
+    g = 0.2
+    return Workload(
+        name="dual_L12_N6", n_sites=L, n_up=6, n_dn=6,
+        bonds=[(i, (i + 1) % L, 1.0, 1.0) for i in range(L)], U=8.0, Uc=-4.0, Gamma=1.0,
+        w_in=np.linspace(-12.0, 12.0, 200), tol=1e-8, dtype="c128",
+        core_sites=list(range(L)), o2_weights=[None] * L,
+        phases=[complex(math.cos(q * j), math.sin(q * j)) for j in range(L)],
+        w_loss=np.linspace(0.0, 10.0, 256), eta=0.1, t_amp_sys=[math.exp(g), math.exp(-g)],
+        note="L=12 ring, N=6+6, D=853776; H' with hopping e^{0.2} right / e^{-0.2} left; "
+             "12 core-hole sites x 200 shifts in [-12,12]")
+
+
 WORKLOADS = {
     "tiny": _tiny,
     "scale": _scale,
@@ -226,6 +245,7 @@ WORKLOADS = {
     "learned": _learned,
     "reseed": _reseed,
     "dipole": _dipole,
+    "dual": _dual,
 }
 
 
