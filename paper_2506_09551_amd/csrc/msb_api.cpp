@@ -114,19 +114,32 @@ struct DevBuf {               // scratch device memory released on scope exit
 static ApplyArgs apply_args(const msb_ctx* ctx, const SysDev* sys, int nsys, const void* x, void* v);
 constexpr int kMaxCand = 128;   // compiled shapes x passes x row orders
 
-// Times every usable shape for (e, shape_class(nsys)) on zero vectors and keeps
-// the fastest in the context.  `table` (optional) receives every measurement.
+// Times every usable shape for (e, shape_class(nsys), mode) on zero vectors
+// and keeps the fastest in the context.  `table` (optional) receives every
+// measurement.
 static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
-                              std::vector<std::pair<ApplyShape, double>>* table) {
+                              std::vector<std::pair<ApplyShape, double>>* table, int mode = kModePlain) {
   const int n = shape_class(nsys);
   const size_t eb = elem_bytes(e);
   ApplyShape cand[kMaxCand];
-  const int nc = apply_candidates(ctx->dn.n, eb, n, ctx->lds_max, cand, kMaxCand);
+  int nc = apply_candidates(ctx->dn.n, eb, n, ctx->lds_max, cand, kMaxCand);
+  if (mode == kModeResid) {      // the residual check runs single-pass shapes only
+    int k = 0;
+    for (int i = 0; i < nc; ++i)
+      if (cand[i].passes == 1) cand[k++] = cand[i];
+    nc = k;
+  }
   if (nc == 0) return fail(MSB_EINVAL, "autotune: no compiled apply shape covers a row");
   const size_t vb = (size_t)n * ctx->D * eb;
-  DevBuf x, y, ds;
-  if (hipMalloc(&x.p, vb) != hipSuccess || hipMalloc(&y.p, vb) != hipSuccess ||
-      hipMalloc(&ds.p, n * sizeof(SysDev)) != hipSuccess) {
+  const int nbx = apply_nbx(ctx->up.n, n);
+  DevBuf x, y, ds, aux, part, red;
+  bool ok = hipMalloc(&x.p, vb) == hipSuccess && hipMalloc(&y.p, vb) == hipSuccess &&
+            hipMalloc(&ds.p, n * sizeof(SysDev)) == hipSuccess;
+  if (ok && mode != kModePlain)
+    ok = hipMalloc(&part.p, (size_t)n * nbx * 4 * sizeof(double)) == hipSuccess &&
+         hipMalloc(&red.p, (size_t)n * 4 * sizeof(double)) == hipSuccess;
+  if (ok && mode == kModeResid) ok = hipMalloc(&aux.p, (size_t)n * ctx->D * 16) == hipSuccess;
+  if (!ok) {
     (void)hipGetLastError();
     return fail(MSB_ENOMEM, "autotune: scratch vectors do not fit");
   }
@@ -140,7 +153,13 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   std::vector<SysDev> h(n, hs);
   MSB_HIP(hipMemcpyAsync(ds.p, h.data(), n * sizeof(SysDev), hipMemcpyHostToDevice, st));
   MSB_HIP(hipMemsetAsync(x.p, 0, vb, st));
+  if (aux.p) MSB_HIP(hipMemsetAsync(aux.p, 0, (size_t)n * ctx->D * 16, st));
   ApplyArgs a = apply_args(ctx, (const SysDev*)ds.p, n, x.p, y.p);
+  if (mode != kModePlain) {
+    a.partials = (double*)part.p;
+    a.red = (double*)red.p;
+    a.aux = (mode == kModeResid) ? aux.p : x.p;     // sigma reads a residual, the check reads E
+  }
   hipEvent_t e0, e1;
   MSB_HIP(hipEventCreate(&e0));
   MSB_HIP(hipEventCreate(&e1));
@@ -151,7 +170,7 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   // so far stops there, the others are timed over four more launches
   auto timed = [&](int reps, double* out) -> hipError_t {
     hipError_t r = hipEventRecord(e0, st);
-    for (int k = 0; k < reps && r == hipSuccess; ++k) r = launch_apply(e, kModePlain, a, st);
+    for (int k = 0; k < reps && r == hipSuccess; ++k) r = launch_apply(e, mode, a, st);
     if (r == hipSuccess) r = hipEventRecord(e1, st);
     if (r == hipSuccess) r = hipEventSynchronize(e1);
     float ms = 0;
@@ -161,7 +180,7 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   };
   for (int i = 0; i < nc && err == hipSuccess; ++i) {
     a.shape = cand[i];
-    err = launch_apply(e, kModePlain, a, st);
+    err = launch_apply(e, mode, a, st);
     double m = 0;
     if (err == hipSuccess) err = timed(1, &m);
     if (err == hipSuccess && !(best.blk != 0 && m > 1.5 * best_ms)) err = timed(4, &m);
@@ -175,17 +194,18 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   MSB_HIP(err);
-  ctx->shapes[{(int)e, n}] = best;
+  ctx->shapes[std::make_tuple((int)e, n, mode)] = best;
   return MSB_OK;
 }
 
 // Shape to use for an apply of nsys systems: the tuned or pinned one, tuning
 // now if allowed; {0,0,0} (the default shape) if tuning is off or failed.
-static ApplyShape shape_for(msb_ctx* ctx, Elem e, int nsys, hipStream_t st, bool tune) {
-  const auto key = std::make_pair((int)e, shape_class(nsys));
+static ApplyShape shape_for(msb_ctx* ctx, Elem e, int nsys, hipStream_t st, bool tune,
+                            int mode = kModePlain) {
+  const auto key = std::make_tuple((int)e, shape_class(nsys), mode);
   auto it = ctx->shapes.find(key);
   if (it != ctx->shapes.end()) return it->second;
-  if (!tune || tune_shapes(ctx, e, nsys, st, nullptr) != MSB_OK) {
+  if (!tune || tune_shapes(ctx, e, nsys, st, nullptr, mode) != MSB_OK) {
     (void)hipGetLastError();
     return ApplyShape{0, 0, 0, 0, 0};
   }
@@ -549,7 +569,7 @@ extern "C" msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, cons
   if (r != MSB_OK) return r;
   if (!sysdev_symmetric(ctx, hs))
     return fail(MSB_EINVAL, "Lanczos needs a symmetric H: give directed types equal amplitudes");
-  const ApplyShape shp = shape_for(ctx, Elem::R64, 1, st, true);
+  const ApplyShape shp = shape_for(ctx, Elem::R64, 1, st, true, kModeHerm);
 
   const size_t part_doubles = std::max<size_t>(
       {(size_t)apply_nbx(ctx->up.n, 1) * 4, (size_t)gram_blocks(D) * (kmax + 1),
@@ -812,11 +832,12 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   // apply launch shapes: tuned on first use, before the workspace is sized
   hipStream_t ust = (hipStream_t)stream;
   const bool tune = !(opts && opts->autotune < 0);
-  (void)shape_for(ctx, ev, nsys, ust, tune);
+  (void)shape_for(ctx, ev, nsys, ust, tune, kModeBilinear);
   if (replace_every > 0) (void)shape_for(ctx, Elem::C128, nsys, ust, tune);
   // the residual check stages FP64 rows whatever the storage: tune it as complex128
   if (want_true)
-    (void)shape_for(ctx, Elem::C128, (int)std::min<int64_t>((int64_t)nsys * n_shift, kTuneMaxSys), ust, tune);
+    (void)shape_for(ctx, Elem::C128, (int)std::min<int64_t>((int64_t)nsys * n_shift, kTuneMaxSys), ust, tune,
+                    kModeResid);
 
   // ---- plan: batch size and bank capacity from the memory that is free ----
   size_t fr = 0, tot = 0;
@@ -962,7 +983,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     MSB_HIP(launch_cocg_init(ev, ia, st));
 
     ApplyArgs aa = apply_args(ctx, dsys, nb, pvec, vvec);
-    aa.shape = shape_for(ctx, ev, nb, st, tune);
+    aa.shape = shape_for(ctx, ev, nb, st, tune, kModeBilinear);
     seed_shape = apply_shape_used(ev, kModeBilinear, aa);
     aa.aux = bank;
     aa.partials = partials;
@@ -1243,7 +1264,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       MSB_HIP(hipMemcpyAsync(bf.tsys, tsys.data(), need_sys, hipMemcpyHostToDevice, st));
       MSB_HIP(hipEventRecord(ev0, st));
       ApplyArgs ta = apply_args(ctx, bf.tsys, nt, psib, nullptr);
-      ta.shape = shape_for(ctx, Elem::C128, nt, st, tune);   // FP64 rows, as tuned above
+      ta.shape = shape_for(ctx, Elem::C128, nt, st, tune, kModeResid);   // FP64 rows, as tuned above
       ta.aux = Eb;
       ta.aux_div = n_shift;
       ta.partials = bf.tpart;
@@ -1429,7 +1450,7 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
   if (r != MSB_OK) return r;
   if (!sysdev_symmetric(ctx, hs))
     return fail(MSB_EINVAL, "Lanczos needs a symmetric H: give directed types equal amplitudes");
-  const ApplyShape shp = shape_for(ctx, Elem::C128, n, st, true);
+  const ApplyShape shp = shape_for(ctx, Elem::C128, n, st, true, kModeHerm);
   std::vector<SysDev> hsys(n, hs);
   const int nbx_l = lanczos_nbx(D, n);
   const size_t part_doubles =
@@ -1606,9 +1627,9 @@ extern "C" msb_status msb_set_shape(msb_ctx* ctx, int nsys, msb_prec prec, const
   if (nsys <= 0) return fail(MSB_EINVAL, "msb_set_shape: nsys must be positive");
   if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_set_shape: invalid precision");
   const Elem e = prec == MSB_C128 ? Elem::C128 : Elem::C64;
-  const auto key = std::make_pair((int)e, shape_class(nsys));
+  const int modes[] = {kModePlain, kModeBilinear, kModeHerm, kModeResid};
   if (shape->threads == 0) {
-    ctx->shapes.erase(key);
+    for (int md : modes) ctx->shapes.erase(std::make_tuple((int)e, shape_class(nsys), md));
     return MSB_OK;
   }
   ApplyShape cand[kMaxCand];
@@ -1617,7 +1638,7 @@ extern "C" msb_status msb_set_shape(msb_ctx* ctx, int nsys, msb_prec prec, const
     if (cand[i].blk == shape->threads && cand[i].ept == shape->elems_per_thread &&
         cand[i].nv == shape->vectors && cand[i].passes == (shape->passes == 2 ? 2 : 1) &&
         cand[i].order == (shape->row_order == 1 ? 1 : 0)) {
-      ctx->shapes[key] = cand[i];
+      for (int md : modes) ctx->shapes[std::make_tuple((int)e, shape_class(nsys), md)] = cand[i];
       return MSB_OK;
     }
   return fail(MSB_EINVAL, "msb_set_shape: shape not compiled or not usable for this row length");

@@ -10,6 +10,7 @@
 
 #include <cstdint>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -390,8 +391,10 @@ struct msb_ctx {
   // growable workspace
   void* ws = nullptr;
   size_t ws_size = 0;
-  // apply launch shapes chosen by the autotuner (or pinned), key (Elem, min(nsys, 4))
-  std::map<std::pair<int, int>, msb::ApplyShape> shapes;
+  // apply launch shapes chosen by the autotuner (or pinned), key (Elem,
+  // min(nsys, 16), apply mode): the fused reductions change a kernel's
+  // registers and occupancy, so each mode is tuned where it runs
+  std::map<std::tuple<int, int, int>, msb::ApplyShape> shapes;
   msb::TablesDev tables() const {
     msb::TablesDev t;
     t.conf_up = d_conf_up; t.conf_dn = d_conf_dn;
