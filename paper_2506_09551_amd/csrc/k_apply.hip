@@ -294,72 +294,108 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
 // of kPanel down-spin states.  The panels are dealt to the XCDs round robin
 // (panel p on XCD p % 8) and one XCD works through a panel before the next, so
 // the panel (n_up x kPanel elements, 2.2 MB for 4368 rows in complex64) stays
-// in that XCD's L2 while every row gathers its up-spin neighbours from it; the
-// single-pass kernel fetches those neighbour rows from the Infinity Cache.
-// One wave handles one row of a panel (one element per lane), a workgroup
-// kRowsPerWg consecutive rows.  The row kernel then adds I (x) H_dn in place
-// (ApplyArgs::vin).
-constexpr int kPanel = 64, kRowsPerWg = 16;
+// in that XCD's L2 while every row gathers its up-spin neighbours from it.
+// A workgroup takes kRowsPerWg consecutive rows of one panel: it first lists
+// their work items in LDS (per row the diagonal, then every up-spin hop with
+// its signed amplitude), then each wavefront walks the items of its own rows
+// (one column per lane) with the neighbour-row load kPrefetch items ahead of
+// its use, across row boundaries, so the gathers stay in flight.  The row
+// kernel then adds I (x) H_dn in place (ApplyArgs::vin).
+constexpr int kPanel = 64, kRowsPerWg = 16, kPanelItems = 1024, kPrefetch = 8;
+constexpr uint32_t kDiagItem = 0x80000000u;
 
 int panel_nbx(int n_up, int n_dn) {
   const int n_panels = (n_dn + kPanel - 1) / kPanel;
   const int chunks = (n_up + kRowsPerWg - 1) / kRowsPerWg;
   return kNumXcd * ((n_panels + kNumXcd - 1) / kNumXcd) * chunks;
 }
+bool panel_fits(int k_up_max) { return kRowsPerWg * (1 + k_up_max) <= kPanelItems; }
 
 template <typename S, typename Tc, bool CPLX>
 __global__ __launch_bounds__(256) void k_apply_up(ApplyArgs a) {
   using Ax = Access<S, CPLX>;
+  __shared__ int s_off[kRowsPerWg + 1];
+  __shared__ uint32_t s_tgt[kPanelItems];     // input row (kDiagItem | u for a row's diagonal)
+  __shared__ Tc s_cf[kPanelItems];            // signed hop amplitude
   const int s = blockIdx.y;
   const int nd = a.T.n_dn, nu = a.T.n_up;
   const int chunks = (nu + kRowsPerWg - 1) / kRowsPerWg;
   const int x = blockIdx.x % kNumXcd, l = blockIdx.x / kNumXcd;
   const int panel = x + kNumXcd * (l / chunks), chunk = l % chunks;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int d = panel * kPanel + lane;
   if (panel * kPanel >= nd) return;
   if (a.status && a.status[(int64_t)s * a.status_stride] != kActive) return;
   const SysDev* sd = a.sys + s;
-  const Tc U = (Tc)sd->U, Uc = (Tc)sd->Uc, dre = (Tc)sd->d_re, dim = (Tc)sd->d_im;
-  const int core = sd->core;
-  void* vv = Ax::offset(a.v, (int64_t)s * a.D);
+  const int r0 = chunk * kRowsPerWg;
+  const int nrows = min(kRowsPerWg, nu - r0);
+  if (threadIdx.x == 0) {
+    int o = 0;
+    for (int r = 0; r < nrows; ++r) {
+      s_off[r] = o;
+      o += 1 + (int)(a.T.off_up[r0 + r + 1] - a.T.off_up[r0 + r]);
+    }
+    s_off[nrows] = o;                          // <= kPanelItems (panel_fits on the host)
+  }
+  __syncthreads();
+  const int n_items = s_off[nrows];
+  for (int t = threadIdx.x; t < n_items; t += blockDim.x) {
+    int r = 0;
+    while (t >= s_off[r + 1]) ++r;
+    const int u = r0 + r, k = t - s_off[r];
+    if (k == 0) {
+      s_tgt[t] = kDiagItem | (uint32_t)u;
+      s_cf[t] = (Tc)0;
+    } else {
+      const uint32_t h = a.T.hop_up[a.T.off_up[u] + k - 1];
+      s_tgt[t] = h >> 16;
+      s_cf[t] = flip_sign((Tc)sd->amp[(h >> 1) & (MSB_MAX_BOND_TYPES - 1)], (h & 1u) ? 0u : 0x80000000u);
+    }
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rows_per_wave = kRowsPerWg / 4;
+  const int i0 = s_off[min(wave * rows_per_wave, nrows)];
+  const int i1 = s_off[min((wave + 1) * rows_per_wave, nrows)];
+  const int d = panel * kPanel + lane;
   const bool ok = d < nd;
   const uint32_t dc = (uint32_t)(ok ? d : nd - 1);        // idle lanes read a valid column
   const uint32_t cd = a.T.conf_dn[dc];
-  for (int r = wave; r < kRowsPerWg; r += 4) {
-    const int u = chunk * kRowsPerWg + r;
-    if (u >= nu) break;
-    const uint32_t cu = a.T.conf_up[u];
-    const cv<Tc> xo = Ax::template load<Tc>(Ax::offset(a.x, (int64_t)s * a.D + (int64_t)u * nd), dc);
-    Tc dg = U * (Tc)__builtin_popcount(cu & cd) + dre;
-    if (core >= 0) dg += Uc * (Tc)(((cu >> core) & 1u) + ((cd >> core) & 1u));
-    cv<Tc> acc = {dg * xo.re - dim * xo.im, dg * xo.im + dim * xo.re};
-    const int h0 = (int)a.T.off_up[u], nh = (int)a.T.off_up[u + 1] - h0;
-    // the hop list is uniform per wavefront: scalar loads, scalar coefficients
-    auto hops = [&](auto G, int k) {
-      constexpr int NG = decltype(G)::value;
-      cv<Tc> xn[NG];
-      Tc cf[NG];
+  const Tc U = (Tc)sd->U, Uc = (Tc)sd->Uc, dre = (Tc)sd->d_re, dim = (Tc)sd->d_im;
+  const int core = sd->core;
+  const void* xsys = Ax::offset(a.x, (int64_t)s * a.D);
+  void* vv = Ax::offset(a.v, (int64_t)s * a.D);
+  cv<Tc> buf[kPrefetch];
 #pragma unroll
-      for (int j = 0; j < NG; ++j) {
-        const uint32_t h = a.T.hop_up[h0 + k + j];
-        const uint32_t sb = (h & 1u) ? 0u : 0x80000000u;   // parity 0: -t
-        cf[j] = flip_sign((Tc)sd->amp[(h >> 1) & (MSB_MAX_BOND_TYPES - 1)], sb);
-        xn[j] = Ax::template load<Tc>(Ax::offset(a.x, (int64_t)s * a.D + (int64_t)(h >> 16) * nd), dc);
-      }
+  for (int j = 0; j < kPrefetch; ++j)
+    if (i0 + j < i1) buf[j] = Ax::template load<Tc>(xsys, (int64_t)(s_tgt[i0 + j] & ~kDiagItem) * nd + dc);
+  int row = -1;
+  cv<Tc> acc = {(Tc)0, (Tc)0};
+  for (int i = i0; i < i1; i += kPrefetch) {
 #pragma unroll
-      for (int j = 0; j < NG; ++j) {
-        acc.re += cf[j] * xn[j].re;
-        acc.im += cf[j] * xn[j].im;
+    for (int j = 0; j < kPrefetch; ++j) {
+      const int it = i + j;
+      if (it < i1) {                          // uniform across the wavefront
+        const uint32_t tg = s_tgt[it];
+        const cv<Tc> xv = buf[j];
+        if (it + kPrefetch < i1)
+          buf[j] = Ax::template load<Tc>(xsys, (int64_t)(s_tgt[it + kPrefetch] & ~kDiagItem) * nd + dc);
+        if (tg & kDiagItem) {
+          if (row >= 0 && ok) Ax::store(vv, (int64_t)row * nd + d, acc);
+          row = (int)(tg & ~kDiagItem);
+          const uint32_t cu = a.T.conf_up[row];
+          Tc dg = U * (Tc)__builtin_popcount(cu & cd) + dre;
+          if (core >= 0) dg += Uc * (Tc)(((cu >> core) & 1u) + ((cd >> core) & 1u));
+          acc = {dg * xv.re - dim * xv.im, dg * xv.im + dim * xv.re};
+        } else {
+          const Tc c = s_cf[it];
+          acc.re += c * xv.re;
+          acc.im += c * xv.im;
+        }
       }
-    };
-    constexpr int HG = 8;
-    int k = 0;
-    for (; k + HG <= nh; k += HG) hops(std::integral_constant<int, HG>{}, k);
-    for (; k < nh; ++k) hops(std::integral_constant<int, 1>{}, k);
-    if (ok) Ax::store(vv, (int64_t)u * nd + d, acc);
+    }
   }
+  if (row >= 0 && ok) Ax::store(vv, (int64_t)row * nd + d, acc);
 }
 
 int apply_rows_per_xcd(int n_up) { return (n_up + kNumXcd - 1) / kNumXcd; }
@@ -412,10 +448,11 @@ static bool usable(const ApplyShape& sh, int nd, size_t row_bytes, int nsys, siz
   return true;
 }
 
-int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, ApplyShape* out, int max_out) {
+int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, int k_up_max, ApplyShape* out,
+                     int max_out) {
   int n = 0;
   for (int order = 0; order <= 1; ++order)
-    for (int passes = 1; passes <= 2; ++passes)
+    for (int passes = 1; passes <= (panel_fits(k_up_max) ? 2 : 1); ++passes)
       for (int i = 0; i < kNumShapes && n < max_out; ++i) {
         ApplyShape sh = kShapes[i];
         sh.passes = passes;
@@ -453,7 +490,7 @@ static ApplyShape resolve_shape(const ApplyArgs& a, size_t row_bytes, bool allow
   const int nd = a.T.n_dn;
   ApplyShape sh = a.shape;
   if (sh.blk > 0) {
-    if (sh.passes == 2 && !allow_two) sh.passes = 1;
+    if (sh.passes == 2 && (!allow_two || !panel_fits(a.T.k_up_max))) sh.passes = 1;
     for (; sh.nv >= 1; sh.nv /= 2)
       if (usable(sh, nd, row_bytes, a.nsys, a.lds_max)) return sh;
   }

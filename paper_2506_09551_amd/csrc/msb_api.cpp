@@ -122,7 +122,7 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   const int n = shape_class(nsys);
   const size_t eb = elem_bytes(e);
   ApplyShape cand[kMaxCand];
-  int nc = apply_candidates(ctx->dn.n, eb, n, ctx->lds_max, cand, kMaxCand);
+  int nc = apply_candidates(ctx->dn.n, eb, n, ctx->lds_max, ctx->up.max_hops, cand, kMaxCand);
   if (mode == kModeResid) {      // the residual check runs single-pass shapes only
     int k = 0;
     for (int i = 0; i < nc; ++i)
@@ -1635,7 +1635,8 @@ extern "C" msb_status msb_set_shape(msb_ctx* ctx, int nsys, msb_prec prec, const
     return MSB_OK;
   }
   ApplyShape cand[kMaxCand];
-  const int nc = apply_candidates(ctx->dn.n, elem_bytes(e), shape_class(nsys), ctx->lds_max, cand, kMaxCand);
+  const int nc = apply_candidates(ctx->dn.n, elem_bytes(e), shape_class(nsys), ctx->lds_max, ctx->up.max_hops,
+                                  cand, kMaxCand);
   for (int i = 0; i < nc; ++i)
     if (cand[i].blk == shape->threads && cand[i].ept == shape->elems_per_thread &&
         cand[i].nv == shape->vectors && cand[i].passes == (shape->passes == 2 ? 2 : 1) &&

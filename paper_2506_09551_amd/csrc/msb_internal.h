@@ -80,6 +80,7 @@ struct TablesDev {
   const uint32_t* ell_dn;
   const uint32_t* order_up;   // [n_up] up-spin rows in level order (SpinTable::order)
   int n_up, n_dn, k_dn;       // k_dn: sum of k_type
+  int k_up_max;               // most up-spin hops of one row
   int n_types;
   int k_type[MSB_MAX_BOND_TYPES];
 };
@@ -136,7 +137,8 @@ int apply_nbx(int n_up, int nsys);  // grid.x (workgroups per system) for the ap
 int apply_rows_per_xcd(int n_up);
 // Compiled shapes usable for rows of nd elements (row_bytes per element of the
 // staged row) and nsys systems; returns how many were written to out.
-int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, ApplyShape* out, int max_out);
+int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, int k_up_max, ApplyShape* out,
+                     int max_out);
 // The shape launch_apply(e, mode, a) will use.
 ApplyShape apply_shape_used(Elem e, int mode, const ApplyArgs& a);
 
@@ -403,6 +405,7 @@ struct msb_ctx {
     t.ell_dn = d_ell_dn;
     t.order_up = d_order_up;
     t.n_up = up.n; t.n_dn = dn.n; t.k_dn = 0;
+    t.k_up_max = up.max_hops;
     t.n_types = n_types;
     for (int i = 0; i < MSB_MAX_BOND_TYPES; ++i) {
       t.k_type[i] = i < n_types ? k_type_dn[i] : 0;
