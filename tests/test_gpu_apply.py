@@ -142,3 +142,52 @@ def test_every_apply_shape_matches_oracle(gpu, name, prec):
             msb.msb_set_shape(ctx, 1, p, (512, 3, 1))      # not a compiled shape
     finally:
         msb.msb_destroy(ctx)
+
+
+def test_longest_row_and_the_lds_limit(gpu):
+    """The longest down-spin row one workgroup can stage: L = 16, N_dn = 8
+    (12,870 states, 103 KB in complex64) applies correctly in complex64 and is
+    refused in complex128 (206 KB would exceed the 160 KB of LDS)."""
+    import torch
+    msb = gpu
+    m = dict(L=16, nu=1, nd=8, bonds=W.square_bonds(4, 4, 1.0, -0.25), U=8.0)
+    ctx = msb.msb_create(m["L"], m["nu"], m["nd"], m["bonds"], m["U"])
+    try:
+        D = msb.msb_dim(ctx)
+        assert D == 16 * 12870
+        s = msb.make_system(core_site=3, Uc=-4.0, E_G=-2.0, Gamma=1.0)
+        x = W.random_complex(D, 77)
+        xt = torch.from_numpy(x).to(torch.complex64).cuda()
+        yt = torch.empty_like(xt)
+        msb.msb_apply(ctx, [s], 0.0, msb.MSB_C64, xt, yt)
+        torch.cuda.synchronize()
+        xr = x.astype(np.complex64).astype(np.complex128)
+        ref = oracle_H(m, core_site=3, Uc=-4.0) @ xr - (-2.0 + 1j) * xr
+        got = yt.cpu().numpy().astype(np.complex128)
+        assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref))
+        x2 = torch.from_numpy(x).cuda()
+        with pytest.raises(msb.MsbError):
+            msb.msb_apply(ctx, [s], 0.0, msb.MSB_C128, x2, torch.empty_like(x2))
+    finally:
+        msb.msb_destroy(ctx)
+
+
+def test_one_state_spin_sector(gpu):
+    """N_up = 0: a single up-spin configuration (no up hops, one row)."""
+    import torch
+    msb = gpu
+    m = dict(L=6, nu=0, nd=3, bonds=W.chain_bonds(6, 1.0, -0.3), U=8.0)
+    ctx = msb.msb_create(m["L"], m["nu"], m["nd"], m["bonds"], m["U"])
+    try:
+        D = msb.msb_dim(ctx)
+        assert D == 20
+        s = msb.make_system(core_site=1, Uc=-4.0, E_G=-1.0, Gamma=0.5)
+        x = W.random_complex(D, 78)
+        xt = torch.from_numpy(x).cuda()
+        yt = torch.empty_like(xt)
+        msb.msb_apply(ctx, [s], 0.25, msb.MSB_C128, xt, yt)
+        torch.cuda.synchronize()
+        ref = oracle_H(m, core_site=1, Uc=-4.0) @ x - (-1.0 + 0.25 + 0.5j) * x
+        assert np.max(np.abs(yt.cpu().numpy() - ref)) <= 1e-14 * np.max(np.abs(ref))
+    finally:
+        msb.msb_destroy(ctx)
