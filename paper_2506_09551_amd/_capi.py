@@ -60,7 +60,7 @@ class msb_shape(ctypes.Structure):
 class msb_opts(ctypes.Structure):
     _fields_ = [("chunk", c_int), ("bank_slots", c_int), ("batch", c_int),
                 ("replace_every", c_int), ("use_graph", c_int), ("mem_fraction", c_double),
-                ("assembly_engine", c_int), ("autotune", c_int), ("dual", c_int)]
+                ("assembly_engine", c_int), ("autotune", c_int), ("dual", c_int), ("direct_ap", c_int)]
 
 
 _lib = None

@@ -85,6 +85,15 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
   bool any = false;
 #pragma unroll
   for (int v = 0; v < NV; ++v) any |= act[v];
+  // operand of each vector: x[s] or, when the operand is the aux bank slot
+  // itself, that slot; a ragged last group's slots past the last system
+  // point at system s0 (always present) and are added with coefficient 0
+  int64_t xoff[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const bool in = s0 + v < a.nsys;
+    xoff[v] = a.x_from_aux ? aux_off[in ? v : 0] : (int64_t)(in ? s0 + v : s0) * a.D;
+  }
 
   double part[NV][3];
 #pragma unroll
@@ -104,7 +113,7 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
     cv<Tc> xs[NV][EPT];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const void* x = Ax::offset(a.x, (int64_t)(s0 + v) * a.D + row0);
+      const void* x = Ax::offset(a.x_from_aux ? a.aux : a.x, xoff[v] + row0);
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         xs[v][e] = act[v] ? Ax::template load<Tc>(x, voff[e]) : cv<Tc>{(Tc)0, (Tc)0};
@@ -120,7 +129,7 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
           auxv[v][e] = {0.0, 0.0};
-          if (act[v]) {
+          if (act[v] && !a.x_from_aux) {
             if constexpr (MODE == kModeBilinear)
               auxv[v][e] = Ax::template load_nt<double>(a.aux, aux_off[v] + row0 + voff[e]);
             else
@@ -158,6 +167,7 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
     // (256-thread shapes have the registers for twice as many)
     constexpr int kLoadsInFlight = (sizeof(Tc) == 4 ? 12 : 8) * (BLK >= 1024 ? 1 : 2);
     constexpr int HG = (EPT * NV >= kLoadsInFlight) ? 1 : kLoadsInFlight / (EPT * NV);
+    const void* xsrc = a.x_from_aux ? a.aux : a.x;
     const int h0 = second_pass ? 0 : (int)a.T.off_up[u];
     const int nh = second_pass ? 0 : (int)a.T.off_up[u + 1] - h0;
     auto up_hops = [&](auto G, int k) {
@@ -173,10 +183,7 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           cf[j][v] = act[v] ? flip_sign((Tc)a.sys[s0 + v].amp[ty], sb) : (Tc)0;
-          // a ragged last group has slots past the last system: they read
-          // system s0 (always present) and add it with coefficient 0
-          const int sv = (s0 + v < a.nsys) ? s0 + v : s0;
-          const void* x = Ax::offset(a.x, (int64_t)sv * a.D + nrow);
+          const void* x = Ax::offset(xsrc, xoff[v] + nrow);
 #pragma unroll
           for (int e = 0; e < EPT; ++e) xn[j][v][e] = Ax::template load<Tc>(x, voff[e]);
         }
@@ -247,9 +254,16 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
         if constexpr (MODE != kModeResid) Ax::store_nt(a.v, vbase + gi, vv);
         if constexpr (MODE == kModeBilinear) {
           // sigma = sum r_i v_i (unconjugated, r^T v) with r the stored residual
+          // (the staged row when the operand is r itself)
           cv<double> r;
-          if constexpr (kAuxEarly) r = auxv[v][e];
-          else r = Ax::template load_nt<double>(a.aux, aux_off[v] + gi);
+          if (a.x_from_aux) {
+            const cv<Tc> q = rows[v * ldr + d];
+            r = {(double)q.re, (double)q.im};
+          } else if constexpr (kAuxEarly) {
+            r = auxv[v][e];
+          } else {
+            r = Ax::template load_nt<double>(a.aux, aux_off[v] + gi);
+          }
           const cv<double> vs = {(double)(S)vv.re, (double)(S)vv.im};   // value as stored
           part[v][0] += r.re * vs.re - r.im * vs.im;
           part[v][1] += r.re * vs.im + r.im * vs.re;
@@ -363,7 +377,11 @@ __global__ __launch_bounds__(256) void k_apply_up(ApplyArgs a) {
   const uint32_t cd = a.T.conf_dn[dc];
   const Tc U = (Tc)sd->U, Uc = (Tc)sd->Uc, dre = (Tc)sd->d_re, dim = (Tc)sd->d_im;
   const int core = sd->core;
-  const void* xsys = Ax::offset(a.x, (int64_t)s * a.D);
+  // the operand: x[s], or the aux bank slot of an active system
+  const int64_t xo = (a.x_from_aux && a.aux_m)
+                         ? ((int64_t)s * a.aux_cap + (a.aux_m[(int64_t)s * a.status_stride] - *a.aux_base)) * a.D
+                         : (int64_t)s * a.D;
+  const void* xsys = Ax::offset(a.x_from_aux ? a.aux : a.x, xo);
   void* vv = Ax::offset(a.v, (int64_t)s * a.D);
   cv<Tc> buf[kPrefetch];
 #pragma unroll
@@ -501,6 +519,9 @@ template <typename S, typename Tc, bool CPLX, int MODE>
 static hipError_t launch_mode(const ApplyArgs& a0, hipStream_t st) {
   ApplyArgs a = a0;
   const int nd = a.T.n_dn;
+  // an operand read from the bank needs the slot of every active system
+  if (a.x_from_aux && (MODE != kModeBilinear || !a.aux || !a.aux_m || !a.aux_base || !a.status))
+    return hipErrorInvalidValue;
   const ApplyShape sh = resolve_shape(a, sizeof(cv<Tc>), MODE != kModeResid);
   if (sh.ept == 0 || (int64_t)sh.blk * sh.ept < nd || (size_t)sh.nv * (nd + 1) * sizeof(cv<Tc>) > a.lds_max)
     return hipErrorInvalidValue;

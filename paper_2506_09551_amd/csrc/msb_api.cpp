@@ -738,7 +738,7 @@ struct SolveBufs {
     Pc = carry ? c.take<void>((size_t)B * n_shift * D * s_out) : nullptr;
     dsys = c.take<SysDev>(B * sizeof(SysDev));
     dst = c.take<SysState>(B * sizeof(SysState));
-    partials = c.take<double>(part_n * 4 * sizeof(double));
+    partials = c.take<double>(part_n * 8 * sizeof(double));   // up to 8 sums per entry
     red1 = c.take<double>((size_t)B * 4 * sizeof(double));
     red2 = c.take<double>((size_t)B * 4 * sizeof(double));
     dbase = c.take<int>(4 * sizeof(int));
@@ -825,6 +825,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     if (r != MSB_OK) return r;
     dual = dual || !sysdev_symmetric(ctx, hsys[s]);
   }
+  // recurred seed form (A p_m carried by recurrence, p_m never formed); the
+  // dual form and residual replacement use p_m and run the direct form
+  const bool recur = !dual && replace_every == 0 && !(opts && opts->direct_ap == 1);
   if (dual) {
     if (prec != MSB_C128) return fail(MSB_EINVAL, "msb_solve: the dual-space form runs in complex128");
     hsysT.resize(nsys);
@@ -995,6 +998,11 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     aa.aux_m = &dst[0].m;
     aa.aux_base = dbase;
     aa.aux_cap = cap;
+    if (recur) {                 // w = A r_m from the bank slot in place, into pvec
+      aa.x = nullptr;
+      aa.x_from_aux = 1;
+      aa.v = pvec;
+    }
     ApplyArgs ta = apply_args(ctx, bf.dsysT, nb, bf.pt, bf.vt);   // dual: v~ = A^T p~
     if (dual) {
       aa.aux = bf.rt;            // sigma = r~^T A p
@@ -1017,6 +1025,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ca.rt = dual ? bf.rt : nullptr;
     ca.pt = dual ? bf.pt : nullptr;
     ca.vt = dual ? bf.vt : nullptr;
+    ca.recur = recur ? 1 : 0;
 
     int base = 0;
     bool first_flush = true;
@@ -1107,6 +1116,12 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     hipGraphExec_t gexec = nullptr;
     auto enqueue_chunk = [&]() -> hipError_t {
       for (int c = 0; c < chunk; ++c) {
+        if (recur) {
+          hipError_t e = launch_apply(ev, kModeBilinear, aa, st);
+          if (e == hipSuccess) e = launch_cocg_w(ev, ca, st);
+          if (e != hipSuccess) return e;
+          continue;
+        }
         hipError_t e = launch_cocg_p(ev, ca, st);
         if (e == hipSuccess) e = launch_apply(ev, kModeBilinear, aa, st);
         if (e == hipSuccess && dual) e = launch_apply(ev, kModePlain, ta, st);

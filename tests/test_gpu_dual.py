@@ -76,7 +76,8 @@ def test_dual_space_form_on_symmetric_system_is_identical(directed):
     E = W.random_complex(B.dim, 6)
     w = np.linspace(-6.0, 6.0, 16)
     sysd = _sys(msb, 0.0, core_site=0, Uc=-4.0, E_G=-3.0, Gamma=1.0)
-    _, i1, p1 = _run(msb, ctx, [sysd], E, w, 1e-12, 3000, msb.MSB_C128)
+    # the dual form applies A to p_m itself, as the direct COCG form does
+    _, i1, p1 = _run(msb, ctx, [sysd], E, w, 1e-12, 3000, msb.MSB_C128, opts={"direct_ap": 1})
     _, i2, p2 = _run(msb, ctx, [sysd], E, w, 1e-12, 3000, msb.MSB_C128, opts={"dual": 1})
     assert i1["iters"] == i2["iters"] and i2["mvms"] == 2 * i1["mvms"]
     assert np.array_equal(p1, p2)

@@ -91,9 +91,42 @@ def test_seed_shift_and_batched_systems(tiny):
         assert err <= 1e-9, f"system {j}: {err:.3e}"
 
 
+@pytest.mark.parametrize("direct_ap", [0, 1])
+def test_seed_forms_agree(tiny, direct_ap):
+    """The recurred seed form (A p_m = A r_m + beta_{m-1} A p_{m-1}, the default)
+    and the direct one (A p_m applied, as Algorithm 1 writes it) both match the
+    direct solves, and their seed residual histories agree while rounding has
+    not yet separated them."""
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E_G = -2.6661474201323485
+    systems = [msb.make_system(core_site=j, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma) for j in (0, 2, 4)]
+    E = np.stack([W.random_complex(D, 40 + j) for j in range(3)])
+    w = np.linspace(-5.0, 8.0, 29)
+    st, info, psi = _run(msb, ctx, systems, E, w, 1e-12, 3000, msb.MSB_C128, seed_shift=0.5,
+                         opts={"direct_ap": direct_ap}, hist_len=3001)
+    for j, s in enumerate(systems):
+        ref = osolve.direct_solve(oracle_H(m, core_site=s.core_site, Uc=wl.Uc), E[j], E_G,
+                                  wl.Gamma, w, method="eig")
+        assert _rel(psi[j], ref) <= 1e-9
+    assert info["mvms"] == int(np.sum(info["sys_iters"]))   # one product per iteration
+    assert np.max(info["resid_true"]) <= 1e-11
+    _, info_o, psi_o = _run(msb, ctx, systems, E, w, 1e-12, 3000, msb.MSB_C128, seed_shift=0.5,
+                            opts={"direct_ap": 1 - direct_ap}, hist_len=3001)
+    for j in range(3):
+        n = min(info["sys_iters"][j], info_o["sys_iters"][j])
+        assert abs(int(info["sys_iters"][j]) - int(info_o["sys_iters"][j])) <= max(2, n // 30)
+        k = min(40, int(n))
+        h, ho = info["seed_hist"][j][:k], info_o["seed_hist"][j][:k]
+        assert np.max(np.abs(h - ho) / ho) <= 1e-9
+    assert _rel(psi.reshape(-1, D), psi_o.reshape(-1, D)) <= 1e-9
+
+
+@pytest.mark.parametrize("direct_ap", [0, 1])
 @pytest.mark.parametrize("slots", [5, 37, 120])
-def test_small_bank_forces_carry_flushes(tiny, slots):
-    """A bank smaller than the iteration count: blocked assembly with carried p^w."""
+def test_small_bank_forces_carry_flushes(tiny, slots, direct_ap):
+    """A bank smaller than the iteration count: blocked assembly with carried p^w
+    (in the recurred seed form A p_{m-1} simply carries over the bank restart)."""
     msb, ctx, wl, m = tiny
     D = msb.msb_dim(ctx)
     E = W.random_vector(D, 5).astype(np.complex128)
@@ -102,7 +135,7 @@ def test_small_bank_forces_carry_flushes(tiny, slots):
     w = wl.w_in[::3]
     ref = osolve.direct_solve(oracle_H(m, core_site=0, Uc=wl.Uc), E, E_G, wl.Gamma, w, method="eig")
     st, info, psi = _run(msb, ctx, [sysd], E, w, 1e-12, 3000, msb.MSB_C128,
-                         opts={"bank_slots": slots})
+                         opts={"bank_slots": slots, "direct_ap": direct_ap})
     assert info["flushes"] > 1
     err = _rel(psi[0], ref)
     assert err <= 1e-9, f"slots={slots}: {err:.3e}"
