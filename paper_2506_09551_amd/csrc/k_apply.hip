@@ -63,14 +63,24 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
   int64_t aux_off[NV];
   Tc Uv[NV], Ucv[NV], dre[NV], dim[NV];
   int core[NV];
+  // status and bank slot are loaded side by side (neither waits for the
+  // other): every operand load of the workgroup waits for them
+  const int abase = a.aux_m ? *a.aux_base : 0;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int s = s0 + v;
-    act[v] = row_ok && s < a.nsys;
-    if (act[v] && a.status) act[v] = (a.status[(int64_t)s * a.status_stride] == kActive);
+    const bool in = row_ok && s < a.nsys;
+    const int stv = (in && a.status) ? a.status[(int64_t)s * a.status_stride] : (int)kActive;
+    const int mv = (in && a.aux_m) ? a.aux_m[(int64_t)s * a.status_stride] : 0;
+    act[v] = in && stv == (int)kActive;
     aux_off[v] = (int64_t)(s / a.aux_div) * a.D;
-    if (act[v] && a.aux_m)
-      aux_off[v] = ((int64_t)s * a.aux_cap + (a.aux_m[(int64_t)s * a.status_stride] - *a.aux_base)) * a.D;
+    if (in && a.aux_m) {
+      // clamped: an idle system's m may lie past the bank (its slot is read
+      // with coefficient 0 or not at all)
+      int slot = mv - abase;
+      slot = slot < 0 ? 0 : (slot >= a.aux_cap ? a.aux_cap - 1 : slot);
+      aux_off[v] = ((int64_t)s * a.aux_cap + slot) * a.D;
+    }
     Uv[v] = Ucv[v] = dre[v] = dim[v] = (Tc)0;
     core[v] = -1;
     if (act[v]) {

@@ -132,9 +132,12 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   if (nc == 0) return fail(MSB_EINVAL, "autotune: no compiled apply shape covers a row");
   const size_t vb = (size_t)n * ctx->D * eb;
   const int nbx = apply_nbx(ctx->up.n, n);
-  DevBuf x, y, ds, aux, part, red;
+  const bool self = mode == kTuneBilinearSelf;
+  const int kmode = self ? (int)kModeBilinear : mode;
+  DevBuf x, y, ds, aux, part, red, zi;
   bool ok = hipMalloc(&x.p, vb) == hipSuccess && hipMalloc(&y.p, vb) == hipSuccess &&
             hipMalloc(&ds.p, n * sizeof(SysDev)) == hipSuccess;
+  if (ok && self) ok = hipMalloc(&zi.p, (size_t)n * sizeof(int)) == hipSuccess;
   if (ok && mode != kModePlain)
     ok = hipMalloc(&part.p, (size_t)n * nbx * 4 * sizeof(double)) == hipSuccess &&
          hipMalloc(&red.p, (size_t)n * 4 * sizeof(double)) == hipSuccess;
@@ -162,6 +165,16 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
     a.red = (double*)red.p;
     a.aux = (mode == kModeResid) ? aux.p : x.p;     // sigma reads a residual, the check reads E
   }
+  if (self) {
+    // a one-slot bank (x itself), every system active at iteration 0
+    MSB_HIP(hipMemsetAsync(zi.p, 0, (size_t)n * sizeof(int), st));
+    a.x_from_aux = 1;
+    a.aux_m = (const int*)zi.p;
+    a.aux_base = (const int*)zi.p;
+    a.aux_cap = 1;
+    a.status = (const int*)zi.p;
+    a.status_stride = 1;
+  }
   hipEvent_t e0, e1;
   MSB_HIP(hipEventCreate(&e0));
   MSB_HIP(hipEventCreate(&e1));
@@ -172,7 +185,7 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   // so far stops there, the others are timed over four more launches
   auto timed = [&](int reps, double* out) -> hipError_t {
     hipError_t r = hipEventRecord(e0, st);
-    for (int k = 0; k < reps && r == hipSuccess; ++k) r = launch_apply(e, mode, a, st);
+    for (int k = 0; k < reps && r == hipSuccess; ++k) r = launch_apply(e, kmode, a, st);
     if (r == hipSuccess) r = hipEventRecord(e1, st);
     if (r == hipSuccess) r = hipEventSynchronize(e1);
     float ms = 0;
@@ -182,7 +195,7 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   };
   for (int i = 0; i < nc && err == hipSuccess; ++i) {
     a.shape = cand[i];
-    err = launch_apply(e, mode, a, st);
+    err = launch_apply(e, kmode, a, st);
     double m = 0;
     if (err == hipSuccess) err = timed(1, &m);
     if (err == hipSuccess && !(best.blk != 0 && m > 1.5 * best_ms)) err = timed(4, &m);
@@ -837,7 +850,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   // apply launch shapes: tuned on first use, before the workspace is sized
   hipStream_t ust = (hipStream_t)stream;
   const bool tune = !(opts && opts->autotune < 0);
-  (void)shape_for(ctx, ev, nsys, ust, tune, kModeBilinear);
+  const int seed_mode = recur ? (int)kTuneBilinearSelf : (int)kModeBilinear;
+  (void)shape_for(ctx, ev, nsys, ust, tune, seed_mode);
   if (replace_every > 0) (void)shape_for(ctx, Elem::C128, nsys, ust, tune);
   // the residual check stages FP64 rows whatever the storage: tune it as complex128
   if (want_true)
@@ -988,7 +1002,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     MSB_HIP(launch_cocg_init(ev, ia, st));
 
     ApplyArgs aa = apply_args(ctx, dsys, nb, pvec, vvec);
-    aa.shape = shape_for(ctx, ev, nb, st, tune, kModeBilinear);
+    aa.shape = shape_for(ctx, ev, nb, st, tune, seed_mode);
     seed_shape = apply_shape_used(ev, kModeBilinear, aa);
     aa.aux = bank;
     aa.partials = partials;
@@ -1644,7 +1658,7 @@ extern "C" msb_status msb_set_shape(msb_ctx* ctx, int nsys, msb_prec prec, const
   if (nsys <= 0) return fail(MSB_EINVAL, "msb_set_shape: nsys must be positive");
   if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_set_shape: invalid precision");
   const Elem e = prec == MSB_C128 ? Elem::C128 : Elem::C64;
-  const int modes[] = {kModePlain, kModeBilinear, kModeHerm, kModeResid};
+  const int modes[] = {kModePlain, kModeBilinear, kModeHerm, kModeResid, kTuneBilinearSelf};
   if (shape->threads == 0) {
     for (int md : modes) ctx->shapes.erase(std::make_tuple((int)e, shape_class(nsys), md));
     return MSB_OK;

@@ -91,7 +91,9 @@ enum ApplyMode : int {
   kModePlain = 0,       // v = A x
   kModeBilinear = 1,    // v = A x;  partial (sum aux*v, sum |v|^2)        -- COCG sigma
   kModeHerm = 2,        // v = A x;  partial (sum conj(x)*v, sum |v|^2)    -- Lanczos a_k
-  kModeResid = 3        // no v;     partial (sum |aux - A x|^2)           -- true residual
+  kModeResid = 3,       // no v;     partial (sum |aux - A x|^2)           -- true residual
+  kTuneBilinearSelf = 4 // shape key only: kModeBilinear with the operand read in place from
+                        // the bank (ApplyArgs::x_from_aux), the recurred seed form
 };
 
 // Launch shape of the apply kernel: threads per workgroup, elements per
