@@ -167,9 +167,10 @@ typedef struct {
   int dual;              /* 0 = the dual-space (BiCG) form only when some system's A is not
                             symmetric (default), 1 = always; MSB_C128 only */
   int direct_ap;         /* 0 = (default) where neither the dual form nor residual replacement
-                            runs, the seed applies A to its residual r_m in place and carries
-                            A p_m = A r_m + beta_{m-1} A p_{m-1} by recurrence, so p_m is never
-                            formed; 1 = apply A to p_m every iteration (Algorithm 1 as written) */
+                            runs, the seed applies A to its residual r_m in place and forms
+                            A p_m = A r_m + beta_{m-1} A p_{m-1} in the same pass, so p_m is
+                            never formed; 1 = form p_m and apply A to it (Algorithm 1 as
+                            written) */
 } msb_opts;
 
 /* ---- context -------------------------------------------------------------- */
@@ -258,9 +259,10 @@ msb_status msb_dipole(const msb_ctx* src, const msb_ctx* dst, int spin, int crea
  * with FP64 reductions and scalars, and replaces the seed residual by the
  * FP64 true residual every opts->replace_every iterations.
  * Otherwise the seed by default carries A p_m by recurrence (opts->direct_ap):
- * one apply of A to r_m, sigma_m = r_m^T A p_m formed from r_m^T A r_m and
- * the exact product r_m^T A p_{m-1}; the same alpha, beta and iterates as
- * Algorithm 1 up to rounding.
+ * the apply reads r_m in place from the residual bank and writes
+ * A p_m = A r_m + beta_{m-1} A p_{m-1} over the previous product, so p_m is
+ * never formed; sigma_m = r_m^T A p_m and every scalar are as in Algorithm 1,
+ * the iterates equal up to rounding.
  * When some system's A is not symmetric (directed bonds with different
  * amplitudes, msb_model) the dual-space form runs instead: a shadow residual
  * r~ and direction p~ follow the same recurrences with A^T (a second apply per

@@ -38,6 +38,7 @@ __device__ __forceinline__ double flip_sign(double a, uint32_t sb) {
 template <typename S, typename Tc, bool CPLX, int EPT, int MODE, int NV, int BLK>
 __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k_apply(ApplyArgs a) {
   using Ax = Access<S, CPLX>;
+  constexpr bool kSelf = MODE == kModeSelf;   // operand = the aux bank slot, in place
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cv<Tc>* rows = reinterpret_cast<cv<Tc>*>(smem_raw);    // [NV][nd + 1], element nd = 0
 
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const bool in = s0 + v < a.nsys;
-    xoff[v] = a.x_from_aux ? aux_off[in ? v : 0] : (int64_t)(in ? s0 + v : s0) * a.D;
+    xoff[v] = kSelf ? aux_off[in ? v : 0] : (int64_t)(in ? s0 + v : s0) * a.D;
   }
 
   double part[NV][3];
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
     cv<Tc> xs[NV][EPT];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const void* x = Ax::offset(a.x_from_aux ? a.aux : a.x, xoff[v] + row0);
+      const void* x = Ax::offset(kSelf ? a.aux : a.x, xoff[v] + row0);
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         xs[v][e] = act[v] ? Ax::template load<Tc>(x, voff[e]) : cv<Tc>{(Tc)0, (Tc)0};
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
           auxv[v][e] = {0.0, 0.0};
-          if (act[v] && !a.x_from_aux) {
+          if (act[v]) {
             if constexpr (MODE == kModeBilinear)
               auxv[v][e] = Ax::template load_nt<double>(a.aux, aux_off[v] + row0 + voff[e]);
             else
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
     // (256-thread shapes have the registers for twice as many)
     constexpr int kLoadsInFlight = (sizeof(Tc) == 4 ? 12 : 8) * (BLK >= 1024 ? 1 : 2);
     constexpr int HG = (EPT * NV >= kLoadsInFlight) ? 1 : kLoadsInFlight / (EPT * NV);
-    const void* xsrc = a.x_from_aux ? a.aux : a.x;
+    const void* xsrc = kSelf ? a.aux : a.x;
     const int h0 = second_pass ? 0 : (int)a.T.off_up[u];
     const int nh = second_pass ? 0 : (int)a.T.off_up[u + 1] - h0;
     auto up_hops = [&](auto G, int k) {
@@ -255,18 +256,31 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
     for (int v = 0; v < NV; ++v) {
       if (!act[v]) continue;
       const int64_t vbase = (int64_t)(s0 + v) * a.D;
+      // kModeSelf: v = A x + beta_s v (loaded here, so it holds no register
+      // through the hops; 0: the old v is not read)
+      cv<Tc> bacc = {(Tc)0, (Tc)0};
+      if (kSelf && a.beta)
+        bacc = {(Tc)a.beta[(int64_t)(s0 + v) * a.beta_stride], (Tc)a.beta[(int64_t)(s0 + v) * a.beta_stride + 1]};
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const int d = tid + e * BLK;
         if (d >= nd) continue;
         const int64_t gi = row0 + d;
-        const cv<Tc> vv = acc[v][e];
+        cv<Tc> vv = acc[v][e];
+        if constexpr (kSelf) {
+          // v_m = A r_m + beta_{m-1} v_{m-1}, in place (the first pass already added it)
+          if (!second_pass && (bacc.re != (Tc)0 || bacc.im != (Tc)0)) {
+            const cv<Tc> vo = Ax::template load_nt<Tc>(a.v, vbase + gi);
+            vv.re += bacc.re * vo.re - bacc.im * vo.im;
+            vv.im += bacc.re * vo.im + bacc.im * vo.re;
+          }
+        }
         if constexpr (MODE != kModeResid) Ax::store_nt(a.v, vbase + gi, vv);
-        if constexpr (MODE == kModeBilinear) {
+        if constexpr (MODE == kModeBilinear || kSelf) {
           // sigma = sum r_i v_i (unconjugated, r^T v) with r the stored residual
           // (the staged row when the operand is r itself)
           cv<double> r;
-          if (a.x_from_aux) {
+          if constexpr (kSelf) {
             const cv<Tc> q = rows[v * ldr + d];
             r = {(double)q.re, (double)q.im};
           } else if constexpr (kAuxEarly) {
@@ -279,7 +293,7 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
           part[v][1] += r.re * vs.im + r.im * vs.re;
           part[v][2] += vs.re * vs.re + vs.im * vs.im;
         } else if constexpr (MODE == kModeHerm) {
-          const cv<Tc> qv = xs[v][e];
+          const cv<Tc> qv = rows[v * ldr + d];   // the staged operand (frees xs early)
           part[v][0] += (double)qv.re * (double)vv.re + (double)qv.im * (double)vv.im;
           part[v][1] += (double)qv.re * (double)vv.im - (double)qv.im * (double)vv.re;
           part[v][2] += (double)vv.re * (double)vv.re + (double)vv.im * (double)vv.im;
@@ -393,6 +407,19 @@ __global__ __launch_bounds__(256) void k_apply_up(ApplyArgs a) {
                          : (int64_t)s * a.D;
   const void* xsys = Ax::offset(a.x_from_aux ? a.aux : a.x, xo);
   void* vv = Ax::offset(a.v, (int64_t)s * a.D);
+  // kModeSelf: v = A x + beta_s v, the old v added here (the row pass does not)
+  cv<Tc> bs = {(Tc)0, (Tc)0};
+  if (a.x_from_aux && a.beta) bs = {(Tc)a.beta[(int64_t)s * a.beta_stride], (Tc)a.beta[(int64_t)s * a.beta_stride + 1]};
+  const bool badd = bs.re != (Tc)0 || bs.im != (Tc)0;
+  auto put = [&](int r, cv<Tc> v) {
+    const int64_t o = (int64_t)r * nd + d;
+    if (badd) {
+      const cv<Tc> vo = Ax::template load<Tc>(vv, o);
+      v.re += bs.re * vo.re - bs.im * vo.im;
+      v.im += bs.re * vo.im + bs.im * vo.re;
+    }
+    Ax::store(vv, o, v);
+  };
   cv<Tc> buf[kPrefetch];
 #pragma unroll
   for (int j = 0; j < kPrefetch; ++j)
@@ -409,7 +436,7 @@ __global__ __launch_bounds__(256) void k_apply_up(ApplyArgs a) {
         if (it + kPrefetch < i1)
           buf[j] = Ax::template load<Tc>(xsys, (int64_t)(s_tgt[it + kPrefetch] & ~kDiagItem) * nd + dc);
         if (tg & kDiagItem) {
-          if (row >= 0 && ok) Ax::store(vv, (int64_t)row * nd + d, acc);
+          if (row >= 0 && ok) put(row, acc);
           row = (int)(tg & ~kDiagItem);
           const uint32_t cu = a.T.conf_up[row];
           Tc dg = U * (Tc)__builtin_popcount(cu & cd) + dre;
@@ -423,7 +450,7 @@ __global__ __launch_bounds__(256) void k_apply_up(ApplyArgs a) {
       }
     }
   }
-  if (row >= 0 && ok) Ax::store(vv, (int64_t)row * nd + d, acc);
+  if (row >= 0 && ok) put(row, acc);
 }
 
 int apply_rows_per_xcd(int n_up) { return (n_up + kNumXcd - 1) / kNumXcd; }
@@ -530,8 +557,8 @@ static hipError_t launch_mode(const ApplyArgs& a0, hipStream_t st) {
   ApplyArgs a = a0;
   const int nd = a.T.n_dn;
   // an operand read from the bank needs the slot of every active system
-  if (a.x_from_aux && (MODE != kModeBilinear || !a.aux || !a.aux_m || !a.aux_base || !a.status))
-    return hipErrorInvalidValue;
+  a.x_from_aux = MODE == kModeSelf ? 1 : 0;
+  if (MODE == kModeSelf && (!a.aux || !a.aux_m || !a.aux_base || !a.status)) return hipErrorInvalidValue;
   const ApplyShape sh = resolve_shape(a, sizeof(cv<Tc>), MODE != kModeResid);
   if (sh.ept == 0 || (int64_t)sh.blk * sh.ept < nd || (size_t)sh.nv * (nd + 1) * sizeof(cv<Tc>) > a.lds_max)
     return hipErrorInvalidValue;
@@ -577,12 +604,14 @@ hipError_t launch_apply(Elem e, int mode, const ApplyArgs& a, hipStream_t st) {
     case Elem::C128:
       if (mode == kModePlain) return launch_mode<double, double, true, kModePlain>(a, st);
       if (mode == kModeBilinear) return launch_mode<double, double, true, kModeBilinear>(a, st);
+      if (mode == kModeSelf) return launch_mode<double, double, true, kModeSelf>(a, st);
       if (mode == kModeHerm) return launch_mode<double, double, true, kModeHerm>(a, st);
       if (mode == kModeResid) return launch_mode<double, double, true, kModeResid>(a, st);
       break;
     case Elem::C64:
       if (mode == kModePlain) return launch_mode<float, float, true, kModePlain>(a, st);
       if (mode == kModeBilinear) return launch_mode<float, float, true, kModeBilinear>(a, st);
+      if (mode == kModeSelf) return launch_mode<float, float, true, kModeSelf>(a, st);
       if (mode == kModeResid) return launch_mode<float, double, true, kModeResid>(a, st);
       break;
   }

@@ -13,15 +13,12 @@
 // The x / p vectors of the shifted systems are not touched here: the
 // residuals r_m stay in the bank and the shifted solutions are assembled
 // from them in k_shift.hip.
-// Recurred form (CocgArgs::recur; neither the dual form nor residual
-// replacement): p_m is never formed.  The apply takes the bank slot r_m in
-// place, w_m = A r_m with delta_m = r_m^T w_m, and k_cocg_w carries
-//   A p_m = w_m + beta_{m-1} A p_{m-1}            (as p_m = r_m + beta_{m-1} p_{m-1})
-//   sigma_m = r_m^T A p_m = delta_m + beta_{m-1} gamma_{m-1}
-// with gamma_{m-1} = r_m^T A p_{m-1} summed when r_m was formed (no
-// orthogonality is assumed), then alpha_m and r_{m+1} as above.  Per
-// iteration that is one streaming update of five vector passes instead of
-// two of three each, and the apply reads its operand once.
+// Recurred form (neither the dual form nor residual replacement, which need
+// p_m): k_cocg_p is skipped and p_m never formed.  The apply (kModeSelf)
+// reads r_m in place from its bank slot and writes
+//   v_m = A r_m + beta_{m-1} v_{m-1} = A (r_m + beta_{m-1} p_{m-1}) = A p_m
+// over v_{m-1}, with sigma = r_m^T v_m as before; k_cocg_r and the
+// bookkeeping are unchanged.
 // Dual-space form (non-symmetric A; CocgArgs::rt set): the shadow residual
 // r~ and direction p~ follow the same recurrences with v~ = A^T p~ (a second
 // apply, plain mode), sigma = r~^T A p (the apply reads r~ instead of the bank
@@ -43,23 +40,6 @@ __device__ __forceinline__ bool sigma_breakdown(const SysState& st, const double
   if (!(sabs > 1e-14 * st.rtnorm * vnorm)) return true;   // also catches NaN (r~ = r unless dual)
   alpha = cdiv({st.rho_re, st.rho_im}, sigma);
   return false;
-}
-
-// Recurred form: sigma_m = delta_m + beta_{m-1} gamma_{m-1}; the breakdown test
-// takes |w| + |beta_{m-1}| |A p_{m-1}| >= |A p_m| for |v|.
-__device__ __forceinline__ bool recur_breakdown(const SysState& st, const double* red1, int s,
-                                                cv<double>& alpha) {
-  const cv<double> beta = {st.bp_re, st.bp_im};
-  const cv<double> sigma = cadd({red1[s * 4 + 0], red1[s * 4 + 1]}, cmul(beta, {st.g_re, st.g_im}));
-  const double vbound = sqrt(red1[s * 4 + 2]) + cabs(beta) * st.vnorm;
-  if (!(cabs(sigma) > 1e-14 * st.rtnorm * vbound)) return true;
-  alpha = cdiv({st.rho_re, st.rho_im}, sigma);
-  return false;
-}
-
-__device__ __forceinline__ bool seed_breakdown(const CocgArgs& a, const SysState& st, int s,
-                                               cv<double>& alpha) {
-  return a.recur ? recur_breakdown(st, a.red1, s, alpha) : sigma_breakdown(st, a.red1, s, alpha);
 }
 
 template <typename S>
@@ -107,8 +87,6 @@ __global__ __launch_bounds__(kBlock) void k_cocg_init_fin(InitArgs a) {
     st.normE = st.rnorm;
     st.ap_re = 1.0; st.ap_im = 0.0;     // alpha_{-1} = 1
     st.bp_re = 0.0; st.bp_im = 0.0;     // beta_{-1} = 0
-    st.g_re = st.g_im = 0.0;            // A p_{-1} = 0
-    st.vnorm = 0.0;
     st.al_re = st.al_im = st.be_re = st.be_im = 0.0;
     st.m = 0;
     st.rbest = st.normE;
@@ -200,13 +178,12 @@ __global__ __launch_bounds__(kBlock) void k_cocg_r(CocgArgs a) {
 // the freeze test and the status for the next iteration.
 __global__ __launch_bounds__(kBlock) void k_cocg_book(CocgArgs a) {
   const int s = blockIdx.x;
-  __shared__ double red2[6];
-  if (a.recur) reduce_partials<6, 8>(a.partials, a.nbx, s, red2);
-  else reduce_partials<4>(a.partials, a.nbx, s, red2);
+  __shared__ double red2[4];
+  reduce_partials<4>(a.partials, a.nbx, s, red2);
   SysState t = a.st[s];
   if (t.status != kActive) return;
   cv<double> alpha;
-  if (seed_breakdown(a, t, s, alpha)) {
+  if (sigma_breakdown(t, a.red1, s, alpha)) {
     if (threadIdx.x == 0) {
       a.st[s].status = kBreakdown;
       a.st[s].breakdown_iter = t.m;
@@ -258,11 +235,6 @@ __global__ __launch_bounds__(kBlock) void k_cocg_book(CocgArgs a) {
     t.rho_re = rho_new.re; t.rho_im = rho_new.im;
     t.rnorm = rn;
     t.rtnorm = rtn;
-    if (a.recur) {                      // gamma_m = r_{m+1}^T A p_m, |A p_m|
-      t.g_re = red2[3];
-      t.g_im = red2[4];
-      t.vnorm = sqrt(red2[5]);
-    }
     t.m = m + 1;
     if (t.n_active == 0) {
       t.status = kDone;
@@ -314,58 +286,6 @@ __global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
   }
 }
 
-// Recurred form, one pass over the vectors: A p_m = w + beta_{m-1} A p_{m-1}
-// (in place in vvec; at m = 0 beta_{-1} = 0 and A p_0 = w), r_{m+1} = r_m -
-// alpha_m A p_m into the next bank slot, and the partials of rho_{m+1} =
-// r^T r, |r_{m+1}|^2, gamma_m = r_{m+1}^T A p_m and |A p_m|^2 (as stored).
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_cocg_w(CocgArgs a) {
-  using Ax = Access<S, true>;
-  const int s = blockIdx.y, bx = blockIdx.x;
-  double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  const SysState st = a.st[s];
-  if (st.status == kActive) {
-    cv<double> alpha;
-    if (!recur_breakdown(st, a.red1, s, alpha)) {
-      const int slot = st.m - *a.base;
-      const void* r = Ax::offset((const void*)a.bank, ((int64_t)s * a.cap + slot) * a.D);
-      void* rn = Ax::offset(a.bank, ((int64_t)s * a.cap + slot + 1) * a.D);
-      const void* w = Ax::offset((const void*)a.pvec, (int64_t)s * a.D);
-      void* ap = Ax::offset(const_cast<void*>(a.vvec), (int64_t)s * a.D);
-      const cv<double> beta = {st.bp_re, st.bp_im};
-      const bool carry = !(beta.re == 0.0 && beta.im == 0.0);   // uniform; false at m = 0
-      for (int64_t base = (int64_t)bx * kPerStep; base < a.D; base += (int64_t)a.nbx * kPerStep) {
-#pragma unroll
-        for (int e = 0; e < kEptStream; ++e) {
-          const int64_t i = base + e * kBlock + threadIdx.x;
-          if (i < a.D) {
-            const cv<double> ri = Ax::template load<double>(r, i);
-            cv<double> vi = Ax::template load<double>(w, i);
-            if (carry) {
-              const cv<double> vo = Ax::template load<double>(ap, i);
-              vi = {vi.re + (beta.re * vo.re - beta.im * vo.im), vi.im + (beta.re * vo.im + beta.im * vo.re)};
-            }
-            vi.re = (double)(S)vi.re;
-            vi.im = (double)(S)vi.im;
-            Ax::store(ap, i, vi);
-            cv<double> x = {ri.re - (alpha.re * vi.re - alpha.im * vi.im),
-                            ri.im - (alpha.re * vi.im + alpha.im * vi.re)};
-            x.re = (double)(S)x.re;
-            x.im = (double)(S)x.im;
-            Ax::store(rn, i, x);
-            part[0] += x.re * x.re - x.im * x.im;
-            part[1] += 2.0 * x.re * x.im;
-            part[2] += x.re * x.re + x.im * x.im;
-            part[3] += x.re * vi.re - x.im * vi.im;
-            part[4] += x.re * vi.im + x.im * vi.re;
-            part[5] += vi.re * vi.re + vi.im * vi.im;
-          }
-        }
-      }
-    }
-  }
-  block_partial<6, 8>(part, a.partials, a.nbx, s, bx);
-}
 
 // A system's residual is replaced while it is iterating and its recurrence
 // residual is above rep_floor |E|.  Below that the seed is as accurate as the
@@ -457,18 +377,6 @@ hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st) {
   dim3 grid(a.nbx, a.nsys);
   if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_r<double>, grid, dim3(kBlock), 0, st, a);
   else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_r<float>, grid, dim3(kBlock), 0, st, a);
-  else return hipErrorInvalidValue;
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_cocg_book, dim3(a.nsys), dim3(kBlock), 0, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_cocg_w(Elem e, const CocgArgs& a, hipStream_t st) {
-  if (!a.recur || a.rt || a.xseed) return hipErrorInvalidValue;
-  dim3 grid(a.nbx, a.nsys);
-  if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_w<double>, grid, dim3(kBlock), 0, st, a);
-  else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_w<float>, grid, dim3(kBlock), 0, st, a);
   else return hipErrorInvalidValue;
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;

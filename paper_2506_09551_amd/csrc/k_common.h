@@ -116,36 +116,33 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[BLK / kW
 }
 
 // Cross-workgroup reductions are done in two launches: every workgroup of
-// system s writes its NV partial sums to partials[s][bx][0..NV) (block_partial;
-// W doubles per entry, 4 unless a kernel sums more than four),
+// system s writes its NV partial sums to partials[s][bx][0..NV) (block_partial),
 // and a following finalize launch with one workgroup per system sums them in
 // index order (reduce_partials), so the result does not depend on scheduling.
 // Device-scope atomics and fences are avoided on purpose: on MI355X they
 // serialise across the whole device (about 50 ns each).
-template <int NV, int W = 4>
+template <int NV>
 __device__ __forceinline__ void block_partial(double (&v)[NV], double* partials, int nbx, int s,
                                               int bx) {
-  static_assert(NV <= W, "partial entry too small");
   __shared__ double sh[NV][kBlock / kWave];
   block_sum<NV>(v, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) partials[((int64_t)s * nbx + bx) * W + i] = v[i];
+    for (int i = 0; i < NV; ++i) partials[((int64_t)s * nbx + bx) * 4 + i] = v[i];
   }
 }
 
 // Sum of system s's partials into out[0..NV) (shared memory, all threads see it on return).
-template <int NV, int W = 4>
+template <int NV>
 __device__ __forceinline__ void reduce_partials(const double* partials, int nbx, int s,
                                                 double* out) {
-  static_assert(NV <= W, "partial entry too small");
   __shared__ double sh[NV][kBlock / kWave];
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   for (int j = threadIdx.x; j < nbx; j += kBlock) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += partials[((int64_t)s * nbx + j) * W + i];
+    for (int i = 0; i < NV; ++i) acc[i] += partials[((int64_t)s * nbx + j) * 4 + i];
   }
   block_sum<NV>(acc, sh);
   if (threadIdx.x == 0) {

@@ -132,12 +132,13 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   if (nc == 0) return fail(MSB_EINVAL, "autotune: no compiled apply shape covers a row");
   const size_t vb = (size_t)n * ctx->D * eb;
   const int nbx = apply_nbx(ctx->up.n, n);
-  const bool self = mode == kTuneBilinearSelf;
-  const int kmode = self ? (int)kModeBilinear : mode;
-  DevBuf x, y, ds, aux, part, red, zi;
+  const bool self = mode == kModeSelf;
+  DevBuf x, y, ds, aux, part, red, zi, bt;
   bool ok = hipMalloc(&x.p, vb) == hipSuccess && hipMalloc(&y.p, vb) == hipSuccess &&
             hipMalloc(&ds.p, n * sizeof(SysDev)) == hipSuccess;
-  if (ok && self) ok = hipMalloc(&zi.p, (size_t)n * sizeof(int)) == hipSuccess;
+  if (ok && self)
+    ok = hipMalloc(&zi.p, (size_t)n * sizeof(int)) == hipSuccess &&
+         hipMalloc(&bt.p, (size_t)n * 2 * sizeof(double)) == hipSuccess;
   if (ok && mode != kModePlain)
     ok = hipMalloc(&part.p, (size_t)n * nbx * 4 * sizeof(double)) == hipSuccess &&
          hipMalloc(&red.p, (size_t)n * 4 * sizeof(double)) == hipSuccess;
@@ -166,9 +167,13 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
     a.aux = (mode == kModeResid) ? aux.p : x.p;     // sigma reads a residual, the check reads E
   }
   if (self) {
-    // a one-slot bank (x itself), every system active at iteration 0
+    // a one-slot bank (x itself), every system active at iteration 0, and a
+    // nonzero beta so the old v is read and added as in the solve
     MSB_HIP(hipMemsetAsync(zi.p, 0, (size_t)n * sizeof(int), st));
-    a.x_from_aux = 1;
+    MSB_HIP(hipMemsetAsync(bt.p, 0x3F, (size_t)n * 2 * sizeof(double), st));
+    MSB_HIP(hipMemsetAsync(y.p, 0x3F, vb, st));
+    a.beta = (const double*)bt.p;
+    a.beta_stride = 2;
     a.aux_m = (const int*)zi.p;
     a.aux_base = (const int*)zi.p;
     a.aux_cap = 1;
@@ -185,7 +190,7 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   // so far stops there, the others are timed over four more launches
   auto timed = [&](int reps, double* out) -> hipError_t {
     hipError_t r = hipEventRecord(e0, st);
-    for (int k = 0; k < reps && r == hipSuccess; ++k) r = launch_apply(e, kmode, a, st);
+    for (int k = 0; k < reps && r == hipSuccess; ++k) r = launch_apply(e, mode, a, st);
     if (r == hipSuccess) r = hipEventRecord(e1, st);
     if (r == hipSuccess) r = hipEventSynchronize(e1);
     float ms = 0;
@@ -195,7 +200,7 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   };
   for (int i = 0; i < nc && err == hipSuccess; ++i) {
     a.shape = cand[i];
-    err = launch_apply(e, kmode, a, st);
+    err = launch_apply(e, mode, a, st);
     double m = 0;
     if (err == hipSuccess) err = timed(1, &m);
     if (err == hipSuccess && !(best.blk != 0 && m > 1.5 * best_ms)) err = timed(4, &m);
@@ -850,7 +855,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   // apply launch shapes: tuned on first use, before the workspace is sized
   hipStream_t ust = (hipStream_t)stream;
   const bool tune = !(opts && opts->autotune < 0);
-  const int seed_mode = recur ? (int)kTuneBilinearSelf : (int)kModeBilinear;
+  const int seed_mode = recur ? (int)kModeSelf : (int)kModeBilinear;
   (void)shape_for(ctx, ev, nsys, ust, tune, seed_mode);
   if (replace_every > 0) (void)shape_for(ctx, Elem::C128, nsys, ust, tune);
   // the residual check stages FP64 rows whatever the storage: tune it as complex128
@@ -1003,7 +1008,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
 
     ApplyArgs aa = apply_args(ctx, dsys, nb, pvec, vvec);
     aa.shape = shape_for(ctx, ev, nb, st, tune, seed_mode);
-    seed_shape = apply_shape_used(ev, kModeBilinear, aa);
+    seed_shape = apply_shape_used(ev, seed_mode, aa);
     aa.aux = bank;
     aa.partials = partials;
     aa.red = red1;
@@ -1012,10 +1017,11 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     aa.aux_m = &dst[0].m;
     aa.aux_base = dbase;
     aa.aux_cap = cap;
-    if (recur) {                 // w = A r_m from the bank slot in place, into pvec
+    if (recur) {                 // v = A r_m + beta_{m-1} v, r_m read in place from the bank
+      static_assert(sizeof(SysState) % sizeof(double) == 0, "beta stride");
       aa.x = nullptr;
-      aa.x_from_aux = 1;
-      aa.v = pvec;
+      aa.beta = &dst[0].bp_re;
+      aa.beta_stride = (int)(sizeof(SysState) / sizeof(double));
     }
     ApplyArgs ta = apply_args(ctx, bf.dsysT, nb, bf.pt, bf.vt);   // dual: v~ = A^T p~
     if (dual) {
@@ -1039,7 +1045,6 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ca.rt = dual ? bf.rt : nullptr;
     ca.pt = dual ? bf.pt : nullptr;
     ca.vt = dual ? bf.vt : nullptr;
-    ca.recur = recur ? 1 : 0;
 
     int base = 0;
     bool first_flush = true;
@@ -1131,8 +1136,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     auto enqueue_chunk = [&]() -> hipError_t {
       for (int c = 0; c < chunk; ++c) {
         if (recur) {
-          hipError_t e = launch_apply(ev, kModeBilinear, aa, st);
-          if (e == hipSuccess) e = launch_cocg_w(ev, ca, st);
+          hipError_t e = launch_apply(ev, kModeSelf, aa, st);
+          if (e == hipSuccess) e = launch_cocg_r(ev, ca, st);
           if (e != hipSuccess) return e;
           continue;
         }
@@ -1658,7 +1663,7 @@ extern "C" msb_status msb_set_shape(msb_ctx* ctx, int nsys, msb_prec prec, const
   if (nsys <= 0) return fail(MSB_EINVAL, "msb_set_shape: nsys must be positive");
   if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_set_shape: invalid precision");
   const Elem e = prec == MSB_C128 ? Elem::C128 : Elem::C64;
-  const int modes[] = {kModePlain, kModeBilinear, kModeHerm, kModeResid, kTuneBilinearSelf};
+  const int modes[] = {kModePlain, kModeBilinear, kModeHerm, kModeResid, kModeSelf};
   if (shape->threads == 0) {
     for (int md : modes) ctx->shapes.erase(std::make_tuple((int)e, shape_class(nsys), md));
     return MSB_OK;

@@ -92,8 +92,8 @@ enum ApplyMode : int {
   kModeBilinear = 1,    // v = A x;  partial (sum aux*v, sum |v|^2)        -- COCG sigma
   kModeHerm = 2,        // v = A x;  partial (sum conj(x)*v, sum |v|^2)    -- Lanczos a_k
   kModeResid = 3,       // no v;     partial (sum |aux - A x|^2)           -- true residual
-  kTuneBilinearSelf = 4 // shape key only: kModeBilinear with the operand read in place from
-                        // the bank (ApplyArgs::x_from_aux), the recurred seed form
+  kModeSelf = 4         // v = A x + beta v with x the aux bank slot read in place; partial
+                        // (sum x*v, sum |v|^2), x from the staged row -- recurred COCG sigma
 };
 
 // Launch shape of the apply kernel: threads per workgroup, elements per
@@ -130,8 +130,10 @@ struct ApplyArgs {
   size_t lds_max;             // LDS bytes one workgroup may use (device limit)
   const void* vin;            // set by the launcher for the second pass: v holds diag + up-spin hops
   int ordered;                // set by the launcher: row order of the shape (ApplyShape::order)
-  int x_from_aux;             // kModeBilinear: the operand is the aux bank slot itself (x unused)
-                              //   and the partial is x^T v, its x taken from the staged row
+  int x_from_aux;             // set by the launcher in kModeSelf: the operand is the aux bank
+                              //   slot of each system (x unused)
+  const double* beta;         // kModeSelf, optional: v = A x + beta_s v (v read in place, skipped
+  int beta_stride;            //   where beta_s = 0); beta_s = beta[s * beta_stride + {0, 1}]
 };
 
 enum class Elem { R64, C128, C64 };   // real float64, complex128, complex64 storage
@@ -184,8 +186,6 @@ struct SysState {
   int n_stall;                  // replacements in a row that exposed a false improvement
   int pad;
   double rtnorm;                // |r~_m| of the dual-space form (= rnorm otherwise)
-  double g_re, g_im;            // recurred form: gamma_{m-1} = r_m^T (A p_{m-1})
-  double vnorm;                 // recurred form: |A p_{m-1}|
 };
 
 struct CocgArgs {
@@ -219,16 +219,10 @@ struct CocgArgs {
   void* rt;
   void* pt;
   const void* vt;
-  // recurred form: the apply wrote w = A r_m into pvec (delta = r_m^T w in
-  // red1) and vvec carries A p_{m-1} -> A p_m
-  int recur;
 };
 
 hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st);   // r_{m+1} = r_m - alpha v
 hipError_t launch_cocg_p(Elem e, const CocgArgs& a, hipStream_t st);   // p_m = r_m + beta_{m-1} p_{m-1}
-// Recurred form: A p_m = w + beta_{m-1} A p_{m-1}, r_{m+1} = r_m - alpha_m A p_m
-// (then the bookkeeping, as launch_cocg_r)
-hipError_t launch_cocg_w(Elem e, const CocgArgs& a, hipStream_t st);
 // Residual replacement: r_m <- E - w (w = A_s x_m in complex128, computed by the
 // apply), rho_m and |r_m| recomputed in FP64, beta_{m-1} rescaled accordingly.
 hipError_t launch_cocg_replace(Elem e, const CocgArgs& a, const double* E, const double* w,
