@@ -148,9 +148,23 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
           }
         }
     }
+    const bool second_pass = a.vin != nullptr;   // diagonal and up-spin hops already in vin
+    // kModeSelf: the old v (added as beta v) is requested now as well; with
+    // beta = 0 (first iteration) the loaded values are not used
+    constexpr bool kOldEarly = kSelf && EPT * NV <= 8 && BLK < 1024;
+    cv<Tc> vold[kOldEarly ? NV : 1][kOldEarly ? EPT : 1];
+    if constexpr (kOldEarly) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          vold[v][e] = {(Tc)0, (Tc)0};
+          if (act[v] && a.beta && !second_pass)
+            vold[v][e] = Ax::template load_nt<Tc>(a.v, (int64_t)(s0 + v) * a.D + row0 + voff[e]);
+        }
+    }
     const uint32_t cu = a.T.conf_up[u];
     cv<Tc> acc[NV][EPT];
-    const bool second_pass = a.vin != nullptr;   // diagonal and up-spin hops already in vin
     // diagonal
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -270,7 +284,9 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
         if constexpr (kSelf) {
           // v_m = A r_m + beta_{m-1} v_{m-1}, in place (the first pass already added it)
           if (!second_pass && (bacc.re != (Tc)0 || bacc.im != (Tc)0)) {
-            const cv<Tc> vo = Ax::template load_nt<Tc>(a.v, vbase + gi);
+            cv<Tc> vo;
+            if constexpr (kOldEarly) vo = vold[v][e];
+            else vo = Ax::template load_nt<Tc>(a.v, vbase + gi);
             vv.re += bacc.re * vo.re - bacc.im * vo.im;
             vv.im += bacc.re * vo.im + bacc.im * vo.re;
           }
