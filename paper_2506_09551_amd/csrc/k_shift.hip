@@ -230,13 +230,16 @@ __global__ __launch_bounds__(kBlock) void k_flush_mfma(FlushArgs a, int ow_mode)
 // VALU form of the same contraction (the default: on MI355X FP64 FMA issues
 // faster from the vector ALUs than from the FP64 matrix instructions).  A
 // workgroup owns 32 shift slots (8 per wavefront) x 256 elements (4 per lane).
-// Each chunk of 8 residual slots is staged in LDS.  The coefficients are
+// Residual slots are staged in LDS in chunks of 6; with a complex128 bank the
+// chunks go straight from memory to LDS and the next one is in flight while
+// the FMAs of the current one run (two 24 KB buffers: three workgroups still
+// fit a CU's LDS, as many as the registers allow).  The coefficients are
 // wave-uniform and come through the scalar cache, so they cost neither LDS
 // nor vector-memory bandwidth; the next slot's coefficients are requested
 // before the current slot's FMAs so the scalar-cache misses overlap with them.
 constexpr int kValuM = 8;         // shift slots per wavefront
 constexpr int kValuEPL = 4;       // elements per lane
-constexpr int kValuKT = 8;        // residual slots per staged chunk
+constexpr int kValuKT = 6;        // residual slots per staged chunk
 
 template <typename SB, typename SO>
 __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double* __restrict__ coef,
@@ -249,6 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double
   constexpr int RPT = KT;                                 // residual slots staged per thread per chunk
   static_assert(TILE == kBlock, "one staged element per thread");
   __shared__ cv<double> rt[KT][TILE];
+  // second chunk buffer of the complex128 form (an empty array otherwise)
+  __shared__ cv<double> rt2[std::is_same<SB, double>::value ? KT : 1][TILE];
 
   const int s = blockIdx.y;
   const int b = blockIdx.x;
@@ -285,14 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double
   };
   int64_t my_e = e0 + tid;
   my_e = my_e < last_e ? my_e : last_e;                   // clamped: feeds only unstored outputs
-  for (int kb = 0; kb < Kext; kb += KT) {
-    const int kn = min(KT, Kext - kb);
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      const int kc = kb + (j < kn ? j : kn - 1);          // clamped: its coefficient is never used
-      rt[j][tid] = AB::template load<double>(bank_s, (int64_t)kc * a.D + my_e);
-    }
-    __syncthreads();
+  // the FMAs of the slots [kb, kb + kn) staged in buf
+  auto run = [&](const cv<double> (*buf)[TILE], int kb, int kn) {
     cv<double> c_cur[M], c_nxt[M];
     const int kw = min(kn, Kw - kb);                      // wave-uniform; may be <= 0
     if (kw > 0) load_c(kb, c_cur);
@@ -300,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double
       if (kk + 1 < kw) load_c(kb + kk + 1, c_nxt);
       cv<double> r[EPL];
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) r[e] = rt[kk][lane + kWave * e];
+      for (int e = 0; e < EPL; ++e) r[e] = buf[kk][lane + kWave * e];
 #pragma unroll
       for (int t = 0; t < M; ++t) {
 #pragma unroll
@@ -314,7 +313,46 @@ __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double
 #pragma unroll
       for (int t = 0; t < M; ++t) c_cur[t] = c_nxt[t];
     }
-    __syncthreads();
+  };
+  if constexpr (std::is_same<SB, double>::value) {
+    // complex128 bank: each chunk goes straight from memory to LDS
+    // (global_load_lds, 16 bytes per lane at the wavefront's LDS base), and
+    // chunk kb + KT is in flight while the FMAs of chunk kb run
+    const cv<double>* bank_c = reinterpret_cast<const cv<double>*>(bank_s);
+    auto stage = [&](cv<double> (*buf)[TILE], int kb) {
+      const int kn = min(KT, Kext - kb);
+#pragma unroll
+      for (int j = 0; j < KT; ++j) {
+        const int kc = kb + (j < kn ? j : kn - 1);        // clamped: its coefficient is never used
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(bank_c + (int64_t)kc * a.D + my_e),
+                                         (__attribute__((address_space(3))) void*)&buf[j][wave * kWave],
+                                         16, 0, 0);
+      }
+    };
+    if (Kext > 0) stage(rt, 0);
+    for (int kb = 0; kb < Kext; kb += 2 * KT) {
+      __builtin_amdgcn_s_waitcnt(0);                      // this wavefront's part of chunk kb landed
+      __syncthreads();                                    // every part; rt2 no longer read
+      if (kb + KT < Kext) stage(rt2, kb + KT);
+      run(rt, kb, min(KT, Kext - kb));
+      if (kb + KT >= Kext) break;
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (kb + 2 * KT < Kext) stage(rt, kb + 2 * KT);
+      run(rt2, kb + KT, min(KT, Kext - kb - KT));
+    }
+  } else {
+    for (int kb = 0; kb < Kext; kb += KT) {
+      const int kn = min(KT, Kext - kb);
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int kc = kb + (j < kn ? j : kn - 1);        // clamped: its coefficient is never used
+        rt[j][tid] = AB::template load<double>(bank_s, (int64_t)kc * a.D + my_e);
+      }
+      __syncthreads();
+      run(rt, kb, kn);
+      __syncthreads();
+    }
   }
 
 #pragma unroll
