@@ -13,12 +13,14 @@
 // The x / p vectors of the shifted systems are not touched here: the
 // residuals r_m stay in the bank and the shifted solutions are assembled
 // from them in k_shift.hip.
-// Recurred form (neither the dual form nor residual replacement, which need
-// p_m): k_cocg_p is skipped and p_m never formed.  The apply (kModeSelf)
-// reads r_m in place from its bank slot and writes
+// Recurred form (not with the dual form, whose shadow vectors need p~):
+// k_cocg_p is skipped.  The apply (kModeSelf) reads r_m in place from its
+// bank slot and writes
 //   v_m = A r_m + beta_{m-1} v_{m-1} = A (r_m + beta_{m-1} p_{m-1}) = A p_m
 // over v_{m-1}, with sigma = r_m^T v_m as before; k_cocg_r and the
-// bookkeeping are unchanged.
+// bookkeeping are unchanged.  Where residual replacement needs the seed
+// solution, x_m and p_{m-1} are rebuilt from the bank slots at each
+// replacement (k_seed_rebuild) instead of being updated every iteration.
 // Dual-space form (non-symmetric A; CocgArgs::rt set): the shadow residual
 // r~ and direction p~ follow the same recurrences with v~ = A^T p~ (a second
 // apply, plain mode), sigma = r~^T A p (the apply reads r~ instead of the bank
@@ -286,6 +288,40 @@ __global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
   }
 }
 
+// Seed solution and last direction rebuilt from the bank slots (recurred
+// form with residual replacement); one pass over the L slots per element.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_seed_rebuild(RebuildArgs a) {
+  using Ax = Access<S, true>;
+  using A64 = Access<double, true>;
+  const int s = blockIdx.y, bx = blockIdx.x;
+  const int status = a.st[s].status;
+  if (status != kActive && status != kPaused) return;
+  extern __shared__ double cf[];                          // [2][L + 1] complex
+  const double* src = a.coef + (int64_t)s * 2 * (a.L + 1) * 2;
+  for (int k = threadIdx.x; k < 4 * (a.L + 1); k += kBlock) cf[k] = src[k];
+  __syncthreads();
+  const double* cx = cf;
+  const double* cp = cf + 2 * (a.L + 1);
+  const void* b0 = Ax::offset(a.bank, ((int64_t)s * a.cap + a.slot0) * a.D);
+  void* p = Ax::offset(a.p, (int64_t)s * a.D);
+  for (int64_t i = (int64_t)bx * kBlock + threadIdx.x; i < a.D; i += (int64_t)a.nbx * kBlock) {
+    cv<double> ax = {0.0, 0.0}, ap = {0.0, 0.0};
+    for (int l = 0; l < a.L; ++l) {
+      const cv<double> r = Ax::template load<double>(b0, (int64_t)l * a.D + i);
+      ax = cadd(ax, cmul({cx[2 * l], cx[2 * l + 1]}, r));
+      ap = cadd(ap, cmul({cp[2 * l], cp[2 * l + 1]}, r));
+    }
+    const cv<double> po = Ax::template load<double>(p, i);
+    const cv<double> xo = A64::template load<double>(a.x, (int64_t)s * a.D + i);
+    const cv<double> xn = cadd(cadd(xo, ax), cmul({cx[2 * a.L], cx[2 * a.L + 1]}, po));
+    cv<double> pn = cadd(ap, cmul({cp[2 * a.L], cp[2 * a.L + 1]}, po));
+    pn.re = (double)(S)pn.re;
+    pn.im = (double)(S)pn.im;
+    A64::store(a.x, (int64_t)s * a.D + i, xn);
+    Ax::store(p, i, pn);
+  }
+}
 
 // A system's residual is replaced while it is iterating and its recurrence
 // residual is above rep_floor |E|.  Below that the seed is as accurate as the
@@ -381,6 +417,16 @@ hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st) {
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_cocg_book, dim3(a.nsys), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_rebuild(Elem e, const RebuildArgs& a, hipStream_t st) {
+  if (a.L < 0 || a.slot0 < 0 || a.slot0 + a.L > a.cap) return hipErrorInvalidValue;
+  dim3 grid(a.nbx, a.nsys);
+  const size_t lds = (size_t)4 * (a.L + 1) * sizeof(double);
+  if (e == Elem::C128) hipLaunchKernelGGL(k_seed_rebuild<double>, grid, dim3(kBlock), lds, st, a);
+  else if (e == Elem::C64) hipLaunchKernelGGL(k_seed_rebuild<float>, grid, dim3(kBlock), lds, st, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

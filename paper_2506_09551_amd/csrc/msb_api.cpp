@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <limits>
 #include <numeric>
@@ -736,6 +737,7 @@ struct SolveBufs {
   double* ab = nullptr;
   double* xseed = nullptr;      // residual replacement: seed solution [B][D] c128
   double* wrep = nullptr;       // residual replacement: A_s x [B][D] c128
+  double* rcoef = nullptr;      // residual replacement, recurred form: rebuild coefficients
   SysDev* tsys = nullptr;       // true-residual systems
   double* tpart = nullptr;
   double* tred = nullptr;
@@ -778,6 +780,7 @@ struct SolveBufs {
     if (replace) {
       xseed = c.take<double>((size_t)B * D * 16);
       wrep = c.take<double>((size_t)B * D * 16);
+      rcoef = c.take<double>((size_t)B * 2 * (cap + 1) * 2 * sizeof(double));
     }
     if (dual) {
       rt = c.take<void>((size_t)B * D * s_el);
@@ -843,9 +846,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     if (r != MSB_OK) return r;
     dual = dual || !sysdev_symmetric(ctx, hsys[s]);
   }
-  // recurred seed form (A p_m carried by recurrence, p_m never formed); the
-  // dual form and residual replacement use p_m and run the direct form
-  const bool recur = !dual && replace_every == 0 && !(opts && opts->direct_ap == 1);
+  // recurred seed form (A p_m carried by recurrence; p_m formed only for the
+  // seed solution of residual replacement); the dual form runs the direct one
+  const bool recur = !dual && !(opts && opts->direct_ap == 1);
   if (dual) {
     if (prec != MSB_C128) return fail(MSB_EINVAL, "msb_solve: the dual-space form runs in complex128");
     hsysT.resize(nsys);
@@ -1045,6 +1048,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ca.rt = dual ? bf.rt : nullptr;
     ca.pt = dual ? bf.pt : nullptr;
     ca.vt = dual ? bf.vt : nullptr;
+    // recurred form: x is rebuilt from the bank at each replacement
+    if (recur) ca.xseed = nullptr;
 
     int base = 0;
     bool first_flush = true;
@@ -1174,6 +1179,63 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       ~GraphGuard() { if (*g) (void)hipGraphExecDestroy(*g); }
     } graph_guard{&gexec};
 
+    // recurred form with replacement: fold the bank slots written since the
+    // last rebuild (iterations m0 .. m_now - 1) into x and p (Alg. 1's
+    // x_{j+1} = x_j + alpha_j p_j, p_j = r_j + beta_{j-1} p_{j-1} as linear
+    // combinations of r_j, from the logged alpha / beta in FP64 on the host)
+    int m0 = 0;
+    std::vector<double> hal, hbl, hcoef;
+    auto rebuild = [&](int m_now) -> msb_status {
+      if (!recur || !bf.xseed) return MSB_OK;   // the direct form updates x every iteration
+      const int L = m_now - m0;
+      if (L <= 0) return MSB_OK;
+      if (m0 < base || L > cap) return fail(MSB_EINVAL, "internal: rebuild range outside the bank");
+      hal.resize((size_t)nb * mx * 2);
+      hbl.resize((size_t)nb * mx * 2);
+      MSB_HIP(hipMemcpyAsync(hal.data(), alog, hal.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      MSB_HIP(hipMemcpyAsync(hbl.data(), blog, hbl.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      MSB_HIP(hipStreamSynchronize(st));
+      using cd = std::complex<double>;
+      hcoef.assign((size_t)nb * 2 * (L + 1) * 2, 0.0);
+      std::vector<cd> d(L), sx(L);
+      for (int s = 0; s < nb; ++s) {
+        if (hst[s].status != kActive && hst[s].status != kPaused) continue;
+        auto alpha = [&](int j) { return cd(hal[((size_t)s * mx + j) * 2], hal[((size_t)s * mx + j) * 2 + 1]); };
+        auto beta = [&](int j) { return cd(hbl[((size_t)s * mx + j) * 2], hbl[((size_t)s * mx + j) * 2 + 1]); };
+        std::fill(d.begin(), d.end(), cd(0.0));
+        std::fill(sx.begin(), sx.end(), cd(0.0));
+        cd e = (m0 > 0) ? beta(m0 - 1) : cd(0.0);   // p_j = sum_l d_l r_l + e p_{m0-1}
+        cd sxp = 0.0;
+        for (int j = m0; j < m_now; ++j) {
+          if (j > m0) {
+            const cd b = beta(j - 1);
+            for (int l = 0; l < j - m0; ++l) d[l] *= b;
+            e *= b;
+          }
+          d[j - m0] = 1.0;
+          const cd a = alpha(j);
+          for (int l = 0; l <= j - m0; ++l) sx[l] += a * d[l];
+          sxp += a * e;
+        }
+        double* cx = hcoef.data() + (size_t)s * 2 * (L + 1) * 2;
+        double* cp = cx + (size_t)(L + 1) * 2;
+        for (int l = 0; l < L; ++l) {
+          cx[2 * l] = sx[l].real(); cx[2 * l + 1] = sx[l].imag();
+          cp[2 * l] = d[l].real(); cp[2 * l + 1] = d[l].imag();
+        }
+        cx[2 * L] = sxp.real(); cx[2 * L + 1] = sxp.imag();
+        cp[2 * L] = e.real(); cp[2 * L + 1] = e.imag();
+      }
+      MSB_HIP(hipMemcpyAsync(bf.rcoef, hcoef.data(), hcoef.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      RebuildArgs rb;
+      rb.bank = bank; rb.cap = cap; rb.slot0 = m0 - base; rb.L = L; rb.D = D; rb.nbx = cocg_nbx(D, nb);
+      rb.nsys = nb; rb.coef = bf.rcoef; rb.x = bf.xseed; rb.p = pvec; rb.st = dst;
+      MSB_HIP(launch_seed_rebuild(ev, rb, st));
+      MSB_HIP(hipStreamSynchronize(st));    // hcoef is reused by the next rebuild
+      m0 = m_now;
+      return MSB_OK;
+    };
+
     ApplyArgs ra = apply_args(ctx, dsys, nb, bf.xseed, bf.wrep);
     ra.shape = shape_for(ctx, Elem::C128, nb, st, tune);
     ra.status = &dst[0].status;
@@ -1204,6 +1266,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
           }
         if (n_want > 0 && m_now - last_rep >= replace_every) {
           // r_m <- E - A_s x_m with x_m and the product in complex128
+          msb_status r = rebuild(m_now);
+          if (r != MSB_OK) return r;
           MSB_HIP(launch_apply(Elem::C128, kModePlain, ra, st));
           MSB_HIP(launch_cocg_replace(ev, ca, Eb, bf.wrep, st));
           last_rep = m_now;
@@ -1225,6 +1289,10 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
             if (m >= 0 && hst[s].m != m) return fail(MSB_EINVAL, "internal: paused systems out of step");
             m = hst[s].m;
           }
+        {
+          msb_status r = rebuild(m);        // before slot 0 is overwritten
+          if (r != MSB_OK) return r;
+        }
         MSB_HIP(launch_copy_slot(ev, (const char*)bank + (size_t)(m - base) * D * s_el, bank, D, nb,
                                  (int64_t)cap * D, (int64_t)cap * D, st));
         base = m;

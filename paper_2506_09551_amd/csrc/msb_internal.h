@@ -223,6 +223,25 @@ struct CocgArgs {
 
 hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st);   // r_{m+1} = r_m - alpha v
 hipError_t launch_cocg_p(Elem e, const CocgArgs& a, hipStream_t st);   // p_m = r_m + beta_{m-1} p_{m-1}
+// Recurred seed form with residual replacement: the seed solution and the
+// last direction, as linear combinations of the bank slots written since the
+// previous rebuild (Alg. 1: x_{j+1} = x_j + alpha_j p_j, p_j = r_j + beta_{j-1} p_{j-1}):
+//   x <- x + sum_l cx[l] r_l + cx[L] p,   p <- sum_l cp[l] r_l + cp[L] p
+// for systems that are active or paused.  coef: [nsys][2][L + 1] complex.
+struct RebuildArgs {
+  const void* bank;             // [nsys][cap][D] of the vector precision
+  int cap;
+  int slot0;                    // bank slot of the first residual combined
+  int L;                        // residuals combined (slots slot0 .. slot0 + L - 1)
+  int64_t D;
+  int nbx;
+  int nsys;
+  const double* coef;
+  double* x;                    // [nsys][D] complex128
+  void* p;                      // [nsys][D] of the vector precision
+  const SysState* st;
+};
+hipError_t launch_seed_rebuild(Elem e, const RebuildArgs& a, hipStream_t st);
 // Residual replacement: r_m <- E - w (w = A_s x_m in complex128, computed by the
 // apply), rho_m and |r_m| recomputed in FP64, beta_{m-1} rescaled accordingly.
 hipError_t launch_cocg_replace(Elem e, const CocgArgs& a, const double* E, const double* w,

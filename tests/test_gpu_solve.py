@@ -174,13 +174,16 @@ def test_c64_form_accuracy(tiny):
     assert err <= 5e-5, f"c64 rel err {err:.3e}"
 
 
+@pytest.mark.parametrize("direct_ap", [0, 1])
 @pytest.mark.parametrize("opts", [None, {"replace_every": 7, "chunk": 3},
                                   {"replace_every": 20, "bank_slots": 33}])
-def test_c64_residual_replacement(tiny, opts):
+def test_c64_residual_replacement(tiny, opts, direct_ap):
     """complex64 vectors with residual replacement r_m <- E - A_s x_m (complex128):
     same accuracy as the plain form, replacements counted, and with a small
-    bank the replacement survives the flush / bank restart."""
+    bank the replacement survives the flush / bank restart; in the recurred
+    seed form (p_m formed inside the r-update for x) and the direct one."""
     msb, ctx, wl, m = tiny
+    opts = dict(opts or {}, direct_ap=direct_ap)
     D = msb.msb_dim(ctx)
     E = W.random_vector(D, 4).astype(np.complex128)
     E_G = -2.6661474201323485
