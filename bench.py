@@ -69,7 +69,7 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(wl, iters_gpu: int, n_iter: int = 2):
+def cpu_baseline(wl, iters_gpu: int, n_iter: int = 6):
     """Oracle recurrence (one system, all shifts) for a few iterations, extrapolated."""
     import numpy as np
     from threadpoolctl import threadpool_limits
