@@ -25,14 +25,17 @@ __global__ __launch_bounds__(kBlock) void k_coef(CoefArgs a, double* scratch) {
   if (tid >= total) return;
   const int s = tid / a.n_list;
   const int j = tid % a.n_list;
-  double* crow = a.coef + (int64_t)tid * a.K * 2;
-  double* grow = a.gcoef ? a.gcoef + (int64_t)tid * a.K * 2 : nullptr;
+  // coefficient tables are slot-major, [s][l][j] complex: for one slot the
+  // shifts of a tile are adjacent (one scalar load serves a wavefront's shifts)
+  const int64_t cstride = (int64_t)a.n_list * 2;
+  double* crow = a.coef + ((int64_t)s * a.K * a.n_list + j) * 2;
+  double* grow = a.gcoef ? a.gcoef + ((int64_t)s * a.K * a.n_list + j) * 2 : nullptr;
   double* zrow = scratch + (int64_t)tid * a.K * 4;    // (zeta_l, bw_l)
   const int k = a.list[tid];
   const int lend = (k >= 0) ? a.lend[tid] : 0;
   for (int l = lend; l < a.K; ++l) {
-    crow[2 * l] = crow[2 * l + 1] = 0.0;
-    if (grow) grow[2 * l] = grow[2 * l + 1] = 0.0;
+    crow[cstride * l] = crow[cstride * l + 1] = 0.0;
+    if (grow) grow[cstride * l] = grow[cstride * l + 1] = 0.0;
   }
   double* ab = a.ab + (int64_t)tid * 4;
   ab[0] = ab[1] = ab[2] = ab[3] = 0.0;
@@ -58,8 +61,8 @@ __global__ __launch_bounds__(kBlock) void k_coef(CoefArgs a, double* scratch) {
       const cv<double> aw = cmul(cdiv(z, zn), alpha);
       const cv<double> q = cdiv(zp, z);
       const cv<double> bw = cmul(cmul(q, q), bp);
-      crow[2 * l] = aw.re;
-      crow[2 * l + 1] = aw.im;
+      crow[cstride * l] = aw.re;
+      crow[cstride * l + 1] = aw.im;
       zrow[4 * l + 0] = z.re;
       zrow[4 * l + 1] = z.im;
       zrow[4 * l + 2] = bw.re;
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_coef(CoefArgs a, double* scratch) {
   // backward accumulation
   cv<double> S = {0.0, 0.0}, G = {1.0, 0.0};
   for (int l = lend - 1; l >= 0; --l) {
-    const cv<double> aw = {crow[2 * l], crow[2 * l + 1]};
+    const cv<double> aw = {crow[cstride * l], crow[cstride * l + 1]};
     if (l < lend - 1) {
       const cv<double> bnext = {zrow[4 * (l + 1) + 2], zrow[4 * (l + 1) + 3]};
       S = cadd(aw, cmul(bnext, S));
@@ -83,12 +86,12 @@ __global__ __launch_bounds__(kBlock) void k_coef(CoefArgs a, double* scratch) {
     }
     const cv<double> zl = {zrow[4 * l], zrow[4 * l + 1]};
     const cv<double> c = cdiv(S, zl);
-    crow[2 * l] = c.re;
-    crow[2 * l + 1] = c.im;
+    crow[cstride * l] = c.re;
+    crow[cstride * l + 1] = c.im;
     if (grow) {
       const cv<double> g = carry ? cdiv(G, zl) : cv<double>{0.0, 0.0};
-      grow[2 * l] = g.re;
-      grow[2 * l + 1] = g.im;
+      grow[cstride * l] = g.re;
+      grow[cstride * l + 1] = g.im;
     }
   }
   if (a.base > 0) {
@@ -151,7 +154,8 @@ __global__ __launch_bounds__(kBlock) void k_flush_mfma(FlushArgs a, int ow_mode)
   const int64_t e0 = (int64_t)et * TILE;
   const void* bank_s = AB::offset(a.bank, (int64_t)s * a.cap * a.D);
   // this lane's A-operand row: shift slot0 + li
-  const double* crow = a.coef + ((int64_t)s * a.n_list + slot0 + li) * a.K * 2;
+  const double* crow = a.coef + ((int64_t)s * a.K * a.n_list + slot0 + li) * 2;   // slot-major
+  const int64_t cstride = (int64_t)a.n_list * 2;
 
   v4d accr[kFlushNT], acci[kFlushNT];
 #pragma unroll
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_flush_mfma(FlushArgs a, int ow_mode)
     const int kk = kb + lk;
     const bool kin = kk < Kext;
     const int kc = kin ? kk : Kext - 1;
-    const double cr = crow[2 * kc], ci = crow[2 * kc + 1];
+    const double cr = crow[cstride * kc], ci = crow[cstride * kc + 1];
     o.ar = kin ? cr : 0.0;
     o.ai = kin ? ci : 0.0;
     const void* rs = AB::offset(bank_s, (int64_t)kc * a.D);
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double
   const int Kw = a.lend ? __builtin_amdgcn_readfirstlane(a.lend[s * a.n_list + slot0]) : Kext;
   // uniform address in the constant address space: read through the scalar cache
   typedef __attribute__((address_space(4))) const double cdouble;
-  cdouble* crow = (cdouble*)(coef + ((int64_t)s * a.n_list + slot0) * a.K * 2);
+  cdouble* crow = (cdouble*)(coef + ((int64_t)s * a.K * a.n_list + slot0) * 2);   // slot-major
 
   cv<double> acc[M][EPL];
 #pragma unroll
@@ -286,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double
   // the next slot's are requested before the current slot's FMAs are issued
   auto load_c = [&](int l, cv<double> (&c)[M]) {
 #pragma unroll
-    for (int t = 0; t < M; ++t) c[t] = {crow[((int64_t)t * a.K + l) * 2], crow[((int64_t)t * a.K + l) * 2 + 1]};
+    for (int t = 0; t < M; ++t) c[t] = {crow[((int64_t)l * a.n_list + t) * 2], crow[((int64_t)l * a.n_list + t) * 2 + 1]};
   };
   int64_t my_e = e0 + tid;
   my_e = my_e < last_e ? my_e : last_e;                   // clamped: feeds only unstored outputs

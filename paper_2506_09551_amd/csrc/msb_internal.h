@@ -280,8 +280,8 @@ struct CoefArgs {
   const int* conv_iter;         // [nsys][n_shift]
   const int* list;              // [nsys][n_list] shift index per sorted slot (-1 = empty)
   const int* lend;              // [nsys][n_list] end of the shift's range within the block
-  double* coef;                 // [nsys][n_list][K][2]   Psi coefficients of r_base+l
-  double* gcoef;                // [nsys][n_list][K][2]   p coefficients (carry) or null
+  double* coef;                 // [nsys][K][n_list][2]   Psi coefficients of r_base+l
+  double* gcoef;                // [nsys][K][n_list][2]   p coefficients (carry) or null
   double* ab;                   // [nsys][n_list][4]: (a_re,a_im) = p_prev weight in Psi, (h_re,h_im) in p
   int nsys, n_shift, n_list, maxit, K, base;
 };
@@ -290,7 +290,7 @@ hipError_t launch_coef(const CoefArgs& a, double* scratch /*[nsys*n_list][K][4]*
 struct FlushArgs {
   const void* bank;             // [nsys][cap][D]
   int cap;
-  const double* coef;           // [nsys][n_list][K][2]
+  const double* coef;           // [nsys][K][n_list][2] (slot-major)
   const double* pw;             // [nsys][n_list][2]: weight of X (p_prev) term, or null
   const double* ow;             // [nsys][n_list][2]: weight of old output, or null (= 0)
   int pw_stride, ow_stride;     // doubles between consecutive entries of pw / ow
