@@ -140,7 +140,9 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
           auxv[v][e] = {0.0, 0.0};
-          if (act[v]) {
+          if (v > 0 && act[v] && aux_off[v] == aux_off[v - 1]) {
+            auxv[v][e] = auxv[v - 1][e];       // shifts of one system share their right-hand side
+          } else if (act[v]) {
             if constexpr (MODE == kModeBilinear)
               auxv[v][e] = Ax::template load_nt<double>(a.aux, aux_off[v] + row0 + voff[e]);
             else

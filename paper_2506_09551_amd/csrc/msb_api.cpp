@@ -166,6 +166,8 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
     a.partials = (double*)part.p;
     a.red = (double*)red.p;
     a.aux = (mode == kModeResid) ? aux.p : x.p;     // sigma reads a residual, the check reads E
+    // the check runs over the shifts of a system, which share E
+    if (mode == kModeResid) a.aux_div = n;
   }
   if (self) {
     // a one-slot bank (x itself), every system active at iteration 0, and a
