@@ -33,8 +33,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # profiles/solve_scale_L12_hbm_counters.md: raw FETCH_SIZE / WRITE_SIZE in KiB
 # and the copy-calibrated factors; valid while the kernel source is unchanged.
 FLUSH_COUNTERS = {
-    "source": "paper_2506_09551_amd/csrc/k_shift.hip", "sha256_16": "ba91710ee4dfaa26",
-    "fetch_kib": 88175497.1, "write_kib": 32016600.0, "fetch_factor": 2.0, "write_factor": 1.0,
+    "source": "paper_2506_09551_amd/csrc/k_shift.hip", "sha256_16": "10bdddd03be22a2a",
+    "fetch_kib": 91709992.4, "write_kib": 32016600.0, "fetch_factor": 2.0, "write_factor": 1.0,
     "workload": "scale_L12_N6",
 }
 
