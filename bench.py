@@ -575,7 +575,7 @@ def main():
                     help="learned form: only time this many training steps on seeded random points")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "one GPU only: the solver has no multi-GPU path; run with --gpus 1"}))
         sys.exit(2)
     if args.workload == "learned" and args.mlp_train_steps > 0:
         mlp_train_main(args)
