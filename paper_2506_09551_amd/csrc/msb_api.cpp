@@ -392,6 +392,7 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   }
   if (e == hipSuccess) e = upload(&c->d_order_up, c->up.order);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->half_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc(&c->d_small, 4096 * sizeof(double));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -413,6 +414,7 @@ extern "C" void msb_destroy(msb_ctx* c) {
   (void)hipFree(c->d_ell_dn);
   (void)hipFree(c->d_order_up);
   if (c->solve_stream) (void)hipStreamDestroy(c->solve_stream);
+  if (c->half_stream) (void)hipStreamDestroy(c->half_stream);
   (void)hipFree(c->d_small);
   if (c->ws) (void)hipFree(c->ws);
   delete c;
@@ -720,6 +722,7 @@ struct SolveBufs {
   SysDev* dsys = nullptr;
   SysState* dst = nullptr;
   double* partials = nullptr;
+  size_t part_half = 0;         // doubles: the second half of partials starts here
   double* red1 = nullptr;
   double* red2 = nullptr;
   int* dbase = nullptr;
@@ -760,7 +763,9 @@ struct SolveBufs {
     Pc = carry ? c.take<void>((size_t)B * n_shift * D * s_out) : nullptr;
     dsys = c.take<SysDev>(B * sizeof(SysDev));
     dst = c.take<SysState>(B * sizeof(SysState));
-    partials = c.take<double>(part_n * 8 * sizeof(double));   // up to 8 sums per entry
+    // two regions of [nsys][nbx][4]: the two halves of a split batch run at once
+    part_half = part_n * 4;
+    partials = c.take<double>(part_n * 8 * sizeof(double));
     red1 = c.take<double>((size_t)B * 4 * sizeof(double));
     red2 = c.take<double>((size_t)B * 4 * sizeof(double));
     dbase = c.take<int>(4 * sizeof(int));
@@ -968,7 +973,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   for (int k = 0; k < n_shift; ++k) hw[k] = w_in[k] - seed_shift;
   MSB_HIP(hipMemcpyAsync(wshift, hw.data(), n_shift * sizeof(double), hipMemcpyHostToDevice, st));
 
-  hipEvent_t ev0, ev1, eg0, eg1;
+  hipEvent_t ev0, ev1, eg0, eg1, fork_ev, join_ev;
+  MSB_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+  MSB_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
   MSB_HIP(hipEventCreate(&ev0));
   MSB_HIP(hipEventCreate(&ev1));
   MSB_HIP(hipEventCreate(&eg0));
@@ -1139,7 +1146,54 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
 
     // one chunk of seed iterations; kernels skip systems that are not active.
     // The chunk is captured once per batch into a hipGraph and replayed.
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec = nullptr, gexec2 = nullptr;
+    // Recurred form, two or more systems: the chunk is captured as two
+    // independent branches (systems [0, h) and [h, nb)), so one half's
+    // latency-bound apply overlaps the other half's streaming r-update.
+    const bool split = use_graph && recur && nb >= 2;
+    const int h_split = nb / 2;
+    auto half_args = [&](int s0, int n, double* part, ApplyArgs& ha, CocgArgs& hc) {
+      ha = aa;
+      ha.sys = dsys + s0;
+      ha.aux = (const char*)bank + (size_t)s0 * cap * D * s_el;
+      ha.v = (char*)vvec + (size_t)s0 * D * s_el;
+      ha.aux_m = &dst[s0].m;
+      ha.status = &dst[s0].status;
+      ha.beta = &dst[s0].bp_re;
+      ha.partials = part;
+      ha.red = red1 + 4 * (size_t)s0;
+      ha.nsys = n;
+      hc = ca;
+      hc.st = dst + s0;
+      hc.red1 = red1 + 4 * (size_t)s0;
+      hc.partials = part;
+      hc.red2 = red2 + 4 * (size_t)s0;
+      hc.bank = (char*)bank + (size_t)s0 * cap * D * s_el;
+      hc.vvec = (const char*)vvec + (size_t)s0 * D * s_el;
+      hc.pvec = (char*)pvec + (size_t)s0 * D * s_el;
+      hc.nbx = cocg_nbx(D, n);
+      hc.nsys = n;
+      hc.zeta = zeta + 2 * (size_t)s0 * n_shift;
+      hc.zeta_prev = zeta_prev + 2 * (size_t)s0 * n_shift;
+      hc.conv_iter = conv + (size_t)s0 * n_shift;
+      hc.alpha_log = alog + 2 * (size_t)s0 * mx;
+      hc.beta_log = blog + 2 * (size_t)s0 * mx;
+      hc.rnorm_log = rlog + (size_t)s0 * (mx + 1);
+    };
+    ApplyArgs aa_h[2];
+    CocgArgs ca_h[2];
+    if (split) {
+      half_args(0, h_split, partials, aa_h[0], ca_h[0]);
+      half_args(h_split, nb - h_split, partials + bf.part_half, aa_h[1], ca_h[1]);
+    }
+    auto enqueue_half = [&](const ApplyArgs& ha, const CocgArgs& hc, hipStream_t s) -> hipError_t {
+      for (int c = 0; c < chunk; ++c) {
+        hipError_t e = launch_apply(ev, kModeSelf, ha, s);
+        if (e == hipSuccess) e = launch_cocg_r(ev, hc, s);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
     auto enqueue_chunk = [&]() -> hipError_t {
       for (int c = 0; c < chunk; ++c) {
         if (recur) {
@@ -1163,7 +1217,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       }
       if (!gexec) {
         MSB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        const hipError_t e_launch = enqueue_chunk();
+        const hipError_t e_launch = split ? enqueue_half(aa_h[0], ca_h[0], st) : enqueue_chunk();
         hipGraph_t g = nullptr;
         const hipError_t e_end = hipStreamEndCapture(st, &g);
         hipError_t e_inst = hipSuccess;
@@ -1173,13 +1227,35 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
         MSB_HIP(e_end);
         MSB_HIP(e_inst);
       }
-      MSB_HIP(hipGraphLaunch(gexec, st));
+      if (split && !gexec2) {      // the second half: its own graph on its own stream
+        const hipStream_t st2 = ctx->half_stream;
+        MSB_HIP(hipStreamBeginCapture(st2, hipStreamCaptureModeThreadLocal));
+        const hipError_t e_launch = enqueue_half(aa_h[1], ca_h[1], st2);
+        hipGraph_t g = nullptr;
+        const hipError_t e_end = hipStreamEndCapture(st2, &g);
+        hipError_t e_inst = hipSuccess;
+        if (e_launch == hipSuccess && e_end == hipSuccess) e_inst = hipGraphInstantiate(&gexec2, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        MSB_HIP(e_launch);
+        MSB_HIP(e_end);
+        MSB_HIP(e_inst);
+      }
+      if (split) {                 // both halves start after the work queued on st, st waits for both
+        MSB_HIP(hipEventRecord(fork_ev, st));
+        MSB_HIP(hipStreamWaitEvent(ctx->half_stream, fork_ev, 0));
+        MSB_HIP(hipGraphLaunch(gexec, st));
+        MSB_HIP(hipGraphLaunch(gexec2, ctx->half_stream));
+        MSB_HIP(hipEventRecord(join_ev, ctx->half_stream));
+        MSB_HIP(hipStreamWaitEvent(st, join_ev, 0));
+      } else {
+        MSB_HIP(hipGraphLaunch(gexec, st));
+      }
       return MSB_OK;
     };
     struct GraphGuard {
       hipGraphExec_t* g;
       ~GraphGuard() { if (*g) (void)hipGraphExecDestroy(*g); }
-    } graph_guard{&gexec};
+    } graph_guard{&gexec}, graph_guard2{&gexec2};
 
     // recurred form with replacement: fold the bank slots written since the
     // last rebuild (iterations m0 .. m_now - 1) into x and p (Alg. 1's
@@ -1395,6 +1471,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   (void)hipEventDestroy(ev1);
   (void)hipEventDestroy(eg0);
   (void)hipEventDestroy(eg1);
+  (void)hipEventDestroy(fork_ev);
+  (void)hipEventDestroy(join_ev);
   if (info) {
     info->t_gemm_ms = t_gemm;
     info->n_gemm = n_gemm;
