@@ -114,6 +114,7 @@ struct DevBuf {               // scratch device memory released on scope exit
 
 static ApplyArgs apply_args(const msb_ctx* ctx, const SysDev* sys, int nsys, const void* x, void* v);
 constexpr int kMaxCand = 128;   // compiled shapes x passes x row orders
+constexpr int kSeedParts = 2;   // streams a recurred seed batch is split over (at most 4; 2 measured best)
 
 // Times every usable shape for (e, shape_class(nsys), mode) on constant vectors
 // and keeps the fastest in the context.  `table` (optional) receives every
@@ -392,7 +393,7 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   }
   if (e == hipSuccess) e = upload(&c->d_order_up, c->up.order);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->half_stream, hipStreamNonBlocking);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&c->part_stream[k], hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc(&c->d_small, 4096 * sizeof(double));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -414,7 +415,8 @@ extern "C" void msb_destroy(msb_ctx* c) {
   (void)hipFree(c->d_ell_dn);
   (void)hipFree(c->d_order_up);
   if (c->solve_stream) (void)hipStreamDestroy(c->solve_stream);
-  if (c->half_stream) (void)hipStreamDestroy(c->half_stream);
+  for (int k = 0; k < 3; ++k)
+    if (c->part_stream[k]) (void)hipStreamDestroy(c->part_stream[k]);
   (void)hipFree(c->d_small);
   if (c->ws) (void)hipFree(c->ws);
   delete c;
@@ -424,6 +426,7 @@ extern "C" msb_status msb_release_workspace(msb_ctx* c) {
   (void)hipGetLastError();   // do not report an earlier call's failure
   if (!c) return fail(MSB_EINVAL, "msb_release_workspace: null context");
   MSB_HIP(hipStreamSynchronize(c->solve_stream));
+  for (int k = 0; k < 3; ++k) MSB_HIP(hipStreamSynchronize(c->part_stream[k]));
   if (c->ws) MSB_HIP(hipFree(c->ws));
   c->ws = nullptr;
   c->ws_size = 0;
@@ -722,7 +725,7 @@ struct SolveBufs {
   SysDev* dsys = nullptr;
   SysState* dst = nullptr;
   double* partials = nullptr;
-  size_t part_half = 0;         // doubles: the second half of partials starts here
+  size_t part_cap = 0;          // doubles in partials (the parts of a split batch take regions)
   double* red1 = nullptr;
   double* red2 = nullptr;
   int* dbase = nullptr;
@@ -763,9 +766,10 @@ struct SolveBufs {
     Pc = carry ? c.take<void>((size_t)B * n_shift * D * s_out) : nullptr;
     dsys = c.take<SysDev>(B * sizeof(SysDev));
     dst = c.take<SysState>(B * sizeof(SysState));
-    // two regions of [nsys][nbx][4]: the two halves of a split batch run at once
-    part_half = part_n * 4;
-    partials = c.take<double>(part_n * 8 * sizeof(double));
+    // room for twice [nsys][nbx][4]: the parts of a split batch run at once,
+    // each in a region of its own
+    part_cap = part_n * 8;
+    partials = c.take<double>(part_cap * sizeof(double));
     red1 = c.take<double>((size_t)B * 4 * sizeof(double));
     red2 = c.take<double>((size_t)B * 4 * sizeof(double));
     dbase = c.take<int>(4 * sizeof(int));
@@ -973,9 +977,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   for (int k = 0; k < n_shift; ++k) hw[k] = w_in[k] - seed_shift;
   MSB_HIP(hipMemcpyAsync(wshift, hw.data(), n_shift * sizeof(double), hipMemcpyHostToDevice, st));
 
-  hipEvent_t ev0, ev1, eg0, eg1, fork_ev, join_ev;
+  hipEvent_t ev0, ev1, eg0, eg1, fork_ev, join_ev[kSeedParts - 1];
   MSB_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
-  MSB_HIP(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
+  for (auto& j : join_ev) MSB_HIP(hipEventCreateWithFlags(&j, hipEventDisableTiming));
   MSB_HIP(hipEventCreate(&ev0));
   MSB_HIP(hipEventCreate(&ev1));
   MSB_HIP(hipEventCreate(&eg0));
@@ -1146,50 +1150,59 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
 
     // one chunk of seed iterations; kernels skip systems that are not active.
     // The chunk is captured once per batch into a hipGraph and replayed.
-    hipGraphExec_t gexec = nullptr, gexec2 = nullptr;
-    // Recurred form, two or more systems: the chunk is captured as two
-    // independent branches (systems [0, h) and [h, nb)), so one half's
-    // latency-bound apply overlaps the other half's streaming r-update.
-    const bool split = use_graph && recur && nb >= 2;
-    const int h_split = nb / 2;
-    auto half_args = [&](int s0, int n, double* part, ApplyArgs& ha, CocgArgs& hc) {
-      ha = aa;
-      ha.sys = dsys + s0;
-      ha.aux = (const char*)bank + (size_t)s0 * cap * D * s_el;
-      ha.v = (char*)vvec + (size_t)s0 * D * s_el;
-      ha.aux_m = &dst[s0].m;
-      ha.status = &dst[s0].status;
-      ha.beta = &dst[s0].bp_re;
-      ha.partials = part;
-      ha.red = red1 + 4 * (size_t)s0;
-      ha.nsys = n;
-      hc = ca;
-      hc.st = dst + s0;
-      hc.red1 = red1 + 4 * (size_t)s0;
-      hc.partials = part;
-      hc.red2 = red2 + 4 * (size_t)s0;
-      hc.bank = (char*)bank + (size_t)s0 * cap * D * s_el;
-      hc.vvec = (const char*)vvec + (size_t)s0 * D * s_el;
-      hc.pvec = (char*)pvec + (size_t)s0 * D * s_el;
-      hc.nbx = cocg_nbx(D, n);
-      hc.nsys = n;
-      hc.zeta = zeta + 2 * (size_t)s0 * n_shift;
-      hc.zeta_prev = zeta_prev + 2 * (size_t)s0 * n_shift;
-      hc.conv_iter = conv + (size_t)s0 * n_shift;
-      hc.alpha_log = alog + 2 * (size_t)s0 * mx;
-      hc.beta_log = blog + 2 * (size_t)s0 * mx;
-      hc.rnorm_log = rlog + (size_t)s0 * (mx + 1);
-    };
-    ApplyArgs aa_h[2];
-    CocgArgs ca_h[2];
-    if (split) {
-      half_args(0, h_split, partials, aa_h[0], ca_h[0]);
-      half_args(h_split, nb - h_split, partials + bf.part_half, aa_h[1], ca_h[1]);
+    // Recurred form, two or more systems: the batch is split into parts of
+    // consecutive systems, each captured as its own chunk graph and launched on
+    // its own stream, so one part's latency-bound apply overlaps another
+    // part's streaming r-update.  Each part has its own region of partials.
+    int n_parts = (use_graph && recur) ? std::min(nb, kSeedParts) : 1;
+    std::vector<ApplyArgs> aa_p;
+    std::vector<CocgArgs> ca_p;
+    if (n_parts > 1) {
+      size_t off = 0;
+      for (int p = 0; p < n_parts; ++p) {
+        const int s0 = (int)((int64_t)nb * p / n_parts), s1 = (int)((int64_t)nb * (p + 1) / n_parts);
+        const int n = s1 - s0;
+        const size_t need = (size_t)n * std::max(apply_nbx(ctx->up.n, n), cocg_nbx(D, n)) * 4;
+        if (off + need > bf.part_cap) {   // not enough room: one graph for the whole batch
+          n_parts = 1;
+          break;
+        }
+        ApplyArgs ha = aa;
+        ha.sys = dsys + s0;
+        ha.aux = (const char*)bank + (size_t)s0 * cap * D * s_el;
+        ha.v = (char*)vvec + (size_t)s0 * D * s_el;
+        ha.aux_m = &dst[s0].m;
+        ha.status = &dst[s0].status;
+        ha.beta = &dst[s0].bp_re;
+        ha.partials = partials + off;
+        ha.red = red1 + 4 * (size_t)s0;
+        ha.nsys = n;
+        CocgArgs hc = ca;
+        hc.st = dst + s0;
+        hc.red1 = red1 + 4 * (size_t)s0;
+        hc.partials = partials + off;
+        hc.red2 = red2 + 4 * (size_t)s0;
+        hc.bank = (char*)bank + (size_t)s0 * cap * D * s_el;
+        hc.vvec = (const char*)vvec + (size_t)s0 * D * s_el;
+        hc.pvec = (char*)pvec + (size_t)s0 * D * s_el;
+        hc.nbx = cocg_nbx(D, n);
+        hc.nsys = n;
+        hc.zeta = zeta + 2 * (size_t)s0 * n_shift;
+        hc.zeta_prev = zeta_prev + 2 * (size_t)s0 * n_shift;
+        hc.conv_iter = conv + (size_t)s0 * n_shift;
+        hc.alpha_log = alog + 2 * (size_t)s0 * mx;
+        hc.beta_log = blog + 2 * (size_t)s0 * mx;
+        hc.rnorm_log = rlog + (size_t)s0 * (mx + 1);
+        aa_p.push_back(ha);
+        ca_p.push_back(hc);
+        off += need;
+      }
     }
-    auto enqueue_half = [&](const ApplyArgs& ha, const CocgArgs& hc, hipStream_t s) -> hipError_t {
+    auto part_stream = [&](int p) { return p == 0 ? st : ctx->part_stream[p - 1]; };
+    auto enqueue_part = [&](int p) -> hipError_t {
       for (int c = 0; c < chunk; ++c) {
-        hipError_t e = launch_apply(ev, kModeSelf, ha, s);
-        if (e == hipSuccess) e = launch_cocg_r(ev, hc, s);
+        hipError_t e = launch_apply(ev, kModeSelf, aa_p[p], part_stream(p));
+        if (e == hipSuccess) e = launch_cocg_r(ev, ca_p[p], part_stream(p));
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
@@ -1210,52 +1223,46 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       }
       return hipSuccess;
     };
+    hipGraphExec_t gexec[kSeedParts] = {};
+    struct GraphGuard {
+      hipGraphExec_t* g;
+      ~GraphGuard() {
+        for (int p = 0; p < kSeedParts; ++p)
+          if (g[p]) (void)hipGraphExecDestroy(g[p]);
+      }
+    } graph_guard{gexec};
     auto run_chunk = [&]() -> msb_status {
       if (!use_graph) {
         MSB_HIP(enqueue_chunk());
         return MSB_OK;
       }
-      if (!gexec) {
-        MSB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        const hipError_t e_launch = split ? enqueue_half(aa_h[0], ca_h[0], st) : enqueue_chunk();
+      for (int p = 0; p < n_parts; ++p) {
+        if (gexec[p]) continue;
+        const hipStream_t s = part_stream(p);
+        MSB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const hipError_t e_launch = n_parts > 1 ? enqueue_part(p) : enqueue_chunk();
         hipGraph_t g = nullptr;
-        const hipError_t e_end = hipStreamEndCapture(st, &g);
+        const hipError_t e_end = hipStreamEndCapture(s, &g);
         hipError_t e_inst = hipSuccess;
-        if (e_launch == hipSuccess && e_end == hipSuccess) e_inst = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+        if (e_launch == hipSuccess && e_end == hipSuccess) e_inst = hipGraphInstantiate(&gexec[p], g, nullptr, nullptr, 0);
         if (g) (void)hipGraphDestroy(g);
         MSB_HIP(e_launch);
         MSB_HIP(e_end);
         MSB_HIP(e_inst);
       }
-      if (split && !gexec2) {      // the second half: its own graph on its own stream
-        const hipStream_t st2 = ctx->half_stream;
-        MSB_HIP(hipStreamBeginCapture(st2, hipStreamCaptureModeThreadLocal));
-        const hipError_t e_launch = enqueue_half(aa_h[1], ca_h[1], st2);
-        hipGraph_t g = nullptr;
-        const hipError_t e_end = hipStreamEndCapture(st2, &g);
-        hipError_t e_inst = hipSuccess;
-        if (e_launch == hipSuccess && e_end == hipSuccess) e_inst = hipGraphInstantiate(&gexec2, g, nullptr, nullptr, 0);
-        if (g) (void)hipGraphDestroy(g);
-        MSB_HIP(e_launch);
-        MSB_HIP(e_end);
-        MSB_HIP(e_inst);
-      }
-      if (split) {                 // both halves start after the work queued on st, st waits for both
+      if (n_parts > 1) {           // every part starts after the work queued on st; st waits for all
         MSB_HIP(hipEventRecord(fork_ev, st));
-        MSB_HIP(hipStreamWaitEvent(ctx->half_stream, fork_ev, 0));
-        MSB_HIP(hipGraphLaunch(gexec, st));
-        MSB_HIP(hipGraphLaunch(gexec2, ctx->half_stream));
-        MSB_HIP(hipEventRecord(join_ev, ctx->half_stream));
-        MSB_HIP(hipStreamWaitEvent(st, join_ev, 0));
+        for (int p = 1; p < n_parts; ++p) MSB_HIP(hipStreamWaitEvent(part_stream(p), fork_ev, 0));
+        for (int p = 0; p < n_parts; ++p) MSB_HIP(hipGraphLaunch(gexec[p], part_stream(p)));
+        for (int p = 1; p < n_parts; ++p) {
+          MSB_HIP(hipEventRecord(join_ev[p - 1], part_stream(p)));
+          MSB_HIP(hipStreamWaitEvent(st, join_ev[p - 1], 0));
+        }
       } else {
-        MSB_HIP(hipGraphLaunch(gexec, st));
+        MSB_HIP(hipGraphLaunch(gexec[0], st));
       }
       return MSB_OK;
     };
-    struct GraphGuard {
-      hipGraphExec_t* g;
-      ~GraphGuard() { if (*g) (void)hipGraphExecDestroy(*g); }
-    } graph_guard{&gexec}, graph_guard2{&gexec2};
 
     // recurred form with replacement: fold the bank slots written since the
     // last rebuild (iterations m0 .. m_now - 1) into x and p (Alg. 1's
@@ -1472,7 +1479,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   (void)hipEventDestroy(eg0);
   (void)hipEventDestroy(eg1);
   (void)hipEventDestroy(fork_ev);
-  (void)hipEventDestroy(join_ev);
+  for (auto& j : join_ev) (void)hipEventDestroy(j);
   if (info) {
     info->t_gemm_ms = t_gemm;
     info->n_gemm = n_gemm;

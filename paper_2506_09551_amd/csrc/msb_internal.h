@@ -414,7 +414,7 @@ struct msb_ctx {
   int type_partner[MSB_MAX_BOND_TYPES] = {0}; // type of the reverse hop (itself when symmetric)
   // private stream for the captured seed iterations (default priority)
   hipStream_t solve_stream = nullptr;
-  hipStream_t half_stream = nullptr;       // second branch of a captured seed chunk
+  hipStream_t part_stream[3] = {};         // the other parts of a split seed batch
   double* d_small = nullptr;          // small reduction outputs
   // growable workspace
   void* ws = nullptr;
