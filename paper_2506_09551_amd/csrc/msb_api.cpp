@@ -115,6 +115,7 @@ struct DevBuf {               // scratch device memory released on scope exit
 static ApplyArgs apply_args(const msb_ctx* ctx, const SysDev* sys, int nsys, const void* x, void* v);
 constexpr int kMaxCand = 128;   // compiled shapes x passes x row orders
 constexpr int kSeedParts = 2;   // streams a recurred seed batch is split over (at most 4; 2 measured best)
+constexpr int kSeedPartMin = 4; // systems per part at least
 
 // Times every usable shape for (e, shape_class(nsys), mode) on constant vectors
 // and keeps the fastest in the context.  `table` (optional) receives every
@@ -1154,7 +1155,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     // consecutive systems, each captured as its own chunk graph and launched on
     // its own stream, so one part's latency-bound apply overlaps another
     // part's streaming r-update.  Each part has its own region of partials.
-    int n_parts = (use_graph && recur) ? std::min(nb, kSeedParts) : 1;
+    // (measured: 12 systems of the L=12 ring gain 8% per iteration; 4 systems
+    // of the 4x4 cluster, whose apply dominates and gathers from L2, lose 8%)
+    int n_parts = (use_graph && recur && nb >= kSeedPartMin * kSeedParts) ? kSeedParts : 1;
     std::vector<ApplyArgs> aa_p;
     std::vector<CocgArgs> ca_p;
     if (n_parts > 1) {

@@ -122,6 +122,34 @@ def test_seed_forms_agree(tiny, direct_ap):
     assert _rel(psi.reshape(-1, D), psi_o.reshape(-1, D)) <= 1e-9
 
 
+def test_large_batch_runs_in_two_parts(tiny):
+    """Nine systems (the recurred seed then runs as two parts of 4 and 5 on two
+    streams): every shift of every system against its direct solve, and the
+    same iterations per system as the direct form, which runs unsplit."""
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E_G = -2.6661474201323485
+    L = m["L"]
+    systems = [msb.make_system(core_site=j % L, Uc=wl.Uc - 0.25 * (j // L), E_G=E_G, Gamma=wl.Gamma)
+               for j in range(9)]
+    E = np.stack([W.random_complex(D, 80 + j) for j in range(9)])
+    w = np.linspace(-6.0, 8.0, 23)
+    st, info, psi = _run(msb, ctx, systems, E, w, 1e-12, 3000, msb.MSB_C128, hist_len=3001)
+    for j, s in enumerate(systems):
+        ref = osolve.direct_solve(oracle_H(m, core_site=s.core_site, Uc=s.Uc), E[j], E_G,
+                                  wl.Gamma, w, method="eig")
+        assert _rel(psi[j], ref) <= 1e-9, f"system {j}"
+    assert np.max(info["resid_true"]) <= 1e-11
+    _, info_d, _ = _run(msb, ctx, systems, E, w, 1e-12, 3000, msb.MSB_C128, opts={"direct_ap": 1},
+                        hist_len=3001)
+    for j in range(9):
+        n = int(min(info["sys_iters"][j], info_d["sys_iters"][j]))
+        assert abs(int(info["sys_iters"][j]) - int(info_d["sys_iters"][j])) <= max(2, n // 30)
+        k = min(40, n)
+        assert np.max(np.abs(info["seed_hist"][j][:k] - info_d["seed_hist"][j][:k])
+                      / info_d["seed_hist"][j][:k]) <= 1e-9
+
+
 @pytest.mark.parametrize("direct_ap", [0, 1])
 @pytest.mark.parametrize("slots", [5, 37, 120])
 def test_small_bank_forces_carry_flushes(tiny, slots, direct_ap):
