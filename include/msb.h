@@ -166,10 +166,14 @@ typedef struct {
                             unless one was tuned or pinned before */
   int dual;              /* 0 = the dual-space (BiCG) form only when some system's A is not
                             symmetric (default), 1 = always; MSB_C128 only */
-  int direct_ap;         /* 0 = (default) except in the dual form, the seed applies A to its
-                            residual r_m in place and forms A p_m = A r_m + beta_{m-1} A p_{m-1}
-                            in the same pass; 1 = form p_m and apply A to it (Algorithm 1 as
-                            written) */
+  int direct_ap;         /* 0 = (default) in MSB_C128 (not in the dual form) the seed applies A
+                            to its residual r_m in place and forms
+                            A p_m = A r_m + beta_{m-1} A p_{m-1} in the same pass; MSB_C64 forms
+                            p_m and applies A to it (Algorithm 1 as written); 1 = that direct
+                            form in both precisions; -1 = the recurred form in MSB_C64 too,
+                            with residual replacement only (A p is recomputed from the
+                            rebuilt p at every replacement; on hard systems its final true
+                            residuals are several times the direct form's) */
 } msb_opts;
 
 /* ---- context -------------------------------------------------------------- */
@@ -257,12 +261,11 @@ msb_status msb_dipole(const msb_ctx* src, const msb_ctx* dst, int spin, int crea
  * |r_m| / |zeta_m(w_k)| <= tol |E_s|.  MSB_C64 runs the vectors in complex64
  * with FP64 reductions and scalars, and replaces the seed residual by the
  * FP64 true residual every opts->replace_every iterations.
- * By default the seed carries A p_m by recurrence (opts->direct_ap): the
- * apply reads r_m in place from the residual bank and writes
- * A p_m = A r_m + beta_{m-1} A p_{m-1} over the previous product, so no
- * separate update of p_m runs (MSB_C64 forms p_m inside the r-update, for the
- * seed solution its replacements need); sigma_m = r_m^T A p_m and every
- * scalar are as in Algorithm 1, the iterates equal up to rounding.
+ * In MSB_C128 the seed by default carries A p_m by recurrence
+ * (opts->direct_ap): the apply reads r_m in place from the residual bank and
+ * writes A p_m = A r_m + beta_{m-1} A p_{m-1} over the previous product, so
+ * no separate update of p_m runs; sigma_m = r_m^T A p_m and every scalar are
+ * as in Algorithm 1, the iterates equal up to rounding.
  * When some system's A is not symmetric (directed bonds with different
  * amplitudes, msb_model) the dual-space form runs instead: a shadow residual
  * r~ and direction p~ follow the same recurrences with A^T (a second apply per

@@ -860,7 +860,14 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   }
   // recurred seed form (A p_m carried by recurrence; p_m formed only for the
   // seed solution of residual replacement); the dual form runs the direct one
-  const bool recur = !dual && !(opts && opts->direct_ap == 1);
+  // complex64 carries A p_m in float storage, so the recurred product drifts
+  // from A p_m: it runs recurred only on request (direct_ap = -1) and with
+  // residual replacement, which resets the product to A p_{m-1} at every
+  // replacement (measured: without the reset single systems stall above tol;
+  // with it the final true residuals of hard systems are several times the
+  // direct form's)
+  const int dap = opts ? opts->direct_ap : 0;
+  const bool recur = !dual && dap != 1 && (prec == MSB_C128 || (dap == -1 && replace_every > 0));
   if (dual) {
     if (prec != MSB_C128) return fail(MSB_EINVAL, "msb_solve: the dual-space form runs in complex128");
     hsysT.resize(nsys);
@@ -1325,6 +1332,10 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     };
 
     ApplyArgs ra = apply_args(ctx, dsys, nb, bf.xseed, bf.wrep);
+    ApplyArgs pa = apply_args(ctx, dsys, nb, pvec, vvec);          // recurred form: v <- A p at a replacement
+    pa.shape = shape_for(ctx, ev, nb, st, tune);
+    pa.status = &dst[0].status;
+    pa.status_stride = (int)(sizeof(SysState) / sizeof(int));
     ra.shape = shape_for(ctx, Elem::C128, nb, st, tune);
     ra.status = &dst[0].status;
     ra.status_stride = (int)(sizeof(SysState) / sizeof(int));
@@ -1356,6 +1367,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
           // r_m <- E - A_s x_m with x_m and the product in complex128
           msb_status r = rebuild(m_now);
           if (r != MSB_OK) return r;
+          if (recur) MSB_HIP(launch_apply(ev, kModePlain, pa, st));   // A p_{m-1} afresh from the rebuilt p
           MSB_HIP(launch_apply(Elem::C128, kModePlain, ra, st));
           MSB_HIP(launch_cocg_replace(ev, ca, Eb, bf.wrep, st));
           last_rep = m_now;
