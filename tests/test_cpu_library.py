@@ -56,3 +56,27 @@ def test_surrogate_fallback_rule_matches_oracle():
     sd = rng.uniform(0, 0.06, (16, 40)).astype(np.float32)
     for frac in (0.02, 0.05, 0.1):
         assert np.array_equal(msb.msb_mlp_fallback(mean, sd, frac), omlp.fallback_rows(mean, sd, frac))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """`bench.py --gpus 2` prints one JSON line naming the limit and exits with
+    status 2 before it touches a GPU."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=str(ROOT))
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+@pytest.mark.parametrize("name", ["msb_opts", "msb_shape"])
+def test_struct_layout_matches_header(name):
+    """The ctypes mirrors of the plain-value structs list the header's fields in order."""
+    from paper_2506_09551_amd import _capi
+    text = (ROOT / "include" / "msb.h").read_text()
+    end = text.index("} " + name + ";")
+    body = text[text.rindex("typedef struct {", 0, end):end]
+    fields = re.findall(r"^\s*(?:int|double)\s+(\w+);", body, flags=re.M)
+    assert [f[0] for f in getattr(_capi, name)._fields_] == fields
