@@ -161,6 +161,21 @@ def test_large_batch_runs_in_two_parts(tiny, case):
                       / info_d["seed_hist"][j][:k]) <= 1e-9
 
 
+def test_two_part_batch_is_deterministic(tiny):
+    """The two parts of a split batch share no mutable state, so two solves give
+    the same bits whatever the interleaving of their streams."""
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    systems = [msb.make_system(core_site=j % m["L"], Uc=wl.Uc, E_G=-2.6661474201323485, Gamma=wl.Gamma)
+               for j in range(8)]
+    E = np.stack([W.random_complex(D, 90 + j) for j in range(8)])
+    w = np.linspace(-4.0, 6.0, 17)
+    _, i1, p1 = _run(msb, ctx, systems, E, w, 1e-11, 3000, msb.MSB_C128)
+    _, i2, p2 = _run(msb, ctx, systems, E, w, 1e-11, 3000, msb.MSB_C128)
+    assert np.array_equal(i1["sys_iters"], i2["sys_iters"])
+    assert np.array_equal(p1, p2)
+
+
 @pytest.mark.parametrize("direct_ap", [0, 1])
 @pytest.mark.parametrize("slots", [5, 37, 120])
 def test_small_bank_forces_carry_flushes(tiny, slots, direct_ap):
