@@ -241,6 +241,11 @@ def residual_polynomial(alpha, beta, x):
     P_{m+1}(x) = (1 - alpha_m x) P_m + (alpha_m beta_{m-1}/alpha_{m-1}) (P_m - P_{m-1}),
     the residual polynomial of the seed evaluated at scalar x; by Eq. ``zeta``
     this equals zeta_m(x).  Independent of the vector recurrence.
+
+    Pinned by ``tests/test_oracle_solve.py``: r_m = P_m(A_s) r_0 with the
+    polynomial applied in the eigenbasis of A_s (App. C's definition of the
+    residual polynomial), P_m(0) = 1, P_1(x) = 1 - alpha_0 x, and the two
+    misreadings ((1 + alpha_m x), beta_m for beta_{m-1}) break that identity.
     """
     x = np.asarray(x, dtype=np.complex128)
     P_prev = np.ones_like(x)

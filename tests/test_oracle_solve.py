@@ -301,3 +301,99 @@ def test_dual_space_form_reduces_to_the_symmetric_one(ring):
     b = so.msbicg_reference(A, E, w, 1e-12, 500, AT_apply=A)
     assert a.iters == b.iters
     assert np.array_equal(a.psi, b.psi)
+
+
+# ---- residual polynomial (App. C, Eqs. zeta and poly_recurrsion) ------------
+
+def _seed_scalars(Hp, E_G, Gamma, E, seed, m):
+    """alpha_j, beta_j of the oracle's seed recurrence for m iterations, and its
+    seed iterate x_m (the shift equal to the seed has zeta = 1, so its Psi is x_m)."""
+    A = lambda x: Hp @ x - (E_G + 1j * Gamma) * x
+    res = so.msbicg_reference(A, E, np.array([seed, seed + 0.9, seed - 2.3]), 0.0, m,
+                              seed_shift=seed, keep_zeta=True)
+    assert res.iters == m and not res.breakdown
+    return res
+
+
+def _poly_of_matrix(P_at, lam, V, E):
+    """P(A_s) E for the diagonalisable A_s = V diag(lam) V^{-1}: the polynomial's
+    values at the eigenvalues applied in the eigenbasis."""
+    return V @ (P_at * np.linalg.solve(V, E))
+
+
+@pytest.mark.parametrize("seed", [0.0, 1.7])
+def test_residual_polynomial_gives_the_seed_residuals(ring, seed):
+    """r_m = P_m(A_s) r_0 (the residual-polynomial definition of App. C), with
+    P_m from the seed scalars alone: the polynomial evaluated at the eigenvalues
+    of A_s and applied in its eigenbasis reproduces the seed residual
+    E - A_s x_m of the vector recurrence, at every m checked."""
+    B, H, Hp, E_G, G = ring
+    Gamma = 0.8
+    E = W.random_complex(B.dim, 11)
+    As = Hp.toarray() - (E_G + seed + 1j * Gamma) * np.eye(B.dim)
+    lam, V = np.linalg.eig(As)
+    for m in (1, 2, 5, 17, 40):
+        res = _seed_scalars(Hp, E_G, Gamma, E, seed, m)
+        x_m = res.psi[0]
+        r_m = E - As @ x_m
+        P = so.residual_polynomial(res.alpha, res.beta, lam)[m]
+        r_poly = _poly_of_matrix(P, lam, V, E)
+        assert np.linalg.norm(r_poly - r_m) <= 1e-9 * np.linalg.norm(E), m
+        assert abs(np.linalg.norm(r_poly) - res.rnorm[m]) <= 1e-9 * np.linalg.norm(E), m
+
+
+def test_residual_polynomial_normalisation_and_first_degree(ring):
+    """P_m(0) = 1 for every m (r_m = E - A x_m with x_m in the Krylov space),
+    and P_1(x) = 1 - alpha_0 x."""
+    B, H, Hp, E_G, G = ring
+    E = W.random_complex(B.dim, 12)
+    res = _seed_scalars(Hp, E_G, 1.0, E, 0.0, 25)
+    x = np.array([0.0, 0.3 - 0.2j, -4.0 + 1j, 7.5])
+    P = so.residual_polynomial(res.alpha, res.beta, x)
+    assert np.allclose(P[:, 0], 1.0, rtol=0, atol=1e-12)
+    assert np.allclose(P[1], 1.0 - res.alpha[0] * x, rtol=1e-15, atol=1e-15)
+    assert P.shape == (26, 4)
+
+
+def test_residual_polynomial_equals_zeta(ring):
+    """Eq. zeta: the shift coefficient zeta_m(w') of the recurrence is P_m(w')
+    evaluated from the seed scalars, for shifts on both sides of the seed."""
+    B, H, Hp, E_G, G = ring
+    E = W.random_complex(B.dim, 13)
+    seed = 1.7
+    res = _seed_scalars(Hp, E_G, 0.8, E, seed, 30)
+    w_prime = np.array([0.0, 0.9, -2.3])                   # the three shifts minus the seed
+    P = so.residual_polynomial(res.alpha, res.beta, w_prime)
+    assert np.max(np.abs(P - res.zeta) / np.abs(res.zeta)) <= 1e-12
+
+
+def test_residual_polynomial_pin_rejects_misprints(ring):
+    """The two plausible misreadings of Eq. poly_recurrsion, the printed
+    (1 + alpha_m x) sign and beta_m in place of beta_{m-1}, break the identity
+    r_m = P_m(A_s) E that the correct recurrence satisfies."""
+    B, H, Hp, E_G, G = ring
+    Gamma = 0.8
+    E = W.random_complex(B.dim, 14)
+    As = Hp.toarray() - (E_G + 1j * Gamma) * np.eye(B.dim)
+    lam, V = np.linalg.eig(As)
+    m = 12
+    res = _seed_scalars(Hp, E_G, Gamma, E, 0.0, m)
+    r_m = E - As @ res.psi[0]
+
+    def variant(x, sign, shift_beta):
+        P_prev = np.ones_like(x)
+        P = np.ones_like(x)
+        a_prev, b_prev = 1.0 + 0j, 0.0 + 0j
+        for j in range(m):
+            a, b = res.alpha[j], res.beta[j]
+            bb = b if shift_beta else b_prev
+            P_next = (1 + sign * a * x) * P + (a * bb / a_prev) * (P - P_prev)
+            P_prev, P = P, P_next
+            a_prev, b_prev = a, b
+        return P
+
+    good = so.residual_polynomial(res.alpha, res.beta, lam)[m]
+    assert np.allclose(variant(lam, -1, False), good, rtol=1e-13, atol=1e-13)
+    for sign, shift_beta in ((+1, False), (-1, True)):
+        r_bad = _poly_of_matrix(variant(lam, sign, shift_beta), lam, V, E)
+        assert np.linalg.norm(r_bad - r_m) >= 1e-3 * np.linalg.norm(E), (sign, shift_beta)
