@@ -29,8 +29,19 @@
  *   library never frees or retains them.  The library owns the context:
  *   basis tables, workspace and captured graphs, released by msb_destroy.
  *   Inputs are never modified.
- * Streams.  `stream` is a hipStream_t (NULL = default stream).  Calls are
- *   blocking: they return after their work on `stream` has completed.
+ * Streams.  `stream` is a hipStream_t of the HIP runtime this library is
+ *   linked against (one made by msb_stream_create, or any other stream of
+ *   that runtime), or NULL for that runtime's null stream.  Every call first
+ *   orders itself after the work already queued on `stream`: calls that run
+ *   on `stream` itself (msb_apply, msb_apply_timed, msb_number_op,
+ *   msb_dipole, msb_combine, msb_spectrum, msb_ground_state, msb_autotune)
+ *   enqueue behind it, and calls that run on the context's own streams
+ *   (msb_solve, msb_solve_reseed, msb_mlp_train, msb_mlp_predict) wait for it with
+ *   hipStreamSynchronize before they start.  Calls are blocking: they return
+ *   after all of their device work has completed, so outputs are ready on
+ *   any stream.  A stream of another HIP runtime instance (a framework that
+ *   bundles its own runtime, such as a ROCm build of PyTorch) is not a valid
+ *   handle here: synchronise it and pass NULL.
  * Errors.  Every call returns an msb_status; msb_last_error() returns a
  *   thread-local message for the last failure on the calling thread.
  * Threads.  A context may be used by one thread at a time.
@@ -198,6 +209,12 @@ msb_status msb_sector_info(const msb_ctx* ctx, int* n_up_states, int* n_dn_state
 const char* msb_last_error(void);
 /* 1 if the library was built for and found a gfx950 device. */
 int msb_device_ok(void);
+/* A default-priority, non-blocking stream of the library's HIP runtime on the
+ * current device, for callers that have no stream of that runtime; release
+ * it with msb_stream_destroy (after the last call that uses it).
+ * Errors: MSB_EINVAL for a null `out`; MSB_EHIP if the runtime refuses. */
+msb_status msb_stream_create(void** out);
+msb_status msb_stream_destroy(void* stream);
 
 /* ---- operators -------------------------------------------------------------- */
 

@@ -78,6 +78,10 @@ def lib():
         L = ctypes.CDLL(str(LIB_PATH))
         L.msb_last_error.restype = ctypes.c_char_p
         L.msb_device_ok.restype = c_int
+        L.msb_stream_create.argtypes = [POINTER(c_void_p)]
+        L.msb_stream_create.restype = c_int
+        L.msb_stream_destroy.argtypes = [c_void_p]
+        L.msb_stream_destroy.restype = c_int
         L.msb_create.argtypes = [POINTER(msb_model), POINTER(c_void_p)]
         L.msb_create.restype = c_int
         L.msb_destroy.argtypes = [c_void_p]
@@ -150,7 +154,7 @@ def lib():
 def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["msb_create", "msb_destroy", "msb_release_workspace", "msb_dim", "msb_sector_info", "msb_last_error",
-            "msb_device_ok", "msb_apply", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
+            "msb_device_ok", "msb_stream_create", "msb_stream_destroy", "msb_apply", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
             "msb_solve_reseed", "msb_dipole",
             "msb_combine", "msb_spectrum", "msb_autotune", "msb_set_shape",
             "msb_mlp_num_params", "msb_mlp_create", "msb_mlp_destroy", "msb_mlp_set_params",
@@ -162,15 +166,42 @@ def _check(status: int):
         raise MsbError(status, lib().msb_last_error().decode())
 
 
-def _stream_ptr(stream):
-    """Order the call after the work queued on torch's stream, then let the
-    library run on its own default stream.
+class LibStream:
+    """A stream of the library's own HIP runtime (msb_stream_create).
 
-    torch ships its own HIP runtime, separate from the one the library links,
-    so a torch stream handle means nothing to the library (device pointers
-    are shared: both runtimes map into the same process address space).
-    Every library call is blocking, so its outputs are complete on return.
+    Its handle goes to the C ABI as it is; the call is ordered after the work
+    already queued on it.  Release it with ``close()``."""
+
+    def __init__(self):
+        h = c_void_p()
+        _check(lib().msb_stream_create(ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _check(lib().msb_stream_destroy(self.handle))
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _stream_ptr(stream):
+    """Stream argument of a C call.
+
+    A ``LibStream`` is passed through: it belongs to the library's runtime.
+    A torch stream (or None: torch's current stream) is synchronised and NULL
+    is passed: torch ships its own HIP runtime, separate from the one the
+    library links, so a torch stream handle means nothing to the library
+    (device pointers are shared: both runtimes map into the same process
+    address space).  Every library call is blocking, so its outputs are
+    complete on return.
     """
+    if isinstance(stream, LibStream):
+        return stream.handle
     import torch
     (stream if stream is not None else torch.cuda.current_stream()).synchronize()
     return c_void_p(0)

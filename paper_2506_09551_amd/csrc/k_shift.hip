@@ -189,7 +189,9 @@ __global__ __launch_bounds__(kBlock) void k_flush_mfma(FlushArgs a, int ow_mode)
     }
   };
   Ops cur, nxt;
-  load_ops(0, cur);
+  // an empty tile (every listed shift froze before this block) has Kext = 0:
+  // nothing is loaded and the zero sums are stored (or added to the old output)
+  if (Kext > 0) load_ops(0, cur);
   for (int kb = 0; kb < Kext; kb += 4) {
     if (kb + 4 < Kext) load_ops(kb + 4, nxt);
 #pragma unroll

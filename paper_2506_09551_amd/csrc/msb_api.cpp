@@ -273,6 +273,22 @@ extern "C" int msb_device_ok(void) {
   return std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
 }
 
+extern "C" msb_status msb_stream_create(void** out) {
+  if (!out) return fail(MSB_EINVAL, "msb_stream_create: null argument");
+  *out = nullptr;
+  hipStream_t s = nullptr;
+  MSB_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  *out = (void*)s;
+  return MSB_OK;
+}
+
+extern "C" msb_status msb_stream_destroy(void* stream) {
+  if (!stream) return fail(MSB_EINVAL, "msb_stream_destroy: null stream");
+  MSB_HIP(hipStreamSynchronize((hipStream_t)stream));
+  MSB_HIP(hipStreamDestroy((hipStream_t)stream));
+  return MSB_OK;
+}
+
 extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   if (!m || !out) return fail(MSB_EINVAL, "msb_create: null argument");
   *out = nullptr;
