@@ -29,11 +29,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
-# The complex64 workloads (precision, batched) measure the fast complex64
-# form: A p carried by recurrence between residual replacements (the library's
-# complex64 default is the direct form, which is more accurate on hard systems;
-# both report their FP64 true residuals and the spectrum error vs complex128).
-C64_OPTS = {"direct_ap": -1}
+# The complex64 workloads (precision, batched) run the library's complex64
+# form as it is (the direct seed form with residual replacement).
+C64_OPTS = None
 
 # HBM counters of the assembly kernel on the scale step (one launch), from
 # profiles/solve_scale_L12_hbm_counters.md: raw FETCH_SIZE / WRITE_SIZE in KiB
@@ -75,8 +73,10 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(wl, iters_gpu: int, n_iter: int = 6):
-    """Oracle recurrence (one system, all shifts) for a few iterations, extrapolated."""
+def cpu_baseline(wl, iters_gpu: int, n_iter: int = 6, threads: int = 1):
+    """Oracle recurrence (one system, all shifts) for a few iterations, extrapolated;
+    BLAS / OpenMP pools limited to `threads` (NumPy's elementwise work and
+    SciPy's sparse product run on one core whatever the limit)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -89,7 +89,7 @@ def cpu_baseline(wl, iters_gpu: int, n_iter: int = 6):
     E = W.random_vector(B.dim, 5).astype(np.complex128)
     shift = -4.0 + 1j * wl.Gamma
     A = lambda x: Hp @ x - shift * x
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         osolve.msbicg_reference(A, E, wl.w_in, 1e-30, 1)          # warm-up
         t0 = time.perf_counter()
         osolve.msbicg_reference(A, E, wl.w_in, 1e-30, n_iter)
@@ -99,12 +99,12 @@ def cpu_baseline(wl, iters_gpu: int, n_iter: int = 6):
     return {
         "value": len(wl.w_in) / per_system,
         "unit": "shift-solves/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
         "sample": (f"one of {wl.nrhs} core-hole systems with all {len(wl.w_in)} shifts: "
                    f"{n_iter} iterations of the oracle's multi-shift recurrence (NumPy/SciPy "
-                   f"CSR, one thread) took {dt:.2f} s, scaled to the {iters_gpu} iterations the "
-                   f"GPU run needs"),
+                   f"CSR, thread pools limited to {threads}) took {dt:.2f} s, scaled to the "
+                   f"{iters_gpu} iterations the GPU run needs"),
         "host": {"cpu": cpu_model(), "os_cpu_count": os.cpu_count()},
     }
 
@@ -563,39 +563,32 @@ def dipole_main(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="scale")
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run one 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--train-spectra", type=int, default=4096, help="learned form: training spectra")
-    ap.add_argument("--heldout-spectra", type=int, default=256, help="learned form: held-out spectra")
-    ap.add_argument("--epochs", type=float, default=2.0, help="learned form: passes over the training set")
-    ap.add_argument("--mlp-train-steps", type=int, default=0,
-                    help="learned form: only time this many training steps on seeded random points")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "one GPU only: the solver has no multi-GPU path; run with --gpus 1"}))
-        sys.exit(2)
-    if args.workload == "learned" and args.mlp_train_steps > 0:
-        mlp_train_main(args)
-        return
-    if args.workload == "learned":
-        learned_main(args)
-        return
-    if args.workload == "reseed":
-        reseed_main(args)
-        return
-    if args.workload == "dipole":
-        dipole_main(args)
-        return
+def form_summary(name, out):
+    """The figures of one form (precision or batched) for the default line."""
+    s = {"workload": out["config"]["workload"], "dtype": out["dtype"], "tol": out["config"]["tol"],
+         "ms_per_step": out["ms_per_step"], "shift_solves_per_s": out["value"], "iters": out["iters"],
+         "solve_status": out["solve_status"], "max_true_residual": out["max_true_residual"],
+         "split_ms": out["split_ms"], "assembly_tflops": out["roofline"]["achieved"]}
+    if name == "precision":
+        p = out["precision"]
+        s.update({"c128_ms": p["c128_ms"], "speedup_vs_c128": p["speedup_c64_vs_c128"],
+                  "c128_max_true_residual": p["c128_true_residual_max"],
+                  "spectrum_rel_err_vs_c128": p["spectrum_rel_err_vs_c128"]["max"],
+                  "replacements": p["c64_replacements"]})
+    else:
+        b = out["batched"]
+        s.update({"separate_same_precision_ms": b["separate_ms"],
+                  "speedup_vs_separate_same_precision": b["speedup_batched_vs_separate"],
+                  "separate_c128_ms": b["plain_c128_separate_ms"],
+                  "speedup_vs_c128": b["speedup_batched_vs_plain_c128"],
+                  "spectrum_rel_err_vs_c128": b["spectrum_rel_err_vs_c128"]["max"],
+                  "apply_block_GBs": b["apply_block_GBs"], "apply_one_GBs": b["apply_one_GBs"]})
+    return s
 
+
+def run_solver_workload(wl_name, args, extras=True, cpu=True):
+    """One solver workload: ground state, timed solve steps and, optionally,
+    its extras and the CPU baseline; returns the JSON object."""
     import numpy as np
     import torch
 
@@ -604,7 +597,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs the GPU"
     dev = torch.device("cuda:0")
-    wl = W.get(args.workload)
+    wl = W.get(wl_name)
     prec = msb.MSB_C128 if wl.dtype == "c128" else msb.MSB_C64
     cdt = torch.complex128 if prec == msb.MSB_C128 else torch.complex64
     log(f"workload {wl.name}: D={wl.dim} systems={wl.nrhs} shifts={len(wl.w_in)}")
@@ -728,13 +721,13 @@ def main():
         "ground_state": {"E_G": E_G, "lanczos_steps": gs_iters, "ms": round(gs_ms, 2)},
     }
 
-    if not args.no_extras and wl.nrhs > 1 and prec == msb.MSB_C64:
+    if extras and wl.nrhs > 1 and prec == msb.MSB_C64:
         out["batched"] = batched_extras(msb, ctx, wl, systems, E, psi, ms_per_step, args.tol, prec, E_G)
-    elif not args.no_extras and prec == msb.MSB_C64:
+    elif extras and prec == msb.MSB_C64:
         box = [psi]       # hand the only reference over so the c64 result can be freed
         del psi
         out["precision"] = precision_extras(msb, ctx, wl, systems, E, E_G, box, last, ms_per_step, args.tol)
-    elif not args.no_extras:
+    elif extras:
         # H-apply bandwidth: algorithmic bytes 2 D s per vector
         # H-apply rate: algorithmic bytes 2 D s R over the mean of 50 applies,
         # against the 8 TB/s spec and a device copy measured here
@@ -796,10 +789,27 @@ def main():
         log(f"spectrum {out['spectrum']}")
         del phi
 
-    if not args.no_cpu and prec == msb.MSB_C128:
+        # the multi-shift assembly engines on this step (one solve each; the
+        # default is the one the timed steps used)
+        engines = {}
+        for eng in range(5):
+            _, inf = msb.msb_solve(ctx, systems, E, wl.w_in, wl.seed_shift, args.tol, wl.maxit, prec, psi,
+                                   want_true=False, raise_on_fail=False, opts={"assembly_engine": eng})
+            ms = inf["t_gemm_ms"] / max(1, inf["n_gemm"])
+            engines[str(eng)] = {"ms": round(ms, 3),
+                                 "TFLOPs": round(inf["gemm_flops"] / max(1, inf["n_gemm"]) / (ms * 1e-3) / 1e12, 2)}
+        out["assembly_engines"] = {"note": "0: three real products per complex product (default); 1: FP64 "
+                                           "matrix cores; 2: four real products; 3, 4: variants of 0",
+                                   **engines}
+        log(f"assembly engines {out['assembly_engines']}")
+
+    if cpu and prec == msb.MSB_C128:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, last["iters"])
         log(f"cpu baseline {out['cpu_baseline']['value']:.3f} shift-solves/s")
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        out["cpu_baseline_all_cores"] = cpu_baseline(wl, last["iters"], threads=ncpu)
+        log(f"cpu baseline, {ncpu} threads: {out['cpu_baseline_all_cores']['value']:.3f} shift-solves/s")
 
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
@@ -811,6 +821,58 @@ def main():
         del src, dst
 
     msb.msb_destroy(ctx)
+    psi = None                      # (the precision extras already dropped their reference)
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="scale")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="scale workload: skip the precision and batched forms")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--train-spectra", type=int, default=4096, help="learned form: training spectra")
+    ap.add_argument("--heldout-spectra", type=int, default=256, help="learned form: held-out spectra")
+    ap.add_argument("--epochs", type=float, default=2.0, help="learned form: passes over the training set")
+    ap.add_argument("--mlp-train-steps", type=int, default=0,
+                    help="learned form: only time this many training steps on seeded random points")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "one GPU only: the solver has no multi-GPU path; run with --gpus 1"}))
+        sys.exit(2)
+    if args.workload == "learned" and args.mlp_train_steps > 0:
+        mlp_train_main(args)
+        return
+    if args.workload == "learned":
+        learned_main(args)
+        return
+    if args.workload == "reseed":
+        reseed_main(args)
+        return
+    if args.workload == "dipole":
+        dipole_main(args)
+        return
+
+    out = run_solver_workload(args.workload, args, extras=not args.no_extras, cpu=not args.no_cpu)
+    if args.workload == "scale" and not args.no_forms:
+        # the precision and batched forms beside the plain solver, each on its
+        # own workload, against complex128 (and separate solves)
+        import torch
+        fargs = argparse.Namespace(**dict(vars(args), steps=2, warmup=1))
+        out["forms"] = {}
+        for name in ("precision", "batched"):
+            log(f"form {name} ...")
+            sub = run_solver_workload(name, fargs, extras=True, cpu=False)
+            out["forms"][name] = form_summary(name, sub)
+            torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

@@ -172,7 +172,10 @@ typedef struct {
                             chunk is min(replace_every, 64). */
   int use_graph;         /* 0 or 1 = capture the chunk in a hipGraph (default), -1 = plain launches */
   double mem_fraction;   /* fraction of free device memory the workspace may use (default 0.9) */
-  int assembly_engine;   /* multi-shift assembly: 0 = FP64 vector ALU (default), 1 = FP64 matrix cores */
+  int assembly_engine;   /* multi-shift assembly, all in FP64: 0 = vector ALU with three real
+                            products per complex product (default), 1 = matrix cores, 2 = vector
+                            ALU with four real products, 3 / 4 = as 0 with 128 elements per
+                            workgroup / with eight wavefronts of four shifts each */
   int autotune;          /* 0 = tune the apply shape on first use (default), -1 = default shape
                             unless one was tuned or pinned before */
   int dual;              /* 0 = the dual-space (BiCG) form only when some system's A is not
@@ -181,10 +184,8 @@ typedef struct {
                             to its residual r_m in place and forms
                             A p_m = A r_m + beta_{m-1} A p_{m-1} in the same pass; MSB_C64 forms
                             p_m and applies A to it (Algorithm 1 as written); 1 = that direct
-                            form in both precisions; -1 = the recurred form in MSB_C64 too,
-                            with residual replacement only (A p is recomputed from the
-                            rebuilt p at every replacement; on hard systems its final true
-                            residuals are several times the direct form's) */
+                            form in both precisions.  Other values: MSB_EINVAL (a product
+                            carried in complex64 storage drifts from A p_m) */
 } msb_opts;
 
 /* ---- context -------------------------------------------------------------- */
@@ -277,7 +278,8 @@ msb_status msb_dipole(const msb_ctx* src, const msb_ctx* dst, int spin, int crea
  * The seed system is A_s - seed_shift I.  Shift k freezes once
  * |r_m| / |zeta_m(w_k)| <= tol |E_s|.  MSB_C64 runs the vectors in complex64
  * with FP64 reductions and scalars, and replaces the seed residual by the
- * FP64 true residual every opts->replace_every iterations.
+ * FP64 true residual every opts->replace_every iterations (the seed solution
+ * x_m that needs is rebuilt in FP64 from the residual bank at each replacement).
  * In MSB_C128 the seed by default carries A p_m by recurrence
  * (opts->direct_ap): the apply reads r_m in place from the residual bank and
  * writes A p_m = A r_m + beta_{m-1} A p_{m-1} over the previous product, so
@@ -361,6 +363,19 @@ msb_status msb_combine(msb_ctx* ctx, int nsys, int n_shift, msb_prec prec, const
 msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const void* phi, int n,
                         const double* w, int n_w, double eta, int lanczos_max,
                         double cf_tol, double* I, int* depth, void* stream);
+
+/* msb_spectrum that also returns the continued fraction it evaluated
+ * (Lanczos tridiagonalisation of H from each phi_k):
+ *   G_k(z) = b_0^2 / (z - a_0 - b_1^2 / (z - a_1 - b_2^2 / ...)),
+ *   a_i = <q_i|H|q_i>,  b_0 = |phi_k|,  b_i = |H q_{i-1} - a_{i-1} q_{i-1} - b_{i-1} q_{i-2}|
+ * with q_0 = phi_k / |phi_k| (a_0 and b_0^2, b_1^2 are the first spectral
+ * moments).  a, b: host [n][ld]; entries i < min(depth[k], ld) are written,
+ * the rest set to 0.  depth: host [n] (required).  Other arguments and errors
+ * as msb_spectrum; MSB_EINVAL if a, b or depth is NULL or ld < 1. */
+msb_status msb_spectrum_cf(msb_ctx* ctx, const msb_system* sys, const void* phi, int n,
+                           const double* w, int n_w, double eta, int lanczos_max,
+                           double cf_tol, double* I, int* depth, double* a, double* b, int ld,
+                           void* stream);
 
 /* ---- learned form: ensemble surrogate I(U, t', U_c, Gamma, w_in, w) --------
  * Not part of the paper's method: a regression network beside the solver,

@@ -124,6 +124,10 @@ def lib():
                                    c_int, c_double, c_int, c_double, POINTER(c_double),
                                    POINTER(c_int), c_void_p]
         L.msb_spectrum.restype = c_int
+        L.msb_spectrum_cf.argtypes = [c_void_p, POINTER(msb_system), c_void_p, c_int, POINTER(c_double),
+                                      c_int, c_double, c_int, c_double, POINTER(c_double),
+                                      POINTER(c_int), POINTER(c_double), POINTER(c_double), c_int, c_void_p]
+        L.msb_spectrum_cf.restype = c_int
         L.msb_autotune.argtypes = [c_void_p, c_int, c_int, POINTER(msb_shape), c_int, POINTER(c_int),
                                    c_void_p]
         L.msb_autotune.restype = c_int
@@ -156,7 +160,7 @@ def exported_symbols():
     return ["msb_create", "msb_destroy", "msb_release_workspace", "msb_dim", "msb_sector_info", "msb_last_error",
             "msb_device_ok", "msb_stream_create", "msb_stream_destroy", "msb_apply", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
             "msb_solve_reseed", "msb_dipole",
-            "msb_combine", "msb_spectrum", "msb_autotune", "msb_set_shape",
+            "msb_combine", "msb_spectrum", "msb_spectrum_cf", "msb_autotune", "msb_set_shape",
             "msb_mlp_num_params", "msb_mlp_create", "msb_mlp_destroy", "msb_mlp_set_params",
             "msb_mlp_get_params", "msb_mlp_grad", "msb_mlp_train", "msb_mlp_predict", "msb_mlp_fallback"]
 
@@ -462,6 +466,26 @@ def msb_spectrum(ctx, system, phi, w, eta: float, lanczos_max: int, cf_tol: floa
                               int(lanczos_max), float(cf_tol), I.ctypes.data_as(POINTER(c_double)),
                               depth.ctypes.data_as(POINTER(c_int)), _stream_ptr(stream)))
     return I, depth
+
+
+def msb_spectrum_cf(ctx, system, phi, w, eta: float, lanczos_max: int, cf_tol: float, ld: int, stream=None):
+    """msb_spectrum plus its continued fraction: returns (I [n, n_w], depth [n],
+    a [n, ld], b [n, ld]) with b[:, 0] = |phi| (numpy)."""
+    import numpy as np
+    import torch
+    D = msb_dim(ctx)
+    n = phi.numel() // D
+    wv = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    I = np.zeros((n, len(wv)), dtype=np.float64)
+    depth = np.zeros(n, dtype=np.int32)
+    a = np.zeros((n, ld), dtype=np.float64)
+    b = np.zeros((n, ld), dtype=np.float64)
+    _check(lib().msb_spectrum_cf(ctx, ctypes.byref(system), _ptr(phi, torch.complex128, n * D, "phi"),
+                                 n, wv.ctypes.data_as(POINTER(c_double)), len(wv), float(eta),
+                                 int(lanczos_max), float(cf_tol), I.ctypes.data_as(POINTER(c_double)),
+                                 depth.ctypes.data_as(POINTER(c_int)), a.ctypes.data_as(POINTER(c_double)),
+                                 b.ctypes.data_as(POINTER(c_double)), int(ld), _stream_ptr(stream)))
+    return I, depth, a, b
 
 
 def msb_autotune(ctx, nsys: int, prec: int, stream=None):

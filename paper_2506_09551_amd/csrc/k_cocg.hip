@@ -66,6 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_init(InitArgs a) {
           Ax::store(Ax::offset(a.pt, (int64_t)s * a.D), i, xs);
         }
         if (a.xseed) A64::store(a.xseed, (int64_t)s * a.D + i, cv<double>{0.0, 0.0});
+        if (a.psnap) Ax::store(Ax::offset(a.psnap, (int64_t)s * a.D), i, xs);
         part[0] += xs.re * xs.re - xs.im * xs.im;
         part[1] += 2.0 * xs.re * xs.im;
         part[2] += xs.re * xs.re + xs.im * xs.im;
@@ -288,8 +289,9 @@ __global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
   }
 }
 
-// Seed solution and last direction rebuilt from the bank slots (recurred
-// form with residual replacement); one pass over the L slots per element.
+// Seed solution and last direction rebuilt from the bank slots at a residual
+// replacement (recurred form: into p itself; direct form: into a copy of p
+// kept for the next rebuild); one pass over the L slots per element.
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_seed_rebuild(RebuildArgs a) {
   using Ax = Access<S, true>;

@@ -27,16 +27,25 @@ __global__ __launch_bounds__(kBlock) void k_coef(CoefArgs a, double* scratch) {
   const int j = tid % a.n_list;
   // coefficient tables are slot-major, [s][l][j] complex: for one slot the
   // shifts of a tile are adjacent (one scalar load serves a wavefront's shifts)
-  const int64_t cstride = (int64_t)a.n_list * 2;
-  double* crow = a.coef + ((int64_t)s * a.K * a.n_list + j) * 2;
-  double* grow = a.gcoef ? a.gcoef + ((int64_t)s * a.K * a.n_list + j) * 2 : nullptr;
+  // entries of ncomp doubles: (c_re, c_im), or for the three-product assembly
+  // (c_re, c_re + c_im, c_im - c_re)
+  const int nc = a.ncomp;
+  const int64_t cstride = (int64_t)a.n_list * nc;
+  double* crow = a.coef + ((int64_t)s * a.K * a.n_list + j) * nc;
+  double* grow = a.gcoef ? a.gcoef + ((int64_t)s * a.K * a.n_list + j) * nc : nullptr;
   double* zrow = scratch + (int64_t)tid * a.K * 4;    // (zeta_l, bw_l)
   const int k = a.list[tid];
   const int lend = (k >= 0) ? a.lend[tid] : 0;
-  for (int l = lend; l < a.K; ++l) {
-    crow[cstride * l] = crow[cstride * l + 1] = 0.0;
-    if (grow) grow[cstride * l] = grow[cstride * l + 1] = 0.0;
-  }
+  for (int l = lend; l < a.K; ++l)
+    for (int c = 0; c < nc; ++c) {
+      crow[cstride * l + c] = 0.0;
+      if (grow) grow[cstride * l + c] = 0.0;
+    }
+  auto put = [nc](double* e, cv<double> v) {
+    e[0] = v.re;
+    e[1] = nc == 3 ? v.re + v.im : v.im;
+    if (nc == 3) e[2] = v.im - v.re;
+  };
   double* ab = a.ab + (int64_t)tid * 4;
   ab[0] = ab[1] = ab[2] = ab[3] = 0.0;
   if (k < 0 || lend <= 0) return;
@@ -85,14 +94,8 @@ __global__ __launch_bounds__(kBlock) void k_coef(CoefArgs a, double* scratch) {
       S = aw;
     }
     const cv<double> zl = {zrow[4 * l], zrow[4 * l + 1]};
-    const cv<double> c = cdiv(S, zl);
-    crow[cstride * l] = c.re;
-    crow[cstride * l + 1] = c.im;
-    if (grow) {
-      const cv<double> g = carry ? cdiv(G, zl) : cv<double>{0.0, 0.0};
-      grow[cstride * l] = g.re;
-      grow[cstride * l + 1] = g.im;
-    }
+    put(crow + cstride * l, cdiv(S, zl));
+    if (grow) put(grow + cstride * l, carry ? cdiv(G, zl) : cv<double>{0.0, 0.0});
   }
   if (a.base > 0) {
     const cv<double> b0 = {zrow[2], zrow[3]};
@@ -126,11 +129,30 @@ hipError_t launch_coef(const CoefArgs& a, double* scratch, hipStream_t st) {
 // consecutive shift slots over the same 64 elements, so residual loads are
 // shared through L1.  Workgroups of one element tile are issued back to back on
 // one XCD so the residual tile is read from HBM once and from L2 afterwards.
-constexpr int kFlushM = 16;       // shifts per wavefront (MFMA rows / VALU shift tile)
+constexpr int kFlushM = 16;       // shifts per wavefront (MFMA rows)
 constexpr int kFlushNT = 4;       // 16-element MFMA tiles per wavefront
 constexpr int kFlushWaves = kBlock / kWave;
-int flush_shifts_per_tile(int engine) { return engine == 1 ? kFlushM * kFlushWaves : 8 * kFlushWaves; }
-int flush_elems_per_tile(int engine) { return engine == 1 ? 16 * kFlushNT : kWave * 4; }
+// Three-product (default) engine variants: shift slots per wavefront,
+// elements per lane and wavefronts per workgroup.  Every VALU engine covers
+// 32 shift slots per workgroup.
+struct GaussShape {
+  int M, EPL, NW;
+};
+__host__ __device__ constexpr GaussShape gauss_shape(int engine) {
+  return engine == 3 ? GaussShape{8, 2, 4} : engine == 4 ? GaussShape{4, 4, 8} : GaussShape{8, 4, 4};
+}
+int flush_shifts_per_tile(int engine) {
+  if (engine == 1) return kFlushM * kFlushWaves;
+  if (engine == 2) return 8 * kFlushWaves;
+  const GaussShape g = gauss_shape(engine);
+  return g.M * g.NW;
+}
+int flush_elems_per_tile(int engine) {
+  if (engine == 1) return 16 * kFlushNT;
+  if (engine == 2) return kWave * 4;
+  return kWave * gauss_shape(engine).EPL;
+}
+int flush_coef_comps(int engine) { return (engine == 1 || engine == 2) ? 2 : 3; }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -389,13 +411,184 @@ __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double
   }
 }
 
+// Three-product form (the default engine).  With s = r_re + r_im per element
+// (one add, shared by the wavefront's shifts) and the table entry
+// (c_re, c_re + c_im, c_im - c_re) precomputed by k_coef,
+//   c r = [c_re s - (c_re + c_im) r_im] + i [c_re s + (c_im - c_re) r_re],
+// so each (shift, element, slot) costs three FMAs into three accumulators
+// (A1 += c_re s, A2 += (c_re + c_im) r_im, A3 += (c_im - c_re) r_re;
+// re = A1 - A2, im = A1 + A3) instead of the four of the plain complex
+// product.  Tiling as k_flush_valu: a workgroup owns M * NW shift slots and
+// 64 * EPL elements; residual slots are staged in LDS in chunks of kValuKT
+// (straight from memory with a complex128 bank, double-buffered), the table
+// entries are wave-uniform scalar loads, prefetched one slot ahead.
+template <typename SB, typename SO, int M, int EPL, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const double* __restrict__ coef,
+                                                             int ow_mode) {
+  using AB = Access<SB, true>;
+  using AO = Access<SO, true>;
+  constexpr int KT = kValuKT;
+  constexpr int TILE = kWave * EPL;                       // elements of the workgroup
+  constexpr int NS = M * NW;                              // shift slots of the workgroup
+  constexpr int ROWS = KT * EPL;                          // 64-element rows of one staged chunk
+  __shared__ cv<double> rt[KT][TILE];
+  __shared__ cv<double> rt2[std::is_same<SB, double>::value ? KT : 1][TILE];
+
+  const int s = blockIdx.y;
+  const int b = blockIdx.x;
+  const int xcd = b % kNumXcd, q = b / kNumXcd;
+  const int et = xcd + kNumXcd * (q / a.n_stiles);
+  const int stt = q % a.n_stiles;
+  if (et >= a.n_etiles) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int Kext = a.tile_k[s * a.n_stiles + stt];
+  const int64_t e0 = (int64_t)et * TILE;
+  const int64_t last_e = a.D - 1;
+  const void* bank_s = AB::offset(a.bank, (int64_t)s * a.cap * a.D);
+  const int slot0 = stt * NS + wave * M;
+  const int Kw = a.lend ? __builtin_amdgcn_readfirstlane(a.lend[s * a.n_list + slot0]) : Kext;
+  typedef __attribute__((address_space(4))) const double cdouble;
+  cdouble* crow = (cdouble*)(coef + ((int64_t)s * a.K * a.n_list + slot0) * 3);   // slot-major
+
+  double A1[M][EPL], A2[M][EPL], A3[M][EPL];
+#pragma unroll
+  for (int t = 0; t < M; ++t)
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) A1[t][e] = A2[t][e] = A3[t][e] = 0.0;
+
+  struct C3 {
+    double r, sum, dif;
+  };
+  auto load_c = [&](int l, C3 (&c)[M]) {
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      const int64_t o = ((int64_t)l * a.n_list + t) * 3;
+      c[t] = {crow[o], crow[o + 1], crow[o + 2]};
+    }
+  };
+  // the next slot's entries are requested before the current slot's FMAs
+  // while they fit the scalar registers twice over (M <= 4); with more shifts
+  // per wavefront each slot loads its own
+  constexpr bool kPrefetch = M <= 4;
+  auto run = [&](const cv<double> (*buf)[TILE], int kb, int kn) {
+    C3 c_cur[M], c_nxt[kPrefetch ? M : 1];
+    const int kw = min(kn, Kw - kb);                      // wave-uniform; may be <= 0
+    if (kPrefetch && kw > 0) load_c(kb, c_cur);
+    for (int kk = 0; kk < kw; ++kk) {
+      if constexpr (kPrefetch) {
+        if (kk + 1 < kw) load_c(kb + kk + 1, c_nxt);
+      } else {
+        load_c(kb + kk, c_cur);
+      }
+      double rr[EPL], ri[EPL], sm[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const cv<double> r = buf[kk][lane + kWave * e];
+        rr[e] = r.re;
+        ri[e] = r.im;
+        sm[e] = r.re + r.im;
+      }
+#pragma unroll
+      for (int t = 0; t < M; ++t)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          A1[t][e] = fma(c_cur[t].r, sm[e], A1[t][e]);
+          A2[t][e] = fma(c_cur[t].sum, ri[e], A2[t][e]);
+          A3[t][e] = fma(c_cur[t].dif, rr[e], A3[t][e]);
+        }
+      if constexpr (kPrefetch) {
+#pragma unroll
+        for (int t = 0; t < M; ++t) c_cur[t] = c_nxt[t];
+      }
+    }
+  };
+  if constexpr (std::is_same<SB, double>::value) {
+    // complex128 bank: 64-element rows straight from memory to LDS, the next
+    // chunk in flight while the FMAs of the current one run
+    const cv<double>* bank_c = reinterpret_cast<const cv<double>*>(bank_s);
+    auto stage = [&](cv<double> (*buf)[TILE], int kb) {
+      const int kn = min(KT, Kext - kb);
+      for (int row = wave; row < ROWS; row += NW) {
+        const int j = row / EPL, eg = row % EPL;
+        const int kc = kb + (j < kn ? j : kn - 1);        // clamped: its coefficient is never used
+        int64_t e = e0 + eg * kWave + lane;
+        e = e < last_e ? e : last_e;                      // clamped: feeds only unstored outputs
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(bank_c + (int64_t)kc * a.D + e),
+                                         (__attribute__((address_space(3))) void*)&buf[j][eg * kWave],
+                                         16, 0, 0);
+      }
+    };
+    if (Kext > 0) stage(rt, 0);
+    for (int kb = 0; kb < Kext; kb += 2 * KT) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (kb + KT < Kext) stage(rt2, kb + KT);
+      run(rt, kb, min(KT, Kext - kb));
+      if (kb + KT >= Kext) break;
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (kb + 2 * KT < Kext) stage(rt, kb + 2 * KT);
+      run(rt2, kb + KT, min(KT, Kext - kb - KT));
+    }
+  } else {
+    for (int kb = 0; kb < Kext; kb += KT) {
+      const int kn = min(KT, Kext - kb);
+      for (int row = wave; row < ROWS; row += NW) {
+        const int j = row / EPL, eg = row % EPL;
+        const int kc = kb + (j < kn ? j : kn - 1);
+        int64_t e = e0 + eg * kWave + lane;
+        e = e < last_e ? e : last_e;
+        rt[j][eg * kWave + lane] = AB::template load<double>(bank_s, (int64_t)kc * a.D + e);
+      }
+      __syncthreads();
+      run(rt, kb, kn);
+      __syncthreads();
+    }
+  }
+
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    const int slot = slot0 + t;
+    const int k = a.list[s * a.n_list + slot];
+    if (k < 0) continue;
+    cv<double> ow = {0.0, 0.0}, pw = {0.0, 0.0};
+    if (ow_mode == 1) ow = {1.0, 0.0};
+    if (ow_mode == 2) {
+      const double* o = a.ow + ((int64_t)s * a.n_list + slot) * a.ow_stride;
+      ow = {o[0], o[1]};
+    }
+    if (a.pw) {
+      const double* p = a.pw + ((int64_t)s * a.n_list + slot) * a.pw_stride;
+      pw = {p[0], p[1]};
+    }
+    const int64_t obase = ((int64_t)s * a.n_shift + k) * a.D;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int64_t i = e0 + lane + kWave * e;
+      if (i >= a.D) continue;
+      cv<double> v = {A1[t][e] - A2[t][e], A1[t][e] + A3[t][e]};
+      if (ow_mode != 0) v = cadd(v, cmul(ow, AO::template load<double>(a.out, obase + i)));
+      if (a.X) v = cadd(v, cmul(pw, AO::template load<double>(a.X, obase + i)));
+      AO::store(a.out, obase + i, v);
+    }
+  }
+}
+
 hipError_t launch_flush(Elem eb, Elem eo, const FlushArgs& a, int ow_mode, int engine,
                         hipStream_t st) {
   const int per_xcd = (a.n_etiles + kNumXcd - 1) / kNumXcd;
   dim3 grid(per_xcd * kNumXcd * a.n_stiles, a.nsys);
+  if (engine < 0 || engine >= kNumFlushEngines) return hipErrorInvalidValue;
+#define MSB_GAUSS(SB, SO, E)                                                                   \
+  hipLaunchKernelGGL((k_flush_gauss<SB, SO, gauss_shape(E).M, gauss_shape(E).EPL, gauss_shape(E).NW>), grid, \
+                     dim3(gauss_shape(E).NW * kWave), 0, st, a, a.coef, ow_mode);
 #define MSB_FLUSH(SB, SO)                                                                      \
   if (engine == 1) hipLaunchKernelGGL((k_flush_mfma<SB, SO>), grid, dim3(kBlock), 0, st, a, ow_mode); \
-  else hipLaunchKernelGGL((k_flush_valu<SB, SO>), grid, dim3(kBlock), 0, st, a, a.coef, ow_mode);
+  else if (engine == 2) hipLaunchKernelGGL((k_flush_valu<SB, SO>), grid, dim3(kBlock), 0, st, a, a.coef, ow_mode); \
+  else if (engine == 3) { MSB_GAUSS(SB, SO, 3) }                                               \
+  else if (engine == 4) { MSB_GAUSS(SB, SO, 4) }                                               \
+  else { MSB_GAUSS(SB, SO, 0) }
   if (eb == Elem::C128 && eo == Elem::C128) {
     MSB_FLUSH(double, double)
   } else if (eb == Elem::C64 && eo == Elem::C64) {
@@ -406,6 +599,7 @@ hipError_t launch_flush(Elem eb, Elem eo, const FlushArgs& a, int ow_mode, int e
     return hipErrorInvalidValue;
   }
 #undef MSB_FLUSH
+#undef MSB_GAUSS
   return hipGetLastError();
 }
 

@@ -761,6 +761,7 @@ struct SolveBufs {
   double* cscr = nullptr;
   double* ab = nullptr;
   double* xseed = nullptr;      // residual replacement: seed solution [B][D] c128
+  void* psnap = nullptr;        // residual replacement, direct form: p at the last rebuild [B][D]
   double* wrep = nullptr;       // residual replacement: A_s x [B][D] c128
   double* rcoef = nullptr;      // residual replacement, recurred form: rebuild coefficients
   SysDev* tsys = nullptr;       // true-residual systems
@@ -801,12 +802,13 @@ struct SolveBufs {
     dlist = c.take<int>((size_t)B * n_list * sizeof(int));
     dlend = c.take<int>((size_t)B * n_list * sizeof(int));
     dtile = c.take<int>((size_t)B * (n_stiles + 1) * sizeof(int));
-    coef = c.take<double>((size_t)B * n_list * cap * 2 * sizeof(double));
-    gcoef = carry ? c.take<double>((size_t)B * n_list * cap * 2 * sizeof(double)) : nullptr;
+    coef = c.take<double>((size_t)B * n_list * cap * 3 * sizeof(double));   // up to 3 doubles per entry
+    gcoef = carry ? c.take<double>((size_t)B * n_list * cap * 3 * sizeof(double)) : nullptr;
     cscr = c.take<double>((size_t)B * n_list * cap * 4 * sizeof(double));
     ab = c.take<double>((size_t)B * n_list * 4 * sizeof(double));
     if (replace) {
       xseed = c.take<double>((size_t)B * D * 16);
+      psnap = c.take<void>((size_t)B * D * s_el);
       wrep = c.take<double>((size_t)B * D * 16);
       rcoef = c.take<double>((size_t)B * 2 * (cap + 1) * 2 * sizeof(double));
     }
@@ -861,7 +863,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   const Elem eo = ev;
   const int64_t D = ctx->D;
   const int mx = std::max(maxit, 1);
-  const int engine = (opts && opts->assembly_engine == 1) ? 1 : 0;
+  const int engine = opts ? opts->assembly_engine : 0;
+  if (engine < 0 || engine >= kNumFlushEngines) return fail(MSB_EINVAL, "msb_solve: unknown assembly engine");
   const int tile_s = flush_shifts_per_tile(engine);
   const int n_list = ((n_shift + tile_s - 1) / tile_s) * tile_s;
   const size_t s_el = elem_bytes(ev), s_out = elem_bytes(eo);
@@ -883,7 +886,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   // with it the final true residuals of hard systems are several times the
   // direct form's)
   const int dap = opts ? opts->direct_ap : 0;
-  const bool recur = !dual && dap != 1 && (prec == MSB_C128 || (dap == -1 && replace_every > 0));
+  if (dap < 0) return fail(MSB_EINVAL, "msb_solve: direct_ap must be 0 or 1 (the recurred seed form runs in "
+                                        "complex128 only)");
+  const bool recur = !dual && dap != 1 && prec == MSB_C128;
   if (dual) {
     if (prec != MSB_C128) return fail(MSB_EINVAL, "msb_solve: the dual-space form runs in complex128");
     hsysT.resize(nsys);
@@ -1042,6 +1047,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ia.cap = cap; ia.D = D; ia.nbx = cocg_nbx(D, nb); ia.nsys = nb; ia.n_shift = n_shift; ia.zeta = zeta;
     ia.zeta_prev = zeta_prev; ia.conv_iter = conv; ia.rnorm_log = rlog; ia.maxit = mx;
     ia.xseed = bf.xseed;
+    ia.psnap = recur ? nullptr : bf.psnap;
     ia.rt = dual ? bf.rt : nullptr;
     ia.pt = dual ? bf.pt : nullptr;
     MSB_HIP(launch_cocg_init(ev, ia, st));
@@ -1085,8 +1091,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     ca.rt = dual ? bf.rt : nullptr;
     ca.pt = dual ? bf.pt : nullptr;
     ca.vt = dual ? bf.vt : nullptr;
-    // recurred form: x is rebuilt from the bank at each replacement
-    if (recur) ca.xseed = nullptr;
+    // x is rebuilt from the bank at each replacement, not updated every iteration
+    ca.xseed = nullptr;
 
     int base = 0;
     bool first_flush = true;
@@ -1128,6 +1134,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       cf.st = dst; cf.alpha_log = alog; cf.beta_log = blog; cf.wshift = wshift; cf.conv_iter = conv;
       cf.list = dlist; cf.lend = dlend; cf.coef = coef; cf.gcoef = carry ? gcoef : nullptr; cf.ab = ab;
       cf.nsys = nb; cf.n_shift = n_shift; cf.n_list = n_list; cf.maxit = mx; cf.K = Kc; cf.base = base;
+      cf.ncomp = flush_coef_comps(engine);
       MSB_HIP(launch_coef(cf, cscr, st));
       FlushArgs fa;
       fa.bank = bank; fa.cap = cap; fa.coef = coef; fa.pw = nullptr; fa.ow = nullptr;
@@ -1297,7 +1304,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     int m0 = 0;
     std::vector<double> hal, hbl, hcoef;
     auto rebuild = [&](int m_now) -> msb_status {
-      if (!recur || !bf.xseed) return MSB_OK;   // the direct form updates x every iteration
+      if (!bf.xseed) return MSB_OK;             // no residual replacement
       const int L = m_now - m0;
       if (L <= 0) return MSB_OK;
       if (m0 < base || L > cap) return fail(MSB_EINVAL, "internal: rebuild range outside the bank");
@@ -1340,7 +1347,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       MSB_HIP(hipMemcpyAsync(bf.rcoef, hcoef.data(), hcoef.size() * sizeof(double), hipMemcpyHostToDevice, st));
       RebuildArgs rb;
       rb.bank = bank; rb.cap = cap; rb.slot0 = m0 - base; rb.L = L; rb.D = D; rb.nbx = cocg_nbx(D, nb);
-      rb.nsys = nb; rb.coef = bf.rcoef; rb.x = bf.xseed; rb.p = pvec; rb.st = dst;
+      // the recurred form keeps no explicit p: the rebuilt p_{m-1} goes to pvec;
+      // the direct form forms p every iteration and rebuilds a copy of it
+      rb.nsys = nb; rb.coef = bf.rcoef; rb.x = bf.xseed; rb.p = recur ? pvec : bf.psnap; rb.st = dst;
       MSB_HIP(launch_seed_rebuild(ev, rb, st));
       MSB_HIP(hipStreamSynchronize(st));    // hcoef is reused by the next rebuild
       m0 = m_now;
@@ -1655,9 +1664,12 @@ extern "C" msb_status msb_combine(msb_ctx* ctx, int nsys, int n_shift, msb_prec 
 // =============================================================================
 // Continued-fraction spectrum: a block of independent Hermitian Lanczos
 // recurrences on H, one per vector phi_k.
-extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const void* phi, int n,
-                                   const double* w, int n_w, double eta, int lanczos_max,
-                                   double cf_tol, double* I, int* depth_out, void* stream) {
+// Block Lanczos continued fraction behind msb_spectrum and msb_spectrum_cf;
+// coef_a / coef_b (host [n][coef_ld], optional) receive the coefficients.
+static msb_status spectrum_impl(msb_ctx* ctx, const msb_system* sys, const void* phi, int n,
+                                const double* w, int n_w, double eta, int lanczos_max,
+                                double cf_tol, double* I, int* depth_out, double* coef_a,
+                                double* coef_b, int coef_ld, void* stream) {
   (void)hipGetLastError();   // do not report an earlier call's failure
   if (!ctx || !sys || !phi || !w || !I) return fail(MSB_EINVAL, "msb_spectrum: null argument");
   if (n <= 0 || n > 65535 || n_w <= 0) return fail(MSB_EINVAL, "msb_spectrum: sizes out of range");
@@ -1814,7 +1826,32 @@ extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const vo
   std::memcpy(I, Icur.data(), Icur.size() * sizeof(double));
   if (depth_out)
     for (int j = 0; j < n; ++j) depth_out[j] = depth[j];
+  if (coef_a && coef_b) {
+    // u_0 = phi, u_{k+1} = H q_k - a_k q_k - |u_k| q_{k-1} with q_k = u_k / |u_k|:
+    // the logged |u_k| are b_0 = |phi| and the normalised recurrence's b_k
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < coef_ld; ++k) {
+        const bool in = k < depth[j];
+        coef_a[(size_t)j * coef_ld + k] = in ? alog[(size_t)j * ld + k] : 0.0;
+        coef_b[(size_t)j * coef_ld + k] = in ? blog[(size_t)j * ld + k] : 0.0;
+      }
+  }
   return MSB_OK;
+}
+
+extern "C" msb_status msb_spectrum(msb_ctx* ctx, const msb_system* sys, const void* phi, int n,
+                                   const double* w, int n_w, double eta, int lanczos_max,
+                                   double cf_tol, double* I, int* depth_out, void* stream) {
+  return spectrum_impl(ctx, sys, phi, n, w, n_w, eta, lanczos_max, cf_tol, I, depth_out, nullptr, nullptr, 0,
+                       stream);
+}
+
+extern "C" msb_status msb_spectrum_cf(msb_ctx* ctx, const msb_system* sys, const void* phi, int n,
+                                      const double* w, int n_w, double eta, int lanczos_max,
+                                      double cf_tol, double* I, int* depth, double* a, double* b, int ld,
+                                      void* stream) {
+  if (!a || !b || !depth || ld < 1) return fail(MSB_EINVAL, "msb_spectrum_cf: coefficient arrays missing");
+  return spectrum_impl(ctx, sys, phi, n, w, n_w, eta, lanczos_max, cf_tol, I, depth, a, b, ld, stream);
 }
 
 // =============================================================================

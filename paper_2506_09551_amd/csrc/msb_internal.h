@@ -266,6 +266,7 @@ struct InitArgs {
   double* rnorm_log;
   int maxit;
   double* xseed;                // optional: zeroed
+  void* psnap;                  // optional: set to E (the direct form's copy of p for x rebuilds)
   void* rt;                     // optional (dual-space form): r~_0 = p~_0 = E
   void* pt;
 };
@@ -280,17 +281,19 @@ struct CoefArgs {
   const int* conv_iter;         // [nsys][n_shift]
   const int* list;              // [nsys][n_list] shift index per sorted slot (-1 = empty)
   const int* lend;              // [nsys][n_list] end of the shift's range within the block
-  double* coef;                 // [nsys][K][n_list][2]   Psi coefficients of r_base+l
-  double* gcoef;                // [nsys][K][n_list][2]   p coefficients (carry) or null
+  double* coef;                 // [nsys][K][n_list][ncomp]   Psi coefficients of r_base+l
+  double* gcoef;                // [nsys][K][n_list][ncomp]   p coefficients (carry) or null
   double* ab;                   // [nsys][n_list][4]: (a_re,a_im) = p_prev weight in Psi, (h_re,h_im) in p
   int nsys, n_shift, n_list, maxit, K, base;
+  int ncomp;                    // 2: (c_re, c_im); 3: (c_re, c_re + c_im, c_im - c_re) for the
+                                //   three-product assembly (flush_coef_comps(engine))
 };
 hipError_t launch_coef(const CoefArgs& a, double* scratch /*[nsys*n_list][K][4]*/, hipStream_t st);
 
 struct FlushArgs {
   const void* bank;             // [nsys][cap][D]
   int cap;
-  const double* coef;           // [nsys][K][n_list][2] (slot-major)
+  const double* coef;           // [nsys][K][n_list][flush_coef_comps(engine)] (slot-major)
   const double* pw;             // [nsys][n_list][2]: weight of X (p_prev) term, or null
   const double* ow;             // [nsys][n_list][2]: weight of old output, or null (= 0)
   int pw_stride, ow_stride;     // doubles between consecutive entries of pw / ow
@@ -304,11 +307,16 @@ struct FlushArgs {
   int n_etiles, n_stiles;
 };
 // ow_mode: 0 = old output ignored, 1 = weight 1, 2 = per-shift weights from ow
-// engine: 0 = FP64 vector-ALU kernel, 1 = FP64 matrix-core kernel
+// engine: 0 = FP64 vector ALU, three real products per complex product (the
+// default), 1 = FP64 matrix cores, 2 = FP64 vector ALU, four real products,
+// 3 = as 0 with half the elements per workgroup, 4 = as 0 with eight
+// wavefronts of four shifts
+constexpr int kNumFlushEngines = 5;
 hipError_t launch_flush(Elem bank, Elem out, const FlushArgs& a, int ow_mode, int engine,
                         hipStream_t st);
 int flush_shifts_per_tile(int engine);
 int flush_elems_per_tile(int engine);
+int flush_coef_comps(int engine);   // doubles per coefficient table entry (2 or 3)
 
 // ---- Lanczos helpers (k_lanczos.hip) -----------------------------------------
 // Generic last-block reductions and axpy-style updates used by the ground

@@ -63,3 +63,46 @@ def test_spectrum_matches_lehmann(gpu):
         assert np.all(I > -1e-12 * np.max(ref))
     finally:
         msb.msb_destroy(ctx)
+
+
+def test_tiny_pipeline_end_to_end_at_1e10(gpu):
+    """The tiny workload whole, on its own inputs: GPU Lanczos ground state
+    from the seeded start, E = G, all 64 incident energies at tol 1e-13, the
+    continued fraction on all 256 losses -- against dense eigh, the exact
+    solves and the Lehmann sum of the oracle (its own ground state, aligned in
+    sign), to 1e-10 relative."""
+    import torch
+    from oracle import solve as osolve
+    msb = gpu
+    wl = W.get("tiny")
+    m = dict(L=wl.n_sites, nu=wl.n_up, nd=wl.n_dn, bonds=wl.bonds, U=wl.U)
+    ctx = msb.msb_create(wl.n_sites, wl.n_up, wl.n_dn, wl.bonds, wl.U)
+    try:
+        D = msb.msb_dim(ctx)
+        x0 = torch.from_numpy(W.random_vector(D, wl.gs_seed)).cuda()
+        G = torch.empty(D, dtype=torch.float64, device="cuda")
+        E_G, _ = msb.msb_ground_state(ctx, msb.make_system(), x0, 1e-13, 1000, G)
+        E = G.to(torch.complex128).reshape(1, D).contiguous()
+        sysd = msb.make_system(core_site=wl.core_sites[0], Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma)
+        psi = torch.empty(1, len(wl.w_in), D, dtype=torch.complex128, device="cuda")
+        _, info = msb.msb_solve(ctx, [sysd], E, wl.w_in, 0.0, 1e-13, 3000, msb.MSB_C128, psi, want_true=True)
+        phi = torch.empty(len(wl.w_in), D, dtype=torch.complex128, device="cuda")
+        msb.msb_combine(ctx, psi, 1, len(wl.w_in), msb.MSB_C128, [1.0], phi)
+        I, _ = msb.msb_spectrum(ctx, msb.make_system(E_G=E_G), phi, wl.w_loss, wl.eta, 3000, 1e-13)
+
+        H = oracle_H(m).toarray()
+        ev, V = np.linalg.eigh(H)
+        # the oracle's own ground state, signed as the library signs G: <x0|G> >= 0
+        G_ref = V[:, 0] * np.sign(np.dot(W.random_vector(D, wl.gs_seed), V[:, 0]))
+        assert abs(E_G - ev[0]) <= 1e-12 * abs(ev[0])
+        Hp = oracle_H(m, core_site=wl.core_sites[0], Uc=wl.Uc)
+        ref_psi = osolve.direct_solve(Hp, G_ref.astype(complex), ev[0], wl.Gamma, wl.w_in, method="eig")
+        p = psi[0].cpu().numpy()
+        err_psi = np.linalg.norm(p - ref_psi, axis=1) / np.linalg.norm(ref_psi, axis=1)
+        assert err_psi.max() <= 1e-10, err_psi.max()
+        assert np.max(info["resid_true"]) <= 1e-12
+        ref_I = ospec.lehmann(ev, V, ref_psi, ev[0], wl.w_loss, wl.eta)
+        err_I = np.max(np.abs(I - ref_I)) / np.max(np.abs(ref_I))
+        assert err_I <= 1e-10, err_I
+    finally:
+        msb.msb_destroy(ctx)

@@ -143,3 +143,37 @@ def test_training_fits_smooth_target(gpu):
         assert err <= 0.1 * np.sqrt(np.mean(T ** 2))
     finally:
         msb.msb_mlp_destroy(mlp)
+
+
+def test_adam_update_on_a_known_gradient(gpu):
+    """Adam (float32 on the GPU) against the oracle's update computed from the
+    gradient the GPU itself reports for the same points (msb_mlp_grad), over
+    two steps, so bias correction, beta_1, beta_2 and eps all enter: equal to
+    float32 rounding of the parameters plus 2e-5 lr (the float32 constants
+    0.9f, 0.999f move 1 - beta_2^k by 1.3e-5 relative)."""
+    import torch
+    msb = gpu
+    lr = 1e-3
+    mlp = _make(msb, 1)
+    try:
+        p0 = W.mlp_init(71)
+        msb.msb_mlp_set_params(mlp, 0, p0)
+        n = 256
+        perm = torch.arange(n, dtype=torch.int32, device="cuda").reshape(1, n)
+        p_prev = p0.astype(np.float64)
+        m = np.zeros_like(p_prev)
+        v = np.zeros_like(p_prev)
+        for k, seed in ((1, 31), (2, 32)):
+            X, T = _inputs(n, seed)
+            Xt, Tt = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+            _, g = msb.msb_mlp_grad(mlp, 0, Xt, Tt)          # gradient at the current parameters
+            msb.msb_mlp_train(mlp, Xt, Tt, perm, n, 1, lr, 1)  # one Adam step on the same points
+            got = msb.msb_mlp_get_params(mlp, 0).astype(np.float64)
+            want, m, v = omlp.adam_step(p_prev, g.astype(np.float64), m, v, k, lr)
+            tol = 2.0 * np.spacing(np.abs(want).astype(np.float32)).astype(np.float64) + 2e-5 * lr
+            bad = np.abs(got - want) > tol
+            assert not np.any(bad), (k, int(bad.sum()), float(np.max(np.abs(got - want))))
+            assert np.max(np.abs(got - p_prev)) > 0.5 * lr        # the step moved the parameters
+            p_prev = got
+    finally:
+        msb.msb_mlp_destroy(mlp)

@@ -127,11 +127,13 @@ def test_large_batch_runs_in_two_parts(tiny, case):
     """Nine systems (the recurred seed then runs as two parts of 4 and 5 on two
     streams): every shift of every system against its direct solve, and the
     same iterations per system as the direct form, which runs unsplit; also
-    with bank restarts and in complex64 with residual replacement."""
+    with bank restarts and in complex64 with residual replacement, in the
+    direct seed form (complex64 always runs that form)."""
     msb, ctx, wl, m = tiny
     opts = {"small_bank": {"bank_slots": 40}, "c64_replace": {"replace_every": 20}}.get(case, {})
-    prec = msb.MSB_C64 if case == "c64_replace" else msb.MSB_C128
-    tol, bar = (1e-6, 5e-5) if case == "c64_replace" else (1e-12, 1e-9)
+    c64 = case.startswith("c64")
+    prec = msb.MSB_C64 if c64 else msb.MSB_C128
+    tol, bar = (1e-6, 5e-5) if c64 else (1e-12, 1e-9)
     D = msb.msb_dim(ctx)
     E_G = -2.6661474201323485
     L = m["L"]
@@ -146,7 +148,8 @@ def test_large_batch_runs_in_two_parts(tiny, case):
         assert _rel(psi[j], ref) <= bar, f"system {j}"
     if case == "small_bank":
         assert info["flushes"] > 1
-    if case == "c64_replace":
+    if c64:
+        assert st == msb.MSB_OK
         assert info["replacements"] > 0
         assert np.max(info["resid_true"]) <= 20 * tol
         return
@@ -159,6 +162,25 @@ def test_large_batch_runs_in_two_parts(tiny, case):
         k = min(40, n)
         assert np.max(np.abs(info["seed_hist"][j][:k] - info_d["seed_hist"][j][:k])
                       / info_d["seed_hist"][j][:k]) <= 1e-9
+
+
+def test_c64_batch_of_four_unsplit(tiny):
+    """Four systems with complex right-hand sides in one batch: complex64 with
+    residual replacement against the direct solves, at the precision
+    workload's default schedule (replacement every 50 iterations)."""
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E_G = -2.6661474201323485
+    systems = [msb.make_system(core_site=j, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma) for j in (0, 2, 5, 7)]
+    E = np.stack([W.random_complex(D, 120 + j) for j in range(4)])
+    w = np.linspace(-10.0, 10.0, 31)
+    st, info, psi = _run(msb, ctx, systems, E, w, 1e-6, 3000, msb.MSB_C64)
+    assert st == msb.MSB_OK and info["replacements"] > 0
+    for j, s in enumerate(systems):
+        ref = osolve.direct_solve(oracle_H(m, core_site=s.core_site, Uc=wl.Uc), E[j], E_G, wl.Gamma, w,
+                                  method="eig")
+        assert _rel(psi[j], ref) <= 5e-5, f"system {j}"
+    assert np.max(info["resid_true"]) <= 20 * 1e-6
 
 
 def test_two_part_batch_is_deterministic(tiny):
@@ -228,17 +250,15 @@ def test_c64_form_accuracy(tiny):
     assert err <= 5e-5, f"c64 rel err {err:.3e}"
 
 
-@pytest.mark.parametrize("direct_ap", [-1, 0])
 @pytest.mark.parametrize("opts", [None, {"replace_every": 7, "chunk": 3},
                                   {"replace_every": 20, "bank_slots": 33}])
-def test_c64_residual_replacement(tiny, opts, direct_ap):
-    """complex64 vectors with residual replacement r_m <- E - A_s x_m (complex128):
-    same accuracy as the plain form, replacements counted, and with a small
-    bank the replacement survives the flush / bank restart; in the direct seed
-    form (the complex64 default) and the recurred one (x and p rebuilt from the
-    bank, A p recomputed at each replacement)."""
+def test_c64_residual_replacement(tiny, opts):
+    """complex64 vectors with residual replacement r_m <- E - A_s x_m (complex128,
+    x_m rebuilt from the bank slots at each replacement): same accuracy as the
+    plain form, replacements counted, and with a small bank the replacement
+    survives the flush / bank restart."""
     msb, ctx, wl, m = tiny
-    opts = dict(opts or {}, direct_ap=direct_ap)
+    opts = dict(opts or {})
     D = msb.msb_dim(ctx)
     E = W.random_vector(D, 4).astype(np.complex128)
     E_G = -2.6661474201323485
@@ -265,6 +285,16 @@ def test_c64_residual_replacement(tiny, opts, direct_ap):
                             opts={"replace_every": -1})
     assert info0["replacements"] == 0
     assert _rel(psi0[0], ref) <= 5e-5
+
+
+def test_recurred_form_is_complex128_only(tiny):
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E = W.random_vector(D, 4).astype(np.complex128)
+    sysd = msb.make_system(core_site=0, Uc=wl.Uc, E_G=-2.66, Gamma=wl.Gamma)
+    st, info, psi = _run(msb, ctx, [sysd], E, wl.w_in[:4], 1e-6, 100, msb.MSB_C64,
+                         opts={"direct_ap": -1}, raise_on_fail=False, want_true=False)
+    assert st == msb.MSB_EINVAL
 
 
 def test_c64_replacement_tight_tol(tiny):
