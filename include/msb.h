@@ -232,6 +232,22 @@ msb_status msb_apply_timed(msb_ctx* ctx, const msb_system* sys, int nsys, double
                            msb_prec prec, const void* x, void* y, int reps,
                            double* ms_per_apply, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the apply
+ * of msb_apply with no allocation at all.  The per-system parameters are
+ * staged in a fixed device array of the library (MSB_NOALLOC_MAX_SYS systems,
+ * about 104 bytes each; one copy per GPU, set up by msb_create and held until
+ * the process ends); the launch shape is the one tuned or pinned before for
+ * this (system count, precision), else the default shape -- no tuning runs.
+ * Same arguments and results as msb_apply.  Every call on one GPU shares that
+ * GPU's staging array, so calls that overlap on one GPU (other threads, other
+ * contexts) race: serialise them.
+ * Errors: MSB_EINVAL for nsys outside [1, MSB_NOALLOC_MAX_SYS] and as msb_apply;
+ * MSB_EHIP if the staging array of the context's device was not set up. */
+#define MSB_NOALLOC_MAX_SYS 1024
+msb_status msb_apply_noalloc(msb_ctx* ctx, const msb_system* sys, int nsys, double shift,
+                             msb_prec prec, const void* x, void* y, void* stream);
+
 /* y = (w_up n_{site up} + w_dn n_{site dn}) x, or y = x if site < 0 (the
  * sector-preserving operators O1 / O2 used by the workloads).
  * x: [count][D] real FP64 (x_real != 0) or C128; y: [count][D] C128. */

@@ -95,6 +95,9 @@ def lib():
         L.msb_apply.argtypes = [c_void_p, POINTER(msb_system), c_int, c_double, c_int, c_void_p,
                                 c_void_p, c_void_p]
         L.msb_apply.restype = c_int
+        L.msb_apply_noalloc.argtypes = [c_void_p, POINTER(msb_system), c_int, c_double, c_int, c_void_p,
+                                        c_void_p, c_void_p]
+        L.msb_apply_noalloc.restype = c_int
         L.msb_apply_timed.argtypes = [c_void_p, POINTER(msb_system), c_int, c_double, c_int,
                                       c_void_p, c_void_p, c_int, POINTER(c_double), c_void_p]
         L.msb_apply_timed.restype = c_int
@@ -158,7 +161,7 @@ def lib():
 def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["msb_create", "msb_destroy", "msb_release_workspace", "msb_dim", "msb_sector_info", "msb_last_error",
-            "msb_device_ok", "msb_stream_create", "msb_stream_destroy", "msb_apply", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
+            "msb_device_ok", "msb_stream_create", "msb_stream_destroy", "msb_apply", "msb_apply_noalloc", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
             "msb_solve_reseed", "msb_dipole",
             "msb_combine", "msb_spectrum", "msb_spectrum_cf", "msb_autotune", "msb_set_shape",
             "msb_mlp_num_params", "msb_mlp_create", "msb_mlp_destroy", "msb_mlp_set_params",
@@ -301,6 +304,15 @@ def msb_apply(ctx, systems, shift: float, prec: int, x, y, stream=None):
     dt = _prec_dtype(prec)
     _check(lib().msb_apply(ctx, arr, n, float(shift), int(prec), _ptr(x, dt, n * D, "x"),
                            _ptr(y, dt, n * D, "y"), _stream_ptr(stream)))
+
+
+def msb_apply_noalloc(ctx, systems, shift: float, prec: int, x, y, stream=None):
+    """msb_apply without any allocation (systems staged in the library's fixed array)."""
+    arr, n = _systems(systems)
+    D = msb_dim(ctx)
+    dt = _prec_dtype(prec)
+    _check(lib().msb_apply_noalloc(ctx, arr, n, float(shift), int(prec), _ptr(x, dt, n * D, "x"),
+                                   _ptr(y, dt, n * D, "y"), _stream_ptr(stream)))
 
 
 def msb_apply_timed(ctx, systems, shift: float, prec: int, x, y, reps: int, stream=None) -> float:

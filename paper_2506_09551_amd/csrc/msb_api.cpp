@@ -8,6 +8,7 @@
 #include <complex>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -260,6 +261,34 @@ static ApplyArgs apply_args(const msb_ctx* ctx, const SysDev* sys, int nsys, con
 
 using namespace msb;
 
+// ---- the fixed staging array of msb_apply_noalloc ---------------------------
+// The per-system parameters of an allocation-free apply are staged here: one
+// copy of the array per GPU, kept until the process ends.  Host code never
+// passes the array's name to a kernel or a copy; it uses the device address
+// looked up once per device (scratch_setup, called by msb_create with that
+// device current).
+static __device__ __align__(256) SysDev scratch[MSB_NOALLOC_MAX_SYS];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+static void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 // =============================================================================
 extern "C" const char* msb_last_error(void) { return g_err.c_str(); }
 
@@ -360,6 +389,7 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
     e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
     if (e == hipSuccess && lds > 0) c->lds_max = (size_t)lds;
   }
+  if (e == hipSuccess) e = scratch_setup(c->device);   // staging array of msb_apply_noalloc
   if (e == hipSuccess && (size_t)(c->dn.n + 1) * 8 > c->lds_max) {
     const int c_dn_n = c->dn.n;
     delete c;
@@ -521,6 +551,38 @@ extern "C" msb_status msb_apply_timed(msb_ctx* ctx, const msb_system* sys, int n
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *ms_per_apply = ms / reps;
+  return MSB_OK;
+}
+
+extern "C" msb_status msb_apply_noalloc(msb_ctx* ctx, const msb_system* sys, int nsys, double shift,
+                                        msb_prec prec, const void* x, void* y, void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx || !sys || !x || !y) return fail(MSB_EINVAL, "msb_apply_noalloc: null argument");
+  if (nsys <= 0 || nsys > MSB_NOALLOC_MAX_SYS)
+    return fail(MSB_EINVAL, "msb_apply_noalloc: nsys must lie in [1, " + std::to_string(MSB_NOALLOC_MAX_SYS) +
+                                "] (the fixed staging array holds that many systems)");
+  if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_apply_noalloc: invalid precision");
+  void* const stage = scratch_address(ctx->device);
+  if (!stage) return fail(MSB_EHIP, "msb_apply_noalloc: staging array of this device not set up");
+  hipStream_t st = (hipStream_t)stream;
+  // systems are staged in chunks through a stack buffer (no host or device
+  // allocation); each chunk's copy completes before the buffer is refilled
+  constexpr int kChunk = 64;
+  SysDev h[kChunk];
+  for (int s0 = 0; s0 < nsys; s0 += kChunk) {
+    const int n = std::min(kChunk, nsys - s0);
+    for (int s = 0; s < n; ++s) {
+      msb_status r = make_sysdev(ctx, sys[s0 + s], -(sys[s0 + s].E_G + shift), -sys[s0 + s].Gamma, true, h[s]);
+      if (r != MSB_OK) return r;
+    }
+    MSB_HIP(hipMemcpyAsync(static_cast<SysDev*>(stage) + s0, h, sizeof(SysDev) * n, hipMemcpyHostToDevice, st));
+    MSB_HIP(hipStreamSynchronize(st));
+  }
+  ApplyArgs a = apply_args(ctx, static_cast<const SysDev*>(stage), nsys, x, y);
+  const Elem e = prec == MSB_C128 ? Elem::C128 : Elem::C64;
+  a.shape = shape_for(ctx, e, nsys, st, false);   // tuned or pinned before, else the default: no tuning
+  MSB_HIP(launch_apply(e, kModePlain, a, st));
+  MSB_HIP(hipStreamSynchronize(st));
   return MSB_OK;
 }
 
