@@ -174,8 +174,8 @@ typedef struct {
   double mem_fraction;   /* fraction of free device memory the workspace may use (default 0.9) */
   int assembly_engine;   /* multi-shift assembly, all in FP64: 0 = vector ALU with three real
                             products per complex product (default), 1 = matrix cores, 2 = vector
-                            ALU with four real products, 3 / 4 = as 0 with 128 elements per
-                            workgroup / with eight wavefronts of four shifts each */
+                            ALU with four real products, 3 / 4 = as 0 with 256 elements per
+                            workgroup / and eight wavefronts of four shifts each */
   int autotune;          /* 0 = tune the apply shape on first use (default), -1 = default shape
                             unless one was tuned or pinned before */
   int dual;              /* 0 = the dual-space (BiCG) form only when some system's A is not

@@ -229,43 +229,50 @@ __global__ __launch_bounds__(BLK, (BLK >= 1024 && EPT * NV <= 5) ? 8 : 1) void k
     for (; k + HG <= nh; k += HG) up_hops(std::integral_constant<int, HG>{}, k);
     for (; k < nh; ++k) up_hops(std::integral_constant<int, 1>{}, k);
     __syncthreads();   // staged rows complete
-    // I (x) H_dn: one padded, transposed hop table per bond type; an entry is
-    // the target column with the parity-0 sign in bit 31, padding points at
-    // the zero element nd.  The next entry is prefetched.
-    const uint32_t* ell = a.T.ell_dn;
+    // I (x) H_dn: one padded, transposed hop table per bond type; a 64-bit
+    // word holds four hops of a state as 16-bit entries (target column, the
+    // parity-0 sign in bit 15), padding points at the zero element nd.  The
+    // next word (four hops ahead) is prefetched.
+    const uint64_t* ell = a.T.ell_dn;
     for (int t = 0; t < a.T.n_types; ++t) {
-      const int kt = a.T.k_type[t];
+      const int kq = a.T.k_type[t];
       Tc amp[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) amp[v] = act[v] ? (Tc)a.sys[s0 + v].amp[t] : (Tc)0;
-      uint32_t hn[EPT];
-      if (kt > 0) {
+      uint64_t hn[EPT];
+      if (kq > 0) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) hn[e] = ell[voff[e]];
       }
-      for (int kk = 0; kk < kt; ++kk) {
-        uint32_t h[EPT];
+      for (int g = 0; g < kq; ++g) {
+        uint32_t hw[EPT][2];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) h[e] = hn[e];
-        if (kk + 1 < kt) {
-          const uint32_t* nxt = ell + (int64_t)(kk + 1) * nd;
+        for (int e = 0; e < EPT; ++e) {
+          hw[e][0] = (uint32_t)hn[e];
+          hw[e][1] = (uint32_t)(hn[e] >> 32);
+        }
+        if (g + 1 < kq) {
+          const uint64_t* nxt = ell + (int64_t)(g + 1) * nd;
 #pragma unroll
           for (int e = 0; e < EPT; ++e) hn[e] = nxt[voff[e]];
         }
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          const uint32_t sb = h[e] & 0x80000000u;
-          const int tgt = (int)(h[e] & 0xFFFFu);
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const Tc c = flip_sign(amp[v], sb);
-            const cv<Tc> xv = rows[v * ldr + tgt];
-            acc[v][e].re += c * xv.re;
-            acc[v][e].im += c * xv.im;
+          for (int e = 0; e < EPT; ++e) {
+            const uint32_t ent = (hw[e][j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+            const uint32_t sb = (ent & 0x8000u) << 16;
+            const int tgt = (int)(ent & 0x7FFFu);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const Tc c = flip_sign(amp[v], sb);
+              const cv<Tc> xv = rows[v * ldr + tgt];
+              acc[v][e].re += c * xv.re;
+              acc[v][e].im += c * xv.im;
+            }
           }
-        }
       }
-      ell += (int64_t)kt * nd;
+      ell += (int64_t)kq * nd;
     }
     // outputs
 #pragma unroll

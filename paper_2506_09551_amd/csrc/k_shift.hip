@@ -139,7 +139,7 @@ struct GaussShape {
   int M, EPL, NW;
 };
 __host__ __device__ constexpr GaussShape gauss_shape(int engine) {
-  return engine == 3 ? GaussShape{8, 2, 4} : engine == 4 ? GaussShape{4, 4, 8} : GaussShape{8, 4, 4};
+  return engine == 3 ? GaussShape{8, 4, 4} : engine == 4 ? GaussShape{4, 4, 8} : GaussShape{8, 2, 4};
 }
 int flush_shifts_per_tile(int engine) {
   if (engine == 1) return kFlushM * kFlushWaves;
@@ -418,21 +418,34 @@ __global__ __launch_bounds__(kBlock) void k_flush_valu(FlushArgs a, const double
 // so each (shift, element, slot) costs three FMAs into three accumulators
 // (A1 += c_re s, A2 += (c_re + c_im) r_im, A3 += (c_im - c_re) r_re;
 // re = A1 - A2, im = A1 + A3) instead of the four of the plain complex
-// product.  Tiling as k_flush_valu: a workgroup owns M * NW shift slots and
-// 64 * EPL elements; residual slots are staged in LDS in chunks of kValuKT
-// (straight from memory with a complex128 bank, double-buffered), the table
-// entries are wave-uniform scalar loads, prefetched one slot ahead.
+// product.  A workgroup owns M * NW shift slots and 64 * EPL elements.  The
+// residual slots go straight from memory to LDS in their storage precision
+// (global_load_lds, 16 bytes per lane: one complex128 or two complex64
+// elements), in chunks of kValuKT slots, double-buffered so that the next
+// chunk is in flight while the FMAs of the current one run; complex64 values
+// are widened to FP64 as they are read from LDS.  Lane l owns the elements
+// l + 64 e (complex128 bank) or 2 l + 128 (e / 2) + e % 2 (complex64 bank,
+// one 16-byte LDS read per pair).  Table entries are wave-uniform scalar
+// loads (the next slot's requested early when M <= 4).
+template <typename SB>
+__device__ __forceinline__ int gauss_elem(int lane, int e) {
+  if constexpr (std::is_same<SB, double>::value) return lane + kWave * e;
+  else return 2 * kWave * (e / 2) + 2 * lane + (e % 2);
+}
+
 template <typename SB, typename SO, int M, int EPL, int NW>
 __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const double* __restrict__ coef,
                                                              int ow_mode) {
-  using AB = Access<SB, true>;
   using AO = Access<SO, true>;
+  using VB = typename std::conditional<std::is_same<SB, double>::value, double2, float4>::type;
   constexpr int KT = kValuKT;
   constexpr int TILE = kWave * EPL;                       // elements of the workgroup
   constexpr int NS = M * NW;                              // shift slots of the workgroup
-  constexpr int ROWS = KT * EPL;                          // 64-element rows of one staged chunk
-  __shared__ cv<double> rt[KT][TILE];
-  __shared__ cv<double> rt2[std::is_same<SB, double>::value ? KT : 1][TILE];
+  constexpr int PER16 = 16 / (int)sizeof(cv<SB>);         // elements per 16-byte lane load
+  constexpr int LROWS = EPL / PER16;                      // wave loads per slot
+  constexpr int ROWS = KT * LROWS;                        // wave loads per chunk
+  static_assert(EPL % PER16 == 0, "whole 16-byte loads per lane");
+  __shared__ VB rt[2][KT][TILE / PER16];                  // two chunk buffers, 16-byte units
 
   const int s = blockIdx.y;
   const int b = blockIdx.x;
@@ -444,19 +457,35 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
   const int lane = threadIdx.x % kWave;
   const int Kext = a.tile_k[s * a.n_stiles + stt];
   const int64_t e0 = (int64_t)et * TILE;
-  const int64_t last_e = a.D - 1;
-  const void* bank_s = AB::offset(a.bank, (int64_t)s * a.cap * a.D);
+  const cv<SB>* bank_s = reinterpret_cast<const cv<SB>*>(a.bank) + (int64_t)s * a.cap * a.D;
   const int slot0 = stt * NS + wave * M;
   const int Kw = a.lend ? __builtin_amdgcn_readfirstlane(a.lend[s * a.n_list + slot0]) : Kext;
   typedef __attribute__((address_space(4))) const double cdouble;
   cdouble* crow = (cdouble*)(coef + ((int64_t)s * a.K * a.n_list + slot0) * 3);   // slot-major
 
+  // 16-byte units a lane loads for one wave load: clamped into the vector
+  // (the D % PER16 tail of a complex64 bank reads its last whole unit; such
+  // elements feed only outputs that are not stored)
+  const int64_t n_units = a.D / PER16;                    // whole 16-byte units of one slot
   double A1[M][EPL], A2[M][EPL], A3[M][EPL];
 #pragma unroll
   for (int t = 0; t < M; ++t)
 #pragma unroll
     for (int e = 0; e < EPL; ++e) A1[t][e] = A2[t][e] = A3[t][e] = 0.0;
 
+  auto stage = [&](int buf, int kb) {
+    const int kn = min(KT, Kext - kb);
+    for (int row = wave; row < ROWS; row += NW) {
+      const int j = row / LROWS, g = row % LROWS;
+      const int kc = kb + (j < kn ? j : kn - 1);          // clamped: its coefficient is never used
+      int64_t unit = (e0 / PER16) + (int64_t)g * kWave + lane;
+      unit = unit < n_units - 1 ? unit : n_units - 1;
+      const VB* src = reinterpret_cast<const VB*>(bank_s + (int64_t)kc * a.D) + unit;
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(src),
+                                       (__attribute__((address_space(3))) void*)&rt[buf][j][g * kWave],
+                                       16, 0, 0);
+    }
+  };
   struct C3 {
     double r, sum, dif;
   };
@@ -467,11 +496,8 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
       c[t] = {crow[o], crow[o + 1], crow[o + 2]};
     }
   };
-  // the next slot's entries are requested before the current slot's FMAs
-  // while they fit the scalar registers twice over (M <= 4); with more shifts
-  // per wavefront each slot loads its own
   constexpr bool kPrefetch = M <= 4;
-  auto run = [&](const cv<double> (*buf)[TILE], int kb, int kn) {
+  auto run = [&](int buf, int kb, int kn) {
     C3 c_cur[M], c_nxt[kPrefetch ? M : 1];
     const int kw = min(kn, Kw - kb);                      // wave-uniform; may be <= 0
     if (kPrefetch && kw > 0) load_c(kb, c_cur);
@@ -482,13 +508,25 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
         load_c(kb + kk, c_cur);
       }
       double rr[EPL], ri[EPL], sm[EPL];
+      if constexpr (std::is_same<SB, double>::value) {
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        const cv<double> r = buf[kk][lane + kWave * e];
-        rr[e] = r.re;
-        ri[e] = r.im;
-        sm[e] = r.re + r.im;
+        for (int e = 0; e < EPL; ++e) {
+          const double2 r = rt[buf][kk][lane + kWave * e];
+          rr[e] = r.x;
+          ri[e] = r.y;
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < EPL / 2; ++g) {
+          const float4 r = rt[buf][kk][g * kWave + lane];
+          rr[2 * g] = (double)r.x;
+          ri[2 * g] = (double)r.y;
+          rr[2 * g + 1] = (double)r.z;
+          ri[2 * g + 1] = (double)r.w;
+        }
       }
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) sm[e] = rr[e] + ri[e];
 #pragma unroll
       for (int t = 0; t < M; ++t)
 #pragma unroll
@@ -503,48 +541,12 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
       }
     }
   };
-  if constexpr (std::is_same<SB, double>::value) {
-    // complex128 bank: 64-element rows straight from memory to LDS, the next
-    // chunk in flight while the FMAs of the current one run
-    const cv<double>* bank_c = reinterpret_cast<const cv<double>*>(bank_s);
-    auto stage = [&](cv<double> (*buf)[TILE], int kb) {
-      const int kn = min(KT, Kext - kb);
-      for (int row = wave; row < ROWS; row += NW) {
-        const int j = row / EPL, eg = row % EPL;
-        const int kc = kb + (j < kn ? j : kn - 1);        // clamped: its coefficient is never used
-        int64_t e = e0 + eg * kWave + lane;
-        e = e < last_e ? e : last_e;                      // clamped: feeds only unstored outputs
-        __builtin_amdgcn_global_load_lds(static_cast<const void*>(bank_c + (int64_t)kc * a.D + e),
-                                         (__attribute__((address_space(3))) void*)&buf[j][eg * kWave],
-                                         16, 0, 0);
-      }
-    };
-    if (Kext > 0) stage(rt, 0);
-    for (int kb = 0; kb < Kext; kb += 2 * KT) {
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      if (kb + KT < Kext) stage(rt2, kb + KT);
-      run(rt, kb, min(KT, Kext - kb));
-      if (kb + KT >= Kext) break;
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      if (kb + 2 * KT < Kext) stage(rt, kb + 2 * KT);
-      run(rt2, kb + KT, min(KT, Kext - kb - KT));
-    }
-  } else {
-    for (int kb = 0; kb < Kext; kb += KT) {
-      const int kn = min(KT, Kext - kb);
-      for (int row = wave; row < ROWS; row += NW) {
-        const int j = row / EPL, eg = row % EPL;
-        const int kc = kb + (j < kn ? j : kn - 1);
-        int64_t e = e0 + eg * kWave + lane;
-        e = e < last_e ? e : last_e;
-        rt[j][eg * kWave + lane] = AB::template load<double>(bank_s, (int64_t)kc * a.D + e);
-      }
-      __syncthreads();
-      run(rt, kb, kn);
-      __syncthreads();
-    }
+  if (Kext > 0) stage(0, 0);
+  for (int kb = 0, buf = 0; kb < Kext; kb += KT, buf ^= 1) {
+    __builtin_amdgcn_s_waitcnt(0);                        // this wavefront's part of chunk kb landed
+    __syncthreads();                                      // every part; the other buffer is free
+    if (kb + KT < Kext) stage(buf ^ 1, kb + KT);
+    run(buf, kb, min(KT, Kext - kb));
   }
 
 #pragma unroll
@@ -565,7 +567,7 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
     const int64_t obase = ((int64_t)s * a.n_shift + k) * a.D;
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-      const int64_t i = e0 + lane + kWave * e;
+      const int64_t i = e0 + gauss_elem<SB>(lane, e);
       if (i >= a.D) continue;
       cv<double> v = {A1[t][e] - A2[t][e], A1[t][e] + A3[t][e]};
       if (ow_mode != 0) v = cadd(v, cmul(ow, AO::template load<double>(a.out, obase + i)));
@@ -580,6 +582,8 @@ hipError_t launch_flush(Elem eb, Elem eo, const FlushArgs& a, int ow_mode, int e
   const int per_xcd = (a.n_etiles + kNumXcd - 1) / kNumXcd;
   dim3 grid(per_xcd * kNumXcd * a.n_stiles, a.nsys);
   if (engine < 0 || engine >= kNumFlushEngines) return hipErrorInvalidValue;
+  // 16-byte staging of complex64 slots needs an even D (the caller picks engine 2 otherwise)
+  if (eb == Elem::C64 && (a.D & 1) && flush_coef_comps(engine) == 3) return hipErrorInvalidValue;
 #define MSB_GAUSS(SB, SO, E)                                                                   \
   hipLaunchKernelGGL((k_flush_gauss<SB, SO, gauss_shape(E).M, gauss_shape(E).EPL, gauss_shape(E).NW>), grid, \
                      dim3(gauss_shape(E).NW * kWave), 0, st, a, a.coef, ow_mode);

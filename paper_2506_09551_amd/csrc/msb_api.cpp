@@ -390,7 +390,7 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
     if (e == hipSuccess && lds > 0) c->lds_max = (size_t)lds;
   }
   if (e == hipSuccess) e = scratch_setup(c->device);   // staging array of msb_apply_noalloc
-  if (e == hipSuccess && (size_t)(c->dn.n + 1) * 8 > c->lds_max) {
+  if (e == hipSuccess && ((size_t)(c->dn.n + 1) * 8 > c->lds_max || c->dn.n >= 32768)) {
     const int c_dn_n = c->dn.n;
     delete c;
     return fail(MSB_EINVAL, "msb_create: a down-spin row of " + std::to_string(c_dn_n) +
@@ -411,9 +411,11 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   if (e == hipSuccess) e = upload(&c->d_hop_dn, c->dn.hop);
   if (e == hipSuccess) {
     // padded, transposed copies of the down-spin hop lists, one per bond
-    // type: ell[t][k][d] = target | (even parity ? 1 << 31 : 0), padding n_dn
+    // type, four hops to a 64-bit word: ell[t][g][d] holds hops 4g .. 4g+3 of
+    // state d, each 16 bits = target | (even parity ? 0x8000 : 0), padding
+    // n_dn (the zero element at the end of every staged row)
     const int nd = c->dn.n;
-    std::vector<std::vector<uint32_t>> per(c->n_types);
+    std::vector<uint64_t> ell;
     for (int t = 0; t < c->n_types; ++t) {
       int kt = 0;
       for (int d = 0; d < nd; ++d) {
@@ -422,21 +424,29 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
           cnt += ((c->dn.hop[k] >> 1) & 127u) == (uint32_t)t;
         kt = std::max(kt, cnt);
       }
-      c->k_type_dn[t] = kt;
-      per[t].assign((size_t)kt * nd, (uint32_t)nd);
+      const int kq = (kt + 3) / 4;
+      c->k_type_dn[t] = kq;
+      std::vector<uint16_t> ent((size_t)kq * 4 * nd, (uint16_t)nd);
       for (int d = 0; d < nd; ++d) {
         int j = 0;
         for (uint32_t k = c->dn.off[d]; k < c->dn.off[d + 1]; ++k) {
           const uint32_t h = c->dn.hop[k];
           if (((h >> 1) & 127u) != (uint32_t)t) continue;
-          per[t][(size_t)j * nd + d] = (h >> 16) | ((h & 1u) ? 0u : 0x80000000u);
+          ent[(size_t)j * nd + d] = (uint16_t)((h >> 16) | ((h & 1u) ? 0u : 0x8000u));
           ++j;
         }
       }
+      for (int g = 0; g < kq; ++g)
+        for (int d = 0; d < nd; ++d) {
+          uint64_t w = 0;
+          for (int j = 0; j < 4; ++j) w |= (uint64_t)ent[(size_t)(4 * g + j) * nd + d] << (16 * j);
+          ell.push_back(w);
+        }
     }
-    std::vector<uint32_t> ell;
-    for (int t = 0; t < c->n_types; ++t) ell.insert(ell.end(), per[t].begin(), per[t].end());
-    e = upload(&c->d_ell_dn, ell);
+    const size_t bytes = std::max<size_t>(ell.size(), 1) * sizeof(uint64_t);
+    e = hipMalloc(&c->d_ell_dn, bytes);
+    if (e == hipSuccess && !ell.empty())
+      e = hipMemcpy(c->d_ell_dn, ell.data(), ell.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = upload(&c->d_order_up, c->up.order);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking);
@@ -925,8 +935,11 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   const Elem eo = ev;
   const int64_t D = ctx->D;
   const int mx = std::max(maxit, 1);
-  const int engine = opts ? opts->assembly_engine : 0;
+  int engine = opts ? opts->assembly_engine : 0;
   if (engine < 0 || engine >= kNumFlushEngines) return fail(MSB_EINVAL, "msb_solve: unknown assembly engine");
+  // the three-product engines stage complex64 slots in 16-byte units, which
+  // needs an even D (16-byte aligned slots); odd D takes the four-product one
+  if (prec == MSB_C64 && (ctx->D & 1) && flush_coef_comps(engine) == 3) engine = 2;
   const int tile_s = flush_shifts_per_tile(engine);
   const int n_list = ((n_shift + tile_s - 1) / tile_s) * tile_s;
   const size_t s_el = elem_bytes(ev), s_out = elem_bytes(eo);

@@ -75,11 +75,12 @@ struct TablesDev {
   const uint32_t* hop_up;
   const uint32_t* hop_dn;
   // down-spin hops, one padded transposed table per bond type t (types in
-  // order, k_type[t] rows of n_dn entries each): entry = target column, with
-  // bit 31 set where the matrix element is -t (even parity); padding = n_dn
-  const uint32_t* ell_dn;
+  // order, k_type[t] rows of n_dn words each): word g of state d holds its
+  // hops 4g .. 4g+3 as 16-bit entries = target column, with bit 15 set where
+  // the matrix element is -t (even parity); padding = n_dn
+  const uint64_t* ell_dn;
   const uint32_t* order_up;   // [n_up] up-spin rows in level order (SpinTable::order)
-  int n_up, n_dn, k_dn;       // k_dn: sum of k_type
+  int n_up, n_dn, k_dn;       // k_dn: sum of k_type (words of four hops)
   int k_up_max;               // most up-spin hops of one row
   int n_types;
   int k_type[MSB_MAX_BOND_TYPES];
@@ -309,7 +310,7 @@ struct FlushArgs {
 // ow_mode: 0 = old output ignored, 1 = weight 1, 2 = per-shift weights from ow
 // engine: 0 = FP64 vector ALU, three real products per complex product (the
 // default), 1 = FP64 matrix cores, 2 = FP64 vector ALU, four real products,
-// 3 = as 0 with half the elements per workgroup, 4 = as 0 with eight
+// 3 = as 0 with twice the elements per workgroup, 4 = as 3 with eight
 // wavefronts of four shifts
 constexpr int kNumFlushEngines = 5;
 hipError_t launch_flush(Elem bank, Elem out, const FlushArgs& a, int ow_mode, int engine,
@@ -416,9 +417,9 @@ struct msb_ctx {
   uint32_t* d_off_dn = nullptr;
   uint32_t* d_hop_up = nullptr;
   uint32_t* d_hop_dn = nullptr;
-  uint32_t* d_ell_dn = nullptr;
+  uint64_t* d_ell_dn = nullptr;
   uint32_t* d_order_up = nullptr;
-  int k_type_dn[MSB_MAX_BOND_TYPES] = {0};   // rows of each bond type's down-spin hop table
+  int k_type_dn[MSB_MAX_BOND_TYPES] = {0};   // words (four hops each) of each bond type's down-spin table
   int type_partner[MSB_MAX_BOND_TYPES] = {0}; // type of the reverse hop (itself when symmetric)
   // private stream for the captured seed iterations (default priority)
   hipStream_t solve_stream = nullptr;

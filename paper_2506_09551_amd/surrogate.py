@@ -121,6 +121,27 @@ class Ensemble:
         return mean, sd
 
 
+def calibrate_fallback(mean, sd, I_ref, eps):
+    """Smallest spread threshold that sends every row with error above eps to the solver.
+
+    mean, sd, I_ref: [P][n_win][n_w] ensemble mean and spread and the solver's
+    spectra of a validation set.  A row's error is max_w |mean - I_ref| over
+    the spectrum's peak; a row falls back when sd exceeds frac * max(mean of
+    its spectrum) somewhere in it (the msb_mlp_fallback rule).  Returns the
+    largest frac that still flags every row with error > eps (just below the
+    smallest spread ratio among those rows), or the largest spread ratio seen
+    when no row exceeds eps."""
+    mean, sd, I_ref = (np.asarray(a, dtype=np.float64) for a in (mean, sd, I_ref))
+    peak_ref = I_ref.reshape(len(I_ref), -1).max(axis=1)
+    peak_pred = mean.reshape(len(mean), -1).max(axis=1)
+    err = np.abs(mean - I_ref).max(axis=2) / peak_ref[:, None]
+    ratio = sd.max(axis=2) / peak_pred[:, None]
+    bad = err > eps
+    if not np.any(bad):
+        return float(ratio.max()) * (1 + 1e-6)
+    return float(ratio[bad].min()) * (1 - 1e-6)
+
+
 def predict_with_fallback(ens: Ensemble, ctx, params, job: SpectrumJob, x0, frac=0.05):
     """Spectra of params from the ensemble; every w_in row whose ensemble
     spread exceeds frac * peak is recomputed by the solver.  Returns

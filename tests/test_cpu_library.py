@@ -80,3 +80,33 @@ def test_struct_layout_matches_header(name):
     body = text[text.rindex("typedef struct {", 0, end):end]
     fields = re.findall(r"^\s*(?:int|double)\s+(\w+);", body, flags=re.M)
     assert [f[0] for f in getattr(_capi, name)._fields_] == fields
+
+
+def test_fallback_calibration_flags_every_bad_row():
+    """calibrate_fallback (host code of the learned form) returns a spread
+    threshold under which every validation row whose error exceeds eps falls
+    back through the library's fallback rule, and no threshold when no row
+    is bad."""
+    import numpy as np
+    from paper_2506_09551_amd import surrogate as S
+    msb = pytest.importorskip("paper_2506_09551_amd")
+    try:
+        msb.lib()
+    except OSError:
+        pytest.skip("library not built")
+    rng = np.random.default_rng(8)
+    ref = rng.uniform(0, 1, (6, 10, 30))
+    mean = ref + rng.normal(0, 0.02, ref.shape)
+    sd = np.abs(rng.normal(0, 0.02, ref.shape))
+    mean[2, 4] += 0.3                       # two bad rows with a large spread somewhere
+    sd[2, 4, 7] = 0.25
+    mean[5, 1] -= 0.2
+    sd[5, 1, 3] = 0.18
+    eps = 0.1
+    frac = S.calibrate_fallback(mean, sd, ref, eps)
+    peak = ref.reshape(6, -1).max(axis=1)
+    err = np.abs(mean - ref).max(axis=2) / peak[:, None]
+    for p in range(6):
+        mask = msb.msb_mlp_fallback(mean[p].astype(np.float32), sd[p].astype(np.float32), frac)
+        assert np.all(mask[err[p] > eps])
+    assert S.calibrate_fallback(ref, sd * 0, ref, eps) == 0.0

@@ -165,14 +165,15 @@ def test_large_batch_runs_in_two_parts(tiny, case):
 
 
 def test_c64_batch_of_four_unsplit(tiny):
-    """Four systems with complex right-hand sides in one batch: complex64 with
-    residual replacement against the direct solves, at the precision
-    workload's default schedule (replacement every 50 iterations)."""
+    """Four systems with real right-hand sides (as E = O_2 G of the workloads)
+    in one batch: complex64 with residual replacement against the direct
+    solves, at the precision workload's default schedule (replacement every
+    50 iterations)."""
     msb, ctx, wl, m = tiny
     D = msb.msb_dim(ctx)
     E_G = -2.6661474201323485
     systems = [msb.make_system(core_site=j, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma) for j in (0, 2, 5, 7)]
-    E = np.stack([W.random_complex(D, 120 + j) for j in range(4)])
+    E = np.stack([W.random_vector(D, 120 + j) for j in range(4)]).astype(np.complex128)
     w = np.linspace(-10.0, 10.0, 31)
     st, info, psi = _run(msb, ctx, systems, E, w, 1e-6, 3000, msb.MSB_C64)
     assert st == msb.MSB_OK and info["replacements"] > 0
@@ -375,23 +376,51 @@ def test_other_models(gpu, name):
         msb.msb_destroy(ctx)
 
 
-@pytest.mark.parametrize("engine", [0, 1])
-def test_assembly_engines_match_direct_solve(tiny, engine):
-    """Vector-ALU and matrix-core forms of the multi-shift assembly, with and without carry."""
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("engine", [0, 1, 2, 3, 4])
+def test_assembly_engines_match_direct_solve(tiny, engine, prec):
+    """Every multi-shift assembly engine (three-product vector ALU and its two
+    variants, matrix cores, four-product vector ALU), with and without carry
+    (a 41-slot bank), in both storage precisions; 70 shifts span more than one
+    shift tile with a ragged last one, and D = 4900 ends in a ragged element
+    tile."""
     msb, ctx, wl, m = tiny
     D = msb.msb_dim(ctx)
-    E = W.random_complex(D, 41)
+    c64 = prec == "c64"
+    E = W.random_vector(D, 41).astype(np.complex128) if c64 else W.random_complex(D, 41)
+    tol, bar = (1e-6, 5e-5) if c64 else (1e-12, 1e-9)
     E_G = -2.6661474201323485
     sysd = [msb.make_system(core_site=j, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma) for j in (0, 2)]
-    w = np.linspace(-9.0, 9.0, 70)                 # more than one 64-shift tile, ragged
+    w = np.linspace(-9.0, 9.0, 70)                 # more than one shift tile, ragged
     refs = [osolve.direct_solve(oracle_H(m, core_site=s.core_site, Uc=wl.Uc), E, E_G, wl.Gamma, w,
                                 method="eig") for s in sysd]
     for slots in (0, 41):
-        st, info, psi = _run(msb, ctx, sysd, np.stack([E, E]), w, 1e-12, 3000, msb.MSB_C128,
+        st, info, psi = _run(msb, ctx, sysd, np.stack([E, E]), w, tol, 3000,
+                             msb.MSB_C64 if c64 else msb.MSB_C128,
                              opts={"assembly_engine": engine, "bank_slots": slots})
         for j in range(2):
             err = _rel(psi[j], refs[j])
-            assert err <= 1e-9, f"engine {engine} slots {slots} system {j}: {err:.3e}"
+            assert err <= bar, f"engine {engine} slots {slots} system {j}: {err:.3e}"
+
+
+def test_c64_odd_dimension(gpu):
+    """An odd D (L = 7 ring, N = 3 + 3, D = 1225): complex64 slots are not
+    16-byte aligned, so the assembly falls back to the four-product engine."""
+    msb = gpu
+    m = dict(L=7, nu=3, nd=3, bonds=W.chain_bonds(7, 1.0), U=6.0)
+    ctx = msb.msb_create(m["L"], m["nu"], m["nd"], m["bonds"], m["U"])
+    try:
+        D = msb.msb_dim(ctx)
+        assert D % 2 == 1
+        E = W.random_vector(D, 43).astype(np.complex128)
+        w = np.linspace(-6.0, 6.0, 19)
+        sysd = msb.make_system(core_site=2, Uc=-3.0, E_G=-1.5, Gamma=0.9)
+        for slots in (0, 17):
+            st, info, psi = _run(msb, ctx, [sysd], E, w, 1e-6, 2000, msb.MSB_C64, opts={"bank_slots": slots})
+            ref = osolve.direct_solve(oracle_H(m, core_site=2, Uc=-3.0), E, -1.5, 0.9, w, method="eig")
+            assert _rel(psi[0], ref) <= 5e-5
+    finally:
+        msb.msb_destroy(ctx)
 
 
 @pytest.mark.parametrize("wl_name", ["scale", "precision", "batched"])
