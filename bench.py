@@ -382,7 +382,6 @@ def learned_main(args):
     sweep = []
     for eps in (0.1, 0.05, 0.02, 0.01, 0.005):
         frac = S.calibrate_fallback(mu[val], sdv[val], I_ho[val], eps)
-        run(p_ho[tst], frac)                              # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         I_r, m_r, tn, tf = run(p_ho[tst], frac)
