@@ -233,6 +233,8 @@ def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec, E_G, n_
     y = torch.empty_like(x)
     ms_blk = msb.msb_apply_timed(ctx, systems, 0.0, prec, x, y, 20)
     ms_one = msb.msb_apply_timed(ctx, systems[0], 0.0, prec, x[0], y[0], 20)
+    # the same block interleaved (groups of four): the apply the batched solve runs
+    ms_il = msb.msb_apply_block(ctx, systems, 0.0, prec, 4, x, y, reps=20) if n % 4 == 0 else None
     el = x.element_size()
     res = {
         "separate_ms": round(ms_sep, 3), "batched_ms": round(ms_batched, 3),
@@ -244,6 +246,8 @@ def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec, E_G, n_
                                      "norm": "max_w |I_batched - I_c128| / max_w I_c128 per (RHS, w_in)"},
         "apply_block_ms": round(ms_blk, 4), "apply_one_ms": round(ms_one, 4),
         "apply_block_GBs": round(2 * n * D * el / (ms_blk * 1e-3) / 1e9, 1),
+        "apply_block_interleaved_ms": None if ms_il is None else round(ms_il, 4),
+        "apply_block_interleaved_GBs": None if ms_il is None else round(2 * n * D * el / (ms_il * 1e-3) / 1e9, 1),
         "apply_one_GBs": round(2 * D * el / (ms_one * 1e-3) / 1e9, 1),
     }
     log(f"batched {res}")
@@ -594,6 +598,62 @@ def dipole_main(args):
     print(json.dumps(out), flush=True)
 
 
+def h_apply_rates(msb, ctx, wl, systems, prec, reps=50):
+    """H-apply rates: algorithmic bytes 2 D s R over the mean of `reps` applies,
+    against the 8 TB/s spec and a 1 GiB device copy measured here, for the
+    given context's block and one vector, and the HBM-resident L = 14 and 4x4
+    workloads."""
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    cdt = torch.complex128 if prec == msb.MSB_C128 else torch.complex64
+    D = msb.msb_dim(ctx)
+    # H-apply bandwidth: algorithmic bytes 2 D s per vector
+    # H-apply rate: algorithmic bytes 2 D s R over the mean of 50 applies,
+    # against the 8 TB/s spec and a device copy measured here
+    happly = {}
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
+    dstc = torch.empty_like(src)
+    for _ in range(3):
+        dstc.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        dstc.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dstc
+    happly["copy_1GiB_GB/s"] = round(copy_gbs, 1)
+
+    def rate(c, syss, pr, dt, Dn, label, note=None):
+        n = len(syss)
+        x = torch.randn(n, Dn, dtype=dt, device=dev)
+        y = torch.empty_like(x)
+        ms = msb.msb_apply_timed(c, syss, 0.0, pr, x, y, reps)
+        gbs = 2 * n * Dn * x.element_size() / (ms * 1e-3) / 1e9
+        happly[label] = {"ms": round(ms, 5), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "frac_of_copy": round(gbs / copy_gbs, 4)}
+        if note:
+            happly[label]["note"] = note
+        del x, y
+    rate(ctx, systems, prec, cdt, D, f"{wl.name}_x{len(systems)}",
+         f"the solve's block of {len(systems)} vectors ({len(systems) * D * (16 if prec == msb.MSB_C128 else 8) / 1e6:.0f} MB)")
+    rate(ctx, systems[:1], prec, cdt, D, wl.name, "one 13.7 MB vector: served from the 256 MB Infinity Cache")
+    for other in ("precision", "batched"):
+        wo = W.get(other)
+        c2 = msb.msb_create(wo.n_sites, wo.n_up, wo.n_dn, wo.bonds, wo.U)
+        D2 = msb.msb_dim(c2)
+        s2 = [msb.make_system(core_site=c, Uc=wo.Uc, E_G=-4.0, Gamma=wo.Gamma) for c in wo.core_sites]
+        if other == "precision":
+            for dname, dt, pr in (("c128", torch.complex128, msb.MSB_C128), ("c64", torch.complex64, msb.MSB_C64)):
+                rate(c2, s2, pr, dt, D2, f"{wo.name}_{dname}", "HBM-resident")
+        else:
+            rate(c2, s2, msb.MSB_C64, torch.complex64, D2, f"{wo.name}_c64_x{len(s2)}", "HBM-resident block")
+        msb.msb_destroy(c2)
+    return happly
+
+
 def form_summary(name, out):
     """The figures of one form (precision or batched) for the default line."""
     s = {"workload": out["config"]["workload"], "dtype": out["dtype"], "tol": out["config"]["tol"],
@@ -613,7 +673,8 @@ def form_summary(name, out):
                   "separate_c128_ms": b["plain_c128_separate_ms"],
                   "speedup_vs_c128": b["speedup_batched_vs_plain_c128"],
                   "spectrum_rel_err_vs_c128": b["spectrum_rel_err_vs_c128"]["max"],
-                  "apply_block_GBs": b["apply_block_GBs"], "apply_one_GBs": b["apply_one_GBs"]})
+                  "apply_block_GBs": b["apply_block_GBs"], "apply_one_GBs": b["apply_one_GBs"],
+                  "apply_block_interleaved_GBs": b["apply_block_interleaved_GBs"]})
     return s
 
 
@@ -759,49 +820,7 @@ def run_solver_workload(wl_name, args, extras=True, cpu=True):
         del psi
         out["precision"] = precision_extras(msb, ctx, wl, systems, E, E_G, box, last, ms_per_step, args.tol)
     elif extras:
-        # H-apply bandwidth: algorithmic bytes 2 D s per vector
-        # H-apply rate: algorithmic bytes 2 D s R over the mean of 50 applies,
-        # against the 8 TB/s spec and a device copy measured here
-        happly = {}
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
-        dstc = torch.empty_like(src)
-        for _ in range(3):
-            dstc.copy_(src)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(20):
-            dstc.copy_(src)
-        e1.record()
-        torch.cuda.synchronize()
-        copy_gbs = 2 * src.numel() * 8 * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        del src, dstc
-        happly["copy_1GiB_GB/s"] = round(copy_gbs, 1)
-
-        def rate(c, syss, pr, dt, Dn, label, note=None):
-            n = len(syss)
-            x = torch.randn(n, Dn, dtype=dt, device=dev)
-            y = torch.empty_like(x)
-            ms = msb.msb_apply_timed(c, syss, 0.0, pr, x, y, 50)
-            gbs = 2 * n * Dn * x.element_size() / (ms * 1e-3) / 1e9
-            happly[label] = {"ms": round(ms, 5), "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                             "frac_of_copy": round(gbs / copy_gbs, 4)}
-            if note:
-                happly[label]["note"] = note
-            del x, y
-        rate(ctx, systems, prec, cdt, D, f"{wl.name}_x{len(systems)}",
-             f"the solve's block of {len(systems)} vectors ({len(systems) * D * (16 if prec == msb.MSB_C128 else 8) / 1e6:.0f} MB)")
-        rate(ctx, systems[:1], prec, cdt, D, wl.name, "one 13.7 MB vector: served from the 256 MB Infinity Cache")
-        for other in ("precision", "batched"):
-            wo = W.get(other)
-            c2 = msb.msb_create(wo.n_sites, wo.n_up, wo.n_dn, wo.bonds, wo.U)
-            D2 = msb.msb_dim(c2)
-            s2 = [msb.make_system(core_site=c, Uc=wo.Uc, E_G=-4.0, Gamma=wo.Gamma) for c in wo.core_sites]
-            if other == "precision":
-                for dname, dt, pr in (("c128", torch.complex128, msb.MSB_C128), ("c64", torch.complex64, msb.MSB_C64)):
-                    rate(c2, s2, pr, dt, D2, f"{wo.name}_{dname}", "HBM-resident")
-            else:
-                rate(c2, s2, msb.MSB_C64, torch.complex64, D2, f"{wo.name}_c64_x{len(s2)}", "HBM-resident block")
-            msb.msb_destroy(c2)
+        happly = h_apply_rates(msb, ctx, wl, systems, prec)
         out["h_apply"] = happly
         log(f"h_apply {happly}")
 
@@ -866,6 +885,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="only the H-apply rates (--steps applies per shape)")
     ap.add_argument("--no-forms", action="store_true",
                     help="scale workload: skip the precision and batched forms")
     ap.add_argument("--copy-probe", action="store_true",
@@ -890,6 +911,18 @@ def main():
         return
     if args.workload == "dipole":
         dipole_main(args)
+        return
+    if args.apply_only:
+        # the H-apply rates alone (for profiling the apply kernels)
+        import paper_2506_09551_amd as msb
+        import workloads as W
+        wl = W.get("scale")
+        ctx = msb.msb_create(wl.n_sites, wl.n_up, wl.n_dn, wl.bonds, wl.U)
+        systems = [msb.make_system(core_site=c, Uc=wl.Uc, E_G=-4.0, Gamma=wl.Gamma) for c in wl.core_sites]
+        out = {"metric": "H-apply HBM GB/s", "h_apply": h_apply_rates(msb, ctx, wl, systems, msb.MSB_C128,
+                                                                     reps=args.steps)}
+        msb.msb_destroy(ctx)
+        print(json.dumps(out), flush=True)
         return
 
     out = run_solver_workload(args.workload, args, extras=not args.no_extras, cpu=not args.no_cpu)

@@ -174,8 +174,8 @@ typedef struct {
   double mem_fraction;   /* fraction of free device memory the workspace may use (default 0.9) */
   int assembly_engine;   /* multi-shift assembly, all in FP64: 0 = vector ALU with three real
                             products per complex product (default), 1 = matrix cores, 2 = vector
-                            ALU with four real products, 3 / 4 = as 0 with 256 elements per
-                            workgroup / and eight wavefronts of four shifts each */
+                            ALU with four real products, 3 = as 0 with 64 shifts per workgroup,
+                            4 = as 0 with 256 elements and eight wavefronts of four shifts */
   int autotune;          /* 0 = tune the apply shape on first use (default), -1 = default shape
                             unless one was tuned or pinned before */
   int dual;              /* 0 = the dual-space (BiCG) form only when some system's A is not
@@ -186,6 +186,11 @@ typedef struct {
                             p_m and applies A to it (Algorithm 1 as written); 1 = that direct
                             form in both precisions.  Other values: MSB_EINVAL (a product
                             carried in complex64 storage drifts from A p_m) */
+  int interleave;        /* 1 = in the direct seed form, batches of two or more systems keep p and
+                            A p with the systems of a group of 4 (or 2) interleaved element by
+                            element and run the two-pass block apply of msb_apply_block (one
+                            neighbour-row gather per group); 0 or -1 = (default) one vector per
+                            system (measured faster on the workloads here) */
 } msb_opts;
 
 /* ---- context -------------------------------------------------------------- */
@@ -230,6 +235,22 @@ msb_status msb_apply(msb_ctx* ctx, const msb_system* sys, int nsys, double shift
  * Same arguments and errors as msb_apply; reps >= 1. */
 msb_status msb_apply_timed(msb_ctx* ctx, const msb_system* sys, int nsys, double shift,
                            msb_prec prec, const void* x, void* y, int reps,
+                           double* ms_per_apply, void* stream);
+
+/* The block apply (SpMM) of the batched form: y_s = (H'_s - E_G_s - i Gamma_s - shift) x_s
+ * for s < nsys, with the vectors of each group of `group` (2 or 4) systems
+ * interleaved element by element: x, y are [ceil(nsys / group)][D][group]
+ * (element i of system s at (s / group * D + i) * group + s % group), so one
+ * gather of a neighbour row serves the whole group.  Runs as two passes
+ * (column panels for the diagonal and H_up (x) I, rows staged in LDS for
+ * I (x) H_dn); y is written in full for the nsys systems (the slots of a
+ * ragged last group are not).  With ms_per_apply != NULL, `reps` more applies
+ * are timed with HIP events and their mean is returned.
+ * Errors: MSB_EINVAL for group not 2 or 4, nsys < group, or rows of `group`
+ * systems that do not fit a workgroup's LDS (MSB_C64: D's row of up to 5119
+ * states for groups of 4; MSB_C128: 2559), and as msb_apply. */
+msb_status msb_apply_block(msb_ctx* ctx, const msb_system* sys, int nsys, double shift,
+                           msb_prec prec, int group, const void* x, void* y, int reps,
                            double* ms_per_apply, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph

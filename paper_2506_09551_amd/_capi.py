@@ -60,7 +60,8 @@ class msb_shape(ctypes.Structure):
 class msb_opts(ctypes.Structure):
     _fields_ = [("chunk", c_int), ("bank_slots", c_int), ("batch", c_int),
                 ("replace_every", c_int), ("use_graph", c_int), ("mem_fraction", c_double),
-                ("assembly_engine", c_int), ("autotune", c_int), ("dual", c_int), ("direct_ap", c_int)]
+                ("assembly_engine", c_int), ("autotune", c_int), ("dual", c_int), ("direct_ap", c_int),
+                ("interleave", c_int)]
 
 
 _lib = None
@@ -95,6 +96,9 @@ def lib():
         L.msb_apply.argtypes = [c_void_p, POINTER(msb_system), c_int, c_double, c_int, c_void_p,
                                 c_void_p, c_void_p]
         L.msb_apply.restype = c_int
+        L.msb_apply_block.argtypes = [c_void_p, POINTER(msb_system), c_int, c_double, c_int, c_int, c_void_p,
+                                      c_void_p, c_int, POINTER(c_double), c_void_p]
+        L.msb_apply_block.restype = c_int
         L.msb_apply_noalloc.argtypes = [c_void_p, POINTER(msb_system), c_int, c_double, c_int, c_void_p,
                                         c_void_p, c_void_p]
         L.msb_apply_noalloc.restype = c_int
@@ -161,7 +165,7 @@ def lib():
 def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["msb_create", "msb_destroy", "msb_release_workspace", "msb_dim", "msb_sector_info", "msb_last_error",
-            "msb_device_ok", "msb_stream_create", "msb_stream_destroy", "msb_apply", "msb_apply_noalloc", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
+            "msb_device_ok", "msb_stream_create", "msb_stream_destroy", "msb_apply", "msb_apply_block", "msb_apply_noalloc", "msb_apply_timed", "msb_number_op", "msb_ground_state", "msb_solve",
             "msb_solve_reseed", "msb_dipole",
             "msb_combine", "msb_spectrum", "msb_spectrum_cf", "msb_autotune", "msb_set_shape",
             "msb_mlp_num_params", "msb_mlp_create", "msb_mlp_destroy", "msb_mlp_set_params",
@@ -304,6 +308,21 @@ def msb_apply(ctx, systems, shift: float, prec: int, x, y, stream=None):
     dt = _prec_dtype(prec)
     _check(lib().msb_apply(ctx, arr, n, float(shift), int(prec), _ptr(x, dt, n * D, "x"),
                            _ptr(y, dt, n * D, "y"), _stream_ptr(stream)))
+
+
+def msb_apply_block(ctx, systems, shift: float, prec: int, group: int, x, y, reps: int = 0, stream=None):
+    """Block apply on interleaved groups: x, y [ceil(nsys/group)][D][group] (any
+    contiguous tensor of that many elements); returns the mean time (ms) of
+    `reps` timed applies, or None when reps == 0."""
+    arr, n = _systems(systems)
+    D = msb_dim(ctx)
+    dt = _prec_dtype(prec)
+    ng = (n + group - 1) // group
+    ms = c_double()
+    _check(lib().msb_apply_block(ctx, arr, n, float(shift), int(prec), int(group), _ptr(x, dt, ng * group * D, "x"),
+                                 _ptr(y, dt, ng * group * D, "y"), int(reps),
+                                 ctypes.byref(ms) if reps > 0 else None, _stream_ptr(stream)))
+    return ms.value if reps > 0 else None
 
 
 def msb_apply_noalloc(ctx, systems, shift: float, prec: int, x, y, stream=None):

@@ -643,4 +643,340 @@ hipError_t launch_apply(Elem e, int mode, const ApplyArgs& a, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
+
+// ---- interleaved block apply (the batched form's SpMM) ----------------------
+// G systems stored interleaved, x[g][D][G] (the element (row u, column d) of
+// system g*G + s at ((g * D + u * n_dn + d) * G + s)), so one neighbour-row
+// gather brings the same element of all G right-hand sides in one contiguous
+// load and one hop-table word serves them all.  Two passes:
+//  * k_apply_up_il: the diagonal and H_up (x) I on column panels of 64 / G
+//    columns x G systems (one lane per (column, system), the panel of every
+//    row stays in one XCD's L2 while the rows gather from it; work items as
+//    in k_apply_up, with one signed amplitude per system);
+//  * k_apply_dn_il: one workgroup per row stages the G interleaved rows in
+//    LDS, adds I (x) H_dn to the first pass's output in place and fuses the
+//    COCG partial sums sigma = r^T v, |v|^2 (r from the residual bank, one
+//    vector per system).
+template <typename S, typename Tc, int G>
+__global__ __launch_bounds__(256) void k_apply_up_il(ApplyArgs a) {
+  using Ax = Access<S, true>;
+  constexpr int W = kWave / G;                           // columns of a panel
+  __shared__ int s_off[kRowsPerWg + 1];
+  __shared__ uint32_t s_tgt[kPanelItems];
+  __shared__ Tc s_cf[kPanelItems][G];
+  const int grp = blockIdx.y;
+  const int nd = a.T.n_dn, nu = a.T.n_up;
+  const int chunks = (nu + kRowsPerWg - 1) / kRowsPerWg;
+  const int xq = blockIdx.x % kNumXcd, l = blockIdx.x / kNumXcd;
+  const int panel = xq + kNumXcd * (l / chunks), chunk = l % chunks;
+  if (panel * W >= nd) return;
+  const int r0 = chunk * kRowsPerWg;
+  const int nrows = min(kRowsPerWg, nu - r0);
+  if (threadIdx.x == 0) {
+    int o = 0;
+    for (int r = 0; r < nrows; ++r) {
+      s_off[r] = o;
+      o += 1 + (int)(a.T.off_up[r0 + r + 1] - a.T.off_up[r0 + r]);
+    }
+    s_off[nrows] = o;                                   // <= kPanelItems (panel_fits on the host)
+  }
+  __syncthreads();
+  const int n_items = s_off[nrows];
+  for (int t = threadIdx.x; t < n_items; t += blockDim.x) {
+    int r = 0;
+    while (t >= s_off[r + 1]) ++r;
+    const int u = r0 + r, k = t - s_off[r];
+    if (k == 0) {
+      s_tgt[t] = kDiagItem | (uint32_t)u;
+#pragma unroll
+      for (int g = 0; g < G; ++g) s_cf[t][g] = (Tc)0;
+    } else {
+      const uint32_t h = a.T.hop_up[a.T.off_up[u] + k - 1];
+      s_tgt[t] = h >> 16;
+      const uint32_t ty = (h >> 1) & (MSB_MAX_BOND_TYPES - 1), sb = (h & 1u) ? 0u : 0x80000000u;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int s = min(grp * G + g, a.nsys - 1);
+        s_cf[t][g] = flip_sign((Tc)a.sys[s].amp[ty], sb);
+      }
+    }
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rows_per_wave = kRowsPerWg / 4;
+  const int i0 = s_off[min(wave * rows_per_wave, nrows)];
+  const int i1 = s_off[min((wave + 1) * rows_per_wave, nrows)];
+  const int gs = lane % G, col = lane / G;
+  const int s = grp * G + gs;
+  const int d = panel * W + col;
+  const bool ok = d < nd && s < a.nsys &&
+                  (!a.status || a.status[(int64_t)min(s, a.nsys - 1) * a.status_stride] == kActive);
+  const uint32_t dc = (uint32_t)(d < nd ? d : nd - 1);   // idle lanes read a valid column
+  const uint32_t cd = a.T.conf_dn[dc];
+  const SysDev* sd = a.sys + min(s, a.nsys - 1);
+  const Tc U = (Tc)sd->U, Uc = (Tc)sd->Uc, dre = (Tc)sd->d_re, dim = (Tc)sd->d_im;
+  const int core = sd->core;
+  const void* xg = Ax::offset(a.x, (int64_t)grp * a.D * G);
+  void* vg = Ax::offset(a.v, (int64_t)grp * a.D * G);
+  auto idx = [&](int row) { return ((int64_t)row * nd + dc) * G + gs; };
+  cv<Tc> buf[kPrefetch];
+#pragma unroll
+  for (int j = 0; j < kPrefetch; ++j)
+    if (i0 + j < i1) buf[j] = Ax::template load<Tc>(xg, idx((int)(s_tgt[i0 + j] & ~kDiagItem)));
+  int row = -1;
+  cv<Tc> acc = {(Tc)0, (Tc)0};
+  for (int i = i0; i < i1; i += kPrefetch) {
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) {
+      const int it = i + j;
+      if (it < i1) {                                    // uniform across the wavefront
+        const uint32_t tg = s_tgt[it];
+        const cv<Tc> xv = buf[j];
+        if (it + kPrefetch < i1)
+          buf[j] = Ax::template load<Tc>(xg, idx((int)(s_tgt[it + kPrefetch] & ~kDiagItem)));
+        if (tg & kDiagItem) {
+          if (row >= 0 && ok) Ax::store(vg, idx(row), acc);
+          row = (int)(tg & ~kDiagItem);
+          const uint32_t cu = a.T.conf_up[row];
+          Tc dg = U * (Tc)__builtin_popcount(cu & cd) + dre;
+          if (core >= 0) dg += Uc * (Tc)(((cu >> core) & 1u) + ((cd >> core) & 1u));
+          acc = {dg * xv.re - dim * xv.im, dg * xv.im + dim * xv.re};
+        } else {
+          const Tc c = s_cf[it][gs];
+          acc.re += c * xv.re;
+          acc.im += c * xv.im;
+        }
+      }
+    }
+  }
+  if (row >= 0 && ok) Ax::store(vg, idx(row), acc);
+}
+
+// G consecutive complex values (one element of the G systems of a group).
+template <typename S, typename Tc, int G>
+struct GroupIO {
+  static __device__ __forceinline__ void load(const void* base, int64_t i, cv<Tc> (&out)[G]) {
+    if constexpr (std::is_same<S, float>::value && G % 2 == 0) {
+      const float4* p = reinterpret_cast<const float4*>(reinterpret_cast<const cv<float>*>(base) + i);
+#pragma unroll
+      for (int h = 0; h < G / 2; ++h) {
+        const float4 t = p[h];
+        out[2 * h] = {(Tc)t.x, (Tc)t.y};
+        out[2 * h + 1] = {(Tc)t.z, (Tc)t.w};
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < G; ++g) out[g] = Access<S, true>::template load<Tc>(base, i + g);
+    }
+  }
+  static __device__ __forceinline__ void store(void* base, int64_t i, const cv<Tc> (&v)[G]) {
+    if constexpr (std::is_same<S, float>::value && G % 2 == 0) {
+      float4* p = reinterpret_cast<float4*>(reinterpret_cast<cv<float>*>(base) + i);
+#pragma unroll
+      for (int h = 0; h < G / 2; ++h)
+        p[h] = make_float4((float)v[2 * h].re, (float)v[2 * h].im, (float)v[2 * h + 1].re, (float)v[2 * h + 1].im);
+    } else {
+#pragma unroll
+      for (int g = 0; g < G; ++g) Access<S, true>::store(base, i + g, v[g]);
+    }
+  }
+};
+
+template <typename S, typename Tc, int G, int EPT, int BLK, int MODE>
+__global__ __launch_bounds__(BLK) void k_apply_dn_il(ApplyArgs a) {
+  using Ax = Access<S, true>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cv<Tc>* rows = reinterpret_cast<cv<Tc>*>(smem_raw);     // [nd + 1][G], element nd = 0
+  const int tid = threadIdx.x;
+  const int nd = a.T.n_dn;
+  const int bx = blockIdx.x, grp = blockIdx.y;
+  const int u = (bx % kNumXcd) * a.rows_per_xcd + bx / kNumXcd;
+  const bool row_ok = u < a.T.n_up;
+  bool act[G];
+  int64_t aux_off[G];
+  const int abase = a.aux_m ? *a.aux_base : 0;
+  bool any = false;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int s = grp * G + g;
+    const bool in = row_ok && s < a.nsys;
+    act[g] = in && (!a.status || a.status[(int64_t)s * a.status_stride] == (int)kActive);
+    any |= act[g];
+    aux_off[g] = 0;
+    if (in && a.aux_m) {
+      int slot = a.aux_m[(int64_t)s * a.status_stride] - abase;
+      slot = slot < 0 ? 0 : (slot >= a.aux_cap ? a.aux_cap - 1 : slot);
+      aux_off[g] = ((int64_t)s * a.aux_cap + slot) * a.D;
+    } else if (in) {
+      aux_off[g] = (int64_t)s * a.D;
+    }
+  }
+  double part[G][3];
+#pragma unroll
+  for (int g = 0; g < G; ++g) part[g][0] = part[g][1] = part[g][2] = 0.0;
+  if (any) {
+    const int64_t row0 = (int64_t)u * nd;
+    const void* xg = Ax::offset(a.x, (int64_t)grp * a.D * G);
+    void* vg = Ax::offset(a.v, (int64_t)grp * a.D * G);
+    uint32_t voff[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int d = tid + e * BLK;
+      voff[e] = (uint32_t)(d < nd ? d : nd - 1);
+    }
+    cv<Tc> acc[EPT][G];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int d = tid + e * BLK;
+      cv<Tc> xs[G];
+      GroupIO<S, Tc, G>::load(xg, (row0 + voff[e]) * G, xs);
+      GroupIO<S, Tc, G>::load(vg, (row0 + voff[e]) * G, acc[e]);   // diagonal and up-spin hops
+      if (d < nd) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) rows[d * G + g] = xs[g];
+      }
+    }
+    if (tid < G) rows[nd * G + tid] = cv<Tc>{(Tc)0, (Tc)0};
+    __syncthreads();
+    const uint64_t* ell = a.T.ell_dn;
+    for (int t = 0; t < a.T.n_types; ++t) {
+      const int kq = a.T.k_type[t];
+      Tc amp[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) amp[g] = act[g] ? (Tc)a.sys[grp * G + g].amp[t] : (Tc)0;
+      uint64_t hn[EPT];
+      if (kq > 0) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) hn[e] = ell[voff[e]];
+      }
+      for (int q = 0; q < kq; ++q) {
+        uint32_t hw[EPT][2];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          hw[e][0] = (uint32_t)hn[e];
+          hw[e][1] = (uint32_t)(hn[e] >> 32);
+        }
+        if (q + 1 < kq) {
+          const uint64_t* nxt = ell + (int64_t)(q + 1) * nd;
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) hn[e] = nxt[voff[e]];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const uint32_t ent = (hw[e][j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+            const uint32_t sb = (ent & 0x8000u) << 16;
+            const int tgt = (int)(ent & 0x7FFFu);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+              const Tc c = flip_sign(amp[g], sb);
+              const cv<Tc> xv = rows[tgt * G + g];
+              acc[e][g].re += c * xv.re;
+              acc[e][g].im += c * xv.im;
+            }
+          }
+      }
+      ell += (int64_t)kq * nd;
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int d = tid + e * BLK;
+      if (d >= nd) continue;
+      cv<Tc> vs[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) vs[g] = act[g] ? acc[e][g] : cv<Tc>{(Tc)0, (Tc)0};
+      GroupIO<S, Tc, G>::store(vg, (row0 + d) * G, vs);
+      if constexpr (MODE == kModeBilinear) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          if (!act[g]) continue;
+          const cv<double> r = Ax::template load_nt<double>(a.aux, aux_off[g] + row0 + d);
+          const cv<double> w = {(double)(S)vs[g].re, (double)(S)vs[g].im};   // value as stored
+          part[g][0] += r.re * w.re - r.im * w.im;
+          part[g][1] += r.re * w.im + r.im * w.re;
+          part[g][2] += w.re * w.re + w.im * w.im;
+        }
+      }
+    }
+  }
+  if constexpr (MODE != kModePlain) {
+    __shared__ double sh[3 * G][BLK / kWave];
+    double flat[3 * G];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) flat[3 * g + i] = part[g][i];
+    block_sum<3 * G, BLK>(flat, sh);
+    if (tid == 0) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int s = grp * G + g;
+        if (s >= a.nsys) continue;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) a.partials[((int64_t)s * a.nbx + bx) * 4 + i] = flat[3 * g + i];
+      }
+    }
+  }
+}
+
+// LDS the row pass takes besides the staged rows (its reduction buffer)
+constexpr size_t kIlStaticLds = 4096;
+
+int apply_il_width(int nd, size_t elem_bytes, int nsys, size_t lds_max, int k_up_max) {
+  if (!panel_fits(k_up_max)) return 0;
+  for (int g : {4, 2})
+    if (nsys >= g && (size_t)g * (nd + 1) * elem_bytes + kIlStaticLds <= lds_max && nd <= 1024 * 10) return g;
+  return 0;
+}
+
+template <typename S, typename Tc, int G, int MODE>
+static hipError_t launch_il_mode(const ApplyArgs& a, hipStream_t st) {
+  const int nd = a.T.n_dn;
+  if ((size_t)G * (nd + 1) * sizeof(cv<Tc>) + kIlStaticLds > a.lds_max) return hipErrorInvalidValue;
+  const int groups = (a.nsys + G - 1) / G;
+  const int W = kWave / G;
+  const int n_panels = (nd + W - 1) / W;
+  const int chunks = (a.T.n_up + kRowsPerWg - 1) / kRowsPerWg;
+  const int pnbx = kNumXcd * ((n_panels + kNumXcd - 1) / kNumXcd) * chunks;
+  hipLaunchKernelGGL((k_apply_up_il<S, Tc, G>), dim3(pnbx, groups), dim3(256), 0, st, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const dim3 grid(a.nbx, groups);
+  const size_t lds = (size_t)G * (nd + 1) * sizeof(cv<Tc>);
+  err = hipErrorInvalidValue;
+  // rows that fit the LDS: at most 5 elements per thread of a 1024-thread
+  // workgroup (10 for pairs of complex64 systems, 3 for quadruples of complex128)
+  constexpr int kMaxE = (sizeof(S) == 4 && G == 2) ? 10 : (sizeof(S) == 8 && G == 4) ? 3 : 5;
+#define MSB_IL_CASE(B, E)                                                                  \
+  else if (((B) == 256) == (nd <= 1024) && (int64_t)(B) * (E) >= nd &&                      \
+           (int64_t)(B) * ((E) - 1) < nd) {                                                 \
+    if constexpr ((E) <= kMaxE) {                                                           \
+      hipLaunchKernelGGL((k_apply_dn_il<S, Tc, G, E, B, MODE>), grid, dim3(B), lds, st, a); \
+      err = hipGetLastError();                                                              \
+    }                                                                                       \
+  }
+  if (false) {}
+  MSB_IL_CASE(256, 1) MSB_IL_CASE(256, 2) MSB_IL_CASE(256, 3) MSB_IL_CASE(256, 4)
+  MSB_IL_CASE(1024, 2) MSB_IL_CASE(1024, 3) MSB_IL_CASE(1024, 4) MSB_IL_CASE(1024, 5)
+  MSB_IL_CASE(1024, 6) MSB_IL_CASE(1024, 7) MSB_IL_CASE(1024, 8) MSB_IL_CASE(1024, 9) MSB_IL_CASE(1024, 10)
+#undef MSB_IL_CASE
+  if (err != hipSuccess || MODE == kModePlain) return err;
+  return launch_reduce(a.partials, a.nbx, a.nsys, a.red, st);
+}
+
+hipError_t launch_apply_il(Elem e, int mode, int G, const ApplyArgs& a, hipStream_t st) {
+  if (a.aux_m && !a.aux) return hipErrorInvalidValue;
+#define MSB_IL_DISPATCH(S, TC)                                                          \
+  if (G == 4 && mode == kModePlain) return launch_il_mode<S, TC, 4, kModePlain>(a, st);       \
+  if (G == 4 && mode == kModeBilinear) return launch_il_mode<S, TC, 4, kModeBilinear>(a, st); \
+  if (G == 2 && mode == kModePlain) return launch_il_mode<S, TC, 2, kModePlain>(a, st);       \
+  if (G == 2 && mode == kModeBilinear) return launch_il_mode<S, TC, 2, kModeBilinear>(a, st);
+  if (e == Elem::C128) { MSB_IL_DISPATCH(double, double) }
+  if (e == Elem::C64) { MSB_IL_DISPATCH(float, float) }
+#undef MSB_IL_DISPATCH
+  return hipErrorInvalidValue;
+}
 }  // namespace msb

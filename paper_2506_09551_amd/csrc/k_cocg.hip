@@ -34,6 +34,15 @@ constexpr int kPerStep = kBlock * kEptStream;
 
 int cocg_nbx(int64_t D, int nsys) { return stream_nbx(D, nsys, kPerStep); }
 
+// Element offset of (system s, index i) in p and v: one vector per system, or
+// groups of il systems interleaved ([nsys / il][D][il]).  With il the grid is
+// (system, block) so that the systems of a group stream the same lines together.
+__device__ __forceinline__ int64_t pv_index(int il, int64_t D, int s, int64_t i) {
+  return il ? ((int64_t)(s / il) * D + i) * il + s % il : (int64_t)s * D + i;
+}
+__device__ __forceinline__ int grid_sys(int il) { return il ? blockIdx.x : blockIdx.y; }
+__device__ __forceinline__ int grid_blk(int il) { return il ? blockIdx.y : blockIdx.x; }
+
 __device__ __forceinline__ bool sigma_breakdown(const SysState& st, const double* red1, int s,
                                                 cv<double>& alpha) {
   const cv<double> sigma = {red1[s * 4 + 0], red1[s * 4 + 1]};
@@ -48,10 +57,9 @@ template <typename S>
 __global__ __launch_bounds__(kBlock) void k_cocg_init(InitArgs a) {
   using Ax = Access<S, true>;
   using A64 = Access<double, true>;
-  const int s = blockIdx.y, bx = blockIdx.x;
+  const int s = grid_sys(a.il), bx = grid_blk(a.il);
   double part[3] = {0.0, 0.0, 0.0};
   void* r0 = Ax::offset(a.bank, (int64_t)s * a.cap * a.D);
-  void* p = Ax::offset(a.pvec, (int64_t)s * a.D);
   for (int64_t base = (int64_t)bx * kPerStep; base < a.D; base += (int64_t)a.nbx * kPerStep) {
 #pragma unroll
     for (int e = 0; e < kEptStream; ++e) {
@@ -60,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_init(InitArgs a) {
         const cv<double> x = A64::template load<double>(a.E, (int64_t)s * a.D + i);
         const cv<double> xs = {(double)(S)x.re, (double)(S)x.im};
         Ax::store(r0, i, xs);
-        Ax::store(p, i, xs);
+        Ax::store(a.pvec, pv_index(a.il, a.D, s, i), xs);
         if (a.rt) {                     // dual-space form: r~_0 = p~_0 = E
           Ax::store(Ax::offset(a.rt, (int64_t)s * a.D), i, xs);
           Ax::store(Ax::offset(a.pt, (int64_t)s * a.D), i, xs);
@@ -123,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_init_fin(InitArgs a) {
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_cocg_r(CocgArgs a) {
   using Ax = Access<S, true>;
-  const int s = blockIdx.y, bx = blockIdx.x;
+  const int s = grid_sys(a.il), bx = grid_blk(a.il);
   // rho_{m+1} (bilinear: r~^T r, or r^T r), |r_{m+1}|^2, |r~_{m+1}|^2
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   const SysState st = a.st[s];
@@ -135,17 +143,16 @@ __global__ __launch_bounds__(kBlock) void k_cocg_r(CocgArgs a) {
       const void* vt = a.rt ? Ax::offset(a.vt, (int64_t)s * a.D) : nullptr;
       const void* r = Ax::offset((const void*)a.bank, ((int64_t)s * a.cap + slot) * a.D);
       void* rn = Ax::offset(a.bank, ((int64_t)s * a.cap + slot + 1) * a.D);
-      const void* v = Ax::offset(a.vvec, (int64_t)s * a.D);
       for (int64_t base = (int64_t)bx * kPerStep; base < a.D; base += (int64_t)a.nbx * kPerStep) {
 #pragma unroll
         for (int e = 0; e < kEptStream; ++e) {
           const int64_t i = base + e * kBlock + threadIdx.x;
           if (i < a.D) {
             const cv<double> ri = Ax::template load<double>(r, i);
-            const cv<double> vi = Ax::template load<double>(v, i);
+            const cv<double> vi = Ax::template load<double>(a.vvec, pv_index(a.il, a.D, s, i));
             if (a.xseed) {          // seed solution for residual replacement: x += alpha p
               using A64 = Access<double, true>;
-              const cv<double> pi = Ax::template load<double>(Ax::offset((const void*)a.pvec, (int64_t)s * a.D), i);
+              const cv<double> pi = Ax::template load<double>(a.pvec, pv_index(a.il, a.D, s, i));
               cv<double> xs = A64::template load<double>(a.xseed, (int64_t)s * a.D + i);
               xs = cadd(xs, cmul(alpha, pi));
               A64::store(a.xseed, (int64_t)s * a.D + i, xs);
@@ -258,12 +265,11 @@ __global__ __launch_bounds__(kBlock) void k_cocg_book(CocgArgs a) {
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
   using Ax = Access<S, true>;
-  const int s = blockIdx.y, bx = blockIdx.x;
+  const int s = grid_sys(a.il), bx = grid_blk(a.il);
   const SysState st = a.st[s];
   if (st.status != kActive) return;
   const int slot = st.m - *a.base;
   const void* r = Ax::offset((const void*)a.bank, ((int64_t)s * a.cap + slot) * a.D);
-  void* p = Ax::offset(a.pvec, (int64_t)s * a.D);
   const cv<double> beta = {st.be_re, st.be_im};
   const void* rt = a.rt ? Ax::offset((const void*)a.rt, (int64_t)s * a.D) : nullptr;
   void* pt = a.rt ? Ax::offset(a.pt, (int64_t)s * a.D) : nullptr;
@@ -272,11 +278,12 @@ __global__ __launch_bounds__(kBlock) void k_cocg_p(CocgArgs a) {
     for (int e = 0; e < kEptStream; ++e) {
       const int64_t i = base + e * kBlock + threadIdx.x;
       if (i < a.D) {
+        const int64_t pi_ = pv_index(a.il, a.D, s, i);
         const cv<double> ri = Ax::template load<double>(r, i);
-        const cv<double> pi = Ax::template load<double>(p, i);
+        const cv<double> pi = Ax::template load<double>(a.pvec, pi_);
         const cv<double> x = {ri.re + beta.re * pi.re - beta.im * pi.im,
                               ri.im + beta.re * pi.im + beta.im * pi.re};
-        Ax::store(p, i, x);
+        Ax::store(a.pvec, pi_, x);
         if (pt) {                       // p~ = r~ + beta p~
           const cv<double> rti = Ax::template load<double>(rt, i);
           const cv<double> pti = Ax::template load<double>(pt, i);
@@ -401,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_cocg_replace_fin(CocgArgs a) {
 }
 
 hipError_t launch_cocg_init(Elem e, const InitArgs& a, hipStream_t st) {
-  dim3 grid(a.nbx, a.nsys);
+  const dim3 grid = a.il ? dim3(a.nsys, a.nbx) : dim3(a.nbx, a.nsys);
   if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_init<double>, grid, dim3(kBlock), 0, st, a);
   else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_init<float>, grid, dim3(kBlock), 0, st, a);
   else return hipErrorInvalidValue;
@@ -412,7 +419,7 @@ hipError_t launch_cocg_init(Elem e, const InitArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st) {
-  dim3 grid(a.nbx, a.nsys);
+  const dim3 grid = a.il ? dim3(a.nsys, a.nbx) : dim3(a.nbx, a.nsys);
   if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_r<double>, grid, dim3(kBlock), 0, st, a);
   else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_r<float>, grid, dim3(kBlock), 0, st, a);
   else return hipErrorInvalidValue;
@@ -433,7 +440,7 @@ hipError_t launch_seed_rebuild(Elem e, const RebuildArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_cocg_p(Elem e, const CocgArgs& a, hipStream_t st) {
-  dim3 grid(a.nbx, a.nsys);
+  const dim3 grid = a.il ? dim3(a.nsys, a.nbx) : dim3(a.nbx, a.nsys);
   if (e == Elem::C128) hipLaunchKernelGGL(k_cocg_p<double>, grid, dim3(kBlock), 0, st, a);
   else if (e == Elem::C64) hipLaunchKernelGGL(k_cocg_p<float>, grid, dim3(kBlock), 0, st, a);
   else return hipErrorInvalidValue;

@@ -139,7 +139,7 @@ struct GaussShape {
   int M, EPL, NW;
 };
 __host__ __device__ constexpr GaussShape gauss_shape(int engine) {
-  return engine == 3 ? GaussShape{8, 4, 4} : engine == 4 ? GaussShape{4, 4, 8} : GaussShape{8, 2, 4};
+  return engine == 3 ? GaussShape{8, 2, 8} : engine == 4 ? GaussShape{4, 4, 8} : GaussShape{8, 2, 4};
 }
 int flush_shifts_per_tile(int engine) {
   if (engine == 1) return kFlushM * kFlushWaves;

@@ -564,6 +564,51 @@ extern "C" msb_status msb_apply_timed(msb_ctx* ctx, const msb_system* sys, int n
   return MSB_OK;
 }
 
+extern "C" msb_status msb_apply_block(msb_ctx* ctx, const msb_system* sys, int nsys, double shift,
+                                      msb_prec prec, int group, const void* x, void* y, int reps,
+                                      double* ms_per_apply, void* stream) {
+  (void)hipGetLastError();   // do not report an earlier call's failure
+  if (!ctx || !sys || !x || !y) return fail(MSB_EINVAL, "msb_apply_block: null argument");
+  if (nsys <= 0 || nsys > 65535) return fail(MSB_EINVAL, "msb_apply_block: nsys out of range");
+  if (!valid_prec(prec)) return fail(MSB_EINVAL, "msb_apply_block: invalid precision");
+  if (ms_per_apply && reps < 1) return fail(MSB_EINVAL, "msb_apply_block: reps must be >= 1");
+  const Elem e = prec == MSB_C128 ? Elem::C128 : Elem::C64;
+  const int width = apply_il_width(ctx->dn.n, elem_bytes(e), nsys, ctx->lds_max, ctx->up.max_hops);
+  if (group != 2 && group != 4) return fail(MSB_EINVAL, "msb_apply_block: group must be 2 or 4");
+  if (width < group)
+    return fail(MSB_EINVAL, "msb_apply_block: a group of " + std::to_string(group) +
+                                " rows does not fit one workgroup's LDS here (or nsys < group)");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<SysDev> h(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    msb_status r = make_sysdev(ctx, sys[s], -(sys[s].E_G + shift), -sys[s].Gamma, true, h[s]);
+    if (r != MSB_OK) return r;
+  }
+  Arena ar(ctx);
+  ar.reserve(sizeof(SysDev) * nsys);
+  MSB_HIP(ar.commit());
+  SysDev* dsys = ar.take<SysDev>(sizeof(SysDev) * nsys);
+  MSB_HIP(hipMemcpyAsync(dsys, h.data(), sizeof(SysDev) * nsys, hipMemcpyHostToDevice, st));
+  ApplyArgs a = apply_args(ctx, dsys, nsys, x, y);
+  MSB_HIP(launch_apply_il(e, kModePlain, group, a, st));
+  if (ms_per_apply) {
+    hipEvent_t e0, e1;
+    MSB_HIP(hipEventCreate(&e0));
+    MSB_HIP(hipEventCreate(&e1));
+    MSB_HIP(hipEventRecord(e0, st));
+    for (int i = 0; i < reps; ++i) MSB_HIP(launch_apply_il(e, kModePlain, group, a, st));
+    MSB_HIP(hipEventRecord(e1, st));
+    MSB_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    MSB_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_apply = ms / reps;
+  }
+  MSB_HIP(hipStreamSynchronize(st));
+  return MSB_OK;
+}
+
 extern "C" msb_status msb_apply_noalloc(msb_ctx* ctx, const msb_system* sys, int nsys, double shift,
                                         msb_prec prec, const void* x, void* y, void* stream) {
   (void)hipGetLastError();   // do not report an earlier call's failure
@@ -851,8 +896,9 @@ struct SolveBufs {
     for (int n = 1; n <= B; ++n)
       part_n = std::max(part_n, (size_t)n * std::max(apply_nbx(ctx->up.n, n), cocg_nbx(D, n)));
     bank = c.take<void>((size_t)cap * B * D * s_el);
-    pvec = c.take<void>((size_t)B * D * s_el);
-    vvec = c.take<void>((size_t)B * D * s_el);
+    const size_t Bp = ((size_t)B + 3) / 4 * 4;   // whole groups of an interleaved batch
+    pvec = c.take<void>(Bp * D * s_el);
+    vvec = c.take<void>(Bp * D * s_el);
     Pc = carry ? c.take<void>((size_t)B * n_shift * D * s_out) : nullptr;
     dsys = c.take<SysDev>(B * sizeof(SysDev));
     dst = c.take<SysState>(B * sizeof(SysState));
@@ -964,6 +1010,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   if (dap < 0) return fail(MSB_EINVAL, "msb_solve: direct_ap must be 0 or 1 (the recurred seed form runs in "
                                         "complex128 only)");
   const bool recur = !dual && dap != 1 && prec == MSB_C128;
+  // interleaved block apply (direct seed form, two or more systems per batch)
+  const bool il_ok = !recur && !dual && opts && opts->interleave > 0;
   if (dual) {
     if (prec != MSB_C128) return fail(MSB_EINVAL, "msb_solve: the dual-space form runs in complex128");
     hsysT.resize(nsys);
@@ -974,7 +1022,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   hipStream_t ust = (hipStream_t)stream;
   const bool tune = !(opts && opts->autotune < 0);
   const int seed_mode = recur ? (int)kModeSelf : (int)kModeBilinear;
-  (void)shape_for(ctx, ev, nsys, ust, tune, seed_mode);
+  const int il_all = il_ok ? apply_il_width(ctx->dn.n, elem_bytes(ev), nsys, ctx->lds_max, ctx->up.max_hops) : 0;
+  if (!il_all) (void)shape_for(ctx, ev, nsys, ust, tune, seed_mode);
   if (replace_every > 0) (void)shape_for(ctx, Elem::C128, nsys, ust, tune);
   // the residual check stages FP64 rows whatever the storage: tune it as complex128
   if (want_true)
@@ -1117,7 +1166,9 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     MSB_HIP(hipMemcpyAsync(dbase, &zero, sizeof(int), hipMemcpyHostToDevice, st));
 
     MSB_HIP(hipEventRecord(ev0, st));
+    const int il = il_ok ? apply_il_width(ctx->dn.n, elem_bytes(ev), nb, ctx->lds_max, ctx->up.max_hops) : 0;
     InitArgs ia;
+    ia.il = il;
     ia.E = Eb; ia.bank = bank; ia.pvec = pvec; ia.st = dst; ia.partials = partials;
     ia.cap = cap; ia.D = D; ia.nbx = cocg_nbx(D, nb); ia.nsys = nb; ia.n_shift = n_shift; ia.zeta = zeta;
     ia.zeta_prev = zeta_prev; ia.conv_iter = conv; ia.rnorm_log = rlog; ia.maxit = mx;
@@ -1128,8 +1179,13 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     MSB_HIP(launch_cocg_init(ev, ia, st));
 
     ApplyArgs aa = apply_args(ctx, dsys, nb, pvec, vvec);
-    aa.shape = shape_for(ctx, ev, nb, st, tune, seed_mode);
-    seed_shape = apply_shape_used(ev, seed_mode, aa);
+    if (il) {
+      const int nd = ctx->dn.n, blk = nd <= 1024 ? 256 : 1024;
+      seed_shape = ApplyShape{blk, (nd + blk - 1) / blk, il, 2, 0};
+    } else {
+      aa.shape = shape_for(ctx, ev, nb, st, tune, seed_mode);
+      seed_shape = apply_shape_used(ev, seed_mode, aa);
+    }
     aa.aux = bank;
     aa.partials = partials;
     aa.red = red1;
@@ -1156,6 +1212,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     }
 
     CocgArgs ca;
+    ca.il = il;
     ca.st = dst; ca.red1 = red1; ca.partials = partials; ca.red2 = red2;
     ca.bank = bank; ca.vvec = vvec; ca.pvec = pvec; ca.base = dbase; ca.cap = cap; ca.D = D;
     ca.nbx = cocg_nbx(D, nb); ca.nsys = nb; ca.n_shift = n_shift; ca.wshift = wshift; ca.zeta = zeta;
@@ -1324,7 +1381,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
           continue;
         }
         hipError_t e = launch_cocg_p(ev, ca, st);
-        if (e == hipSuccess) e = launch_apply(ev, kModeBilinear, aa, st);
+        if (e == hipSuccess) e = il ? launch_apply_il(ev, kModeBilinear, il, aa, st) : launch_apply(ev, kModeBilinear, aa, st);
         if (e == hipSuccess && dual) e = launch_apply(ev, kModePlain, ta, st);
         if (e == hipSuccess) e = launch_cocg_r(ev, ca, st);
         if (e != hipSuccess) return e;

@@ -148,6 +148,14 @@ int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, int k_u
                      int max_out);
 // The shape launch_apply(e, mode, a) will use.
 ApplyShape apply_shape_used(Elem e, int mode, const ApplyArgs& a);
+// Interleaved block apply (modes plain and bilinear): x and v hold groups of
+// G systems interleaved, [nsys / G][D][G] (ApplyArgs::x, v; aux, status and
+// the bank slots keep one vector per system).  Two passes: column panels for
+// the diagonal and H_up (x) I, then rows for I (x) H_dn.
+hipError_t launch_apply_il(Elem e, int mode, int G, const ApplyArgs& a, hipStream_t st);
+// Interleave width for nsys systems of elem_bytes elements (4, 2, or 0 when
+// the staged rows or the panel work lists do not fit).
+int apply_il_width(int nd, size_t elem_bytes, int nsys, size_t lds_max, int k_up_max);
 
 // ---- COCG seed step kernels (k_cocg.hip) -----------------------------------
 // Per-system state.  status codes:
@@ -220,6 +228,7 @@ struct CocgArgs {
   void* rt;
   void* pt;
   const void* vt;
+  int il;                       // > 0: p and v interleaved in groups of il systems ([nsys/il][D][il])
 };
 
 hipError_t launch_cocg_r(Elem e, const CocgArgs& a, hipStream_t st);   // r_{m+1} = r_m - alpha v
@@ -270,6 +279,7 @@ struct InitArgs {
   void* psnap;                  // optional: set to E (the direct form's copy of p for x rebuilds)
   void* rt;                     // optional (dual-space form): r~_0 = p~_0 = E
   void* pt;
+  int il;                       // > 0: p interleaved in groups of il systems
 };
 hipError_t launch_cocg_init(Elem e, const InitArgs& a, hipStream_t st);
 
@@ -310,8 +320,8 @@ struct FlushArgs {
 // ow_mode: 0 = old output ignored, 1 = weight 1, 2 = per-shift weights from ow
 // engine: 0 = FP64 vector ALU, three real products per complex product (the
 // default), 1 = FP64 matrix cores, 2 = FP64 vector ALU, four real products,
-// 3 = as 0 with twice the elements per workgroup, 4 = as 3 with eight
-// wavefronts of four shifts
+// 3 = as 0 with eight wavefronts (64 shifts per workgroup), 4 = eight
+// wavefronts of four shifts and 256 elements
 constexpr int kNumFlushEngines = 5;
 hipError_t launch_flush(Elem bank, Elem out, const FlushArgs& a, int ow_mode, int engine,
                         hipStream_t st);
