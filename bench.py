@@ -37,8 +37,8 @@ C64_OPTS = None
 # profiles/solve_scale_L12_hbm_counters.md: raw FETCH_SIZE / WRITE_SIZE in KiB
 # and the copy-calibrated factors; valid while the kernel source is unchanged.
 FLUSH_COUNTERS = {
-    "source": "paper_2506_09551_amd/csrc/k_shift.hip", "sha256_16": "10bdddd03be22a2a",
-    "fetch_kib": 91709992.4, "write_kib": 32016600.0, "fetch_factor": 2.0, "write_factor": 1.0,
+    "source": "paper_2506_09551_amd/csrc/k_shift.hip", "sha256_16": "23b507cba5ba49bf",
+    "fetch_kib": 56051943.1, "write_kib": 32016600.0, "fetch_factor": 2.0, "write_factor": 1.0,
     "workload": "scale_L12_N6",
 }
 
@@ -771,7 +771,7 @@ def run_solver_workload(wl_name, args, extras=True, cpu=True):
     }
     roofline = {
         "bound": "alu",
-        "kernel": "k_flush (dense multi-shift assembly, FP64 VALU)",
+        "kernel": "k_flush_gauss (dense multi-shift assembly, three-product FP64 VALU)",
         "achieved": round(gemm_tflops, 3),
         "peak": FP64_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s",
