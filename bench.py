@@ -717,7 +717,7 @@ def run_solver_workload(wl_name, args, extras=True, cpu=True):
     n_shift = len(wl.w_in)
     # apply launch shape: the autotuner's table for this batch (the solve reuses the winner)
     tune_table = msb.msb_autotune(ctx, wl.nrhs, prec)
-    log("autotune " + " ".join(f"{t[0]}x{t[1]}/nv{t[2]}/p{t[3]}/o{t[4]}:{t[5]:.4f}ms" for t in tune_table))
+    log("autotune " + " ".join(f"{t[0]}x{t[1]}/nv{t[2]}/p{t[3]}/o{t[4]}/w{t[6]}:{t[5]:.4f}ms" for t in tune_table))
     psi = torch.empty(wl.nrhs, n_shift, D, dtype=cdt, device=dev)
     torch.cuda.synchronize()
 
@@ -803,8 +803,9 @@ def run_solver_workload(wl_name, args, extras=True, cpu=True):
         "solve_status": last["status_name"],
         "apply_shape": {"threads": last["apply_shape"][0], "elems_per_thread": last["apply_shape"][1],
                         "systems_per_workgroup": last["apply_shape"][2], "passes": last["apply_shape"][3],
-                        "row_order": last["apply_shape"][4]},
-        "autotune_ms": {f"{t[0]}x{t[1]}/nv{t[2]}/passes{t[3]}/order{t[4]}": round(t[5], 5)
+                        "row_order": last["apply_shape"][4], "panel_width": last["apply_shape"][5]},
+        "autotune_ms": {f"{t[0]}x{t[1]}/nv{t[2]}/passes{t[3]}/order{t[4]}" + (f"/w{t[6]}" if t[3] == 3 else ""):
+                        round(t[5], 5)
                         for t in sorted(tune_table, key=lambda t: t[5])[:6]},   # the six fastest
         "mvms_per_step": last["mvms"],
         "max_true_residual": max_true,

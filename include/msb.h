@@ -138,11 +138,13 @@ typedef struct {
   int apply_threads;     /* launch shape of the seed apply: threads per workgroup, */
   int apply_ept;         /*   elements of a row per thread, */
   int apply_nv;          /*   systems per workgroup, */
-  int apply_passes;      /*   1, or 2 when the up-spin hops ran as a separate column-panel pass, */
+  int apply_passes;      /*   1, or 2 / 3 when the up-spin hops ran as a separate column-panel
+                            pass (3: panels staged in LDS), */
   int apply_order;       /*   row order: 0 contiguous rank range per XCD, 1 level order */
   double t_setup_ms;     /* host wall time before the workspace: validation, apply tuning, planning */
   double t_alloc_ms;     /* host wall time of (re)allocating the workspace (0 when reused) */
   double t_wall_ms;      /* host wall time of the whole call */
+  int apply_panel_width; /* columns of the seed apply's LDS panel (passes 3), else 0 */
 } msb_info;
 
 /* One launch shape of the Hamiltonian apply and its measured time. */
@@ -152,10 +154,13 @@ typedef struct {
   int vectors;           /* systems handled by one workgroup (they share the hop tables) */
   int passes;            /* 1: one row kernel; 2: diagonal and up-spin hops first, on column
                             panels that stay in one XCD's L2, then the row kernel adds the
-                            down-spin hops in place (not used by the residual check) */
+                            down-spin hops in place; 3: the same with each column panel
+                            (every up-spin row, panel_width columns) staged in LDS (neither
+                            is used by the residual check) */
   int row_order;         /* 0: each XCD walks one contiguous range of up-spin ranks of every
                             system; 1: the rows of all systems in level order (ascending sum
                             of occupied site indices), one contiguous eighth per XCD */
+  int panel_width;       /* passes = 3: down-spin columns of one LDS-staged panel (else 0) */
   double ms;             /* mean time of one apply of min(nsys, 16) vectors (msb_autotune) */
 } msb_shape;
 

@@ -49,12 +49,13 @@ class msb_info(ctypes.Structure):
                 ("gemm_bytes", c_double), ("replacements", c_int),
                 ("seed_hist", POINTER(c_double)), ("hist_len", c_int),
                 ("apply_threads", c_int), ("apply_ept", c_int), ("apply_nv", c_int), ("apply_passes", c_int),
-                ("apply_order", c_int), ("t_setup_ms", c_double), ("t_alloc_ms", c_double), ("t_wall_ms", c_double)]
+                ("apply_order", c_int), ("t_setup_ms", c_double), ("t_alloc_ms", c_double), ("t_wall_ms", c_double),
+                ("apply_panel_width", c_int)]
 
 
 class msb_shape(ctypes.Structure):
     _fields_ = [("threads", c_int), ("elems_per_thread", c_int), ("vectors", c_int), ("passes", c_int),
-                ("row_order", c_int), ("ms", c_double)]
+                ("row_order", c_int), ("panel_width", c_int), ("ms", c_double)]
 
 
 class msb_opts(ctypes.Structure):
@@ -415,7 +416,7 @@ def msb_solve(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit: int, 
         "seed_hist": (np.frombuffer(seed_hist, dtype=np.float64).reshape(n, hist_len).copy()
                       if hist_len > 0 else None),
         "apply_shape": (info.apply_threads, info.apply_ept, info.apply_nv, info.apply_passes,
-                        info.apply_order),
+                        info.apply_order, info.apply_panel_width),
         "t_setup_ms": info.t_setup_ms, "t_alloc_ms": info.t_alloc_ms, "t_wall_ms": info.t_wall_ms,
     }
     if raise_on_fail and st != MSB_OK:
@@ -521,22 +522,23 @@ def msb_spectrum_cf(ctx, system, phi, w, eta: float, lanczos_max: int, cf_tol: f
 
 def msb_autotune(ctx, nsys: int, prec: int, stream=None):
     """Time every usable apply shape; returns
-    [(threads, elems_per_thread, vectors, passes, row_order, ms), ...]."""
-    tab = (msb_shape * 128)()
+    [(threads, elems_per_thread, vectors, passes, row_order, ms, panel_width), ...]."""
+    tab = (msb_shape * 256)()
     n = c_int(0)
-    _check(lib().msb_autotune(ctx, int(nsys), int(prec), tab, 128, ctypes.byref(n), _stream_ptr(stream)))
-    return [(t.threads, t.elems_per_thread, t.vectors, t.passes, t.row_order, t.ms)
-            for t in tab[:min(n.value, 128)]]
+    _check(lib().msb_autotune(ctx, int(nsys), int(prec), tab, 256, ctypes.byref(n), _stream_ptr(stream)))
+    return [(t.threads, t.elems_per_thread, t.vectors, t.passes, t.row_order, t.ms, t.panel_width)
+            for t in tab[:min(n.value, 256)]]
 
 
 def msb_set_shape(ctx, nsys: int, prec: int, shape):
-    """Pin the apply shape (threads, elems_per_thread, vectors[, passes[, row_order]]);
-    None returns to the default."""
+    """Pin the apply shape (threads, elems_per_thread, vectors[, passes[, row_order[, ms[,
+    panel_width]]]]) -- an entry of msb_autotune's table; None returns to the default."""
     sh = msb_shape()
     if shape is not None:
         sh.threads, sh.elems_per_thread, sh.vectors = (int(v) for v in shape[:3])
         sh.passes = int(shape[3]) if len(shape) >= 4 else 1
         sh.row_order = int(shape[4]) if len(shape) >= 5 else 0
+        sh.panel_width = int(shape[6]) if len(shape) >= 7 else 0
     _check(lib().msb_set_shape(ctx, int(nsys), int(prec), ctypes.byref(sh)))
 
 

@@ -478,6 +478,197 @@ __global__ __launch_bounds__(256) void k_apply_up(ApplyArgs a) {
   if (row >= 0 && ok) put(row, acc);
 }
 
+// ---- first pass on LDS-staged column panels (passes = 3) --------------------
+// One workgroup stages the panel x[:, c0 .. c0 + W) of one system -- every
+// up-spin row, W down-spin columns, and a zero row at index n_up -- in LDS
+// (global_load_lds, 16 bytes per lane straight from memory), then each thread
+// forms whole rows of the panel: the diagonal and every up-spin hop, read from
+// LDS through the padded, transposed up-spin table, so one table word and one
+// LDS read of W elements serve W columns and no neighbour row is fetched from
+// the caches again.  The Q panels that share a 128-byte line run side by side
+// on one XCD, so the line leaves HBM once.  The row kernel then adds
+// I (x) H_dn in place (ApplyArgs::vin); in the recurred mode (x_from_aux) the
+// old v is added here with its beta, as in k_apply_up.
+template <int W, typename S>
+constexpr int pan_lines() {
+  return (W * (int)sizeof(cv<S>) >= 128) ? 1 : 128 / (W * (int)sizeof(cv<S>));
+}
+size_t pan_lds_bytes(int n_up, int W, size_t es) {
+  const size_t units = ((size_t)n_up * W * es + 15) / 16;
+  const size_t staged = (units + kWave - 1) / kWave * kWave * 16;   // whole wavefront loads
+  const size_t need = (size_t)(n_up + 1) * W * es;
+  return staged > need ? staged : need;
+}
+// 1024 threads (16 wavefronts to hide the LDS latency) unless the rows are
+// few or a row of W elements needs more registers than 1024 threads have
+int pan_block(int n_up, int W, size_t es) { return (n_up > 600 && W * es <= 128 && W <= 8) ? 1024 : 256; }
+
+template <typename S, int W, int BLK>
+__global__ __launch_bounds__(BLK) void k_apply_pan(ApplyArgs a) {
+  using V16 = typename std::conditional<std::is_same<S, double>::value, double2, float4>::type;
+  constexpr int ES = (int)sizeof(cv<S>);
+  constexpr int CPR = W * ES / 16;                         // 16-byte units of a panel row
+  static_assert(CPR >= 1 && (W * ES) % 16 == 0, "panel rows are whole 16-byte units");
+  constexpr int Q = pan_lines<W, S>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cv<S>* pan = reinterpret_cast<cv<S>*>(smem_raw);         // [n_up + 1][W]
+  const int nd = a.T.n_dn, nu = a.T.n_up;
+  const int s = blockIdx.y;
+  const int xq = blockIdx.x % kNumXcd, l = blockIdx.x / kNumXcd;
+  const int c0 = ((l % Q) + Q * (xq + kNumXcd * (l / Q))) * W;
+  if (c0 >= nd) return;
+  if (a.status && a.status[(int64_t)s * a.status_stride] != kActive) return;
+  const SysDev* sd = a.sys + s;
+  const int tid = threadIdx.x;
+  int64_t xo = (int64_t)s * a.D;
+  if (a.x_from_aux && a.aux_m) {
+    int slot = a.aux_m[(int64_t)s * a.status_stride] - *a.aux_base;
+    slot = slot < 0 ? 0 : (slot >= a.aux_cap ? a.aux_cap - 1 : slot);
+    xo = ((int64_t)s * a.aux_cap + slot) * a.D;
+  }
+  const cv<S>* xs = reinterpret_cast<const cv<S>*>(a.x_from_aux ? a.aux : a.x) + xo;
+  cv<S>* vs = reinterpret_cast<cv<S>*>(a.v) + (int64_t)s * a.D;
+  // whole 16-byte units: a full panel, rows of whole units, aligned vectors
+  const bool fast = c0 + W <= nd && ((int64_t)nd * ES) % 16 == 0 &&
+                    ((reinterpret_cast<uintptr_t>(xs) | reinterpret_cast<uintptr_t>(vs)) & 15) == 0;
+  if (fast) {
+    const int n_units = nu * CPR;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    for (int i0 = wave * kWave; i0 < n_units; i0 += BLK) {
+      // lanes past the panel reload its last unit into the space of the zero
+      // row (written below) or the whole-wavefront tail of the allocation
+      const int i = min(i0 + lane, n_units - 1);
+      const V16* src = reinterpret_cast<const V16*>(xs + (int64_t)(i / CPR) * nd + c0) + i % CPR;
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(src),
+                                       (__attribute__((address_space(3))) void*)(smem_raw + (size_t)i0 * 16),
+                                       16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+  } else {
+    for (int i = tid; i < nu * W; i += BLK) {
+      const int d = c0 + i % W;
+      pan[i] = d < nd ? xs[(int64_t)(i / W) * nd + d] : cv<S>{(S)0, (S)0};
+    }
+  }
+  __syncthreads();
+  if (tid < W) pan[nu * W + tid] = cv<S>{(S)0, (S)0};
+  __syncthreads();
+
+  const S U = (S)sd->U, Uc = (S)sd->Uc, dre = (S)sd->d_re, dim = (S)sd->d_im;
+  const int core = sd->core;
+  uint32_t cdw[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) cdw[w] = a.T.conf_dn[min(c0 + w, nd - 1)];
+  cv<S> bs = {(S)0, (S)0};
+  if (a.x_from_aux && a.beta) bs = {(S)a.beta[(int64_t)s * a.beta_stride], (S)a.beta[(int64_t)s * a.beta_stride + 1]};
+  const bool badd = bs.re != (S)0 || bs.im != (S)0;
+  for (int u = tid; u < nu; u += BLK) {
+    const uint32_t cu = a.T.conf_up[u];
+    cv<S> acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      S dg = U * (S)__builtin_popcount(cu & cdw[w]) + dre;
+      if (core >= 0) dg += Uc * (S)(((cu >> core) & 1u) + ((cdw[w] >> core) & 1u));
+      const cv<S> xv = pan[u * W + w];
+      acc[w] = {dg * xv.re - dim * xv.im, dg * xv.im + dim * xv.re};
+    }
+    const uint64_t* ell = a.T.ell_up;
+    for (int t = 0; t < a.T.n_types; ++t) {
+      const int kq = a.T.k_type_up[t];
+      const S am = (S)sd->amp[t];
+      uint64_t hn = kq > 0 ? ell[u] : 0;
+      for (int q = 0; q < kq; ++q) {
+        const uint64_t hw = hn;
+        if (q + 1 < kq) hn = ell[(int64_t)(q + 1) * nu + u];
+        // the four hops' panel rows are requested before their FMAs
+        cv<S> xv[4][W];
+        S c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t ent = (uint32_t)(hw >> (16 * j)) & 0xFFFFu;
+          c[j] = flip_sign(am, (ent & 0x8000u) << 16);
+          const cv<S>* src = pan + (ent & 0x7FFFu) * W;
+#pragma unroll
+          for (int w = 0; w < W; ++w) xv[j][w] = src[w];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            acc[w].re += c[j] * xv[j][w].re;
+            acc[w].im += c[j] * xv[j][w].im;
+          }
+      }
+      ell += (int64_t)kq * nu;
+    }
+    cv<S>* out = vs + (int64_t)u * nd + c0;
+    if (badd) {
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        if (fast || c0 + w < nd) {
+          const cv<S> vo = out[w];
+          acc[w].re += bs.re * vo.re - bs.im * vo.im;
+          acc[w].im += bs.re * vo.im + bs.im * vo.re;
+        }
+    }
+    if (fast) {
+      V16* o16 = reinterpret_cast<V16*>(out);
+#pragma unroll
+      for (int j = 0; j < CPR; ++j) {
+        if constexpr (std::is_same<S, double>::value) {
+          o16[j] = make_double2(acc[j].re, acc[j].im);
+        } else {
+          o16[j] = make_float4(acc[2 * j].re, acc[2 * j].im, acc[2 * j + 1].re, acc[2 * j + 1].im);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        if (c0 + w < nd) out[w] = acc[w];
+    }
+  }
+}
+
+// Panel widths compiled for the LDS-staged first pass, by storage type.
+static bool pan_compiled(size_t es, int W) {
+  if (es == 16) return W == 1 || W == 2 || W == 4 || W == 8;
+  if (es == 8) return W == 2 || W == 4 || W == 8 || W == 16;
+  return false;
+}
+// Widest compiled panel whose staged rows fit the LDS (0: none).
+int pan_width_max(int n_up, size_t es, size_t lds_max) {
+  int best = 0;
+  for (int W = 1; W <= 16; W *= 2)
+    if (pan_compiled(es, W) && pan_lds_bytes(n_up, W, es) <= lds_max) best = W;
+  return best;
+}
+
+template <typename S>
+static hipError_t launch_pan(const ApplyArgs& a, int W, hipStream_t st) {
+  const int nu = a.T.n_up, nd = a.T.n_dn;
+  const size_t es = sizeof(cv<S>);
+  if (!a.T.ell_up || nu >= 32768 || !pan_compiled(es, W) || pan_lds_bytes(nu, W, es) > a.lds_max)
+    return hipErrorInvalidValue;
+  const int Q = (W * (int)es >= 128) ? 1 : 128 / (W * (int)es);
+  const int n_panels = (nd + W - 1) / W;
+  const int per = kNumXcd * Q;
+  const dim3 grid((unsigned)(per * ((n_panels + per - 1) / per)), (unsigned)a.nsys);
+  const size_t lds = pan_lds_bytes(nu, W, es);
+  const int blk = pan_block(nu, W, es);
+#define MSB_PAN_CASE(WW)                                                                        \
+  if (W == WW) {                                                                               \
+    if constexpr ((WW) * sizeof(cv<S>) % 16 == 0) {                                            \
+      if (blk == 1024) hipLaunchKernelGGL((k_apply_pan<S, WW, 1024>), grid, dim3(1024), lds, st, a); \
+      else hipLaunchKernelGGL((k_apply_pan<S, WW, 256>), grid, dim3(256), lds, st, a);          \
+      return hipGetLastError();                                                                \
+    }                                                                                          \
+  }
+  MSB_PAN_CASE(1) MSB_PAN_CASE(2) MSB_PAN_CASE(4) MSB_PAN_CASE(8)
+  if constexpr (sizeof(S) == 4) { MSB_PAN_CASE(16) }
+#undef MSB_PAN_CASE
+  return hipErrorInvalidValue;
+}
+
 int apply_rows_per_xcd(int n_up) { return (n_up + kNumXcd - 1) / kNumXcd; }
 int apply_nbx(int n_up, int nsys) {
   (void)nsys;
@@ -515,8 +706,14 @@ static bool compiled(const ApplyShape& sh) {
 // Shape usable for rows of nd elements of `row_bytes` bytes each: the row
 // fits, the staged rows fit the workgroup's LDS limit, and EPT is the
 // smallest compiled one for this (BLK, NV) (larger ones only add idle lanes).
-static bool usable(const ApplyShape& sh, int nd, size_t row_bytes, int nsys, size_t lds_max) {
-  if (!compiled(sh) || (sh.passes != 1 && sh.passes != 2) || (sh.order != 0 && sh.order != 1)) return false;
+// A panel first pass (passes = 3) also needs its panel of pw columns of
+// pan_nu rows (elements of pan_es bytes) to fit; pan_nu = 0: not available.
+static bool usable(const ApplyShape& sh, int nd, size_t row_bytes, int nsys, size_t lds_max, int pan_nu,
+                   size_t pan_es) {
+  if (!compiled(sh) || sh.passes < 1 || sh.passes > 3 || (sh.order != 0 && sh.order != 1)) return false;
+  if (sh.passes == 3 && (pan_nu <= 0 || pan_nu >= 32768 || !pan_compiled(pan_es, sh.pw) ||
+                         pan_lds_bytes(pan_nu, sh.pw, pan_es) > lds_max))
+    return false;
   if ((int64_t)sh.blk * sh.ept < nd) return false;
   if ((size_t)sh.nv * (nd + 1) * row_bytes > lds_max) return false;
   if (sh.nv > 1 && sh.nv > nsys) return false;
@@ -528,8 +725,8 @@ static bool usable(const ApplyShape& sh, int nd, size_t row_bytes, int nsys, siz
   return true;
 }
 
-int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, int k_up_max, ApplyShape* out,
-                     int max_out) {
+int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, int k_up_max, int pan_nu,
+                     size_t pan_es, ApplyShape* out, int max_out) {
   int n = 0;
   for (int order = 0; order <= 1; ++order)
     for (int passes = 1; passes <= (panel_fits(k_up_max) ? 2 : 1); ++passes)
@@ -537,8 +734,22 @@ int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, int k_u
         ApplyShape sh = kShapes[i];
         sh.passes = passes;
         sh.order = order;
-        if (usable(sh, nd, row_bytes, nsys, lds_max)) out[n++] = sh;
+        if (usable(sh, nd, row_bytes, nsys, lds_max, 0, 0)) out[n++] = sh;
       }
+  // LDS panel first pass: the widest panel and the half-width one (two
+  // workgroups per CU); the row kernel after it gathers nothing from other
+  // rows, so the row order does not matter
+  const int wmax = pan_nu > 0 ? pan_width_max(pan_nu, pan_es, lds_max) : 0;
+  for (int W : {wmax, wmax / 2}) {
+    if (W <= 0 || (W == wmax / 2 && W == wmax)) continue;
+    for (int i = 0; i < kNumShapes && n < max_out; ++i) {
+      ApplyShape sh = kShapes[i];
+      sh.passes = 3;
+      sh.order = 0;
+      sh.pw = W;
+      if (usable(sh, nd, row_bytes, nsys, lds_max, pan_nu, pan_es)) out[n++] = sh;
+    }
+  }
   return n;
 }
 
@@ -566,15 +777,22 @@ static ApplyShape default_shape(int nd, size_t row_bytes, int nsys, size_t lds_m
 // shape with fewer vectors per workgroup, else the default.
 // The residual mode writes no v, so it has no buffer for the first pass and
 // runs the single-pass form of the requested shape.
-static ApplyShape resolve_shape(const ApplyArgs& a, size_t row_bytes, bool allow_two) {
+static ApplyShape resolve_shape(const ApplyArgs& a, size_t row_bytes, bool allow_two, int pan_nu, size_t pan_es) {
   const int nd = a.T.n_dn;
   ApplyShape sh = a.shape;
   if (sh.blk > 0) {
     if (sh.passes == 2 && (!allow_two || !panel_fits(a.T.k_up_max))) sh.passes = 1;
+    if (sh.passes == 3 && (!allow_two || pan_nu <= 0)) sh.passes = 1;
     for (; sh.nv >= 1; sh.nv /= 2)
-      if (usable(sh, nd, row_bytes, a.nsys, a.lds_max)) return sh;
+      if (usable(sh, nd, row_bytes, a.nsys, a.lds_max, pan_nu, pan_es)) return sh;
   }
   return default_shape(nd, row_bytes, a.nsys, a.lds_max);
+}
+
+// rows of the LDS panel pass for storage S (0: not available)
+template <typename S, bool CPLX>
+static int pan_rows(const ApplyArgs& a) {
+  return (CPLX && a.T.ell_up && a.T.n_up < 32768) ? a.T.n_up : 0;
 }
 
 template <typename S, typename Tc, bool CPLX, int MODE>
@@ -584,7 +802,7 @@ static hipError_t launch_mode(const ApplyArgs& a0, hipStream_t st) {
   // an operand read from the bank needs the slot of every active system
   a.x_from_aux = MODE == kModeSelf ? 1 : 0;
   if (MODE == kModeSelf && (!a.aux || !a.aux_m || !a.aux_base || !a.status)) return hipErrorInvalidValue;
-  const ApplyShape sh = resolve_shape(a, sizeof(cv<Tc>), MODE != kModeResid);
+  const ApplyShape sh = resolve_shape(a, sizeof(cv<Tc>), MODE != kModeResid, pan_rows<S, CPLX>(a), sizeof(cv<S>));
   if (sh.ept == 0 || (int64_t)sh.blk * sh.ept < nd || (size_t)sh.nv * (nd + 1) * sizeof(cv<Tc>) > a.lds_max)
     return hipErrorInvalidValue;
   a.nvec = sh.nv;
@@ -595,6 +813,14 @@ static hipError_t launch_mode(const ApplyArgs& a0, hipStream_t st) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     a.vin = a.v;   // the row kernel adds the down-spin hops in place
+  } else if (sh.passes == 3) {
+    if constexpr (CPLX) {
+      const hipError_t e = launch_pan<S>(a, sh.pw, st);
+      if (e != hipSuccess) return e;
+      a.vin = a.v;
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
   const int groups = (a.nsys + sh.nv - 1) / sh.nv;
   const dim3 grid = sh.order ? dim3(a.nbx * groups, 1) : dim3(a.nbx, groups);
@@ -617,7 +843,9 @@ ApplyShape apply_shape_used(Elem e, int mode, const ApplyArgs& a) {
   size_t b = 16;
   if (e == Elem::R64) b = 8;
   else if (e == Elem::C64) b = (mode == kModeResid) ? 16 : 8;
-  return resolve_shape(a, b, mode != kModeResid);
+  const size_t pes = e == Elem::C128 ? 16 : 8;
+  const int pnu = (e != Elem::R64 && a.T.ell_up && a.T.n_up < 32768) ? a.T.n_up : 0;
+  return resolve_shape(a, b, mode != kModeResid, pnu, pes);
 }
 
 hipError_t launch_apply(Elem e, int mode, const ApplyArgs& a, hipStream_t st) {

@@ -114,7 +114,11 @@ struct DevBuf {               // scratch device memory released on scope exit
 };
 
 static ApplyArgs apply_args(const msb_ctx* ctx, const SysDev* sys, int nsys, const void* x, void* v);
-constexpr int kMaxCand = 128;   // compiled shapes x passes x row orders
+// up-spin rows of the LDS panel pass for element type e (0: not available)
+static int pan_rows(const msb_ctx* ctx, Elem e) {
+  return (e != Elem::R64 && ctx->d_ell_up && ctx->up.n < 32768) ? ctx->up.n : 0;
+}
+constexpr int kMaxCand = 192;   // compiled shapes x passes x row orders
 constexpr int kSeedParts = 2;   // streams a recurred seed batch is split over (at most 4; 2 measured best)
 constexpr int kSeedPartMin = 4; // systems per part at least
 
@@ -126,7 +130,7 @@ static msb_status tune_shapes(msb_ctx* ctx, Elem e, int nsys, hipStream_t st,
   const int n = shape_class(nsys);
   const size_t eb = elem_bytes(e);
   ApplyShape cand[kMaxCand];
-  int nc = apply_candidates(ctx->dn.n, eb, n, ctx->lds_max, ctx->up.max_hops, cand, kMaxCand);
+  int nc = apply_candidates(ctx->dn.n, eb, n, ctx->lds_max, ctx->up.max_hops, pan_rows(ctx, e), eb, cand, kMaxCand);
   if (mode == kModeResid) {      // the residual check runs single-pass shapes only
     int k = 0;
     for (int i = 0; i < nc; ++i)
@@ -318,6 +322,46 @@ extern "C" msb_status msb_stream_destroy(void* stream) {
   return MSB_OK;
 }
 
+// Padded, transposed copy of one spin's hop lists, one table per bond type,
+// four hops to a 64-bit word: ell[t][g][c] holds hops 4g .. 4g+3 of state c,
+// each 16 bits = target | (even parity ? 0x8000 : 0); padding = n (the zero
+// element after every staged row or panel).  k_type[t] = words of type t.
+static hipError_t upload_ell(const SpinTable& sp, int n_types, int* k_type, uint64_t** dst) {
+  const int n = sp.n;
+  std::vector<uint64_t> ell;
+  for (int t = 0; t < n_types; ++t) {
+    int kt = 0;
+    for (int c = 0; c < n; ++c) {
+      int cnt = 0;
+      for (uint32_t k = sp.off[c]; k < sp.off[c + 1]; ++k) cnt += ((sp.hop[k] >> 1) & 127u) == (uint32_t)t;
+      kt = std::max(kt, cnt);
+    }
+    const int kq = (kt + 3) / 4;
+    k_type[t] = kq;
+    std::vector<uint16_t> ent((size_t)kq * 4 * n, (uint16_t)n);
+    for (int c = 0; c < n; ++c) {
+      int j = 0;
+      for (uint32_t k = sp.off[c]; k < sp.off[c + 1]; ++k) {
+        const uint32_t h = sp.hop[k];
+        if (((h >> 1) & 127u) != (uint32_t)t) continue;
+        ent[(size_t)j * n + c] = (uint16_t)((h >> 16) | ((h & 1u) ? 0u : 0x8000u));
+        ++j;
+      }
+    }
+    for (int g = 0; g < kq; ++g)
+      for (int c = 0; c < n; ++c) {
+        uint64_t w = 0;
+        for (int j = 0; j < 4; ++j) w |= (uint64_t)ent[(size_t)(4 * g + j) * n + c] << (16 * j);
+        ell.push_back(w);
+      }
+  }
+  const size_t bytes = std::max<size_t>(ell.size(), 1) * sizeof(uint64_t);
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e == hipSuccess && !ell.empty())
+    e = hipMemcpy(*dst, ell.data(), ell.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+  return e;
+}
+
 extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   if (!m || !out) return fail(MSB_EINVAL, "msb_create: null argument");
   *out = nullptr;
@@ -409,45 +453,10 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   if (e == hipSuccess) e = upload(&c->d_off_dn, c->dn.off);
   if (e == hipSuccess) e = upload(&c->d_hop_up, c->up.hop);
   if (e == hipSuccess) e = upload(&c->d_hop_dn, c->dn.hop);
-  if (e == hipSuccess) {
-    // padded, transposed copies of the down-spin hop lists, one per bond
-    // type, four hops to a 64-bit word: ell[t][g][d] holds hops 4g .. 4g+3 of
-    // state d, each 16 bits = target | (even parity ? 0x8000 : 0), padding
-    // n_dn (the zero element at the end of every staged row)
-    const int nd = c->dn.n;
-    std::vector<uint64_t> ell;
-    for (int t = 0; t < c->n_types; ++t) {
-      int kt = 0;
-      for (int d = 0; d < nd; ++d) {
-        int cnt = 0;
-        for (uint32_t k = c->dn.off[d]; k < c->dn.off[d + 1]; ++k)
-          cnt += ((c->dn.hop[k] >> 1) & 127u) == (uint32_t)t;
-        kt = std::max(kt, cnt);
-      }
-      const int kq = (kt + 3) / 4;
-      c->k_type_dn[t] = kq;
-      std::vector<uint16_t> ent((size_t)kq * 4 * nd, (uint16_t)nd);
-      for (int d = 0; d < nd; ++d) {
-        int j = 0;
-        for (uint32_t k = c->dn.off[d]; k < c->dn.off[d + 1]; ++k) {
-          const uint32_t h = c->dn.hop[k];
-          if (((h >> 1) & 127u) != (uint32_t)t) continue;
-          ent[(size_t)j * nd + d] = (uint16_t)((h >> 16) | ((h & 1u) ? 0u : 0x8000u));
-          ++j;
-        }
-      }
-      for (int g = 0; g < kq; ++g)
-        for (int d = 0; d < nd; ++d) {
-          uint64_t w = 0;
-          for (int j = 0; j < 4; ++j) w |= (uint64_t)ent[(size_t)(4 * g + j) * nd + d] << (16 * j);
-          ell.push_back(w);
-        }
-    }
-    const size_t bytes = std::max<size_t>(ell.size(), 1) * sizeof(uint64_t);
-    e = hipMalloc(&c->d_ell_dn, bytes);
-    if (e == hipSuccess && !ell.empty())
-      e = hipMemcpy(c->d_ell_dn, ell.data(), ell.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
-  }
+  if (e == hipSuccess) e = upload_ell(c->dn, c->n_types, c->k_type_dn, &c->d_ell_dn);
+  // the up-spin table of the same form feeds the column-panel pass (rows of
+  // one panel staged in LDS); up-spin ranks fit its 15-bit targets
+  if (e == hipSuccess && c->up.n < 32768) e = upload_ell(c->up, c->n_types, c->k_type_up, &c->d_ell_up);
   if (e == hipSuccess) e = upload(&c->d_order_up, c->up.order);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking);
   for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&c->part_stream[k], hipStreamNonBlocking);
@@ -470,6 +479,7 @@ extern "C" void msb_destroy(msb_ctx* c) {
   (void)hipFree(c->d_hop_up);
   (void)hipFree(c->d_hop_dn);
   (void)hipFree(c->d_ell_dn);
+  (void)hipFree(c->d_ell_up);
   (void)hipFree(c->d_order_up);
   if (c->solve_stream) (void)hipStreamDestroy(c->solve_stream);
   for (int k = 0; k < 3; ++k)
@@ -1667,6 +1677,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     info->apply_nv = seed_shape.nv;
     info->apply_passes = seed_shape.passes;
     info->apply_order = seed_shape.order;
+    info->apply_panel_width = seed_shape.passes == 3 ? seed_shape.pw : 0;
     info->t_iter_ms = t_iter;
     info->t_flush_ms = t_flush;
     info->t_true_ms = t_true;
@@ -2006,6 +2017,7 @@ extern "C" msb_status msb_autotune(msb_ctx* ctx, int nsys, msb_prec prec, msb_sh
     out[i].vectors = table[i].first.nv;
     out[i].passes = table[i].first.passes;
     out[i].row_order = table[i].first.order;
+    out[i].panel_width = table[i].first.passes == 3 ? table[i].first.pw : 0;
     out[i].ms = table[i].second;
   }
   if (n_out) *n_out = (int)table.size();
@@ -2025,10 +2037,13 @@ extern "C" msb_status msb_set_shape(msb_ctx* ctx, int nsys, msb_prec prec, const
   }
   ApplyShape cand[kMaxCand];
   const int nc = apply_candidates(ctx->dn.n, elem_bytes(e), shape_class(nsys), ctx->lds_max, ctx->up.max_hops,
+                                  pan_rows(ctx, e), elem_bytes(e),
                                   cand, kMaxCand);
   for (int i = 0; i < nc; ++i)
     if (cand[i].blk == shape->threads && cand[i].ept == shape->elems_per_thread &&
-        cand[i].nv == shape->vectors && cand[i].passes == (shape->passes == 2 ? 2 : 1) &&
+        cand[i].nv == shape->vectors &&
+        cand[i].passes == ((shape->passes == 2 || shape->passes == 3) ? shape->passes : 1) &&
+        (cand[i].passes != 3 || cand[i].pw == shape->panel_width) &&
         cand[i].order == (shape->row_order == 1 ? 1 : 0)) {
       for (int md : modes) ctx->shapes[std::make_tuple((int)e, shape_class(nsys), md)] = cand[i];
       return MSB_OK;

@@ -79,11 +79,15 @@ struct TablesDev {
   // hops 4g .. 4g+3 as 16-bit entries = target column, with bit 15 set where
   // the matrix element is -t (even parity); padding = n_dn
   const uint64_t* ell_dn;
+  // up-spin hops in the same form (padding = n_up), k_type_up[t] words of
+  // type t; null when the up-spin sector has 32768 states or more
+  const uint64_t* ell_up;
   const uint32_t* order_up;   // [n_up] up-spin rows in level order (SpinTable::order)
   int n_up, n_dn, k_dn;       // k_dn: sum of k_type (words of four hops)
   int k_up_max;               // most up-spin hops of one row
   int n_types;
   int k_type[MSB_MAX_BOND_TYPES];
+  int k_type_up[MSB_MAX_BOND_TYPES];
 };
 constexpr uint32_t kNoHop = 0xFFFFFFFFu;
 
@@ -100,12 +104,14 @@ enum ApplyMode : int {
 // Launch shape of the apply kernel: threads per workgroup, elements per
 // thread, vectors (systems) per workgroup of the row kernel, whether the
 // diagonal and the up-spin hops run first in a separate column-panel pass
-// (passes = 2), and the order in which the XCDs walk the rows (order 0: each
+// (passes = 2: panels gathered from one XCD's L2; passes = 3: panels of pw
+// columns staged in LDS), and the order in which the XCDs walk the rows (order 0: each
 // XCD one contiguous range of ranks of every system; order 1: the rows of
 // all systems in level order, one contiguous eighth per XCD).  blk == 0
 // selects the default.
 struct ApplyShape {
   int blk, ept, nv, passes, order;
+  int pw;                     // passes = 3: columns of the LDS-staged panel of the first pass
 };
 
 struct ApplyArgs {
@@ -143,9 +149,10 @@ hipError_t launch_apply(Elem e, int mode, const ApplyArgs& a, hipStream_t st);
 int apply_nbx(int n_up, int nsys);  // grid.x (workgroups per system) for the apply kernel
 int apply_rows_per_xcd(int n_up);
 // Compiled shapes usable for rows of nd elements (row_bytes per element of the
-// staged row) and nsys systems; returns how many were written to out.
-int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, int k_up_max, ApplyShape* out,
-                     int max_out);
+// staged row) and nsys systems; pan_nu > 0 adds the LDS panel first pass for
+// n_up = pan_nu rows of pan_es-byte elements.  Returns how many were written.
+int apply_candidates(int nd, size_t row_bytes, int nsys, size_t lds_max, int k_up_max, int pan_nu,
+                     size_t pan_es, ApplyShape* out, int max_out);
 // The shape launch_apply(e, mode, a) will use.
 ApplyShape apply_shape_used(Elem e, int mode, const ApplyArgs& a);
 // Interleaved block apply (modes plain and bilinear): x and v hold groups of
@@ -428,8 +435,10 @@ struct msb_ctx {
   uint32_t* d_hop_up = nullptr;
   uint32_t* d_hop_dn = nullptr;
   uint64_t* d_ell_dn = nullptr;
+  uint64_t* d_ell_up = nullptr;
   uint32_t* d_order_up = nullptr;
   int k_type_dn[MSB_MAX_BOND_TYPES] = {0};   // words (four hops each) of each bond type's down-spin table
+  int k_type_up[MSB_MAX_BOND_TYPES] = {0};   // the same for the up-spin table
   int type_partner[MSB_MAX_BOND_TYPES] = {0}; // type of the reverse hop (itself when symmetric)
   // private stream for the captured seed iterations (default priority)
   hipStream_t solve_stream = nullptr;
@@ -448,12 +457,14 @@ struct msb_ctx {
     t.off_up = d_off_up; t.off_dn = d_off_dn;
     t.hop_up = d_hop_up; t.hop_dn = d_hop_dn;
     t.ell_dn = d_ell_dn;
+    t.ell_up = d_ell_up;
     t.order_up = d_order_up;
     t.n_up = up.n; t.n_dn = dn.n; t.k_dn = 0;
     t.k_up_max = up.max_hops;
     t.n_types = n_types;
     for (int i = 0; i < MSB_MAX_BOND_TYPES; ++i) {
       t.k_type[i] = i < n_types ? k_type_dn[i] : 0;
+      t.k_type_up[i] = i < n_types ? k_type_up[i] : 0;
       t.k_dn += t.k_type[i];
     }
     return t;

@@ -124,7 +124,7 @@ def test_every_apply_shape_matches_oracle(gpu, name, prec):
         for nsys in (1, 3, 4):
             table = msb.msb_autotune(ctx, nsys, p)
             assert table and all(t[5] > 0 for t in table)
-            assert {t[3] for t in table} == {1, 2}          # single- and two-pass forms
+            assert {t[3] for t in table} == {1, 2, 3}       # single-pass, L2- and LDS-panel two-pass forms
             assert {t[4] for t in table} == {0, 1}          # both row orders
             for shape in table:
                 msb.msb_set_shape(ctx, nsys, p, shape)
@@ -134,8 +134,8 @@ def test_every_apply_shape_matches_oracle(gpu, name, prec):
                 torch.cuda.synchronize()
                 y = yt.cpu().numpy().astype(np.complex128)
                 err = np.max(np.abs(y - expect[:nsys])) / np.max(np.abs(expect[:nsys]))
-                assert err <= tol, f"{name} {prec} nsys={nsys} shape={shape[:5]}: {err:.3e}"
-                seen.add(shape[:5])
+                assert err <= tol, f"{name} {prec} nsys={nsys} shape={shape[:5] + shape[6:]}: {err:.3e}"
+                seen.add(shape[:5] + shape[6:])
             msb.msb_set_shape(ctx, nsys, p, None)
         assert len(seen) >= 2
         with pytest.raises(msb.MsbError):
@@ -249,5 +249,98 @@ def test_block_apply_matches_sparse_oracle(gpu, name, m, prec, group, nsys):
         err = np.max(np.abs(y - expect)) / np.max(np.abs(expect))
         tol = 1e-14 if prec == "c128" else 2e-6
         assert err <= tol, f"{name} {prec} group {group}: rel err {err:.3e}"
+    finally:
+        msb.msb_destroy(ctx)
+
+
+PANEL = {
+    # large up-spin sectors (the whole column panel, n_up rows, staged in one
+    # workgroup's LDS) and an odd row length (no whole 16-byte units in
+    # complex64: the element-wise staging path)
+    "square4x4_5_1": dict(L=16, nu=5, nd=1, bonds=W.square_bonds(4, 4, 1.0, -0.25), U=8.0),
+    "chain14_7_1": dict(L=14, nu=7, nd=1, bonds=W.chain_bonds(14, 1.0, -0.2), U=8.0),
+    "chain7_3_3": dict(L=7, nu=3, nd=3, bonds=W.chain_bonds(7, 1.0), U=8.0),
+}
+
+
+@pytest.mark.parametrize("name", list(PANEL))
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_lds_panel_pass_matches_oracle(gpu, name, prec):
+    """Every LDS column-panel shape (passes = 3) gives the oracle's H x, for 1
+    and 3 systems, at up-spin sectors of 4,368 and 3,432 rows and on rows of
+    odd length."""
+    import torch
+    msb = gpu
+    m = PANEL[name]
+    ctx = msb.msb_create(m["L"], m["nu"], m["nd"], m["bonds"], m["U"])
+    p = msb.MSB_C128 if prec == "c128" else msb.MSB_C64
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    try:
+        D = msb.msb_dim(ctx)
+        all_sys = [msb.make_system(core_site=(3 * j) % m["L"], Uc=-4.0 + 0.5 * j, E_G=-2.0 + j, Gamma=1.0 + 0.1 * j)
+                   for j in range(3)]
+        shift = -0.5
+        x = np.stack([W.random_complex(D, seed=700 + s) for s in range(3)])
+        xr = x.astype(np.complex64).astype(np.complex128) if prec == "c64" else x
+        expect = np.stack([oracle_H(m, core_site=s.core_site, Uc=s.Uc) @ xr[j]
+                           - (s.E_G + shift + 1j * s.Gamma) * xr[j] for j, s in enumerate(all_sys)])
+        tol = 1e-14 if prec == "c128" else 2e-6
+        n_panel = 0
+        for nsys in (1, 3):
+            table = [t for t in msb.msb_autotune(ctx, nsys, p) if t[3] == 3]
+            assert table, "no LDS panel shape offered"
+            assert all(t[6] > 0 for t in table)
+            for shape in table:
+                msb.msb_set_shape(ctx, nsys, p, shape)
+                xt = torch.from_numpy(x[:nsys]).to(dt).cuda().contiguous()
+                yt = torch.full_like(xt, float("nan"))
+                msb.msb_apply(ctx, all_sys[:nsys], shift, p, xt, yt)
+                torch.cuda.synchronize()
+                y = yt.cpu().numpy().astype(np.complex128)
+                err = np.max(np.abs(y - expect[:nsys])) / np.max(np.abs(expect[:nsys]))
+                assert err <= tol, f"{name} {prec} nsys={nsys} shape={shape[:5] + shape[6:]}: {err:.3e}"
+                n_panel += 1
+            msb.msb_set_shape(ctx, nsys, p, None)
+        assert n_panel >= 2
+    finally:
+        msb.msb_destroy(ctx)
+
+
+@pytest.mark.parametrize("wl_name", ["precision", "batched"])
+def test_lds_panel_pass_full_size_sampled_rows(gpu, wl_name):
+    """The fastest LDS column-panel shape at the full L = 14 and 4x4 sizes:
+    sampled rows against the oracle's row-by-row apply (the 4x4 block of four
+    systems, complex64)."""
+    import torch
+    msb = gpu
+    wl = W.get(wl_name)
+    ctx = msb.msb_create(wl.n_sites, wl.n_up, wl.n_dn, wl.bonds, wl.U)
+    try:
+        D = msb.msb_dim(ctx)
+        nsys = 4 if wl_name == "batched" else 1
+        prec = msb.MSB_C64
+        table = [t for t in msb.msb_autotune(ctx, nsys, prec) if t[3] == 3]
+        assert table
+        best = min(table, key=lambda t: t[5])
+        msb.msb_set_shape(ctx, nsys, prec, best)
+        B = basis(wl.n_sites, wl.n_up, wl.n_dn)
+        rng = np.random.default_rng(17)
+        rows = np.unique(np.concatenate([rng.integers(0, D, 300), [0, 1, D - 2, D - 1]]))
+        systems = [msb.make_system(core_site=wl.core_sites[j % len(wl.core_sites)], Uc=wl.Uc, E_G=-4.0 + 0.1 * j,
+                                   Gamma=wl.Gamma) for j in range(nsys)]
+        g = torch.Generator(device="cuda").manual_seed(23)
+        xt = torch.randn(nsys, D, dtype=torch.complex64, device="cuda", generator=g)
+        yt = torch.empty_like(xt)
+        msb.msb_apply(ctx, systems, 0.0, prec, xt, yt)
+        torch.cuda.synchronize()
+        for j in (0, nsys - 1):
+            x = xt[j].cpu().numpy().astype(np.complex128)
+            y = yt[j].cpu().numpy().astype(np.complex128)
+            s = systems[j]
+            ref = hb.apply_rows(B, wl.bonds, wl.U, x, rows, core_site=s.core_site, Uc=s.Uc,
+                                shift=s.E_G + 1j * s.Gamma)
+            err = np.max(np.abs(y[rows] - ref)) / np.max(np.abs(ref))
+            assert err <= 2e-6, f"{wl_name} system {j} shape {best[:5] + best[6:]}: sampled rel err {err:.3e}"
+        msb.msb_set_shape(ctx, nsys, prec, None)
     finally:
         msb.msb_destroy(ctx)

@@ -122,6 +122,35 @@ def test_seed_forms_agree(tiny, direct_ap):
     assert _rel(psi.reshape(-1, D), psi_o.reshape(-1, D)) <= 1e-9
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_solve_with_lds_panel_apply(tiny, prec):
+    """The solve with its seed applies pinned to each LDS column-panel shape
+    (the recurred sigma-fused apply in complex128, the direct one in complex64;
+    the residual check keeps a single pass) matches the direct solves."""
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E_G = -2.6661474201323485
+    p = msb.MSB_C128 if prec == "c128" else msb.MSB_C64
+    systems = [msb.make_system(core_site=j, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma) for j in (0, 3, 5)]
+    E = np.stack([W.random_complex(D, 60 + j) for j in range(3)])
+    w = np.linspace(-6.0, 9.0, 23)
+    refs = [osolve.direct_solve(oracle_H(m, core_site=s.core_site, Uc=wl.Uc), E[j], E_G, wl.Gamma, w, method="eig")
+            for j, s in enumerate(systems)]
+    table = [t for t in msb.msb_autotune(ctx, 3, p) if t[3] == 3]
+    assert table
+    try:
+        for shape in table:
+            msb.msb_set_shape(ctx, 3, p, shape)
+            tol, bar = (1e-12, 1e-9) if prec == "c128" else (1e-6, 5e-5)
+            st, info, psi = _run(msb, ctx, systems, E, w, tol, 3000, p)
+            assert info["apply_shape"][3] == 3 and info["apply_shape"][5] == shape[6]
+            for j in range(3):
+                err = _rel(psi[j], refs[j])
+                assert err <= bar, f"{prec} shape {shape[:5] + shape[6:]} system {j}: {err:.3e}"
+    finally:
+        msb.msb_set_shape(ctx, 3, p, None)
+
+
 @pytest.mark.parametrize("case", ["plain", "small_bank", "c64_replace"])
 def test_large_batch_runs_in_two_parts(tiny, case):
     """Nine systems (the recurred seed then runs as two parts of 4 and 5 on two
