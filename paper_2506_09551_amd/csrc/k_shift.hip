@@ -445,7 +445,11 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
   constexpr int LROWS = EPL / PER16;                      // wave loads per slot
   constexpr int ROWS = KT * LROWS;                        // wave loads per chunk
   static_assert(EPL % PER16 == 0, "whole 16-byte loads per lane");
-  __shared__ VB rt[2][KT][TILE / PER16];                  // two chunk buffers, 16-byte units
+  // two chunk buffers, 16-byte units, as two objects: the compiler then
+  // knows that the DMA into one does not write the other, and reads the
+  // current chunk while the next one is in flight
+  __shared__ VB rt0[KT][TILE / PER16];
+  __shared__ VB rt1[KT][TILE / PER16];
 
   const int s = blockIdx.y;
   const int b = blockIdx.x;
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
 #pragma unroll
     for (int e = 0; e < EPL; ++e) A1[t][e] = A2[t][e] = A3[t][e] = 0.0;
 
-  auto stage = [&](int buf, int kb) {
+  auto stage = [&](VB (&rt)[KT][TILE / PER16], int kb) {
     const int kn = min(KT, Kext - kb);
     for (int row = wave; row < ROWS; row += NW) {
       const int j = row / LROWS, g = row % LROWS;
@@ -482,7 +486,7 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
       unit = unit < n_units - 1 ? unit : n_units - 1;
       const VB* src = reinterpret_cast<const VB*>(bank_s + (int64_t)kc * a.D) + unit;
       __builtin_amdgcn_global_load_lds(static_cast<const void*>(src),
-                                       (__attribute__((address_space(3))) void*)&rt[buf][j][g * kWave],
+                                       (__attribute__((address_space(3))) void*)&rt[j][g * kWave],
                                        16, 0, 0);
     }
   };
@@ -497,7 +501,7 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
     }
   };
   constexpr bool kPrefetch = M <= 4;
-  auto run = [&](int buf, int kb, int kn) {
+  auto run = [&](const VB (&rt)[KT][TILE / PER16], int kb, int kn) {
     C3 c_cur[M], c_nxt[kPrefetch ? M : 1];
     const int kw = min(kn, Kw - kb);                      // wave-uniform; may be <= 0
     if (kPrefetch && kw > 0) load_c(kb, c_cur);
@@ -511,14 +515,14 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
       if constexpr (std::is_same<SB, double>::value) {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
-          const double2 r = rt[buf][kk][lane + kWave * e];
+          const double2 r = rt[kk][lane + kWave * e];
           rr[e] = r.x;
           ri[e] = r.y;
         }
       } else {
 #pragma unroll
         for (int g = 0; g < EPL / 2; ++g) {
-          const float4 r = rt[buf][kk][g * kWave + lane];
+          const float4 r = rt[kk][g * kWave + lane];
           rr[2 * g] = (double)r.x;
           ri[2 * g] = (double)r.y;
           rr[2 * g + 1] = (double)r.z;
@@ -541,12 +545,17 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
       }
     }
   };
-  if (Kext > 0) stage(0, 0);
-  for (int kb = 0, buf = 0; kb < Kext; kb += KT, buf ^= 1) {
+  if (Kext > 0) stage(rt0, 0);
+  for (int kb = 0; kb < Kext; kb += 2 * KT) {
     __builtin_amdgcn_s_waitcnt(0);                        // this wavefront's part of chunk kb landed
     __syncthreads();                                      // every part; the other buffer is free
-    if (kb + KT < Kext) stage(buf ^ 1, kb + KT);
-    run(buf, kb, min(KT, Kext - kb));
+    if (kb + KT < Kext) stage(rt1, kb + KT);
+    run(rt0, kb, min(KT, Kext - kb));
+    if (kb + KT >= Kext) break;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (kb + 2 * KT < Kext) stage(rt0, kb + 2 * KT);
+    run(rt1, kb + KT, min(KT, Kext - kb - KT));
   }
 
 #pragma unroll
