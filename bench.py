@@ -722,7 +722,10 @@ def run_solver_workload(wl_name, args, extras=True, cpu=True):
     torch.cuda.synchronize()
 
     ok = (msb.MSB_OK, msb.MSB_FLOOR) if prec == msb.MSB_C64 else (msb.MSB_OK,)
-    step_opts = C64_OPTS if prec == msb.MSB_C64 else None
+    step_opts = dict(C64_OPTS or {}) if prec == msb.MSB_C64 else {}
+    if getattr(args, "assembly_engine", None) is not None:
+        step_opts["assembly_engine"] = args.assembly_engine
+    step_opts = step_opts or None
 
     def step():
         st, info = msb.msb_solve(ctx, systems, E, wl.w_in, wl.seed_shift, args.tol, wl.maxit, prec, psi,
@@ -888,6 +891,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--apply-only", action="store_true",
                     help="only the H-apply rates (--steps applies per shape)")
+    ap.add_argument("--assembly-engine", type=int, default=None,
+                    help="multi-shift assembly engine of the timed steps (msb_opts.assembly_engine)")
     ap.add_argument("--no-forms", action="store_true",
                     help="scale workload: skip the precision and batched forms")
     ap.add_argument("--copy-probe", action="store_true",
