@@ -501,7 +501,7 @@ size_t pan_lds_bytes(int n_up, int W, size_t es) {
 }
 // 1024 threads (16 wavefronts to hide the LDS latency) unless the rows are
 // few or a row of W elements needs more registers than 1024 threads have
-int pan_block(int n_up, int W, size_t es) { return (n_up > 600 && W * es <= 128 && W <= 8) ? 1024 : 256; }
+int pan_block(int n_up, int W, size_t es) { return (n_up > 600 && W * es <= 64) ? 1024 : 256; }
 
 template <typename S, int W, int BLK>
 __global__ __launch_bounds__(BLK) void k_apply_pan(ApplyArgs a) {
@@ -562,45 +562,39 @@ __global__ __launch_bounds__(BLK) void k_apply_pan(ApplyArgs a) {
   cv<S> bs = {(S)0, (S)0};
   if (a.x_from_aux && a.beta) bs = {(S)a.beta[(int64_t)s * a.beta_stride], (S)a.beta[(int64_t)s * a.beta_stride + 1]};
   const bool badd = bs.re != (S)0 || bs.im != (S)0;
-  for (int u = tid; u < nu; u += BLK) {
-    const uint32_t cu = a.T.conf_up[u];
-    cv<S> acc[W];
+  // one panel row: the diagonal, the up-spin hops (four 16-bit entries per
+  // table word; the four hops' panel rows are requested before their FMAs),
+  // the store
+  auto diag = [&](int u, cv<S> (&acc)[W]) {
+    const uint32_t cu = a.T.conf_up[u < nu ? u : nu - 1];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
       S dg = U * (S)__builtin_popcount(cu & cdw[w]) + dre;
       if (core >= 0) dg += Uc * (S)(((cu >> core) & 1u) + ((cdw[w] >> core) & 1u));
-      const cv<S> xv = pan[u * W + w];
+      const cv<S> xv = pan[(u < nu ? u : nu) * W + w];
       acc[w] = {dg * xv.re - dim * xv.im, dg * xv.im + dim * xv.re};
     }
-    const uint64_t* ell = a.T.ell_up;
-    for (int t = 0; t < a.T.n_types; ++t) {
-      const int kq = a.T.k_type_up[t];
-      const S am = (S)sd->amp[t];
-      uint64_t hn = kq > 0 ? ell[u] : 0;
-      for (int q = 0; q < kq; ++q) {
-        const uint64_t hw = hn;
-        if (q + 1 < kq) hn = ell[(int64_t)(q + 1) * nu + u];
-        // the four hops' panel rows are requested before their FMAs
-        cv<S> xv[4][W];
-        S c[4];
+  };
+  auto hops = [&](cv<S> (&acc)[W], uint64_t hw, auto amp_of, uint32_t tmask) {
+    cv<S> xv[4][W];
+    S c[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t ent = (uint32_t)(hw >> (16 * j)) & 0xFFFFu;
-          c[j] = flip_sign(am, (ent & 0x8000u) << 16);
-          const cv<S>* src = pan + (ent & 0x7FFFu) * W;
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t ent = (uint32_t)(hw >> (16 * j)) & 0xFFFFu;
+      c[j] = flip_sign(amp_of(ent), (ent & 0x8000u) << 16);
+      const cv<S>* src = pan + (ent & tmask) * W;
 #pragma unroll
-          for (int w = 0; w < W; ++w) xv[j][w] = src[w];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int w = 0; w < W; ++w) {
-            acc[w].re += c[j] * xv[j][w].re;
-            acc[w].im += c[j] * xv[j][w].im;
-          }
-      }
-      ell += (int64_t)kq * nu;
+      for (int w = 0; w < W; ++w) xv[j][w] = src[w];
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        acc[w].re += c[j] * xv[j][w].re;
+        acc[w].im += c[j] * xv[j][w].im;
+      }
+  };
+  auto store = [&](int u, cv<S> (&acc)[W]) {
     cv<S>* out = vs + (int64_t)u * nd + c0;
     if (badd) {
 #pragma unroll
@@ -625,6 +619,48 @@ __global__ __launch_bounds__(BLK) void k_apply_pan(ApplyArgs a) {
 #pragma unroll
       for (int w = 0; w < W; ++w)
         if (c0 + w < nd) out[w] = acc[w];
+    }
+  };
+  if (a.T.pan_ell) {
+    // rows in hop-count order: each wavefront's words are padded only to its
+    // own longest row; the entry carries the bond type (at most two types)
+    const S am0 = (S)sd->amp[0], am1 = a.T.n_types > 1 ? (S)sd->amp[1] : (S)0;
+    auto amp_of = [&](uint32_t ent) { return (ent & 0x4000u) ? am1 : am0; };
+    const int npos = (nu + kWave - 1) / kWave * kWave;
+    for (int p = tid; p < npos; p += BLK) {
+      const int wv = p / kWave, lane = p % kWave;
+      const int u = (int)a.T.pan_perm[p];                 // nu past the last row
+      const int q0 = a.T.pan_woff[wv], nq = a.T.pan_woff[wv + 1] - q0;
+      const uint64_t* ell = a.T.pan_ell + (int64_t)q0 * kWave + lane;
+      cv<S> acc[W];
+      diag(u, acc);
+      uint64_t hn = nq > 0 ? ell[0] : 0;
+      for (int q = 0; q < nq; ++q) {
+        const uint64_t hw = hn;
+        if (q + 1 < nq) hn = ell[(int64_t)(q + 1) * kWave];
+        hops(acc, hw, amp_of, 0x3FFFu);
+      }
+      if (u < nu) store(u, acc);
+    }
+  } else {
+    // one padded, transposed table per bond type, the amplitude uniform per type
+    for (int u = tid; u < nu; u += BLK) {
+      cv<S> acc[W];
+      diag(u, acc);
+      const uint64_t* ell = a.T.ell_up;
+      for (int t = 0; t < a.T.n_types; ++t) {
+        const int kq = a.T.k_type_up[t];
+        const S am = (S)sd->amp[t];
+        auto amp_of = [&](uint32_t) { return am; };
+        uint64_t hn = kq > 0 ? ell[u] : 0;
+        for (int q = 0; q < kq; ++q) {
+          const uint64_t hw = hn;
+          if (q + 1 < kq) hn = ell[(int64_t)(q + 1) * nu + u];
+          hops(acc, hw, amp_of, 0x7FFFu);
+        }
+        ell += (int64_t)kq * nu;
+      }
+      store(u, acc);
     }
   }
 }

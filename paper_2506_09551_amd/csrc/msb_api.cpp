@@ -362,6 +362,60 @@ static hipError_t upload_ell(const SpinTable& sp, int n_types, int* k_type, uint
   return e;
 }
 
+// The up-spin hops of the LDS panel pass in row-count order: rows sorted by
+// their number of hops (descending) and dealt to wavefronts of 64 positions,
+// each wavefront's hop words padded only to its own longest row.  perm[p]
+// is the row at position p (n_up past the last row); woff[w] .. woff[w + 1]
+// are the words of wavefront w; word q of position p holds four hops as
+// 16-bit entries = target | type << 14 | (even parity ? 0x8000 : 0), padding
+// n_up.  Needs n_up < 16384 and at most two bond types (else not built).
+static hipError_t upload_pan_table(const SpinTable& sp, int n_types, uint32_t** d_perm, int** d_woff,
+                                   uint64_t** d_ell) {
+  const int n = sp.n;
+  if (n >= 16384 || n_types > 2) return hipSuccess;
+  std::vector<uint32_t> perm(n);
+  std::iota(perm.begin(), perm.end(), 0u);
+  std::stable_sort(perm.begin(), perm.end(), [&](uint32_t x, uint32_t y) {
+    return sp.off[x + 1] - sp.off[x] > sp.off[y + 1] - sp.off[y];
+  });
+  const int n_waves = (n + kWave - 1) / kWave;
+  perm.resize((size_t)n_waves * kWave, (uint32_t)n);
+  std::vector<int> woff(n_waves + 1, 0);
+  std::vector<uint64_t> ell;
+  for (int w = 0; w < n_waves; ++w) {
+    int mx = 0;
+    for (int l = 0; l < kWave; ++l) {
+      const uint32_t u = perm[(size_t)w * kWave + l];
+      if (u < (uint32_t)n) mx = std::max<int>(mx, (int)(sp.off[u + 1] - sp.off[u]));
+    }
+    const int nw = (mx + 3) / 4;
+    woff[w + 1] = woff[w] + nw;
+    for (int q = 0; q < nw; ++q)
+      for (int l = 0; l < kWave; ++l) {
+        const uint32_t u = perm[(size_t)w * kWave + l];
+        uint64_t word = 0;
+        for (int j = 0; j < 4; ++j) {
+          uint32_t ent = (uint32_t)n;
+          const uint32_t k = 4 * q + j;
+          if (u < (uint32_t)n && k < sp.off[u + 1] - sp.off[u]) {
+            const uint32_t h = sp.hop[sp.off[u] + k];
+            ent = (h >> 16) | (((h >> 1) & 127u) << 14) | ((h & 1u) ? 0u : 0x8000u);
+          }
+          word |= (uint64_t)ent << (16 * j);
+        }
+        ell.push_back(word);
+      }
+  }
+  hipError_t e = hipMalloc(d_perm, perm.size() * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemcpy(*d_perm, perm.data(), perm.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(d_woff, woff.size() * sizeof(int));
+  if (e == hipSuccess) e = hipMemcpy(*d_woff, woff.data(), woff.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(d_ell, std::max<size_t>(ell.size(), 1) * sizeof(uint64_t));
+  if (e == hipSuccess && !ell.empty())
+    e = hipMemcpy(*d_ell, ell.data(), ell.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+  return e;
+}
+
 extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   if (!m || !out) return fail(MSB_EINVAL, "msb_create: null argument");
   *out = nullptr;
@@ -457,6 +511,7 @@ extern "C" msb_status msb_create(const msb_model* m, msb_ctx** out) {
   // the up-spin table of the same form feeds the column-panel pass (rows of
   // one panel staged in LDS); up-spin ranks fit its 15-bit targets
   if (e == hipSuccess && c->up.n < 32768) e = upload_ell(c->up, c->n_types, c->k_type_up, &c->d_ell_up);
+  if (e == hipSuccess) e = upload_pan_table(c->up, c->n_types, &c->d_pan_perm, &c->d_pan_woff, &c->d_pan_ell);
   if (e == hipSuccess) e = upload(&c->d_order_up, c->up.order);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->solve_stream, hipStreamNonBlocking);
   for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&c->part_stream[k], hipStreamNonBlocking);
@@ -480,6 +535,9 @@ extern "C" void msb_destroy(msb_ctx* c) {
   (void)hipFree(c->d_hop_dn);
   (void)hipFree(c->d_ell_dn);
   (void)hipFree(c->d_ell_up);
+  (void)hipFree(c->d_pan_perm);
+  (void)hipFree(c->d_pan_woff);
+  (void)hipFree(c->d_pan_ell);
   (void)hipFree(c->d_order_up);
   if (c->solve_stream) (void)hipStreamDestroy(c->solve_stream);
   for (int k = 0; k < 3; ++k)

@@ -82,6 +82,14 @@ struct TablesDev {
   // up-spin hops in the same form (padding = n_up), k_type_up[t] words of
   // type t; null when the up-spin sector has 32768 states or more
   const uint64_t* ell_up;
+  // up-spin hops of the LDS panel pass in row-count order (null when not
+  // built: 16384 up-spin states or more, or more than two bond types):
+  // pan_perm[p] = row at position p, pan_woff[w] .. pan_woff[w + 1] = words of
+  // wavefront w (positions 64 w .. 64 w + 63), pan_ell[q * 64 + lane] = four
+  // 16-bit hops (target | type << 14 | even-parity sign bit 15), padding n_up
+  const uint32_t* pan_perm;
+  const int* pan_woff;
+  const uint64_t* pan_ell;
   const uint32_t* order_up;   // [n_up] up-spin rows in level order (SpinTable::order)
   int n_up, n_dn, k_dn;       // k_dn: sum of k_type (words of four hops)
   int k_up_max;               // most up-spin hops of one row
@@ -436,6 +444,9 @@ struct msb_ctx {
   uint32_t* d_hop_dn = nullptr;
   uint64_t* d_ell_dn = nullptr;
   uint64_t* d_ell_up = nullptr;
+  uint32_t* d_pan_perm = nullptr;
+  int* d_pan_woff = nullptr;
+  uint64_t* d_pan_ell = nullptr;
   uint32_t* d_order_up = nullptr;
   int k_type_dn[MSB_MAX_BOND_TYPES] = {0};   // words (four hops each) of each bond type's down-spin table
   int k_type_up[MSB_MAX_BOND_TYPES] = {0};   // the same for the up-spin table
@@ -458,6 +469,9 @@ struct msb_ctx {
     t.hop_up = d_hop_up; t.hop_dn = d_hop_dn;
     t.ell_dn = d_ell_dn;
     t.ell_up = d_ell_up;
+    t.pan_perm = d_pan_perm;
+    t.pan_woff = d_pan_woff;
+    t.pan_ell = d_pan_ell;
     t.order_up = d_order_up;
     t.n_up = up.n; t.n_dn = dn.n; t.k_dn = 0;
     t.k_up_max = up.max_hops;
