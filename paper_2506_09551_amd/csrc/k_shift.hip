@@ -579,9 +579,11 @@ __global__ __launch_bounds__(NW * kWave) void k_flush_gauss(FlushArgs a, const d
       const int64_t i = e0 + gauss_elem<SB>(lane, e);
       if (i >= a.D) continue;
       cv<double> v = {A1[t][e] - A2[t][e], A1[t][e] + A3[t][e]};
-      if (ow_mode != 0) v = cadd(v, cmul(ow, AO::template load<double>(a.out, obase + i)));
-      if (a.X) v = cadd(v, cmul(pw, AO::template load<double>(a.X, obase + i)));
-      AO::store(a.out, obase + i, v);
+      // outputs stream through the caches (non-temporal): they must not
+      // evict the residual chunks that the other shift tiles still read
+      if (ow_mode != 0) v = cadd(v, cmul(ow, AO::template load_nt<double>(a.out, obase + i)));
+      if (a.X) v = cadd(v, cmul(pw, AO::template load_nt<double>(a.X, obase + i)));
+      AO::store_nt(a.out, obase + i, v);
     }
   }
 }
