@@ -260,6 +260,9 @@ PANEL = {
     "square4x4_5_1": dict(L=16, nu=5, nd=1, bonds=W.square_bonds(4, 4, 1.0, -0.25), U=8.0),
     "chain14_7_1": dict(L=14, nu=7, nd=1, bonds=W.chain_bonds(14, 1.0, -0.2), U=8.0),
     "chain7_3_3": dict(L=7, nu=3, nd=3, bonds=W.chain_bonds(7, 1.0), U=8.0),
+    # odd rows (91 states) under a large up-spin sector: complex64 panels
+    # take the element-wise staging path
+    "chain14_7_2": dict(L=14, nu=7, nd=2, bonds=W.chain_bonds(14, 1.0), U=8.0),
     # three bond types (third neighbours added): the per-type panel table,
     # not the hop-count-ordered one (built for at most two types)
     "chain12_6_1_t3": dict(L=12, nu=6, nd=1, U=8.0,
