@@ -177,10 +177,13 @@ typedef struct {
                             chunk is min(replace_every, 64). */
   int use_graph;         /* 0 or 1 = capture the chunk in a hipGraph (default), -1 = plain launches */
   double mem_fraction;   /* fraction of free device memory the workspace may use (default 0.9) */
-  int assembly_engine;   /* multi-shift assembly, all in FP64: 0 = vector ALU with three real
-                            products per complex product (default), 1 = matrix cores, 2 = vector
+  int assembly_engine;   /* multi-shift assembly: 0 = FP64 vector ALU with three real products
+                            per complex product (default), 1 = FP64 matrix cores, 2 = FP64 vector
                             ALU with four real products, 3 = as 0 with 64 shifts per workgroup,
-                            4 = as 0 with 256 elements and eight wavefronts of four shifts */
+                            4 = as 0 with 256 elements and eight wavefronts of four shifts,
+                            5 = int8 matrix cores on 8-bit digit planes of the FP64 operands
+                            (46 bits per operand and 64-slot chunk; MSB_C128 only, MSB_C64
+                            takes 0) */
   int autotune;          /* 0 = tune the apply shape on first use (default), -1 = default shape
                             unless one was tuned or pinned before */
   int dual;              /* 0 = the dual-space (BiCG) form only when some system's A is not

@@ -956,9 +956,10 @@ struct SolveBufs {
   void* pt = nullptr;
   void* vt = nullptr;
   SysDev* dsysT = nullptr;
+  void* ozw = nullptr;          // int8 assembly engine: coefficient digit planes
 
   void carve(Carver& c, const msb_ctx* ctx, int B, int cap, int n_shift, int n_list, int maxit,
-             size_t s_el, size_t s_out, bool carry, bool want_true, bool replace, bool dual) {
+             size_t s_el, size_t s_out, bool carry, bool want_true, bool replace, bool dual, int engine) {
     const int64_t D = ctx->D;
     size_t part_n = 0;   // largest nsys * nbx over the batch sizes that can occur
     for (int n = 1; n <= B; ++n)
@@ -992,6 +993,8 @@ struct SolveBufs {
     gcoef = carry ? c.take<double>((size_t)B * n_list * cap * 3 * sizeof(double)) : nullptr;
     cscr = c.take<double>((size_t)B * n_list * cap * 4 * sizeof(double));
     ab = c.take<double>((size_t)B * n_list * 4 * sizeof(double));
+    const size_t ozb = flush_work_bytes(engine, B, n_list, cap);
+    ozw = ozb ? c.take<void>(ozb) : nullptr;
     if (replace) {
       xseed = c.take<double>((size_t)B * D * 16);
       psnap = c.take<void>((size_t)B * D * s_el);
@@ -1054,6 +1057,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   // the three-product engines stage complex64 slots in 16-byte units, which
   // needs an even D (16-byte aligned slots); odd D takes the four-product one
   if (prec == MSB_C64 && (ctx->D & 1) && flush_coef_comps(engine) == 3) engine = 2;
+  // the int8 matrix-core engine splits complex128 banks only
+  if (prec == MSB_C64 && engine == 5) engine = 0;
   const int tile_s = flush_shifts_per_tile(engine);
   const int n_list = ((n_shift + tile_s - 1) / tile_s) * tile_s;
   const size_t s_el = elem_bytes(ev), s_out = elem_bytes(eo);
@@ -1108,7 +1113,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   auto need_bytes = [&](int B, int cap, bool carry) {
     Carver c(nullptr);
     SolveBufs b;
-    b.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, carry, want_true, replace_every > 0, dual);
+    b.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, carry, want_true, replace_every > 0, dual, engine);
     return c.used();
   };
   int planB = 0, plancap = 0;
@@ -1167,7 +1172,7 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   SolveBufs bf;
   {
     Carver c(ctx->ws);
-    bf.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, plancarry, want_true, replace_every > 0, dual);
+    bf.carve(c, ctx, B, cap, n_shift, n_list, mx, s_el, s_out, plancarry, want_true, replace_every > 0, dual, engine);
   }
   void* bank = bf.bank;
   void* pvec = bf.pvec;
@@ -1342,6 +1347,10 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
       fa.X = nullptr; fa.D = D; fa.n_shift = n_shift; fa.n_list = n_list; fa.K = Kc; fa.nsys = nb;
       fa.n_etiles = (int)((D + flush_elems_per_tile(engine) - 1) / flush_elems_per_tile(engine));
       fa.n_stiles = n_stiles;
+      fa.work = bf.ozw;
+      fa.rnorm = rlog;
+      fa.rn_stride = mx + 1;
+      fa.rn_base = base;
       if (!first_flush && Pc) {
         fa.pw = ab;          // Psi += (bw_base S_base) p_{base-1}
         fa.X = Pc;

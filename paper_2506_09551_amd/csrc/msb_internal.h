@@ -331,13 +331,18 @@ struct FlushArgs {
   int64_t D;
   int n_shift, n_list, K, nsys;
   int n_etiles, n_stiles;
+  void* work = nullptr;         // engine 5: coefficient digit planes (flush_work_bytes)
+  const double* rnorm = nullptr;  // engine 5: |r_m| log [nsys][rn_stride]; slot l is m = rn_base + l
+  int rn_stride = 0, rn_base = 0;
 };
 // ow_mode: 0 = old output ignored, 1 = weight 1, 2 = per-shift weights from ow
 // engine: 0 = FP64 vector ALU, three real products per complex product (the
 // default), 1 = FP64 matrix cores, 2 = FP64 vector ALU, four real products,
 // 3 = as 0 with eight wavefronts (64 shifts per workgroup), 4 = eight
-// wavefronts of four shifts and 256 elements
-constexpr int kNumFlushEngines = 5;
+// wavefronts of four shifts and 256 elements, 5 = int8 matrix cores on
+// 7-bit digit planes of the FP64 operands (complex128 bank and output)
+constexpr int kNumFlushEngines = 6;
+size_t flush_work_bytes(int engine, int nsys, int n_list, int K);
 hipError_t launch_flush(Elem bank, Elem out, const FlushArgs& a, int ow_mode, int engine,
                         hipStream_t st);
 int flush_shifts_per_tile(int engine);

@@ -441,10 +441,12 @@ def test_other_models(gpu, name):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("engine", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("engine", [0, 1, 2, 3, 4, 5])
 def test_assembly_engines_match_direct_solve(tiny, engine, prec):
     """Every multi-shift assembly engine (three-product vector ALU and its two
-    variants, matrix cores, four-product vector ALU), with and without carry
+    variants, FP64 matrix cores, four-product vector ALU, int8 matrix cores
+    on digit planes; complex64 banks take engine 0 in place of 5), with and
+    without carry
     (a 41-slot bank), in both storage precisions; 70 shifts span more than one
     shift tile with a ragged last one, and D = 4900 ends in a ragged element
     tile."""
@@ -465,6 +467,29 @@ def test_assembly_engines_match_direct_solve(tiny, engine, prec):
         for j in range(2):
             err = _rel(psi[j], refs[j])
             assert err <= bar, f"engine {engine} slots {slots} system {j}: {err:.3e}"
+
+
+def test_int8_engine_two_shift_groups_matches_direct_solve(tiny):
+    """The int8 matrix-core assembly (engine 5) over 300 shifts: two groups of
+    256 shift slots, the second ragged; with and without carry (a 37-slot
+    bank, so several flushes add into the output and carry p).  Against the
+    oracle's direct solves at 1e-9 (tol 1e-12), and against the FP64
+    three-product engine on the same bank to 1e-10 relative (the splitting
+    keeps 46 bits of every operand per 64-slot chunk)."""
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E = W.random_complex(D, 45)
+    E_G = -2.6661474201323485
+    sysd = [msb.make_system(core_site=1, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma)]
+    w = np.linspace(-11.0, 11.0, 300)
+    ref = osolve.direct_solve(oracle_H(m, core_site=1, Uc=wl.Uc), E, E_G, wl.Gamma, w, method="eig")
+    for slots in (0, 37):
+        _, _, psi5 = _run(msb, ctx, sysd, E, w, 1e-12, 3000, msb.MSB_C128,
+                          opts={"assembly_engine": 5, "bank_slots": slots})
+        _, _, psi0 = _run(msb, ctx, sysd, E, w, 1e-12, 3000, msb.MSB_C128,
+                          opts={"assembly_engine": 0, "bank_slots": slots})
+        assert _rel(psi5[0], ref) <= 1e-9, f"slots {slots}"
+        assert _rel(psi5[0], psi0[0]) <= 1e-10, f"slots {slots}: {_rel(psi5[0], psi0[0]):.3e}"
 
 
 def test_c64_odd_dimension(gpu):
