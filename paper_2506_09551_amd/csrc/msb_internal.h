@@ -343,6 +343,8 @@ struct FlushArgs {
 // 7-bit digit planes of the FP64 operands (complex128 bank and output)
 constexpr int kNumFlushEngines = 6;
 size_t flush_work_bytes(int engine, int nsys, int n_list, int K);
+// engine 5 (k_flush_oz.hip): coefficient digit planes, then the contraction
+hipError_t launch_flush_oz(const FlushArgs& a, dim3 grid, int ow_mode, hipStream_t st);
 hipError_t launch_flush(Elem bank, Elem out, const FlushArgs& a, int ow_mode, int engine,
                         hipStream_t st);
 int flush_shifts_per_tile(int engine);
