@@ -846,7 +846,7 @@ def run_solver_workload(wl_name, args, extras=True, cpu=True):
         # the multi-shift assembly engines on this step (one solve each; the
         # default is the one the timed steps used)
         engines = {}
-        for eng in range(6):
+        for eng in range(7):
             _, inf = msb.msb_solve(ctx, systems, E, wl.w_in, wl.seed_shift, args.tol, wl.maxit, prec, psi,
                                    want_true=False, raise_on_fail=False, opts={"assembly_engine": eng})
             ms = inf["t_gemm_ms"] / max(1, inf["n_gemm"])
@@ -854,8 +854,9 @@ def run_solver_workload(wl_name, args, extras=True, cpu=True):
                                  "TFLOPs": round(inf["gemm_flops"] / max(1, inf["n_gemm"]) / (ms * 1e-3) / 1e12, 2)}
         out["assembly_engines"] = {"note": "0: three real products per complex product (default); 1: FP64 "
                                            "matrix cores; 2: four real products; 3, 4: variants of 0; 5: int8 "
-                                           "matrix cores on 8-bit digit planes (TFLOPs counts the FP64 "
-                                           "contraction's flops)",
+                                           "matrix cores on 8-bit digit planes; 6: FP64 matrix cores, three "
+                                           "products, bank staged in LDS (TFLOPs counts the contraction's "
+                                           "algorithmic flops)",
                                    **engines}
         log(f"assembly engines {out['assembly_engines']}")
 

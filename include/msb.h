@@ -182,8 +182,9 @@ typedef struct {
                             ALU with four real products, 3 = as 0 with 64 shifts per workgroup,
                             4 = as 0 with 256 elements and eight wavefronts of four shifts,
                             5 = int8 matrix cores on 8-bit digit planes of the FP64 operands
-                            (46 bits per operand and 64-slot chunk; MSB_C128 only, MSB_C64
-                            takes 0) */
+                            (46 bits per operand and 64-slot chunk), 6 = FP64 matrix cores
+                            with three real products, the bank staged in LDS (5 and 6:
+                            MSB_C128 only, MSB_C64 takes 0) */
   int autotune;          /* 0 = tune the apply shape on first use (default), -1 = default shape
                             unless one was tuned or pinned before */
   int dual;              /* 0 = the dual-space (BiCG) form only when some system's A is not

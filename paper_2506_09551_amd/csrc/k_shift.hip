@@ -143,6 +143,7 @@ __host__ __device__ constexpr GaussShape gauss_shape(int engine) {
 }
 int flush_shifts_per_tile(int engine) {
   if (engine == 5) return 256;     // k_flush_oz.hip: shift slots per workgroup
+  if (engine == 6) return 16;      // k_flush_mf64.hip: one wavefront per 16-shift tile
   if (engine == 1) return kFlushM * kFlushWaves;
   if (engine == 2) return 8 * kFlushWaves;
   const GaussShape g = gauss_shape(engine);
@@ -150,6 +151,7 @@ int flush_shifts_per_tile(int engine) {
 }
 int flush_elems_per_tile(int engine) {
   if (engine == 5) return 32;      // k_flush_oz.hip: elements per workgroup
+  if (engine == 6) return 32;      // k_flush_mf64.hip
   if (engine == 1) return 16 * kFlushNT;
   if (engine == 2) return kWave * 4;
   return kWave * gauss_shape(engine).EPL;
@@ -601,6 +603,10 @@ hipError_t launch_flush(Elem eb, Elem eo, const FlushArgs& a, int ow_mode, int e
     // complex128 bank and output only; the digit planes go to a.work
     if (eb != Elem::C128 || eo != Elem::C128 || !a.work) return hipErrorInvalidValue;
     return launch_flush_oz(a, grid, ow_mode, st);
+  }
+  if (engine == 6) {
+    if (eb != Elem::C128) return hipErrorInvalidValue;     // complex128 bank
+    return launch_flush_mf64(eo, a, ow_mode, st);
   }
 #define MSB_GAUSS(SB, SO, E)                                                                   \
   hipLaunchKernelGGL((k_flush_gauss<SB, SO, gauss_shape(E).M, gauss_shape(E).EPL, gauss_shape(E).NW>), grid, \

@@ -1057,8 +1057,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   // the three-product engines stage complex64 slots in 16-byte units, which
   // needs an even D (16-byte aligned slots); odd D takes the four-product one
   if (prec == MSB_C64 && (ctx->D & 1) && flush_coef_comps(engine) == 3) engine = 2;
-  // the int8 matrix-core engine splits complex128 banks only
-  if (prec == MSB_C64 && engine == 5) engine = 0;
+  // the int8 and FP64 matrix-core engines take complex128 banks only
+  if (prec == MSB_C64 && (engine == 5 || engine == 6)) engine = 0;
   const int tile_s = flush_shifts_per_tile(engine);
   const int n_list = ((n_shift + tile_s - 1) / tile_s) * tile_s;
   const size_t s_el = elem_bytes(ev), s_out = elem_bytes(eo);

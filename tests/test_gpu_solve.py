@@ -441,7 +441,7 @@ def test_other_models(gpu, name):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("engine", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("engine", [0, 1, 2, 3, 4, 5, 6])
 def test_assembly_engines_match_direct_solve(tiny, engine, prec):
     """Every multi-shift assembly engine (three-product vector ALU and its two
     variants, FP64 matrix cores, four-product vector ALU, int8 matrix cores
@@ -469,13 +469,16 @@ def test_assembly_engines_match_direct_solve(tiny, engine, prec):
             assert err <= bar, f"engine {engine} slots {slots} system {j}: {err:.3e}"
 
 
-def test_int8_engine_two_shift_groups_matches_direct_solve(tiny):
-    """The int8 matrix-core assembly (engine 5) over 300 shifts: two groups of
-    256 shift slots, the second ragged; with and without carry (a 37-slot
-    bank, so several flushes add into the output and carry p).  Against the
-    oracle's direct solves at 1e-9 (tol 1e-12), and against the FP64
-    three-product engine on the same bank to 1e-10 relative (the splitting
-    keeps 46 bits of every operand per 64-slot chunk)."""
+@pytest.mark.parametrize("engine", [5, 6])
+def test_matrix_core_engines_many_shifts_match_direct_solve(tiny, engine):
+    """The matrix-core assemblies over 300 shifts (19 tiles of 16): the int8
+    engine (5) in two groups of 256 shift slots, the second ragged; the FP64
+    engine (6) in two groups of 10 and 9 tiles, four of each shared by two
+    wavefronts.  With and without carry (a 37-slot bank, so several flushes
+    add into the output and carry p).  Against the oracle's direct solves at
+    1e-9 (tol 1e-12), and against the FP64 three-product vector engine on the
+    same bank to 1e-10 relative (engine 5 keeps 46 bits of every operand per
+    64-slot chunk; engine 6 differs by rounding only)."""
     msb, ctx, wl, m = tiny
     D = msb.msb_dim(ctx)
     E = W.random_complex(D, 45)
@@ -485,7 +488,7 @@ def test_int8_engine_two_shift_groups_matches_direct_solve(tiny):
     ref = osolve.direct_solve(oracle_H(m, core_site=1, Uc=wl.Uc), E, E_G, wl.Gamma, w, method="eig")
     for slots in (0, 37):
         _, _, psi5 = _run(msb, ctx, sysd, E, w, 1e-12, 3000, msb.MSB_C128,
-                          opts={"assembly_engine": 5, "bank_slots": slots})
+                          opts={"assembly_engine": engine, "bank_slots": slots})
         _, _, psi0 = _run(msb, ctx, sysd, E, w, 1e-12, 3000, msb.MSB_C128,
                           opts={"assembly_engine": 0, "bank_slots": slots})
         assert _rel(psi5[0], ref) <= 1e-9, f"slots {slots}"
