@@ -37,8 +37,8 @@ C64_OPTS = None
 # profiles/solve_scale_L12_hbm_counters.md: raw FETCH_SIZE / WRITE_SIZE in KiB
 # and the copy-calibrated factors; valid while the kernel source is unchanged.
 FLUSH_COUNTERS = {
-    "source": "paper_2506_09551_amd/csrc/k_shift.hip", "sha256_16": "bf63a2734b3c989c",
-    "fetch_kib": 64114254.6, "write_kib": 32016600.0, "fetch_factor": 2.0, "write_factor": 1.0,
+    "source": "paper_2506_09551_amd/csrc/k_shift.hip", "sha256_16": "1ae052f0b875109a",
+    "fetch_kib": 64184085.1, "write_kib": 32016600.0, "fetch_factor": 2.0, "write_factor": 1.0,
     "workload": "scale_L12_N6",
 }
 

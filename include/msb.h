@@ -177,14 +177,17 @@ typedef struct {
                             chunk is min(replace_every, 64). */
   int use_graph;         /* 0 or 1 = capture the chunk in a hipGraph (default), -1 = plain launches */
   double mem_fraction;   /* fraction of free device memory the workspace may use (default 0.9) */
-  int assembly_engine;   /* multi-shift assembly: 0 = FP64 vector ALU with three real products
-                            per complex product (default), 1 = FP64 matrix cores, 2 = FP64 vector
-                            ALU with four real products, 3 = as 0 with 64 shifts per workgroup,
-                            4 = as 0 with 256 elements and eight wavefronts of four shifts,
-                            5 = int8 matrix cores on 8-bit digit planes of the FP64 operands
-                            (46 bits per operand and 64-slot chunk), 6 = FP64 matrix cores
-                            with three real products, the bank staged in LDS (5 and 6:
-                            MSB_C128 only, MSB_C64 takes 0) */
+  int assembly_engine;   /* multi-shift assembly: 0 = the default: the FP64 vector ALU with
+                            three real products per complex product, except for an MSB_C64
+                            bank with 128 or more shifts, which takes 5; 1 = FP64 matrix
+                            cores, four products; 2 = FP64 vector ALU, four products; 3 = as
+                            0 with 64 shifts per workgroup; 4 = as 0 with 256 elements and
+                            eight wavefronts of four shifts; 5 = int8 matrix cores on 8-bit
+                            digit planes of the operands (six planes, 46 bits, for an
+                            MSB_C128 bank; five planes, 38 bits, for MSB_C64); 6 = FP64
+                            matrix cores with three products, the bank staged in LDS
+                            (MSB_C128 only: MSB_C64 takes the vector ALU); 7 = the FP64
+                            vector ALU with three products in every case */
   int autotune;          /* 0 = tune the apply shape on first use (default), -1 = default shape
                             unless one was tuned or pinned before */
   int dual;              /* 0 = the dual-space (BiCG) form only when some system's A is not

@@ -15,23 +15,25 @@ namespace msb {
 // the operands of one chunk then have comparable magnitudes).  Within a chunk
 // of 64 slots each coefficient row (shift, product) and each bank column
 // (element, product) gets its own power-of-two scale 2^E with every |v| <
-// 2^E; Y = trunc(v 2^(46 - E)) is an integer with |Y| < 2^46, written in
-// balanced digits Y = sum_p d_p 2^(40 - 8p), p = 0..5: the bytes of
-// Y + 128 (2^32 + 2^24 + 2^16 + 2^8 + 1) minus 128, the top digit (in
-// [-64, 64]) taking the carry.  A digit product has weight 2^(-8(p + q));
-// the 21 pairs with p + q <= 5 are summed exactly in 32-bit integers over
-// the chunk by v_mfma_i32_16x16x64_i8, one integer sum per level t = p + q,
-// and the six level sums become one FP64 value scaled by the two chunk
-// exponents.  The dropped pairs and the truncation leave an error of order
-// 2^-45 of the chunk's largest product per term, with no bias (balanced
-// digits); on Krylov banks of the 8- and 10-site rings the assembled
-// solutions differ from the FP64 sums by at most 2.2e-11 relative.
+// 2^E; with NP planes, Y = trunc(v 2^(8 NP - 2 - E)) is an integer with
+// |Y| < 2^(8 NP - 2), written in balanced digits
+// Y = sum_p d_p 2^(8 (NP - 1 - p)), p = 0..NP-1: the bytes of Y plus 128 in
+// each lower byte, minus 128, the top digit (in [-64, 64]) taking the carry.
+// A digit product has weight 2^(-8(p + q)); the NP (NP + 1) / 2 pairs with
+// p + q < NP are summed exactly in 32-bit integers over the chunk by
+// v_mfma_i32_16x16x64_i8, one integer sum per level t = p + q, and the level
+// sums become one FP64 value scaled by the two chunk exponents.  The dropped
+// pairs and the truncation leave an error of order 2^-(8 NP - 3) of the
+// chunk's largest product per term, with no bias (balanced digits).  A
+// complex128 bank takes NP = 6 (21 pairs; on Krylov banks of the 8- and
+// 10-site rings the assembled solutions differ from the FP64 sums by at
+// most 2.2e-11 relative), a complex64 bank, whose values carry 24 bits,
+// NP = 5 (15 pairs, 256 times that).
 //
 // MFMA operand layout: lane l holds row l % 16 of A and column l % 16 of B
 // for the 16 depth indices 16 (l / 16) .. + 15 (one byte each); the 16 x 16
 // result holds row 4 (l / 16) + r, column l % 16 in register r.
-constexpr int kOzPlanes = 6;      // digit planes per operand
-constexpr int kOzLevels = 6;      // kept levels t = 0..5
+constexpr int kOzPlanes = 6;      // digit planes per operand, at most (workspace size)
 constexpr int kOzKC = 64;         // slots per chunk (one MFMA depth)
 constexpr int kOzNE = 32;         // elements per workgroup (two 16-column tiles)
 constexpr int kOzWaves = 8;
@@ -47,22 +49,26 @@ __device__ __forceinline__ int oz_bexp(double v, int de) {
   const int b = (int)((uint32_t)(__double_as_longlong(v) >> 52) & 0x7FFu);
   return b == 0 ? kOzNone : b + de;
 }
-// Y + bias for Y = trunc(v 2^de 2^(46 - E)), eb the biased chunk exponent
-// (every |v 2^de| < 2^(eb - 1022)): the 53-bit significand shifted right by
-// 7 + eb - (b + de)
+// Y + bias for Y = trunc(v 2^de 2^(8 NP - 2 - E)), eb the biased chunk
+// exponent (every |v 2^de| < 2^(eb - 1022)): the 53-bit significand shifted
+// right by 55 - 8 NP + eb - (b + de); the bias is 128 in each of the NP - 1
+// lower bytes
+template <int NP>
 __device__ __forceinline__ int64_t oz_fixed(double v, int eb, int de) {
   const uint64_t bits = (uint64_t)__double_as_longlong(v);
   const int b = (int)((bits >> 52) & 0x7FFu);
-  const int sh = 7 + eb - (b + de);
+  const int sh = 55 - 8 * NP + eb - (b + de);
   const uint64_t m = (bits & 0xFFFFFFFFFFFFFull) | 0x10000000000000ull;
   int64_t y = (b == 0 || sh > 60) ? 0 : (int64_t)(m >> sh);
   y = (bits >> 63) ? -y : y;
-  return y + 0x8080808080ll;
+  return y + (NP == 6 ? 0x8080808080ll : 0x80808080ll);
 }
-// the six digit planes of four biased values as signed bytes, value j in
-// byte j: plane 0 is byte 5 of each (the top digit), planes 1..5 bytes 4..0
-// with 128 subtracted (a byte transpose by v_perm)
-__device__ __forceinline__ void oz_planes4(const int64_t (&y)[4], int (&pl)[kOzPlanes]) {
+// the NP digit planes of four biased values as signed bytes, value j in
+// byte j: plane 0 is byte NP - 1 of each (the top digit), planes 1..NP-1
+// bytes NP-2..0 with 128 subtracted (a byte transpose by v_perm)
+template <int NP>
+__device__ __forceinline__ void oz_planes4(const int64_t (&y)[4], int (&pl)[NP]) {
+  static_assert(NP == 5 || NP == 6, "five or six planes");
   uint32_t lo[4], hi[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -76,12 +82,13 @@ __device__ __forceinline__ void oz_planes4(const int64_t (&y)[4], int (&pl)[kOzP
   const uint32_t t3 = __builtin_amdgcn_perm(lo[3], lo[2], 0x07030602u);
   const uint32_t h0 = __builtin_amdgcn_perm(hi[1], hi[0], 0x05010400u);
   const uint32_t h2 = __builtin_amdgcn_perm(hi[3], hi[2], 0x05010400u);
-  pl[0] = (int)__builtin_amdgcn_perm(h2, h0, 0x07060302u);                    // byte 5
-  pl[1] = (int)(__builtin_amdgcn_perm(h2, h0, 0x05040100u) ^ 0x80808080u);    // byte 4
-  pl[2] = (int)(__builtin_amdgcn_perm(t3, t1, 0x07060302u) ^ 0x80808080u);    // byte 3
-  pl[3] = (int)(__builtin_amdgcn_perm(t3, t1, 0x05040100u) ^ 0x80808080u);    // byte 2
-  pl[4] = (int)(__builtin_amdgcn_perm(t2, t0, 0x07060302u) ^ 0x80808080u);    // byte 1
-  pl[5] = (int)(__builtin_amdgcn_perm(t2, t0, 0x05040100u) ^ 0x80808080u);    // byte 0
+  constexpr int o = NP - 5;                                                   // planes above byte 4
+  if constexpr (NP == 6) pl[0] = (int)__builtin_amdgcn_perm(h2, h0, 0x07060302u);   // byte 5
+  pl[o] = (int)(__builtin_amdgcn_perm(h2, h0, 0x05040100u) ^ (NP == 6 ? 0x80808080u : 0u));  // byte 4
+  pl[o + 1] = (int)(__builtin_amdgcn_perm(t3, t1, 0x07060302u) ^ 0x80808080u);    // byte 3
+  pl[o + 2] = (int)(__builtin_amdgcn_perm(t3, t1, 0x05040100u) ^ 0x80808080u);    // byte 2
+  pl[o + 3] = (int)(__builtin_amdgcn_perm(t2, t0, 0x07060302u) ^ 0x80808080u);    // byte 1
+  pl[o + 4] = (int)(__builtin_amdgcn_perm(t2, t0, 0x05040100u) ^ 0x80808080u);    // byte 0
 }
 // exponent e_l of slot l (|r_l| in [2^e_l, 2^(e_l + 1))), 0 without norms
 __device__ __forceinline__ int oz_slot_exp(const FlushArgs& a, int s, int l) {
@@ -95,6 +102,7 @@ __device__ __forceinline__ int oz_slot_exp(const FlushArgs& a, int s, int l) {
 // product); lane l takes row l % 16 (list slot 16 T + l % 16) and the slots
 // 64 c + 16 (l / 16) .. + 15.  Writes planes [s][T][c][P][p][64 lanes][16 B]
 // and the biased row exponents [s][T][c][P][16].
+template <int NP>
 __global__ __launch_bounds__(256) void k_oz_coef(FlushArgs a, int n_chunks, v4i* __restrict__ planes,
                                                  int* __restrict__ rexp) {
   const int n_tiles = a.n_list / 16;
@@ -120,16 +128,16 @@ __global__ __launch_bounds__(256) void k_oz_coef(FlushArgs a, int n_chunks, v4i*
   }
   eb = max(eb, __shfl_xor(eb, 16));
   eb = max(eb, __shfl_xor(eb, 32));
-  int pl[4][kOzPlanes];
+  int pl[4][NP];
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
-    const int64_t y[4] = {oz_fixed(v[4 * d], eb, de[4 * d]), oz_fixed(v[4 * d + 1], eb, de[4 * d + 1]),
-                          oz_fixed(v[4 * d + 2], eb, de[4 * d + 2]), oz_fixed(v[4 * d + 3], eb, de[4 * d + 3])};
-    oz_planes4(y, pl[d]);
+    const int64_t y[4] = {oz_fixed<NP>(v[4 * d], eb, de[4 * d]), oz_fixed<NP>(v[4 * d + 1], eb, de[4 * d + 1]),
+                          oz_fixed<NP>(v[4 * d + 2], eb, de[4 * d + 2]), oz_fixed<NP>(v[4 * d + 3], eb, de[4 * d + 3])};
+    oz_planes4<NP>(y, pl[d]);
   }
-  v4i* dst = planes + (w * kOzPlanes) * 64;
+  v4i* dst = planes + (w * NP) * 64;
 #pragma unroll
-  for (int p = 0; p < kOzPlanes; ++p) dst[p * 64 + lane] = v4i{pl[0][p], pl[1][p], pl[2][p], pl[3][p]};
+  for (int p = 0; p < NP; ++p) dst[p * 64 + lane] = v4i{pl[0][p], pl[1][p], pl[2][p], pl[3][p]};
   if (lane < 16) rexp[w * 16 + lane] = eb;
 }
 
@@ -145,11 +153,13 @@ __global__ __launch_bounds__(256) void k_oz_coef(FlushArgs a, int n_chunks, v4i*
 // requested before the split).  Planes are double-buffered: chunk c + 1 is
 // split, and chunk c + 2 is in flight, while the matrix instructions of
 // chunk c run.
+template <typename SB, typename SO, int NP>
 __global__ __launch_bounds__(kOzWaves * kWave) void k_flush_oz(FlushArgs a, const v4i* __restrict__ cplanes,
                                                                 const int* __restrict__ crexp, int n_chunks,
                                                                 int ow_mode) {
-  using AO = Access<double, true>;
-  __shared__ v4i bpl[2][2][3][kOzPlanes][64];             // [buffer][column tile][product][plane][lane]
+  using AB = Access<SB, true>;
+  using AO = Access<SO, true>;
+  __shared__ v4i bpl[2][2][3][NP][64];             // [buffer][column tile][product][plane][lane]
   __shared__ int wexp[2][kOzWaves][kOzNE][3];             // per-wavefront maxima of the biased exponents
   __shared__ int cexp[2][kOzNE][3];                       // chunk exponent per element and product
 
@@ -164,7 +174,7 @@ __global__ __launch_bounds__(kOzWaves * kWave) void k_flush_oz(FlushArgs a, cons
   const int lane = tid % kWave;
   const int Kext = a.tile_k[s * a.n_stiles + stt];
   const int64_t e0 = (int64_t)et * kOzNE;
-  const cv<double>* bank_s = reinterpret_cast<const cv<double>*>(a.bank) + (int64_t)s * a.cap * a.D;
+  const void* bank_s = AB::offset(a.bank, (int64_t)s * a.cap * a.D);
   const int n_tiles = a.n_list / 16;
   // this wavefront's shift tiles (list tiles) and their slot extents
   int tile[kOzTPW], kw[kOzTPW];
@@ -186,7 +196,7 @@ __global__ __launch_bounds__(kOzWaves * kWave) void k_flush_oz(FlushArgs a, cons
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int l = kOzKC * c + 4 * sq + j;
-      rv[j] = l < Kext ? AO::template load_nt<double>(bank_s, (int64_t)l * a.D + my_e) : cv<double>{0.0, 0.0};
+      rv[j] = l < Kext ? AB::template load_nt<double>(bank_s, (int64_t)l * a.D + my_e) : cv<double>{0.0, 0.0};
       rde[j] = l < Kext ? -oz_slot_exp(a, s, l) : 0;
     }
   };
@@ -227,12 +237,12 @@ __global__ __launch_bounds__(kOzWaves * kWave) void k_flush_oz(FlushArgs a, cons
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const double v = P == 0 ? rv[j].re + rv[j].im : (P == 1 ? rv[j].im : rv[j].re);
-        y[j] = oz_fixed(v, eb[P], rde[j]);
+        y[j] = oz_fixed<NP>(v, eb[P], rde[j]);
       }
-      int pl[kOzPlanes];
-      oz_planes4(y, pl);
+      int pl[NP];
+      oz_planes4<NP>(y, pl);
 #pragma unroll
-      for (int p = 0; p < kOzPlanes; ++p) reinterpret_cast<int*>(&bpl[buf][ct][P][p][L])[dw] = pl[p];
+      for (int p = 0; p < NP; ++p) reinterpret_cast<int*>(&bpl[buf][ct][P][p][L])[dw] = pl[p];
     }
   };
 
@@ -248,14 +258,14 @@ __global__ __launch_bounds__(kOzWaves * kWave) void k_flush_oz(FlushArgs a, cons
   // coefficient planes and row exponents of (chunk c, product P, tile u),
   // walked in the order (c, P, u)
   struct AOps {
-    v4i A[kOzPlanes];
+    v4i A[NP];
     v4i ea;
   };
   auto load_a = [&](int c, int P, int u, AOps& o) {
     if (c < nck && kOzKC * c < kw[u]) {
       const int64_t w = (((int64_t)s * n_tiles + tile[u]) * n_chunks + c) * 3 + P;
 #pragma unroll
-      for (int p = 0; p < kOzPlanes; ++p) o.A[p] = cplanes[(w * kOzPlanes + p) * 64 + lane];
+      for (int p = 0; p < NP; ++p) o.A[p] = cplanes[(w * NP + p) * 64 + lane];
       o.ea = *reinterpret_cast<const v4i*>(crexp + w * 16 + 4 * (lane / 16));
     }
   };
@@ -271,26 +281,29 @@ __global__ __launch_bounds__(kOzWaves * kWave) void k_flush_oz(FlushArgs a, cons
         if (kOzKC * c < kw[u]) {
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct) {
-            v4i B[kOzPlanes];
+            v4i B[NP];
 #pragma unroll
-            for (int p = 0; p < kOzPlanes; ++p) B[p] = bpl[buf][ct][P][p][lane];
+            for (int p = 0; p < NP; ++p) B[p] = bpl[buf][ct][P][p][lane];
             const int eb = cexp[buf][16 * ct + lane % 16][P];
-            v4i lv[kOzLevels];
+            v4i lv[NP];
 #pragma unroll
-            for (int t = 0; t < kOzLevels; ++t) lv[t] = v4i{0, 0, 0, 0};
+            for (int t = 0; t < NP; ++t) lv[t] = v4i{0, 0, 0, 0};
 #pragma unroll
-            for (int qb = 0; qb < kOzPlanes; ++qb)
+            for (int qb = 0; qb < NP; ++qb)
 #pragma unroll
-              for (int pa = 0; pa + qb < kOzLevels; ++pa)
+              for (int pa = 0; pa + qb < NP; ++pa)
                 lv[pa + qb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur.A[pa], B[qb], lv[pa + qb], 0, 0, 0);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              // levels 0..5 (weights 2^(-8t)) -> one FP64 value in units of 2^-40
-              const int i01 = lv[0][r] * 256 + lv[1][r];
-              const int i23 = lv[2][r] * 256 + lv[3][r];
-              const int i45 = lv[4][r] * 256 + lv[5][r];
-              const double h = fma((double)i01, 0x1p32, fma((double)i23, 0x1p16, (double)i45));
-              const double x = ldexp(h, cur.ea[r] + eb - 2044 - 52);
+              // levels 0..NP-1 (weights 2^(-8t)) -> one FP64 value in units of
+              // 2^(-8 (NP - 1)); adjacent levels are first joined in 32 bits
+              double h = 0.0;
+#pragma unroll
+              for (int t = 0; t < NP; t += 2) {
+                if (t + 1 < NP) h = fma(h, 65536.0, (double)(lv[t][r] * 256 + lv[t + 1][r]));
+                else h = fma(h, 256.0, (double)lv[t][r]);
+              }
+              const double x = ldexp(h, cur.ea[r] + eb - 2044 - 12 - 8 * (NP - 1));
               if (P == 0) {
                 acc[u][ct][0][r] += x;
                 acc[u][ct][1][r] += x;
@@ -370,16 +383,27 @@ size_t flush_work_bytes(int engine, int nsys, int n_list, int K) {
   return units * (kOzPlanes * kOzPlaneBytes + 16 * sizeof(int));
 }
 
-hipError_t launch_flush_oz(const FlushArgs& a, dim3 grid, int ow_mode, hipStream_t st) {
+template <typename SB, typename SO, int NP>
+static hipError_t launch_oz(const FlushArgs& a, dim3 grid, int ow_mode, hipStream_t st) {
   const int n_chunks = (a.K + kOzKC - 1) / kOzKC;
   const int64_t units = (int64_t)a.nsys * (a.n_list / 16) * n_chunks * 3;
   v4i* planes = static_cast<v4i*>(a.work);
-  int* rexp = reinterpret_cast<int*>(static_cast<char*>(a.work) + units * kOzPlanes * kOzPlaneBytes);
+  int* rexp = reinterpret_cast<int*>(static_cast<char*>(a.work) + units * NP * kOzPlaneBytes);
   const int64_t blocks = (units * kWave + 255) / 256;
   if (blocks > 0)
-    hipLaunchKernelGGL(k_oz_coef, dim3((unsigned)blocks), dim3(256), 0, st, a, n_chunks, planes, rexp);
-  hipLaunchKernelGGL(k_flush_oz, grid, dim3(kOzWaves * kWave), 0, st, a, planes, rexp, n_chunks, ow_mode);
+    hipLaunchKernelGGL(k_oz_coef<NP>, dim3((unsigned)blocks), dim3(256), 0, st, a, n_chunks, planes, rexp);
+  hipLaunchKernelGGL((k_flush_oz<SB, SO, NP>), grid, dim3(kOzWaves * kWave), 0, st, a, planes, rexp, n_chunks,
+                     ow_mode);
   return hipGetLastError();
+}
+
+// complex128 banks: six planes (46 bits); complex64 banks (24-bit values):
+// five planes (38 bits), 15 digit pairs
+hipError_t launch_flush_oz(Elem eb, Elem eo, const FlushArgs& a, dim3 grid, int ow_mode, hipStream_t st) {
+  if (eb == Elem::C128 && eo == Elem::C128) return launch_oz<double, double, 6>(a, grid, ow_mode, st);
+  if (eb == Elem::C64 && eo == Elem::C64) return launch_oz<float, float, 5>(a, grid, ow_mode, st);
+  if (eb == Elem::C64 && eo == Elem::C128) return launch_oz<float, double, 5>(a, grid, ow_mode, st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace msb

@@ -600,9 +600,9 @@ hipError_t launch_flush(Elem eb, Elem eo, const FlushArgs& a, int ow_mode, int e
   // 16-byte staging of complex64 slots needs an even D (the caller picks engine 2 otherwise)
   if (eb == Elem::C64 && (a.D & 1) && flush_coef_comps(engine) == 3) return hipErrorInvalidValue;
   if (engine == 5) {
-    // complex128 bank and output only; the digit planes go to a.work
-    if (eb != Elem::C128 || eo != Elem::C128 || !a.work) return hipErrorInvalidValue;
-    return launch_flush_oz(a, grid, ow_mode, st);
+    // the digit planes go to a.work
+    if (!a.work) return hipErrorInvalidValue;
+    return launch_flush_oz(eb, eo, a, grid, ow_mode, st);
   }
   if (engine == 6) {
     if (eb != Elem::C128) return hipErrorInvalidValue;     // complex128 bank

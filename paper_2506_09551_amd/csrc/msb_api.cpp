@@ -1053,12 +1053,20 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   const int64_t D = ctx->D;
   const int mx = std::max(maxit, 1);
   int engine = opts ? opts->assembly_engine : 0;
-  if (engine < 0 || engine >= kNumFlushEngines) return fail(MSB_EINVAL, "msb_solve: unknown assembly engine");
-  // the three-product engines stage complex64 slots in 16-byte units, which
-  // needs an even D (16-byte aligned slots); odd D takes the four-product one
-  if (prec == MSB_C64 && (ctx->D & 1) && flush_coef_comps(engine) == 3) engine = 2;
-  // the int8 and FP64 matrix-core engines take complex128 banks only
-  if (prec == MSB_C64 && (engine == 5 || engine == 6)) engine = 0;
+  if (engine < 0 || engine > kNumFlushEngines) return fail(MSB_EINVAL, "msb_solve: unknown assembly engine");
+  // 0, the default: the FP64 vector engine, except for a complex64 bank with
+  // many shifts, which the int8 matrix-core engine assembles faster (five
+  // digit planes of 24-bit values; with few shifts per system its workgroups
+  // of 256 shift slots stay mostly idle); kNumFlushEngines: the FP64 vector
+  // engine in every case
+  if (engine == 0 && prec == MSB_C64 && n_shift >= 128) engine = 5;
+  if (engine == kNumFlushEngines) engine = 0;
+  // the FP64 matrix-core engine takes complex128 banks only
+  if (prec == MSB_C64 && engine == 6) engine = 0;
+  // the three-product vector engines stage complex64 slots in 16-byte units,
+  // which needs an even D (16-byte aligned slots); odd D takes the
+  // four-product one
+  if (prec == MSB_C64 && (ctx->D & 1) && flush_coef_comps(engine) == 3 && engine != 5) engine = 2;
   const int tile_s = flush_shifts_per_tile(engine);
   const int n_list = ((n_shift + tile_s - 1) / tile_s) * tile_s;
   const size_t s_el = elem_bytes(ev), s_out = elem_bytes(eo);

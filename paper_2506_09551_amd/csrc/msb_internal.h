@@ -340,12 +340,13 @@ struct FlushArgs {
 // default), 1 = FP64 matrix cores, 2 = FP64 vector ALU, four real products,
 // 3 = as 0 with eight wavefronts (64 shifts per workgroup), 4 = eight
 // wavefronts of four shifts and 256 elements, 5 = int8 matrix cores on
-// 8-bit digit planes of the FP64 operands (complex128 bank and output),
-// 6 = FP64 matrix cores, three real products (complex128 bank)
+// 8-bit digit planes of the FP64 operands (six planes for a complex128 bank,
+// five for complex64), 6 = FP64 matrix cores, three real products
+// (complex128 bank)
 constexpr int kNumFlushEngines = 7;
 size_t flush_work_bytes(int engine, int nsys, int n_list, int K);
 // engine 5 (k_flush_oz.hip): coefficient digit planes, then the contraction
-hipError_t launch_flush_oz(const FlushArgs& a, dim3 grid, int ow_mode, hipStream_t st);
+hipError_t launch_flush_oz(Elem bank, Elem out, const FlushArgs& a, dim3 grid, int ow_mode, hipStream_t st);
 // engine 6 (k_flush_mf64.hip)
 hipError_t launch_flush_mf64(Elem out, const FlushArgs& a, int ow_mode, hipStream_t st);
 hipError_t launch_flush(Elem bank, Elem out, const FlushArgs& a, int ow_mode, int engine,

@@ -441,13 +441,14 @@ def test_other_models(gpu, name):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("engine", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("engine", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_assembly_engines_match_direct_solve(tiny, engine, prec):
     """Every multi-shift assembly engine (three-product vector ALU and its two
     variants, FP64 matrix cores with four products, four-product vector ALU,
-    int8 matrix cores on digit planes, FP64 matrix cores with three products;
-    complex64 banks take engine 0 in place of 5 and 6), with and without
-    carry
+    int8 matrix cores on digit planes (six planes for complex128 banks, five
+    for complex64), FP64 matrix cores with three products (complex64 banks
+    take the vector engine), and 7, the vector engine in every case), with
+    and without carry
     (a 41-slot bank), in both storage precisions; 70 shifts span more than one
     shift tile with a ragged last one, and D = 4900 ends in a ragged element
     tile."""
