@@ -1063,10 +1063,10 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   if (engine == kNumFlushEngines) engine = 0;
   // the FP64 matrix-core engine takes complex128 banks only
   if (prec == MSB_C64 && engine == 6) engine = 0;
-  // the three-product vector engines stage complex64 slots in 16-byte units,
-  // which needs an even D (16-byte aligned slots); odd D takes the
-  // four-product one
-  if (prec == MSB_C64 && (ctx->D & 1) && flush_coef_comps(engine) == 3 && engine != 5) engine = 2;
+  // the three-product engines take complex64 slots in 16-byte units (or
+  // assume them aligned so), which needs an even D; odd D takes the
+  // four-product vector engine
+  if (prec == MSB_C64 && (ctx->D & 1) && flush_coef_comps(engine) == 3) engine = 2;
   const int tile_s = flush_shifts_per_tile(engine);
   const int n_list = ((n_shift + tile_s - 1) / tile_s) * tile_s;
   const size_t s_el = elem_bytes(ev), s_out = elem_bytes(eo);

@@ -497,9 +497,11 @@ def test_matrix_core_engines_many_shifts_match_direct_solve(tiny, engine):
         assert _rel(psi5[0], psi0[0]) <= 1e-10, f"slots {slots}: {_rel(psi5[0], psi0[0]):.3e}"
 
 
-def test_c64_odd_dimension(gpu):
+@pytest.mark.parametrize("engine", [0, 5])
+def test_c64_odd_dimension(gpu, engine):
     """An odd D (L = 7 ring, N = 3 + 3, D = 1225): complex64 slots are not
-    16-byte aligned, so the assembly falls back to the four-product engine."""
+    16-byte aligned, so the assembly (the default, and the int8 engine when
+    asked for) falls back to the four-product vector engine."""
     msb = gpu
     m = dict(L=7, nu=3, nd=3, bonds=W.chain_bonds(7, 1.0), U=6.0)
     ctx = msb.msb_create(m["L"], m["nu"], m["nd"], m["bonds"], m["U"])
@@ -510,7 +512,8 @@ def test_c64_odd_dimension(gpu):
         w = np.linspace(-6.0, 6.0, 19)
         sysd = msb.make_system(core_site=2, Uc=-3.0, E_G=-1.5, Gamma=0.9)
         for slots in (0, 17):
-            st, info, psi = _run(msb, ctx, [sysd], E, w, 1e-6, 2000, msb.MSB_C64, opts={"bank_slots": slots})
+            st, info, psi = _run(msb, ctx, [sysd], E, w, 1e-6, 2000, msb.MSB_C64,
+                                 opts={"bank_slots": slots, "assembly_engine": engine})
             ref = osolve.direct_solve(oracle_H(m, core_site=2, Uc=-3.0), E, -1.5, 0.9, w, method="eig")
             assert _rel(psi[0], ref) <= 5e-5
     finally:
