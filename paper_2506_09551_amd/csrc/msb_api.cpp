@@ -865,12 +865,20 @@ extern "C" msb_status msb_ground_state(msb_ctx* ctx, const msb_system* sys, cons
     MSB_HIP(hipMemcpyAsync(coef, ab, 2 * sizeof(double), hipMemcpyHostToDevice, st));
     MSB_HIP(launch_lanczos_real_update(w, qk, k > 0 ? Q + (size_t)(k - 1) * D : nullptr, coef, D,
                                        partials, red, st));
+    double w2 = 0;   // |w|^2 before the reorthogonalisation
+    MSB_HIP(hipMemcpyAsync(&w2, red, sizeof(double), hipMemcpyDeviceToHost, st));
+    // full reorthogonalisation by classical Gram-Schmidt against every q_j; a
+    // second pass only if the first removed more than half of |w|^2 (the
+    // criterion of Kahan and Parlett: otherwise w is orthogonal to working
+    // precision after one pass)
+    double bb = 0;
     for (int pass = 0; pass < 2; ++pass) {
       MSB_HIP(launch_dot_many(Q, k + 1, w, D, partials, red, st));
       MSB_HIP(launch_gemv_sub(Q, k + 1, red, w, D, st));
+      if ((r = dot(w, w, bb)) != MSB_OK) return r;   // (synchronises: w2 has landed)
+      if (bb >= 0.5 * w2) break;
+      w2 = bb;
     }
-    double bb = 0;
-    if ((r = dot(w, w, bb)) != MSB_OK) return r;
     const double bnext = std::sqrt(bb);
     theta = tridiag_lowest(a, b, y);
     const double est = std::fabs(bnext * y.back());
