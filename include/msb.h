@@ -145,6 +145,8 @@ typedef struct {
   double t_alloc_ms;     /* host wall time of (re)allocating the workspace (0 when reused) */
   double t_wall_ms;      /* host wall time of the whole call */
   int apply_panel_width; /* columns of the seed apply's LDS panel (passes 3), else 0 */
+  int group;             /* systems iterated together: the batch ran in groups of this many */
+  int bank_slots;        /* residual slots per system in the bank (a flush when they are full) */
 } msb_info;
 
 /* One launch shape of the Hamiltonian apply and its measured time. */
@@ -168,7 +170,12 @@ typedef struct {
 typedef struct {
   int chunk;             /* seed iterations per captured graph launch (default 16) */
   int bank_slots;        /* residual slots kept before a flush; 0 = min(maxit + 1, 1024) */
-  int batch;             /* systems iterated together (block apply); 0 = all that fit */
+  int batch;             /* systems iterated together (block apply), at most; 0 = no limit.  The
+                            whole batch runs together when every system's bank holds
+                            `bank_slots` slots; otherwise it runs in the largest groups whose
+                            banks hold min(bank_slots, 512) slots each (a flush before the
+                            last iteration also assembles the search directions), and only
+                            when no group does, all together with the largest bank that fits */
   int replace_every;     /* MSB_C64 only: the seed residual is replaced by E - A_s x_m (x_m and the
                             product in complex128) at the first chunk boundary at least
                             `replace_every` iterations after the previous replacement (a bank

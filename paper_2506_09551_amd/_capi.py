@@ -50,7 +50,7 @@ class msb_info(ctypes.Structure):
                 ("seed_hist", POINTER(c_double)), ("hist_len", c_int),
                 ("apply_threads", c_int), ("apply_ept", c_int), ("apply_nv", c_int), ("apply_passes", c_int),
                 ("apply_order", c_int), ("t_setup_ms", c_double), ("t_alloc_ms", c_double), ("t_wall_ms", c_double),
-                ("apply_panel_width", c_int)]
+                ("apply_panel_width", c_int), ("group", c_int), ("bank_slots", c_int)]
 
 
 class msb_shape(ctypes.Structure):
@@ -418,6 +418,7 @@ def msb_solve(ctx, systems, E, w_in, seed_shift: float, tol: float, maxit: int, 
         "apply_shape": (info.apply_threads, info.apply_ept, info.apply_nv, info.apply_passes,
                         info.apply_order, info.apply_panel_width),
         "t_setup_ms": info.t_setup_ms, "t_alloc_ms": info.t_alloc_ms, "t_wall_ms": info.t_wall_ms,
+        "group": info.group, "bank_slots": info.bank_slots,
     }
     if raise_on_fail and st != MSB_OK:
         raise MsbError(st, lib().msb_last_error().decode())

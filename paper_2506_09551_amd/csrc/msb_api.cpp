@@ -1140,25 +1140,47 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
   // workloads); a fixed size keeps repeated solves on the same workspace.
   int want_cap = std::min(mx + 1, 1024);
   if (opts && opts->bank_slots > 0) want_cap = std::min(mx + 1, std::max(opts->bank_slots, 3));
-  // Prefer the whole batch: first with a bank for every iteration, then with a
-  // smaller bank plus the carried p^w buffer, and only then fewer systems.
   const int min_cap = std::min(want_cap, 64);
-  for (int B = Bmax; B >= 1 && planB == 0; --B) {
-    const bool carry_needed = want_cap < mx + 1;
-    if (need_bytes(B, want_cap, carry_needed) <= budget) {
-      planB = B; plancap = want_cap; plancarry = carry_needed;
-      break;
-    }
-    if (need_bytes(B, min_cap, true) > budget) continue;
-    int lo = min_cap, hi = want_cap;        // largest cap that fits with a carry buffer
+  const bool carry_full = want_cap < mx + 1;
+  // largest bank below want_cap that fits B systems with a carry buffer (0:
+  // not even min_cap), in whole multiples of 32 slots, so that small changes
+  // of the free memory give the same plan (and the same workspace) on the
+  // next call; called only when want_cap itself does not fit
+  auto largest_cap = [&](int B) {
+    if (need_bytes(B, min_cap, true) > budget) return 0;
+    int lo = min_cap, hi = want_cap;
     while (hi - lo > 1) {
       const int mid = lo + (hi - lo) / 2;
       if (need_bytes(B, mid, true) <= budget) lo = mid; else hi = mid;
     }
-    // whole multiples of 32 slots, so that small changes of the free memory
-    // give the same plan (and the same workspace) on the next call
     if (lo > min_cap) lo = std::max(min_cap, lo - lo % 32);
-    planB = B; plancap = lo; plancarry = true;
+    return lo;
+  };
+  // Prefer the whole batch with the full bank.  When that does not fit, take
+  // the largest group of systems whose banks still hold kGroupSlots slots
+  // each: a flush before the last iteration also assembles every shift's
+  // search direction (the carried p^w), twice the assembly work of the slots
+  // it covers, while iterating more systems together saves only a few per
+  // cent of the seed iterations (measured: four 4x4-cluster systems 7%),
+  // because the apply's gathers are per system.  Only when no group reaches
+  // that does the whole batch run with the largest smaller bank that fits.
+  constexpr int kGroupSlots = 512;
+  const int group_slots = std::min(want_cap, kGroupSlots);
+  for (int B = Bmax; B >= 1 && planB == 0; --B) {
+    if (need_bytes(B, want_cap, carry_full) <= budget) {
+      planB = B; plancap = want_cap; plancarry = carry_full;
+      break;
+    }
+    const int c = largest_cap(B);
+    if (c >= group_slots) {
+      planB = B; plancap = c; plancarry = true;
+    }
+  }
+  for (int B = Bmax; B >= 1 && planB == 0; --B) {
+    const int c = largest_cap(B);
+    if (c > 0) {
+      planB = B; plancap = c; plancarry = true;
+    }
   }
   if (planB == 0) {
     for (int cap = min_cap - 1; cap >= 3; --cap) {
@@ -1761,6 +1783,8 @@ extern "C" msb_status msb_solve(msb_ctx* ctx, const msb_system* sys, int nsys, c
     info->apply_passes = seed_shape.passes;
     info->apply_order = seed_shape.order;
     info->apply_panel_width = seed_shape.passes == 3 ? seed_shape.pw : 0;
+    info->group = B;
+    info->bank_slots = cap;
     info->t_iter_ms = t_iter;
     info->t_flush_ms = t_flush;
     info->t_true_ms = t_true;

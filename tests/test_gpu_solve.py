@@ -193,6 +193,52 @@ def test_large_batch_runs_in_two_parts(tiny, case):
                       / info_d["seed_hist"][j][:k]) <= 1e-9
 
 
+def test_memory_bound_batch_runs_in_groups(tiny):
+    """A batch whose residual banks do not fit in the allowed memory runs in
+    groups of systems whose banks hold at least 512 slots each, so that no
+    flush before the last iteration (which also assembles the search
+    directions) is needed; only when no group reaches 512 slots does the
+    whole batch run with a short bank and carried directions.  Both plans
+    give every system's solution to the direct solve's and the unlimited
+    solve's accuracy.  (Budgets of about 100 MB and 34 MB for four systems of
+    D = 4,900: the first holds 2 x ~600 slots but not 3 x 512, the second
+    4 x 64 but not 1 x 512.)"""
+    import torch
+    msb, ctx, wl, m = tiny
+    D = msb.msb_dim(ctx)
+    E_G = -2.6661474201323485
+    systems = [msb.make_system(core_site=j, Uc=wl.Uc, E_G=E_G, Gamma=wl.Gamma) for j in range(4)]
+    E = np.stack([W.random_complex(D, 140 + j) for j in range(4)])
+    w = np.linspace(-6.0, 8.0, 16)
+    tol = 1e-12
+    _, info_u, psi_u = _run(msb, ctx, systems, E, w, tol, 3000, msb.MSB_C128)
+    assert info_u["group"] == 4 and info_u["bank_slots"] == 1024 and info_u["flushes"] == 1
+    ctx2 = msb.msb_create(wl.n_sites, wl.n_up, wl.n_dn, wl.bonds, wl.U)
+    try:
+        for budget, want_group in ((100e6, 2), (34e6, 4)):
+            msb.msb_release_workspace(ctx2)
+            free = torch.cuda.mem_get_info()[0]
+            st, info, psi = _run(msb, ctx2, systems, E, w, tol, 3000, msb.MSB_C128,
+                                 opts={"mem_fraction": budget / free})
+            assert st == msb.MSB_OK
+            assert info["group"] == want_group, (budget, info["group"], info["bank_slots"])
+            if want_group == 2:
+                assert info["bank_slots"] >= 512
+                assert info["iters"] < info["bank_slots"]
+                assert info["flushes"] == 2                  # one per group, none carried
+            else:
+                assert info["bank_slots"] < 512
+                assert info["flushes"] > 1
+            for j, s in enumerate(systems):
+                ref = osolve.direct_solve(oracle_H(m, core_site=s.core_site, Uc=s.Uc), E[j], E_G,
+                                          wl.Gamma, w, method="eig")
+                assert _rel(psi[j], ref) <= 1e-9, f"system {j}"
+                assert _rel(psi[j], psi_u[j]) <= 1e-10, f"system {j}"
+            assert np.max(info["resid_true"]) <= 1e-11
+    finally:
+        msb.msb_destroy(ctx2)
+
+
 def test_c64_batch_of_four_unsplit(tiny):
     """Four systems with real right-hand sides (as E = O_2 G of the workloads)
     in one batch: complex64 with residual replacement against the direct
