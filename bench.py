@@ -190,12 +190,18 @@ def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec, E_G, n_
     kk = torch.as_tensor(sub_k, device=psi.device)
     phi_b = psi[:, kk].to(torch.complex128).reshape(n * len(sub_k), D)
 
+    sep_split = {}
+
     def separate():
+        sep_split.clear()
         for j in range(n):
-            st, _ = msb.msb_solve(ctx, [systems[j]], E[j:j + 1], wl.w_in, wl.seed_shift, tol, wl.maxit,
-                                  prec, psi[j:j + 1], want_true=True, raise_on_fail=False, opts=C64_OPTS)
+            st, inf = msb.msb_solve(ctx, [systems[j]], E[j:j + 1], wl.w_in, wl.seed_shift, tol, wl.maxit,
+                                    prec, psi[j:j + 1], want_true=True, raise_on_fail=False, opts=C64_OPTS)
             if st not in (msb.MSB_OK, msb.MSB_FLOOR):
                 raise msb.MsbError(st, msb.lib().msb_last_error().decode())
+            for key, name in (("t_iter_ms", "seed_iterations_ms"), ("t_flush_ms", "assembly_ms"),
+                              ("t_true_ms", "true_residual_ms")):
+                sep_split[name] = sep_split.get(name, 0.0) + inf[key]
 
     separate()                     # warm-up
     torch.cuda.synchronize()
@@ -238,6 +244,7 @@ def batched_extras(msb, ctx, wl, systems, E, psi, ms_batched, tol, prec, E_G, n_
     el = x.element_size()
     res = {
         "separate_ms": round(ms_sep, 3), "batched_ms": round(ms_batched, 3),
+        "separate_split_ms": {k: round(v, 3) for k, v in sep_split.items()},
         "speedup_batched_vs_separate": round(ms_sep / ms_batched, 3),
         "plain_c128_separate_ms": round(ms128, 3),
         "speedup_batched_vs_plain_c128": round(ms128 / ms_batched, 3),
@@ -670,6 +677,7 @@ def form_summary(name, out):
         b = out["batched"]
         s.update({"separate_same_precision_ms": b["separate_ms"],
                   "speedup_vs_separate_same_precision": b["speedup_batched_vs_separate"],
+                  "separate_split_ms": b["separate_split_ms"], "group": out["group"],
                   "separate_c128_ms": b["plain_c128_separate_ms"],
                   "speedup_vs_c128": b["speedup_batched_vs_plain_c128"],
                   "spectrum_rel_err_vs_c128": b["spectrum_rel_err_vs_c128"]["max"],
@@ -804,6 +812,7 @@ def run_solver_workload(wl_name, args, extras=True, cpu=True):
         },
         "iters": last["iters"],
         "solve_status": last["status_name"],
+        "group": int(last["group"]), "bank_slots": int(last["bank_slots"]),
         "apply_shape": {"threads": last["apply_shape"][0], "elems_per_thread": last["apply_shape"][1],
                         "systems_per_workgroup": last["apply_shape"][2], "passes": last["apply_shape"][3],
                         "row_order": last["apply_shape"][4], "panel_width": last["apply_shape"][5]},
