@@ -20,6 +20,13 @@ __device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erf
 __device__ __forceinline__ float gelu_grad_f(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
+// gelu(x) and gelu'(x) from one erf: the forward pass keeps gelu'(z) for the
+// backward pass (the only use of the pre-activation z)
+__device__ __forceinline__ void gelu_both(float x, float& g, float& gp) {
+  const float c = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+  g = x * c;
+  gp = c + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
 
 // ---- matrix-core product --------------------------------------------------
 // C[M][N] = sum_k A[m][k] B[n][k]: both operands are stored k-contiguous (the
@@ -33,8 +40,13 @@ constexpr int kGM = 128, kGN = 128, kGK = 64, kGPad = 8;
 
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ __align__(16) __bf16 sa[2][kGM][kGK + kGPad];
-  __shared__ __align__(16) __bf16 sb[2][kGN][kGK + kGPad];
+  // operand stages; after the K loop the same bytes hold the transposed
+  // output tile st[column][row] (128 x (128 + 8) bf16 = 34 KB of the 72 KB)
+  __shared__ __align__(16) __bf16 sab[2 * 2 * kGM * (kGK + kGPad)];
+  auto& sa = *reinterpret_cast<__bf16 (*)[2][kGM][kGK + kGPad]>(sab);
+  auto& sb = *reinterpret_cast<__bf16 (*)[2][kGN][kGK + kGPad]>(sab + 2 * kGM * (kGK + kGPad));
+  auto& st = *reinterpret_cast<__bf16 (*)[kGN][kGM + kGPad]>(sab);
+  static_assert(kGN * (kGM + kGPad) <= 4 * kGM * (kGK + kGPad), "transposed tile fits the operand stages");
   const int splits = g.splitk > 1 ? g.splitk : 1;
   const int mem = blockIdx.z / splits, ks = blockIdx.z % splits;
   const int klen = g.K / splits, kbeg = ks * klen;
@@ -110,25 +122,43 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
           const float v = acc[i][j][4 * q + r];
           if constexpr (EPI == kEpiFwd) {
             const float z = v + g.bias[(int64_t)mem * g.sBias + col];
-            g.C[(int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = z;
-            hv[r] = (__bf16)gelu_f(z);
+            float h, hp;
+            if (g.C) {            // training: keep gelu'(z) for the backward pass
+              gelu_both(z, h, hp);
+              g.C[(int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = hp;
+            } else {
+              h = gelu_f(z);
+            }
+            hv[r] = (__bf16)h;
             g.H[(int64_t)mem * g.sH + (int64_t)row * g.ldh + col] = hv[r];
           } else if constexpr (EPI == kEpiDh) {
             const float zp = g.Zp[(int64_t)mem * g.sZ + (int64_t)row * g.ldz + col];
-            hv[r] = (__bf16)(v * gelu_grad_f(zp));
+            hv[r] = (__bf16)(v * zp);
             g.H[(int64_t)mem * g.sH + (int64_t)row * g.ldh + col] = hv[r];
           } else {    // float32 output; a K slice writes its own partial copy
             g.C[(int64_t)ks * g.sCk + (int64_t)mem * g.sC + (int64_t)row * g.ldc + col] = v;
           }
         }
         if constexpr (EPI != kEpiStore) {
-          if (g.HT) {   // transposed copy: four consecutive rows are one 8-byte store
+          if (g.HT) {   // transposed tile in LDS: four consecutive rows are one 8-byte write
             typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
             bf16x4 t4 = {hv[0], hv[1], hv[2], hv[3]};
-            *reinterpret_cast<bf16x4*>(g.HT + (int64_t)mem * g.sHT + (int64_t)col * g.ldht + row0) = t4;
+            *reinterpret_cast<bf16x4*>(&st[col - n0][row0 - m0]) = t4;
           }
         }
       }
+  if constexpr (EPI != kEpiStore) {
+    if (g.HT) {
+      // the 128 x 128 transposed tile leaves as whole 256-byte rows of H^T
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int c = tid + it * 256, cl = c >> 4, rc = (c & 15) * 8;
+        *reinterpret_cast<bf16x8*>(g.HT + (int64_t)mem * g.sHT + (int64_t)(n0 + cl) * g.ldht + m0 + rc) =
+            *reinterpret_cast<const bf16x8*>(&st[cl][rc]);
+      }
+    }
+  }
 }
 
 hipError_t launch_gemm(int epi, const GemmArgs& g, int members, hipStream_t st) {
@@ -167,11 +197,18 @@ __global__ __launch_bounds__(256) void k_layer1_fwd(MlpFwdArgs a) {
       for (int k = 0; k < kMlpIn; ++k) z += (a.X[pt * kMlpIn + k] - a.in_shift[k]) * w[k];
     }
     const int64_t i = (int64_t)mem * a.act_stride + (int64_t)b * kMlpH + n;
-    a.z1[i] = z;
-    const __bf16 h = (__bf16)gelu_f(z);
+    float hf, hp;
+    if (a.z1) {                   // training: keep gelu'(z1) for the backward pass
+      gelu_both(z, hf, hp);
+      a.z1[i] = hp;
+    } else {
+      hf = gelu_f(z);
+    }
+    const __bf16 h = (__bf16)hf;
     a.h1[i] = h;
     tile[threadIdx.x & 63][r] = h;
   }
+  if (!a.h1T) return;             // inference: no transposed copy
   __syncthreads();
   // transposed: h1T[n][b], 4 threads per column, 16 rows each
   const int c = threadIdx.x >> 2, r0 = (threadIdx.x & 3) * 16;
@@ -246,7 +283,7 @@ __global__ __launch_bounds__(256) void k_layer4_bwd(MlpFwdArgs a) {
     const int b = b0 + r;
     const int64_t i = (int64_t)mem * a.act_stride + (int64_t)b * kMlpH + n;
     const float gv = a.g[(int64_t)mem * a.y_stride + b];
-    const __bf16 d = (__bf16)(gv * w * gelu_grad_f(a.z3[i]));
+    const __bf16 d = (__bf16)(gv * w * a.z3[i]);   // z3 holds gelu'(z3)
     a.dz3[i] = d;
     tile[threadIdx.x & 63][r] = d;
   }

@@ -53,7 +53,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t act_need(int members, int cap) {
   const size_t a = (size_t)cap * kMlpH;
   size_t n = 0;
-  n += 3 * align256(members * a * sizeof(float));        // z1..z3
+  n += 3 * align256(members * a * sizeof(float));        // gelu'(z1)..gelu'(z3)
   n += 10 * align256(members * a * sizeof(__bf16));      // h1..h3, dz1..dz3, four transposed copies
   n += 2 * align256((size_t)members * cap * sizeof(float));   // y, g
   n += align256((size_t)members * max_parts(cap) * kMlpIn * kMlpH * sizeof(float));   // partials
@@ -436,6 +436,8 @@ extern "C" msb_status msb_mlp_predict(msb_mlp* m, const float* X, int64_t n, flo
     const int rows = (valid + 127) / 128 * 128;
     MlpFwdArgs a = fwd_args(m, v, X, nullptr, rows, valid);
     a.base = b0;
+    a.z1 = a.z2 = a.z3 = nullptr;     // inference keeps neither gelu'(z) nor transposed copies
+    a.h1T = a.h2T = nullptr;
     MSB_HIP(forward(m, 0, m->members, a, st));
     MSB_HIP(launch_ensemble_stats(v.y, v.y_stride, m->members, valid, 1.0f / m->out_scale, mean + b0, sd + b0, st));
   }

@@ -51,11 +51,11 @@ struct MlpFwdArgs {
   const float* in_shift; const float* in_scale;  // device [6]
   float out_scale;         // model output = out_scale * I
   const float* params; int64_t pstride;
-  float *z1, *z2, *z3;     // [members][batch][512]
+  float *z1, *z2, *z3;     // [members][batch][512] gelu'(z) of layers 1-3 for the backward pass (nullptr: not kept)
   __bf16 *h1, *h2, *h3;
   __bf16 *dz1, *dz2, *dz3;
   int64_t act_stride;
-  __bf16 *h1T, *h2T, *dz2T, *dz3T;  // transposed copies [members][512][ldT] (weight-gradient operands)
+  __bf16 *h1T, *h2T, *dz2T, *dz3T;  // transposed copies [members][512][ldT] (weight-gradient operands; h1T, h2T nullptr: not written)
   int64_t actT_stride, ldT;
   float* y; float* g; int64_t y_stride;          // [members][batch]
   double* loss_part;       // [members][batch / 4]
