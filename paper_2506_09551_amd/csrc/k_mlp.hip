@@ -17,9 +17,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad_f(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
-}
 // gelu(x) and gelu'(x) from one erf: the forward pass keeps gelu'(z) for the
 // backward pass (the only use of the pre-activation z)
 __device__ __forceinline__ void gelu_both(float x, float& g, float& gp) {
