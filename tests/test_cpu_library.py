@@ -71,14 +71,16 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in line["error"]
 
 
-@pytest.mark.parametrize("name", ["msb_opts", "msb_shape"])
+@pytest.mark.parametrize("name", ["msb_opts", "msb_shape", "msb_info", "msb_system"])
 def test_struct_layout_matches_header(name):
-    """The ctypes mirrors of the plain-value structs list the header's fields in order."""
+    """The ctypes mirrors of the structs list the header's fields in order
+    (ints, doubles, pointers to them and fixed arrays)."""
     from paper_2506_09551_amd import _capi
     text = (ROOT / "include" / "msb.h").read_text()
     end = text.index("} " + name + ";")
     body = text[text.rindex("typedef struct {", 0, end):end]
-    fields = re.findall(r"^\s*(?:int|double)\s+(\w+);", body, flags=re.M)
+    fields = re.findall(r"^\s*(?:int|double)\s*\*?\s*(\w+)(?:\[[^\]]*\])?;", body, flags=re.M)
+    assert len(fields) > 3
     assert [f[0] for f in getattr(_capi, name)._fields_] == fields
 
 
